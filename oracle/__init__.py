@@ -1,0 +1,169 @@
+"""ORACLE — TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct CPU implementations of what the GPU library
+computes, written from the paper (GraphBLAST, Yang, Buluc and Owens):
+
+* :func:`Adjacency` — graph cleaning of the experimental section (dataset
+  table caption: self-loops and duplicate edges removed, undirected graphs
+  symmetrised), built from the raw edge list by its own code.
+* :func:`bfs` — level-synchronous BFS of Algorithm 1 as a queue BFS; levels
+  are hop counts (the paper's 1-based d minus one), parents are the
+  smallest-id neighbour one level up.
+* :func:`sssp` — exact single-source shortest paths (Dijkstra), the result
+  the paper's Bellman-Ford variant (Section 7.2) converges to.
+* :func:`pagerank` — FP64 power iteration (Section 7.3) with uniform
+  redistribution of dangling mass and an L1 stopping rule.
+* :func:`msbfs` — k independent BFS runs (multi-nodeset traversal).
+* :mod:`oracle.mxv` — the plain-loop masked semiring mxv / vxm.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU
+library and imports nothing from it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import mxv as mxv_mod  # noqa: F401  (re-export)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so in place (gcc -O2, single-threaded code)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
+               "-pthread", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        p, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.oracle_adj_build.argtypes = [i64, i64, p, p, p, ctypes.c_int]
+        lib.oracle_adj_build.restype = p
+        lib.oracle_adj_free.argtypes = [p]
+        lib.oracle_adj_free.restype = None
+        lib.oracle_adj_nnz.argtypes = [p]
+        lib.oracle_adj_nnz.restype = i64
+        lib.oracle_adj_n.argtypes = [p]
+        lib.oracle_adj_n.restype = i64
+        lib.oracle_adj_copy.argtypes = [p, p, p, p]
+        lib.oracle_adj_copy.restype = None
+        lib.oracle_adj_transpose.argtypes = [p]
+        lib.oracle_adj_transpose.restype = p
+        lib.oracle_bfs.argtypes = [p, i32, p, p]
+        lib.oracle_bfs.restype = i32
+        lib.oracle_sssp.argtypes = [p, i32, p, p]
+        lib.oracle_sssp.restype = i64
+        lib.oracle_pagerank.argtypes = [p, f64, i32, f64, p, p]
+        lib.oracle_pagerank.restype = i32
+        lib.oracle_msbfs.argtypes = [p, i64, p, p, i32]
+        lib.oracle_msbfs.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Adjacency:
+    """Cleaned adjacency lists of a raw edge list (rows ascending)."""
+
+    def __init__(self, n, src, dst, w=None, symmetrise=True, _handle=None):
+        lib = _load()
+        self.n = int(n)
+        if _handle is not None:
+            self._h = _handle
+        else:
+            src = np.ascontiguousarray(src, dtype=np.int32)
+            dst = np.ascontiguousarray(dst, dtype=np.int32)
+            w = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+            self._h = lib.oracle_adj_build(self.n, src.shape[0], _ptr(src), _ptr(dst),
+                                           _ptr(w), 1 if symmetrise else 0)
+            if not self._h:
+                raise ValueError("oracle_adj_build failed (bad vertex id or out of memory)")
+        self.nnz = int(lib.oracle_adj_nnz(self._h))
+        self.weighted = w is not None if _handle is None else None
+
+    @classmethod
+    def from_raw(cls, g):
+        """From a graphgen.RawGraph."""
+        return cls(g.n, g.src, g.dst, g.w, symmetrise=g.symmetric)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.oracle_adj_free(h)
+            self._h = None
+
+    def arrays(self, weights=True):
+        """(off int64[n+1], nbr int32[nnz], w float64[nnz] or None)."""
+        off = np.empty(self.n + 1, dtype=np.int64)
+        nbr = np.empty(self.nnz, dtype=np.int32)
+        w = np.empty(self.nnz, dtype=np.float64) if weights else None
+        _load().oracle_adj_copy(self._h, _ptr(off), _ptr(nbr), _ptr(w))
+        return off, nbr, w
+
+    def transpose(self):
+        h = _load().oracle_adj_transpose(self._h)
+        t = Adjacency(self.n, None, None, _handle=h)
+        t.weighted = self.weighted
+        return t
+
+
+def bfs(adj: Adjacency, source: int, parents: bool = True):
+    """(levels int32[n], parents int32[n] or None, number of levels)."""
+    lev = np.empty(adj.n, dtype=np.int32)
+    par = np.empty(adj.n, dtype=np.int32) if parents else None
+    nl = _load().oracle_bfs(adj._h, int(source), _ptr(lev), _ptr(par))
+    if nl < 0:
+        raise ValueError("oracle_bfs: bad source")
+    return lev, par, int(nl)
+
+
+def sssp(adj: Adjacency, source: int):
+    """(dist float32[n] with +inf unreached, dist float64[n], reached count)."""
+    d32 = np.empty(adj.n, dtype=np.float32)
+    d64 = np.empty(adj.n, dtype=np.float64)
+    r = _load().oracle_sssp(adj._h, int(source), _ptr(d32), _ptr(d64))
+    if r < 0:
+        raise ValueError("oracle_sssp: bad source or unweighted graph")
+    return d32, d64, int(r)
+
+
+def pagerank(adj_out: Adjacency, alpha=0.85, max_iter=50, tol=1e-7):
+    """(p float64[n], iterations run, last L1 delta); adj_out = out-edges."""
+    p = np.empty(adj_out.n, dtype=np.float64)
+    delta = ctypes.c_double(0.0)
+    it = _load().oracle_pagerank(adj_out._h, float(alpha), int(max_iter), float(tol),
+                                 _ptr(p), ctypes.byref(delta))
+    if it < 0:
+        raise ValueError("oracle_pagerank: bad input")
+    return p, int(it), float(delta.value)
+
+
+def msbfs(adj: Adjacency, sources, nthreads: int = 1):
+    """levels int32[k, n] of k independent BFS runs."""
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    lev = np.empty((src.shape[0], adj.n), dtype=np.int32)
+    rc = _load().oracle_msbfs(adj._h, src.shape[0], _ptr(src), _ptr(lev), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_msbfs: bad source")
+    return lev
