@@ -1,0 +1,369 @@
+/*
+ * grb.h — C ABI of an MI355X (gfx950) library for the masked matrix-vector
+ * multiply over a semiring, the operation GraphBLAST (Yang, Buluc, Owens,
+ * "GraphBLAST: A High-Performance Linear Algebra-based Graph Framework on
+ * the GPU", ACM TOMS 2021) builds its graph algorithms on.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All graph and vector buffers are DEVICE memory owned by the caller and
+ *   only borrowed by the library.  The library never allocates device
+ *   memory: temporary storage comes from a caller-provided workspace whose
+ *   size grb_workspace_size() reports.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Work is enqueued on it and the call returns without waiting, except
+ *   where a function is documented as synchronising.
+ * - Indices are int32: a matrix may hold at most 2^31 - 1 stored entries
+ *   and 2^31 - 1 rows/columns.
+ * - Every call returns grb_info.  Argument errors are detected on the host,
+ *   before anything is enqueued, and leave all buffers untouched.  A device
+ *   fault surfaces as GRB_PANIC from the next synchronising call or from
+ *   grb_stream_check().  No C++ exception crosses this interface.
+ * - Handles (grb_matrix, grb_vector) are host objects.  A matrix is
+ *   read-only once prepared and may be used from several streams at once;
+ *   a vector and a workspace may be used by one call at a time.
+ */
+#ifndef GRB_H
+#define GRB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes, named after the GraphBLAS C API codes the paper defers to
+ * (caption of the mxv figure, Section 3.3). */
+typedef enum grb_info {
+  GRB_SUCCESS = 0,
+  GRB_NO_VALUE = 1,
+  GRB_UNINITIALIZED_OBJECT = 2, /* NULL handle, or matrix not prepared */
+  GRB_NULL_POINTER = 3,         /* required pointer argument is NULL */
+  GRB_INVALID_VALUE = 4,        /* bad size, flag, enum or parameter */
+  GRB_INVALID_INDEX = 5,        /* vertex id out of range */
+  GRB_DOMAIN_MISMATCH = 6,      /* vector/matrix type does not fit the semiring */
+  GRB_DIMENSION_MISMATCH = 7,   /* operand sizes disagree */
+  GRB_NOT_IMPLEMENTED = 8,      /* combination this library does not provide */
+  GRB_INSUFFICIENT_SPACE = 9,   /* workspace or metadata buffer too small */
+  GRB_OUT_OF_MEMORY = 10,       /* host allocation failed */
+  GRB_PANIC = 11                /* HIP runtime or device error */
+} grb_info;
+
+/* Element types.  GRB_BOOL is one byte per element (0 = false). */
+typedef enum grb_type {
+  GRB_BOOL = 0,
+  GRB_INT32 = 1,
+  GRB_FP32 = 2,
+  GRB_FP64 = 3
+} grb_type;
+
+/*
+ * Semirings (Table 4 of the paper): (add, multiply, domain, identity).
+ * A matrix without values acts as if every stored entry were 1 (true).
+ *   LOR_LAND    (or, and, {0,1}, false)      structure-only traversal (BFS)
+ *   MIN_PLUS    (min, +, R u {+inf}, +inf)   shortest paths
+ *   PLUS_TIMES  (+, *, R, 0)                 classical products (PageRank)
+ *   MIN_FIRST   (min, first, int32, INT32_MAX)
+ *   MIN_SECOND  (min, second, int32, INT32_MAX)
+ * For mxv the multiply is A(i,j) (x) u(j); for vxm it is u(i) (x) A(i,j).
+ * So vxm with MIN_FIRST, or mxv with MIN_SECOND, returns the smallest
+ * vector value among the contributing neighbours: with u(j) = j on the
+ * frontier that is the smallest-id parent.
+ */
+typedef enum grb_semiring {
+  GRB_LOR_LAND_BOOL = 0,
+  GRB_MIN_PLUS_FP32 = 1,
+  GRB_MIN_PLUS_FP64 = 2,
+  GRB_PLUS_TIMES_FP32 = 3,
+  GRB_PLUS_TIMES_FP64 = 4,
+  GRB_MIN_FIRST_INT32 = 5,
+  GRB_MIN_SECOND_INT32 = 6
+} grb_semiring;
+
+/* Optional accumulator applied between the old output and the product
+ * (GraphBLAS C API semantics; the accumulator must be the semiring's add:
+ * LOR for LOR_LAND, MIN for MIN_*, PLUS for PLUS_TIMES). */
+typedef enum grb_binop {
+  GRB_NOACCUM = 0,
+  GRB_ACCUM_MIN = 1,
+  GRB_ACCUM_PLUS = 2,
+  GRB_ACCUM_LOR = 3
+} grb_binop;
+
+/* Descriptor flags (Table 3 of the paper, plus REPLACE and a structural
+ * mask from the GraphBLAS C API). */
+#define GRB_MASK_COMP   0x1u /* use the structural complement of the mask */
+#define GRB_MASK_STRUCT 0x2u /* mask by presence instead of by value */
+#define GRB_TRAN_A      0x4u /* transpose the matrix operand */
+#define GRB_REPLACE     0x8u /* clear output entries outside the mask */
+#define GRB_PROFILE     0x10u /* drivers: time expand kernels with HIP events */
+
+/* Direction of a product (Section 4): push = sparse-vector SpMSpV over the
+ * input's nonzeros; pull = masked SpMV over the allowed output rows. */
+typedef enum grb_direction {
+  GRB_DIR_AUTO = 0,
+  GRB_DIR_PUSH = 1,
+  GRB_DIR_PULL = 2
+} grb_direction;
+
+/*
+ * Switch rule for GRB_DIR_AUTO (Table 5 and Section 4.4.1 of the paper).
+ *   PAPER: estimate |E_f| = (nnz/n) * nnz(u) and assume |E_u| = nnz, so
+ *          pull iff denominator * nnz(u) > n.
+ *   EXACT: |E_f| = sum of the input's row degrees (computed on the device
+ *          while the input is compacted): pull iff denominator * |E_f| > nnz.
+ * Equality picks push.  Results never depend on the rule, only speed.
+ */
+typedef enum grb_switch_rule {
+  GRB_SWITCH_PAPER = 0,
+  GRB_SWITCH_EXACT = 1
+} grb_switch_rule;
+
+typedef struct grb_descriptor {
+  uint32_t flags;             /* GRB_MASK_COMP | GRB_MASK_STRUCT | ... */
+  int32_t direction;          /* grb_direction */
+  int32_t switch_rule;        /* grb_switch_rule */
+  int32_t switch_denominator; /* 0 selects the paper's 10 */
+  int32_t max_iter;           /* drivers: iteration cap, 0 = unlimited */
+  int32_t reserved[3];        /* must be zero */
+} grb_descriptor;
+
+/* Fills d with the defaults: no flags, AUTO, PAPER rule, denominator 10. */
+grb_info grb_descriptor_init(grb_descriptor *d);
+
+typedef struct grb_matrix_s *grb_matrix;
+typedef struct grb_vector_s *grb_vector;
+
+/* ------------------------------------------------------------------ */
+/* Graph construction on the host (setup, not part of any timed path)  */
+/* ------------------------------------------------------------------ */
+
+typedef struct grb_csr_builder_s *grb_csr_builder;
+
+/*
+ * Builds a CSR graph on the host from a raw edge list (host arrays), as
+ * the paper prepares its datasets (dataset table caption, Section 8):
+ * self-loops dropped; with `symmetrise` each (u, v) also gives (v, u);
+ * duplicates collapse to one entry keeping the smallest weight; rows end up
+ * sorted by column.  w may be NULL (structure only).  Swapping src and dst
+ * builds the transpose.  Errors: GRB_NULL_POINTER, GRB_INVALID_VALUE (n or
+ * m negative, n >= 2^31), GRB_INVALID_INDEX (endpoint outside [0, n)),
+ * GRB_OUT_OF_MEMORY, GRB_INVALID_VALUE if the result exceeds 2^31-1 entries.
+ */
+grb_info grb_csr_build(grb_csr_builder *b, int64_t n, int64_t m, const int32_t *src,
+                       const int32_t *dst, const float *w, int symmetrise);
+/* Number of stored entries of the built CSR. */
+grb_info grb_csr_nnz(grb_csr_builder b, int64_t *nnz);
+/* Copies the CSR out to host arrays: row_ptr (n+1), col_idx (nnz), values
+ * (nnz floats; may be NULL, must be NULL if built without weights). */
+grb_info grb_csr_copy(grb_csr_builder b, int32_t *row_ptr, int32_t *col_idx, float *values);
+grb_info grb_csr_free(grb_csr_builder *b);
+
+/* ------------------------------------------------------------------ */
+/* Matrix                                                              */
+/* ------------------------------------------------------------------ */
+
+#define GRB_MATRIX_SYMMETRIC 0x1u /* A == A^T: the CSR also serves as CSC */
+
+/*
+ * Wraps caller-owned device CSR arrays (borrowed, must stay alive and
+ * unchanged while the handle is used):
+ *   row_ptr[nrows+1], col_idx[nnz] with columns ascending inside each row,
+ *   values[nnz] of vtype (GRB_FP32/GRB_FP64/GRB_INT32) or NULL;
+ *   t_row_ptr/t_col_idx/t_values: the CSR of A^T (= CSC of A), or NULL.
+ * Paper, Section 4.4.3: CSR serves row access (pull), CSC column access
+ * (push).  With GRB_MATRIX_SYMMETRIC the transpose arguments must be NULL
+ * and the CSR is used for both.  A product whose chosen direction needs a
+ * missing orientation fails with GRB_NOT_IMPLEMENTED (AUTO falls back to
+ * the direction that is available).
+ */
+grb_info grb_matrix_create(grb_matrix *A, int64_t nrows, int64_t ncols, int64_t nnz,
+                           const int32_t *row_ptr, const int32_t *col_idx,
+                           const void *values, grb_type vtype,
+                           const int32_t *t_row_ptr, const int32_t *t_col_idx,
+                           const void *t_values, uint32_t flags);
+grb_info grb_matrix_free(grb_matrix *A);
+grb_info grb_matrix_nrows(grb_matrix A, int64_t *n);
+grb_info grb_matrix_ncols(grb_matrix A, int64_t *n);
+grb_info grb_matrix_nvals(grb_matrix A, int64_t *nnz);
+
+/*
+ * Derived metadata (split lists of very long rows for the pull kernels) is
+ * built into a caller-owned device buffer of at least *bytes bytes.
+ * grb_matrix_prepare synchronises `stream` (it reads back how many long
+ * rows exist).  Every product and driver requires a prepared matrix
+ * (else GRB_UNINITIALIZED_OBJECT).  The buffer is borrowed like the CSR.
+ */
+grb_info grb_matrix_meta_size(grb_matrix A, size_t *bytes);
+grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Vector                                                              */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Wraps caller-owned device storage of a length-n vector:
+ *   values[n] elements of `type` (the value of index i lives at values[i]),
+ *   bitmap[(n+63)/64] presence words, bit (i % 64) of word i / 64; bits at
+ *   positions >= n must be zero.
+ * The dense layout serves both directions: pull tests presence bits, push
+ * compacts the bitmap into a sorted index list inside the workspace
+ * (Section 4.4.3: the backend, not the user, switches representations).
+ */
+grb_info grb_vector_create(grb_vector *v, int64_t n, grb_type type, void *values,
+                           uint64_t *bitmap);
+grb_info grb_vector_free(grb_vector *v);
+grb_info grb_vector_size(grb_vector v, int64_t *n);
+/* Removes every entry (presence bits cleared; values untouched). */
+grb_info grb_vector_clear(grb_vector v, void *stream);
+/* Every index present with the value *scalar (host pointer to one element). */
+grb_info grb_vector_fill(grb_vector v, const void *scalar, void *stream);
+/*
+ * Clears v, then sets v(idx[k]) = vals[k] for k < count, from DEVICE arrays
+ * idx (int32) and vals (`type`, or NULL: every value 1).  Indices must be
+ * in [0, n) (out-of-range entries are skipped); with duplicate indices one
+ * of their values is kept.
+ */
+grb_info grb_vector_build(grb_vector v, const int32_t *idx, const void *vals,
+                          int64_t count, void *stream);
+/* Number of present entries.  Synchronises `stream`; needs a workspace of
+ * at least 64 bytes. */
+grb_info grb_vector_nvals(grb_vector v, int64_t *nvals, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Workspace                                                           */
+/* ------------------------------------------------------------------ */
+
+typedef enum grb_op {
+  GRB_OP_MXV = 0,      /* grb_mxv / grb_vxm with this matrix */
+  GRB_OP_BFS = 1,
+  GRB_OP_SSSP = 2,
+  GRB_OP_PAGERANK = 3, /* k = 1 for fp32, 2 for fp64 */
+  GRB_OP_MSBFS = 4,    /* k = number of sources */
+  GRB_OP_NVALS = 5
+} grb_op;
+
+/* Bytes of device workspace the operation needs on matrix A.  Workspace
+ * contents need no initialisation; the address must be 256-byte aligned. */
+grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes);
+
+/* ------------------------------------------------------------------ */
+/* The masked semiring products                                        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * w<mask> = accum(w, A u) over semiring s (Section 3.3 and the mxv figure
+ * caption: w = A u .* mask; descriptor per Table 3).  With GRB_TRAN_A the
+ * product uses A^T.  Definition (per output index i):
+ *   t(i) = (+)_{j : A'(i,j) stored and u(j) present} A'(i,j) (x) u(j);
+ *          t(i) exists iff that set is non-empty;
+ *   z = t without accum; with accum z(i) = accum(w(i), t(i)) where both
+ *          exist, else whichever exists;
+ *   allowed(i) = no mask, or (m(i) xor GRB_MASK_COMP) where m(i) means
+ *          "mask(i) present and non-zero" (or "present" with GRB_MASK_STRUCT);
+ *   w(i) := z(i) (absent if z(i) is) where allowed; elsewhere w keeps its
+ *          entry, or loses it under GRB_REPLACE.
+ * Direction: d->direction forces push or pull; AUTO applies d->switch_rule
+ * on the device (no host synchronisation).  Push needs the CSR of A'^T,
+ * pull the CSR of A'.  Results are identical in either direction for
+ * LOR_LAND, MIN_* (any order) and bitwise-reproducible for PLUS_TIMES in
+ * pull; PLUS_TIMES in push uses atomic adds (order-dependent rounding).
+ * Types: u, w (and accum) must have the semiring's domain type (BOOL,
+ * INT32, FP32 or FP64); the mask may have any type.  w must not alias u or
+ * the mask.  d may be NULL (defaults).
+ * Errors: GRB_UNINITIALIZED_OBJECT, GRB_DIMENSION_MISMATCH, GRB_DOMAIN_MISMATCH,
+ * GRB_INVALID_VALUE, GRB_NOT_IMPLEMENTED, GRB_INSUFFICIENT_SPACE, GRB_PANIC.
+ */
+grb_info grb_mxv(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s,
+                 grb_matrix A, grb_vector u, const grb_descriptor *d, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* w<mask> = accum(w, u A): t(j) = (+)_i u(i) (x) A'(i,j); otherwise as
+ * grb_mxv (vxm is mxv on the transposed matrix, decomposition figure). */
+grb_info grb_vxm(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s,
+                 grb_vector u, grb_matrix A, const grb_descriptor *d, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Graph algorithms built on the products (Section 7)                  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Direction-optimised BFS from `source` (Algorithm 1; Section 7.1):
+ * each level computes f <- A^T f .* not(visited) over LOR_LAND, pushing or
+ * pulling per the descriptor's rule, with early exit in pull.
+ * levels[n]: hop count (source 0, unreached -1; the paper's d minus one).
+ * parents[n] (may be NULL): smallest-id neighbour one level closer
+ * (source: itself, unreached: -1).  A must be square; the traversal follows
+ * stored entries A(u, v) from u to v (push reads the CSR of A, pull the
+ * CSR of A^T; a symmetric matrix serves both).
+ * Synchronises `stream` once per batch of levels (it reads the frontier
+ * size back to detect the end).  d->max_iter caps the levels (0 = none).
+ */
+grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source,
+                 const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * SSSP from `source` (Section 7.2): Bellman-Ford over MIN_PLUS with the
+ * frontier sparsified to the vertices whose distance improved in the last
+ * round; stops when none improved.  dist[n] (fp32): +inf where unreached.
+ * A must carry FP32 values >= 0.  Synchronises like grb_bfs.
+ */
+grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descriptor *d,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * PageRank (Section 7.3, pull form, always SpMV since the vector stays
+ * dense).  A holds the out-edges u -> v and must carry the CSR of A^T (or be
+ * symmetric).  p[n] of `type` (GRB_FP32 or GRB_FP64) receives the ranks:
+ * p0 = 1/n; per iteration D = sum of p over vertices without out-edges,
+ * p'(v) = (1-damping)/n + damping * (sum_{u->v} p(u)/outdeg(u) + D/n),
+ * delta = ||p' - p||_1; stops after max_iter iterations or once
+ * delta < tol.  *iters receives the number of iterations run and
+ * *delta_out (may be NULL) the last delta.  Synchronises once at the end.
+ */
+grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping,
+                      int32_t max_iter, double tol, int32_t *iters, double *delta_out,
+                      const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Statistics and errors                                               */
+/* ------------------------------------------------------------------ */
+
+#define GRB_STATS_MAX 256
+
+/* Per-iteration record of the last driver call on this host thread. */
+typedef struct grb_stats {
+  int32_t op;            /* grb_op of the call */
+  int32_t iterations;    /* levels / rounds / iterations run */
+  int32_t recorded;      /* entries filled below (min(iterations, GRB_STATS_MAX)) */
+  int32_t pushes;        /* iterations that ran push */
+  int32_t pulls;         /* iterations that ran pull */
+  int32_t reserved;
+  int64_t edges_push;    /* total sum of frontier degrees over push iterations */
+  double expand_ms_push; /* GRB_PROFILE: summed push-expand kernel time */
+  double expand_ms_pull; /* GRB_PROFILE: summed pull-expand kernel time */
+  int32_t direction[GRB_STATS_MAX]; /* 1 push, 2 pull */
+  int64_t frontier[GRB_STATS_MAX];  /* frontier size entering the iteration */
+  int64_t edges[GRB_STATS_MAX];     /* sum of frontier degrees */
+  float kernel_ms[GRB_STATS_MAX];   /* GRB_PROFILE: expand kernel time */
+} grb_stats;
+
+grb_info grb_last_stats(grb_stats *s);
+
+/* Static English text for an error code. */
+const char *grb_error_string(grb_info info);
+
+/* Synchronises `stream` and reports a pending HIP error as GRB_PANIC. */
+grb_info grb_stream_check(void *stream);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t grb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRB_H */

@@ -1,0 +1,382 @@
+"""Python binding of libgrb (the C ABI declared in include/grb.h).
+
+Argument marshalling only: torch supplies device memory and the HIP stream,
+every computation runs in the library's HIP kernels.  Importing this package
+on a machine where libgrb.so was not built raises ImportError; there is no
+fallback path.
+
+Low-level functions keep the C names (``grb_bfs``, ``grb_mxv``, ...) and take
+raw pointers; the classes below (:class:`Matrix`, :class:`Vector`) and the
+helpers (:func:`bfs`, :func:`sssp`, :func:`pagerank`, :func:`mxv`,
+:func:`vxm`) wrap them around torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrb.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_1908_01407_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- enums and flags (mirror include/grb.h) ---------------------------------
+GRB_SUCCESS = 0
+ERRORS = {
+    1: "GRB_NO_VALUE", 2: "GRB_UNINITIALIZED_OBJECT", 3: "GRB_NULL_POINTER",
+    4: "GRB_INVALID_VALUE", 5: "GRB_INVALID_INDEX", 6: "GRB_DOMAIN_MISMATCH",
+    7: "GRB_DIMENSION_MISMATCH", 8: "GRB_NOT_IMPLEMENTED", 9: "GRB_INSUFFICIENT_SPACE",
+    10: "GRB_OUT_OF_MEMORY", 11: "GRB_PANIC",
+}
+GRB_BOOL, GRB_INT32, GRB_FP32, GRB_FP64 = 0, 1, 2, 3
+SEMIRINGS = {
+    "lor_land": 0, "min_plus_fp32": 1, "min_plus_fp64": 2, "plus_times_fp32": 3,
+    "plus_times_fp64": 4, "min_first_int32": 5, "min_second_int32": 6,
+}
+ACCUMS = {None: 0, "min": 1, "plus": 2, "lor": 3}
+GRB_MASK_COMP, GRB_MASK_STRUCT, GRB_TRAN_A, GRB_REPLACE, GRB_PROFILE = 0x1, 0x2, 0x4, 0x8, 0x10
+DIR_AUTO, DIR_PUSH, DIR_PULL = 0, 1, 2
+SWITCH_PAPER, SWITCH_EXACT = 0, 1
+GRB_MATRIX_SYMMETRIC = 0x1
+OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS = 0, 1, 2, 3, 4, 5
+STATS_MAX = 256
+
+
+class GrbError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.grb_error_string(code).decode()
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({msg})")
+
+
+class Descriptor(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("direction", ctypes.c_int32),
+                ("switch_rule", ctypes.c_int32), ("switch_denominator", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("recorded", ctypes.c_int32), ("pushes", ctypes.c_int32),
+                ("pulls", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("edges_push", ctypes.c_int64), ("expand_ms_push", ctypes.c_double),
+                ("expand_ms_pull", ctypes.c_double),
+                ("direction", ctypes.c_int32 * STATS_MAX),
+                ("frontier", ctypes.c_int64 * STATS_MAX),
+                ("edges", ctypes.c_int64 * STATS_MAX),
+                ("kernel_ms", ctypes.c_float * STATS_MAX)]
+
+
+_p, _i32, _i64, _u32, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                             ctypes.c_size_t)
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+_SIGS = {
+    "grb_version": ([], _i32),
+    "grb_error_string": ([_i32], ctypes.c_char_p),
+    "grb_descriptor_init": ([ctypes.POINTER(Descriptor)], _i32),
+    "grb_last_stats": ([ctypes.POINTER(Stats)], _i32),
+    "grb_stream_check": ([_p], _i32),
+    "grb_csr_build": ([_PP, _i64, _i64, _p, _p, _p, ctypes.c_int], _i32),
+    "grb_csr_nnz": ([_p, ctypes.POINTER(_i64)], _i32),
+    "grb_csr_copy": ([_p, _p, _p, _p], _i32),
+    "grb_csr_free": ([_PP], _i32),
+    "grb_matrix_create": ([_PP, _i64, _i64, _i64, _p, _p, _p, _i32, _p, _p, _p, _u32], _i32),
+    "grb_matrix_free": ([_PP], _i32),
+    "grb_matrix_nrows": ([_p, ctypes.POINTER(_i64)], _i32),
+    "grb_matrix_ncols": ([_p, ctypes.POINTER(_i64)], _i32),
+    "grb_matrix_nvals": ([_p, ctypes.POINTER(_i64)], _i32),
+    "grb_matrix_meta_size": ([_p, ctypes.POINTER(_sz)], _i32),
+    "grb_matrix_prepare": ([_p, _p, _sz, _p], _i32),
+    "grb_vector_create": ([_PP, _i64, _i32, _p, _p], _i32),
+    "grb_vector_free": ([_PP], _i32),
+    "grb_vector_size": ([_p, ctypes.POINTER(_i64)], _i32),
+    "grb_vector_clear": ([_p, _p], _i32),
+    "grb_vector_fill": ([_p, _p, _p], _i32),
+    "grb_vector_build": ([_p, _p, _p, _i64, _p], _i32),
+    "grb_vector_nvals": ([_p, ctypes.POINTER(_i64), _p, _sz, _p], _i32),
+    "grb_workspace_size": ([_i32, _p, _i64, ctypes.POINTER(_sz)], _i32),
+    "grb_mxv": ([_p, _p, _i32, _i32, _p, _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_vxm": ([_p, _p, _i32, _i32, _p, _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_bfs": ([_p, _p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_sssp": ([_p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
+                      ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
+                      ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+}
+
+#: every C symbol this binding exposes, with its ctypes function
+C_FUNCTIONS = {}
+for _name, (_args, _ret) in _SIGS.items():
+    _f = getattr(_lib, _name, None)
+    if _f is None:
+        continue
+    _f.argtypes = _args
+    _f.restype = _ret
+    C_FUNCTIONS[_name] = _f
+    globals()[_name] = _f
+
+
+def check(code: int, where: str = "grb") -> None:
+    if code != GRB_SUCCESS:
+        raise GrbError(code, where)
+
+
+def descriptor(*, direction: int = DIR_AUTO, rule: int = SWITCH_PAPER, denominator: int = 10,
+               flags: int = 0, max_iter: int = 0) -> Descriptor:
+    d = Descriptor()
+    check(_lib.grb_descriptor_init(ctypes.byref(d)), "grb_descriptor_init")
+    d.flags = flags
+    d.direction = direction
+    d.switch_rule = rule
+    d.switch_denominator = denominator
+    d.max_iter = max_iter
+    return d
+
+
+def last_stats() -> dict:
+    s = Stats()
+    check(_lib.grb_last_stats(ctypes.byref(s)), "grb_last_stats")
+    r = s.recorded
+    return {
+        "op": s.op, "iterations": s.iterations, "pushes": s.pushes, "pulls": s.pulls,
+        "edges_push": s.edges_push, "expand_ms_push": s.expand_ms_push,
+        "expand_ms_pull": s.expand_ms_pull,
+        "direction": list(s.direction[:r]), "frontier": list(s.frontier[:r]),
+        "edges": list(s.edges[:r]), "kernel_ms": list(s.kernel_ms[:r]),
+    }
+
+
+# ---- host CSR construction ---------------------------------------------------
+
+def csr_from_edges(n: int, src, dst, w=None, symmetrise: bool = True):
+    """Cleaned CSR (row_ptr, col_idx, values or None) as numpy arrays."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    wp = None
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        wp = w.ctypes.data
+    h = ctypes.c_void_p()
+    check(_lib.grb_csr_build(ctypes.byref(h), n, src.shape[0], src.ctypes.data, dst.ctypes.data,
+                             wp, 1 if symmetrise else 0), "grb_csr_build")
+    try:
+        nnz = ctypes.c_int64()
+        check(_lib.grb_csr_nnz(h, ctypes.byref(nnz)), "grb_csr_nnz")
+        rp = np.empty(n + 1, dtype=np.int32)
+        ci = np.empty(max(nnz.value, 0), dtype=np.int32)
+        vals = np.empty(nnz.value, dtype=np.float32) if w is not None else None
+        check(_lib.grb_csr_copy(h, rp.ctypes.data, ci.ctypes.data if nnz.value else None,
+                                vals.ctypes.data if vals is not None and nnz.value else None),
+              "grb_csr_copy")
+    finally:
+        _lib.grb_csr_free(ctypes.byref(h))
+    return rp, ci, vals
+
+
+# ---- torch-backed objects ---------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(op: int, A: "Matrix", k: int = 0, device=None):
+    torch = _torch()
+    n = ctypes.c_size_t()
+    check(_lib.grb_workspace_size(op, A.handle if A is not None else None, k, ctypes.byref(n)),
+          "grb_workspace_size")
+    dev = device if device is not None else (A.device if A is not None else "cuda")
+    return torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+
+
+class Matrix:
+    """Device CSR (plus optional CSR of the transpose) wrapped in a grb_matrix."""
+
+    def __init__(self, n_rows, n_cols, row_ptr, col_idx, values=None, t_row_ptr=None,
+                 t_col_idx=None, t_values=None, symmetric=False, device="cuda", stream=None):
+        torch = _torch()
+        dev = torch.device(device)
+        self.device = dev
+
+        def to_dev(a, dt):
+            if a is None:
+                return None
+            if isinstance(a, np.ndarray):
+                a = torch.from_numpy(np.ascontiguousarray(a))
+            if a.numel() == 0:  # keep a valid (non-null) device address
+                return torch.zeros(1, dtype=dt, device=dev)
+            return a.to(device=dev, dtype=dt).contiguous()
+
+        self.row_ptr = to_dev(row_ptr, torch.int32)
+        self.col_idx = to_dev(col_idx, torch.int32)
+        vdt = torch.float64 if (values is not None and getattr(values, "dtype", None) in
+                                (np.float64, torch.float64)) else torch.float32
+        self.values = to_dev(values, vdt)
+        self.t_row_ptr = to_dev(t_row_ptr, torch.int32)
+        self.t_col_idx = to_dev(t_col_idx, torch.int32)
+        self.t_values = to_dev(t_values, vdt)
+        self.nrows, self.ncols = int(n_rows), int(n_cols)
+        self.nnz = int(col_idx.shape[0]) if hasattr(col_idx, "shape") else len(col_idx)
+        vtype = GRB_FP64 if vdt == torch.float64 else GRB_FP32
+        h = ctypes.c_void_p()
+        check(_lib.grb_matrix_create(
+            ctypes.byref(h), self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr),
+            _ptr(self.col_idx) if self.nnz else None, _ptr(self.values), vtype,
+            _ptr(self.t_row_ptr), _ptr(self.t_col_idx) if self.t_row_ptr is not None and self.nnz
+            else None, _ptr(self.t_values), GRB_MATRIX_SYMMETRIC if symmetric else 0),
+            "grb_matrix_create")
+        self.handle = h
+        sz = ctypes.c_size_t()
+        check(_lib.grb_matrix_meta_size(h, ctypes.byref(sz)), "grb_matrix_meta_size")
+        self.meta = torch.empty(max(sz.value, 256), dtype=torch.uint8, device=dev)
+        check(_lib.grb_matrix_prepare(h, _ptr(self.meta), self.meta.numel(), _stream(stream)),
+              "grb_matrix_prepare")
+
+    @classmethod
+    def from_raw(cls, g, device="cuda", weights=True, transpose=True):
+        """From a graphgen.RawGraph: symmetric graphs share one CSR; directed
+        graphs also get the CSR of the transpose (built from swapped edges)."""
+        w = g.w if weights else None
+        rp, ci, vals = csr_from_edges(g.n, g.src, g.dst, w, symmetrise=g.symmetric)
+        if g.symmetric:
+            return cls(g.n, g.n, rp, ci, vals, symmetric=True, device=device)
+        trp = tci = tvals = None
+        if transpose:
+            trp, tci, tvals = csr_from_edges(g.n, g.dst, g.src, w, symmetrise=False)
+        return cls(g.n, g.n, rp, ci, vals, trp, tci, tvals, symmetric=False, device=device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.grb_matrix_free(ctypes.byref(h))
+
+
+_TYPE_OF = {}
+
+
+def _type_code(dtype):
+    torch = _torch()
+    return {torch.uint8: GRB_BOOL, torch.bool: GRB_BOOL, torch.int32: GRB_INT32,
+            torch.float32: GRB_FP32, torch.float64: GRB_FP64}[dtype]
+
+
+class Vector:
+    """values[n] + presence bitmap[(n+63)/64] on the device, as a grb_vector."""
+
+    def __init__(self, n: int, dtype=None, device="cuda"):
+        torch = _torch()
+        dtype = dtype if dtype is not None else torch.float32
+        if dtype == torch.bool:
+            dtype = torch.uint8
+        self.n = int(n)
+        self.dtype = dtype
+        self.values = torch.zeros(max(self.n, 1), dtype=dtype, device=device)
+        self.bitmap = torch.zeros(max((self.n + 63) // 64, 1), dtype=torch.int64, device=device)
+        h = ctypes.c_void_p()
+        check(_lib.grb_vector_create(ctypes.byref(h), self.n, _type_code(dtype),
+                                     _ptr(self.values), _ptr(self.bitmap)), "grb_vector_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _lib.grb_vector_free(ctypes.byref(h))
+
+    def set(self, entries: dict, stream=None):
+        """Clears, then sets the given {index: value} entries (via grb_vector_build)."""
+        torch = _torch()
+        idx = torch.tensor(sorted(entries), dtype=torch.int32, device=self.values.device)
+        vals = torch.tensor([entries[i] for i in sorted(entries)], dtype=self.dtype,
+                            device=self.values.device)
+        check(_lib.grb_vector_build(self.handle, _ptr(idx) if idx.numel() else None,
+                                    _ptr(vals) if vals.numel() else None, idx.numel(),
+                                    _stream(stream)), "grb_vector_build")
+        torch.cuda.current_stream().synchronize()
+
+    def to_dict(self) -> dict:
+        """Present entries as {index: value} (device -> host copy)."""
+        bm = self.bitmap.cpu().numpy().view(np.uint64)
+        vals = self.values.cpu().numpy()
+        bits = np.unpackbits(bm.view(np.uint8), bitorder="little")[: self.n].astype(bool)
+        out = {}
+        for i in np.flatnonzero(bits):
+            v = vals[i]
+            out[int(i)] = bool(v) if self.dtype == _torch().uint8 else v.item()
+        return out
+
+
+# ---- drivers and products --------------------------------------------------------
+
+def bfs(A: Matrix, source: int, *, parents: bool = True, desc: Descriptor | None = None,
+        ws=None, stream=None):
+    """(levels int32[n], parents int32[n] or None) via grb_bfs."""
+    torch = _torch()
+    lev = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device)
+    par = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device) if parents else None
+    ws = ws if ws is not None else workspace(OP_BFS, A)
+    check(_lib.grb_bfs(_ptr(lev), _ptr(par), A.handle, int(source),
+                       ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
+                       _stream(stream)), "grb_bfs")
+    return lev[: A.nrows], (par[: A.nrows] if par is not None else None)
+
+
+def sssp(A: Matrix, source: int, *, desc: Descriptor | None = None, ws=None, stream=None):
+    torch = _torch()
+    dist = torch.empty(max(A.nrows, 1), dtype=torch.float32, device=A.device)
+    ws = ws if ws is not None else workspace(OP_SSSP, A)
+    check(_lib.grb_sssp(_ptr(dist), A.handle, int(source),
+                        ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
+                        _stream(stream)), "grb_sssp")
+    return dist[: A.nrows]
+
+
+def pagerank(A: Matrix, *, dtype=None, damping: float = 0.85, max_iter: int = 50,
+             tol: float = 1e-7, desc: Descriptor | None = None, ws=None, stream=None):
+    """(p[n], iterations, last L1 delta) via grb_pagerank."""
+    torch = _torch()
+    dtype = dtype if dtype is not None else torch.float32
+    t = GRB_FP64 if dtype == torch.float64 else GRB_FP32
+    p = torch.empty(max(A.nrows, 1), dtype=dtype, device=A.device)
+    ws = ws if ws is not None else workspace(OP_PAGERANK, A, 2 if t == GRB_FP64 else 1)
+    iters = ctypes.c_int32()
+    delta = ctypes.c_double()
+    check(_lib.grb_pagerank(_ptr(p), t, A.handle, float(damping), int(max_iter), float(tol),
+                            ctypes.byref(iters), ctypes.byref(delta),
+                            ctypes.byref(desc) if desc is not None else None, _ptr(ws),
+                            ws.numel(), _stream(stream)), "grb_pagerank")
+    return p[: A.nrows], iters.value, delta.value
+
+
+def mxv(w: Vector, mask: Vector | None, accum, semiring: str, A: Matrix, u: Vector, *,
+        desc: Descriptor | None = None, ws=None, stream=None):
+    ws = ws if ws is not None else workspace(OP_MXV, A)
+    check(_lib.grb_mxv(w.handle, mask.handle if mask is not None else None, ACCUMS[accum],
+                       SEMIRINGS[semiring], A.handle, u.handle,
+                       ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
+                       _stream(stream)), "grb_mxv")
+
+
+def vxm(w: Vector, mask: Vector | None, accum, semiring: str, u: Vector, A: Matrix, *,
+        desc: Descriptor | None = None, ws=None, stream=None):
+    ws = ws if ws is not None else workspace(OP_MXV, A)
+    check(_lib.grb_vxm(w.handle, mask.handle if mask is not None else None, ACCUMS[accum],
+                       SEMIRINGS[semiring], u.handle, A.handle,
+                       ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
+                       _stream(stream)), "grb_vxm")

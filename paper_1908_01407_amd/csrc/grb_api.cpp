@@ -1,0 +1,745 @@
+// Host side of the C ABI: argument validation, handles, workspace layout
+// and the driver loops of BFS, SSSP and PageRank.  Every computation step
+// runs in the HIP kernels; this file only validates, carves the caller's
+// workspace and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "grb_internal.h"
+
+using namespace grb;
+
+namespace {
+
+thread_local grb_stats g_stats;
+
+int elem_size(grb_type t) {
+  switch (t) {
+    case GRB_BOOL: return 1;
+    case GRB_INT32: return 4;
+    case GRB_FP32: return 4;
+    case GRB_FP64: return 8;
+  }
+  return 0;
+}
+
+bool valid_type(int t) { return t >= GRB_BOOL && t <= GRB_FP64; }
+
+grb_info check_launch() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GRB_SUCCESS : GRB_PANIC;
+}
+
+grb_info resolve_desc(const grb_descriptor *d, grb_descriptor *out) {
+  grb_descriptor_init(out);
+  if (!d) return GRB_SUCCESS;
+  *out = *d;
+  const uint32_t known = GRB_MASK_COMP | GRB_MASK_STRUCT | GRB_TRAN_A | GRB_REPLACE | GRB_PROFILE;
+  if (out->flags & ~known) return GRB_INVALID_VALUE;
+  if (out->direction < GRB_DIR_AUTO || out->direction > GRB_DIR_PULL) return GRB_INVALID_VALUE;
+  if (out->switch_rule != GRB_SWITCH_PAPER && out->switch_rule != GRB_SWITCH_EXACT)
+    return GRB_INVALID_VALUE;
+  if (out->switch_denominator < 0 || out->max_iter < 0) return GRB_INVALID_VALUE;
+  for (int i = 0; i < 3; ++i)
+    if (out->reserved[i] != 0) return GRB_INVALID_VALUE;
+  if (out->switch_denominator == 0) out->switch_denominator = 10;
+  return GRB_SUCCESS;
+}
+
+// ---- workspace carving ----------------------------------------------------
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base((char *)b) {}
+  template <class T>
+  T *take(size_t count) {
+    T *p = base ? (T *)(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+struct TravWs {
+  uint64_t *visited, *fa, *fb, *status;
+  int32_t *list, *degpre, *tiles;
+  float *lval, *fval;
+  Ctrl *ctrl;
+  int64_t *stats;
+  int nblk;
+  size_t bytes;
+};
+
+TravWs trav_layout(void *ws, int64_t n, int64_t nnz_push, bool sssp) {
+  Carver c(ws);
+  TravWs t{};
+  const int64_t nw = words_of(n);
+  t.nblk = compact_blocks(nw);
+  t.ctrl = c.take<Ctrl>(1);
+  t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
+  t.status = c.take<uint64_t>((size_t)2 * t.nblk);
+  t.visited = c.take<uint64_t>((size_t)nw);
+  t.fa = c.take<uint64_t>((size_t)nw);
+  t.fb = c.take<uint64_t>((size_t)nw);
+  t.list = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
+  t.degpre = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
+  t.tiles = c.take<int32_t>((size_t)((n + nnz_push) / kPushTile + 3));
+  if (sssp) {
+    t.lval = c.take<float>((size_t)std::max<int64_t>(n, 1));
+    t.fval = c.take<float>((size_t)std::max<int64_t>(n, 1));
+  } else {
+    t.lval = t.fval = nullptr;
+  }
+  t.bytes = c.off;
+  return t;
+}
+
+struct PrWs {
+  Ctrl *ctrl;
+  void *x0, *x1, *heavy_part;
+  double *blk_part;
+  int nblk;
+  size_t bytes;
+};
+
+PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
+  Carver c(ws);
+  PrWs t{};
+  t.nblk = pr_grid(words_of(n));
+  t.ctrl = c.take<Ctrl>(1);
+  t.x0 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
+  t.x1 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
+  t.heavy_part = c.take<char>((size_t)std::max<int64_t>(pull.nheavy, 1) * esize);
+  t.blk_part = c.take<double>((size_t)2 * t.nblk);
+  t.bytes = c.off;
+  return t;
+}
+
+struct MxvWs {
+  Ctrl *ctrl;
+  uint64_t *status, *t_bm, *t_vb;
+  int32_t *list, *degpre, *tiles;
+  void *t_val;
+  int nblk;
+  size_t bytes;
+};
+
+MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz) {
+  Carver c(ws);
+  MxvWs t{};
+  t.nblk = compact_blocks(words_of(n_in));
+  t.ctrl = c.take<Ctrl>(1);
+  t.status = c.take<uint64_t>((size_t)2 * t.nblk);
+  t.list = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
+  t.degpre = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
+  t.tiles = c.take<int32_t>((size_t)((n_in + nnz) / kPushTile + 3));
+  t.t_bm = c.take<uint64_t>((size_t)words_of(n_out));
+  t.t_vb = c.take<uint64_t>((size_t)words_of(n_out));
+  t.t_val = c.take<char>((size_t)std::max<int64_t>(n_out, 1) * 8);
+  t.bytes = c.off;
+  return t;
+}
+
+grb_info check_ws(void *ws, size_t have, size_t need) {
+  if (need > have) return GRB_INSUFFICIENT_SPACE;
+  if (!ws) return GRB_NULL_POINTER;
+  if (((uintptr_t)ws) % 256 != 0) return GRB_INVALID_VALUE;
+  return GRB_SUCCESS;
+}
+
+// ---- matrix metadata ---------------------------------------------------------
+struct MetaLayout {
+  size_t heavy_off, heavy_rows_off, bytes;
+  int64_t max_pieces, max_rows;
+};
+
+MetaLayout meta_layout_one(int64_t nnz, size_t base) {
+  MetaLayout m{};
+  m.max_rows = nnz / (kHeavyDeg + 1) + 1;
+  m.max_pieces = nnz / kHeavyChunk + m.max_rows + 1;
+  m.heavy_off = base;
+  m.heavy_rows_off = align_up(base + (size_t)m.max_pieces * 2 * sizeof(int32_t));
+  m.bytes = align_up(m.heavy_rows_off + (size_t)m.max_rows * 3 * sizeof(int32_t));
+  return m;
+}
+
+grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
+  std::vector<int32_t> rp;
+  try {
+    rp.resize((size_t)c.nrows + 1);
+  } catch (const std::bad_alloc &) {
+    return GRB_OUT_OF_MEMORY;
+  }
+  if (hipMemcpyAsync(rp.data(), c.rp, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GRB_PANIC;
+  if (rp[0] != 0 || rp[(size_t)c.nrows] != c.nnz) return GRB_INVALID_VALUE;
+  std::vector<int32_t> pieces, rows;
+  for (int64_t r = 0; r < c.nrows; ++r) {
+    const int32_t b = rp[(size_t)r], e = rp[(size_t)r + 1];
+    if (e < b) return GRB_INVALID_VALUE;
+    if (e - b > kHeavyDeg) {
+      rows.push_back((int32_t)r);
+      rows.push_back((int32_t)(pieces.size() / 2));
+      int32_t np = 0;
+      for (int32_t p = b; p < e; p += kHeavyChunk, ++np) {
+        pieces.push_back((int32_t)r);
+        pieces.push_back(p);
+      }
+      rows.push_back(np);
+    }
+  }
+  if ((int64_t)pieces.size() / 2 > L.max_pieces || (int64_t)rows.size() / 3 > L.max_rows)
+    return GRB_PANIC;
+  int32_t *hp = (int32_t *)(meta + L.heavy_off);
+  int32_t *hr = (int32_t *)(meta + L.heavy_rows_off);
+  if (!pieces.empty() &&
+      hipMemcpyAsync(hp, pieces.data(), pieces.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
+  if (!rows.empty() &&
+      hipMemcpyAsync(hr, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
+  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+  c.heavy = hp;
+  c.nheavy = (int64_t)pieces.size() / 2;
+  c.heavy_rows = hr;
+  c.nheavy_rows = (int64_t)rows.size() / 3;
+  return GRB_SUCCESS;
+}
+
+// ---- profiling events --------------------------------------------------------
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  ~EventPool() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  hipEvent_t get(size_t i) {
+    while (ev.size() <= i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev.push_back(e);
+    }
+    return ev[i];
+  }
+};
+thread_local EventPool g_events;
+
+void finish_stats(int op, int iterations, const std::vector<int64_t> &rec,
+                  const std::vector<float> &kms) {
+  grb_stats &s = g_stats;
+  std::memset(&s, 0, sizeof(s));
+  s.op = op;
+  s.iterations = iterations;
+  s.recorded = std::min(iterations, (int)kStatsCap);
+  for (int i = 0; i < s.recorded; ++i) {
+    s.frontier[i] = rec[(size_t)i * kStatFields + 0];
+    s.edges[i] = rec[(size_t)i * kStatFields + 1];
+    s.direction[i] = (int32_t)rec[(size_t)i * kStatFields + 2];
+    if (s.direction[i] == GRB_DIR_PUSH) {
+      s.pushes++;
+      s.edges_push += s.edges[i];
+    } else if (s.direction[i] == GRB_DIR_PULL) {
+      s.pulls++;
+    }
+    if (i < (int)kms.size()) {
+      s.kernel_ms[i] = kms[(size_t)i];
+      if (s.direction[i] == GRB_DIR_PUSH) s.expand_ms_push += kms[(size_t)i];
+      else s.expand_ms_pull += kms[(size_t)i];
+    }
+  }
+}
+
+enum TravKind { kTravBfs, kTravSssp };
+
+// The level loop shared by BFS and SSSP: expand + compaction per level, all
+// on the device; the host reads the frontier size back once per batch of
+// levels to detect the end.
+grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *levels,
+                       int32_t *parents, float *dist, const grb_descriptor &desc, void *ws,
+                       size_t ws_bytes, void *stream) {
+  const int64_t n = A->nrows;
+  const bool can_pull = A->at.valid();
+  if (desc.direction == GRB_DIR_PULL && !can_pull) return GRB_NOT_IMPLEMENTED;
+  TravWs w = trav_layout(ws, n, A->a.nnz, kind == kTravSssp);
+  grb_info info = check_ws(ws, ws_bytes, w.bytes);
+  if (info != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+
+  TravArgs ta;
+  ta.n = n;
+  ta.nw = words_of(n);
+  ta.nnz = A->nnz;
+  ta.push = A->a;
+  ta.pull = A->at;
+  ta.can_push = true;
+  ta.can_pull = can_pull;
+  ta.visited = w.visited;
+  ta.parents = parents;
+  ta.dist = dist;
+  ta.fval = w.fval;
+  ta.lval = w.lval;
+  ta.wpush = (const float *)A->a.val;
+  ta.wpull = can_pull ? (const float *)A->at.val : nullptr;
+  ta.list = w.list;
+  ta.degpre = w.degpre;
+  ta.tiles = w.tiles;
+  ta.ctrl = w.ctrl;
+  ta.stats = w.stats;
+  ta.rule = desc.switch_rule;
+  ta.denom = desc.switch_denominator;
+  ta.forced = desc.direction;
+
+  const int64_t nstatus = 2 * (int64_t)w.nblk;
+  if (kind == kTravBfs)
+    launch_bfs_init(ta, levels, source, w.visited, w.fa, w.fb, w.status, nstatus, stream);
+  else
+    launch_sssp_init(ta, source, w.visited, w.fa, w.fb, w.status, nstatus, stream);
+
+  CompactArgs ca;
+  ca.nw = ta.nw;
+  ca.rp = A->a.rp;
+  ca.list = w.list;
+  ca.degpre = w.degpre;
+  ca.tiles = w.tiles;
+  ca.ctrl = w.ctrl;
+  ca.visited = w.visited;
+  ca.levels = levels;
+  ca.dist = dist;
+  ca.fval = w.fval;
+  ca.lval = w.lval;
+  const int cmode = kind == kTravBfs ? kCompactBfs : kCompactSssp;
+  int parity = 0;
+  auto compact = [&](uint64_t *nb, uint64_t *clear, int lev) {
+    ca.nb = nb;
+    ca.clear = clear;
+    ca.lev = lev;
+    ca.status_cur = w.status + (size_t)parity * w.nblk;
+    ca.status_next = w.status + (size_t)(parity ^ 1) * w.nblk;
+    launch_compact(cmode, ca, stream);
+    parity ^= 1;
+  };
+  compact(w.fb, nullptr, 0);  // level 0 = {source}
+
+  const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
+  int64_t d = 0;
+  int chunk = 8;
+  Ctrl hc{};
+  std::vector<int> ev_level;
+  for (;;) {
+    for (int i = 0; i < chunk && d < cap; ++i, ++d) {
+      uint64_t *fcur = (d % 2 == 0) ? w.fb : w.fa;
+      uint64_t *fnxt = (d % 2 == 0) ? w.fa : w.fb;
+      ta.fcur = fcur;
+      ta.fnxt = fnxt;
+      ta.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
+      const bool timed = profile && d < kStatsCap;
+      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
+      if (kind == kTravBfs) launch_bfs_expand(ta, stream);
+      else launch_sssp_expand(ta, stream);
+      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
+      compact(fnxt, fcur, (int)std::min<int64_t>(d + 1, INT32_MAX));
+    }
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return GRB_PANIC;
+    if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+    if (hc.count == 0 || d >= cap) break;
+    chunk = std::min(chunk * 2, 256);
+  }
+  const int iters = hc.nlev;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  const int nrec = std::min(iters, (int)kStatsCap);
+  if (nrec > 0) {
+    if (hipMemcpy(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return GRB_PANIC;
+  }
+  std::vector<float> kms;
+  if (profile) {
+    for (int i = 0; i < nrec; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
+      kms.push_back(ms);
+    }
+  }
+  finish_stats(kind == kTravBfs ? GRB_OP_BFS : GRB_OP_SSSP, iters, rec, kms);
+  return GRB_SUCCESS;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+int32_t grb_version(void) { return 100; }
+
+const char *grb_error_string(grb_info info) {
+  switch (info) {
+    case GRB_SUCCESS: return "success";
+    case GRB_NO_VALUE: return "no value";
+    case GRB_UNINITIALIZED_OBJECT: return "uninitialized object (NULL handle or matrix not prepared)";
+    case GRB_NULL_POINTER: return "required pointer is NULL";
+    case GRB_INVALID_VALUE: return "invalid value";
+    case GRB_INVALID_INDEX: return "index out of range";
+    case GRB_DOMAIN_MISMATCH: return "type does not match the semiring";
+    case GRB_DIMENSION_MISMATCH: return "dimension mismatch";
+    case GRB_NOT_IMPLEMENTED: return "not implemented";
+    case GRB_INSUFFICIENT_SPACE: return "workspace or metadata buffer too small";
+    case GRB_OUT_OF_MEMORY: return "host allocation failed";
+    case GRB_PANIC: return "HIP runtime or device error";
+  }
+  return "unknown error code";
+}
+
+grb_info grb_descriptor_init(grb_descriptor *d) {
+  if (!d) return GRB_NULL_POINTER;
+  std::memset(d, 0, sizeof(*d));
+  d->direction = GRB_DIR_AUTO;
+  d->switch_rule = GRB_SWITCH_PAPER;
+  d->switch_denominator = 10;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_last_stats(grb_stats *s) {
+  if (!s) return GRB_NULL_POINTER;
+  *s = g_stats;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_stream_check(void *stream) {
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GRB_PANIC;
+  return check_launch();
+}
+
+// ---- matrix ------------------------------------------------------------------
+
+grb_info grb_matrix_create(grb_matrix *A, int64_t nrows, int64_t ncols, int64_t nnz,
+                           const int32_t *row_ptr, const int32_t *col_idx, const void *values,
+                           grb_type vtype, const int32_t *t_row_ptr, const int32_t *t_col_idx,
+                           const void *t_values, uint32_t flags) {
+  if (!A) return GRB_NULL_POINTER;
+  *A = nullptr;
+  if (nrows < 0 || ncols < 0 || nnz < 0 || nrows >= INT32_MAX || ncols >= INT32_MAX ||
+      nnz > INT32_MAX)
+    return GRB_INVALID_VALUE;
+  if (flags & ~GRB_MATRIX_SYMMETRIC) return GRB_INVALID_VALUE;
+  if (!row_ptr || (nnz > 0 && !col_idx)) return GRB_NULL_POINTER;
+  if (values && vtype != GRB_INT32 && vtype != GRB_FP32 && vtype != GRB_FP64)
+    return GRB_INVALID_VALUE;
+  const bool sym = (flags & GRB_MATRIX_SYMMETRIC) != 0;
+  if (sym && (nrows != ncols || t_row_ptr || t_col_idx || t_values)) return GRB_INVALID_VALUE;
+  if (!t_row_ptr && (t_col_idx || t_values)) return GRB_INVALID_VALUE;
+  if (t_row_ptr && nnz > 0 && !t_col_idx) return GRB_NULL_POINTER;
+  if (t_values && !values) return GRB_INVALID_VALUE;
+  if (values && t_row_ptr && !t_values) return GRB_NULL_POINTER;
+  grb_matrix_s *m = new (std::nothrow) grb_matrix_s;
+  if (!m) return GRB_OUT_OF_MEMORY;
+  m->nrows = nrows;
+  m->ncols = ncols;
+  m->nnz = nnz;
+  m->symmetric = sym;
+  m->a.rp = row_ptr;
+  m->a.ci = col_idx;
+  m->a.val = values;
+  m->a.vtype = values ? (int)vtype : -1;
+  m->a.nrows = nrows;
+  m->a.ncols = ncols;
+  m->a.nnz = nnz;
+  if (sym) {
+    m->at = m->a;
+  } else if (t_row_ptr) {
+    m->at.rp = t_row_ptr;
+    m->at.ci = t_col_idx;
+    m->at.val = t_values;
+    m->at.vtype = t_values ? (int)vtype : -1;
+    m->at.nrows = ncols;
+    m->at.ncols = nrows;
+    m->at.nnz = nnz;
+  }
+  *A = m;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_matrix_free(grb_matrix *A) {
+  if (!A) return GRB_NULL_POINTER;
+  delete *A;
+  *A = nullptr;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_matrix_nrows(grb_matrix A, int64_t *n) {
+  if (!A) return GRB_UNINITIALIZED_OBJECT;
+  if (!n) return GRB_NULL_POINTER;
+  *n = A->nrows;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_matrix_ncols(grb_matrix A, int64_t *n) {
+  if (!A) return GRB_UNINITIALIZED_OBJECT;
+  if (!n) return GRB_NULL_POINTER;
+  *n = A->ncols;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_matrix_nvals(grb_matrix A, int64_t *nnz) {
+  if (!A) return GRB_UNINITIALIZED_OBJECT;
+  if (!nnz) return GRB_NULL_POINTER;
+  *nnz = A->nnz;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_matrix_meta_size(grb_matrix A, size_t *bytes) {
+  if (!A) return GRB_UNINITIALIZED_OBJECT;
+  if (!bytes) return GRB_NULL_POINTER;
+  MetaLayout la = meta_layout_one(A->nnz, 0);
+  size_t total = la.bytes;
+  if (!A->symmetric && A->at.valid()) total = meta_layout_one(A->nnz, total).bytes;
+  *bytes = total;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *stream) {
+  if (!A) return GRB_UNINITIALIZED_OBJECT;
+  size_t need = 0;
+  grb_matrix_meta_size(A, &need);
+  if (meta_bytes < need) return GRB_INSUFFICIENT_SPACE;
+  if (!meta) return GRB_NULL_POINTER;
+  if (((uintptr_t)meta) % 256 != 0) return GRB_INVALID_VALUE;
+  hipStream_t s = (hipStream_t)stream;
+  MetaLayout la = meta_layout_one(A->nnz, 0);
+  grb_info info = build_meta(A->a, (char *)meta, la, s);
+  if (info != GRB_SUCCESS) return info;
+  if (A->symmetric) {
+    A->at = A->a;
+  } else if (A->at.valid()) {
+    MetaLayout lt = meta_layout_one(A->nnz, la.bytes);
+    info = build_meta(A->at, (char *)meta, lt, s);
+    if (info != GRB_SUCCESS) return info;
+  }
+  A->prepared = true;
+  return GRB_SUCCESS;
+}
+
+// ---- vector ------------------------------------------------------------------
+
+grb_info grb_vector_create(grb_vector *v, int64_t n, grb_type type, void *values,
+                           uint64_t *bitmap) {
+  if (!v) return GRB_NULL_POINTER;
+  *v = nullptr;
+  if (n < 0 || n >= INT32_MAX || !valid_type(type)) return GRB_INVALID_VALUE;
+  if (n > 0 && (!values || !bitmap)) return GRB_NULL_POINTER;
+  grb_vector_s *x = new (std::nothrow) grb_vector_s;
+  if (!x) return GRB_OUT_OF_MEMORY;
+  x->n = n;
+  x->type = type;
+  x->values = values;
+  x->bitmap = bitmap;
+  *v = x;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_vector_free(grb_vector *v) {
+  if (!v) return GRB_NULL_POINTER;
+  delete *v;
+  *v = nullptr;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_vector_size(grb_vector v, int64_t *n) {
+  if (!v) return GRB_UNINITIALIZED_OBJECT;
+  if (!n) return GRB_NULL_POINTER;
+  *n = v->n;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_vector_clear(grb_vector v, void *stream) {
+  if (!v) return GRB_UNINITIALIZED_OBJECT;
+  launch_fill_u64(v->bitmap, words_of(v->n), 0ull, stream);
+  return check_launch();
+}
+
+grb_info grb_vector_fill(grb_vector v, const void *scalar, void *stream) {
+  if (!v) return GRB_UNINITIALIZED_OBJECT;
+  if (!scalar) return GRB_NULL_POINTER;
+  if (v->n == 0) return GRB_SUCCESS;
+  launch_fill_bytes_pattern(v->values, v->n, elem_size(v->type), scalar, stream);
+  const int64_t nw = words_of(v->n);
+  launch_fill_u64(v->bitmap, nw, ~0ull, stream);
+  if (v->n % 64) launch_fill_u64(v->bitmap + nw - 1, 1, (1ull << (v->n % 64)) - 1, stream);
+  return check_launch();
+}
+
+grb_info grb_vector_build(grb_vector v, const int32_t *idx, const void *vals, int64_t count,
+                          void *stream) {
+  if (!v) return GRB_UNINITIALIZED_OBJECT;
+  if (count < 0) return GRB_INVALID_VALUE;
+  if (count > 0 && !idx) return GRB_NULL_POINTER;
+  uint64_t one = 0;
+  switch (v->type) {
+    case GRB_BOOL: one = 1; break;
+    case GRB_INT32: one = 1; break;
+    case GRB_FP32: { float f = 1.0f; std::memcpy(&one, &f, 4); break; }
+    case GRB_FP64: { double f = 1.0; std::memcpy(&one, &f, 8); break; }
+  }
+  launch_vector_build(v->bitmap, v->values, elem_size(v->type), v->n, idx, vals, count, one, stream);
+  return check_launch();
+}
+
+grb_info grb_vector_nvals(grb_vector v, int64_t *nvals, void *ws, size_t ws_bytes, void *stream) {
+  if (!v) return GRB_UNINITIALIZED_OBJECT;
+  if (!nvals) return GRB_NULL_POINTER;
+  grb_info info = check_ws(ws, ws_bytes, 64);
+  if (info != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  launch_popcount(v->bitmap, words_of(v->n), (int64_t *)ws, stream);
+  if ((info = check_launch()) != GRB_SUCCESS) return info;
+  int64_t h = 0;
+  if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GRB_PANIC;
+  *nvals = h;
+  return GRB_SUCCESS;
+}
+
+// ---- workspace -----------------------------------------------------------------
+
+grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
+  if (!bytes) return GRB_NULL_POINTER;
+  if (op == GRB_OP_NVALS) {
+    *bytes = 256;
+    return GRB_SUCCESS;
+  }
+  if (!A) return GRB_UNINITIALIZED_OBJECT;
+  switch (op) {
+    case GRB_OP_BFS: *bytes = trav_layout(nullptr, A->nrows, A->nnz, false).bytes; break;
+    case GRB_OP_SSSP: *bytes = trav_layout(nullptr, A->nrows, A->nnz, true).bytes; break;
+    case GRB_OP_PAGERANK: {
+      if (k != 1 && k != 2) return GRB_INVALID_VALUE;
+      Csr pull = A->at;
+      pull.nheavy = A->nnz / kHeavyChunk + A->nnz / (kHeavyDeg + 1) + 2;  // upper bound
+      *bytes = pr_layout(nullptr, A->nrows, pull, k == 2 ? 8 : 4).bytes;
+      break;
+    }
+    case GRB_OP_MXV: {
+      const int64_t m = std::max(A->nrows, A->ncols);
+      *bytes = mxv_layout(nullptr, m, m, A->nnz).bytes;
+      break;
+    }
+    default: return GRB_INVALID_VALUE;
+  }
+  return GRB_SUCCESS;
+}
+
+// ---- drivers -------------------------------------------------------------------
+
+grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source,
+                 const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!levels) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (source < 0 || source >= A->nrows) return GRB_INVALID_INDEX;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  return run_traversal(kTravBfs, A, source, levels, parents, nullptr, desc, ws, ws_bytes, stream);
+}
+
+grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descriptor *d, void *ws,
+                  size_t ws_bytes, void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!dist) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (source < 0 || source >= A->nrows) return GRB_INVALID_INDEX;
+  if (A->a.vtype != GRB_FP32) return GRB_DOMAIN_MISMATCH;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  return run_traversal(kTravSssp, A, source, nullptr, nullptr, dist, desc, ws, ws_bytes, stream);
+}
+
+grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int32_t max_iter,
+                      double tol, int32_t *iters, double *delta_out, const grb_descriptor *d,
+                      void *ws, size_t ws_bytes, void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!p || !iters) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (type != GRB_FP32 && type != GRB_FP64) return GRB_DOMAIN_MISMATCH;
+  if (A->nrows == 0 || max_iter < 0 || !(damping >= 0.0 && damping <= 1.0) || !(tol >= 0.0))
+    return GRB_INVALID_VALUE;
+  if (!A->at.valid()) return GRB_NOT_IMPLEMENTED;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  const int is64 = type == GRB_FP64;
+  const int64_t n = A->nrows;
+  PrWs w = pr_layout(ws, n, A->at, is64 ? 8 : 4);
+  if ((info = check_ws(ws, ws_bytes, w.bytes)) != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+  PrArgs pa;
+  pa.n = n;
+  pa.nw = words_of(n);
+  pa.pull = A->at;
+  pa.out_rp = A->a.rp;
+  pa.p = p;
+  pa.x = w.x0;
+  pa.xn = w.x0;
+  pa.heavy_part = w.heavy_part;
+  pa.blk_part = w.blk_part;
+  pa.nblk = w.nblk;
+  pa.ctrl = w.ctrl;
+  pa.alpha = damping;
+  pa.tol = tol;
+  launch_pr_init(is64, pa, stream);
+  Ctrl hc{};
+  int k = 0;
+  while (k < max_iter) {
+    const int stop = std::min(max_iter, k + 8);
+    for (; k < stop; ++k) {
+      pa.x = (k % 2 == 0) ? w.x0 : w.x1;
+      pa.xn = (k % 2 == 0) ? w.x1 : w.x0;
+      const bool timed = profile && k < kStatsCap;
+      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)k), s);
+      launch_pr_iter(is64, pa, stream);
+      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)k + 1), s);
+    }
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GRB_PANIC;
+    if (hc.converged) break;
+  }
+  if (max_iter == 0) {
+    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GRB_PANIC;
+  }
+  *iters = hc.iters;
+  if (delta_out) *delta_out = hc.delta;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  std::vector<float> kms;
+  for (int i = 0; i < std::min(hc.iters, (int)kStatsCap); ++i) {
+    rec[(size_t)i * kStatFields + 0] = n;
+    rec[(size_t)i * kStatFields + 1] = A->nnz;
+    rec[(size_t)i * kStatFields + 2] = GRB_DIR_PULL;
+    if (profile) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
+      kms.push_back(ms);
+    }
+  }
+  finish_stats(GRB_OP_PAGERANK, hc.iters, rec, kms);
+  return GRB_SUCCESS;
+}
+
+}  // extern "C"

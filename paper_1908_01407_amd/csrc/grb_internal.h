@@ -1,0 +1,186 @@
+// Internal definitions shared by the host API layer and the HIP kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/grb.h"
+
+namespace grb {
+
+// ---- kernel geometry -------------------------------------------------
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kPushTile = 1024;      // merge-path items (entries + edges) per push tile
+constexpr int kCompactWords = 64;    // bitmap words per compaction workgroup
+constexpr int kHeavyDeg = 2048;      // rows longer than this are split for pull
+constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
+constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand kernels
+constexpr int kStatsCap = GRB_STATS_MAX;
+
+// ---- matrix ----------------------------------------------------------
+struct Csr {
+  const int32_t *rp = nullptr;  // row_ptr[nrows + 1]
+  const int32_t *ci = nullptr;  // col_idx[nnz]
+  const void *val = nullptr;    // values[nnz] or nullptr (structure only)
+  int vtype = -1;               // grb_type of val, -1 when val is null
+  int64_t nrows = 0;
+  int64_t ncols = 0;
+  int64_t nnz = 0;
+  // metadata from grb_matrix_prepare
+  const int32_t *heavy = nullptr;      // split pieces: (row, begin) pairs
+  int64_t nheavy = 0;                  // number of pieces
+  const int32_t *heavy_rows = nullptr; // (row, first piece, piece count) triples
+  int64_t nheavy_rows = 0;
+  bool valid() const { return rp != nullptr; }
+};
+
+}  // namespace grb
+
+struct grb_matrix_s {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  grb::Csr a;   // CSR of A
+  grb::Csr at;  // CSR of A^T (aliases a for symmetric matrices)
+  bool symmetric = false;
+  bool prepared = false;
+};
+
+struct grb_vector_s {
+  int64_t n = 0;
+  grb_type type = GRB_BOOL;
+  void *values = nullptr;
+  uint64_t *bitmap = nullptr;
+};
+
+namespace grb {
+
+// ---- device-side control block ------------------------------------------
+struct Ctrl {
+  int32_t count;    // entries in the current frontier list
+  int32_t sumdeg;   // sum of their degrees in the push matrix
+  int32_t ntiles;   // merge-path tiles for push
+  int32_t ticket;   // compaction workgroup ticket counter
+  int32_t nlev;     // levels (BFS) / rounds (SSSP) with a non-empty frontier
+  int32_t dir;      // direction chosen by the last expand
+  int32_t iters;    // PageRank iterations run
+  int32_t converged;
+  double D;         // PageRank: dangling mass of the current iterate
+  double delta;     // PageRank: L1 change of the last iteration
+  int64_t pad[4];
+};
+
+// stats record per iteration: {frontier, sumdeg, direction, unused}
+constexpr int kStatFields = 4;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+inline int64_t words_of(int64_t n) { return (n + 63) / 64; }
+
+// ---- kernel launch interfaces (implemented in grb_kernels.hip) -------------
+struct CompactArgs {
+  const uint64_t *nb = nullptr;  // bitmap to compact
+  int64_t nw = 0;
+  const int32_t *rp = nullptr;   // degrees come from this row_ptr (may be null)
+  int32_t *list = nullptr;
+  int32_t *degpre = nullptr;
+  int32_t *tiles = nullptr;
+  uint64_t *status_cur = nullptr;
+  uint64_t *status_next = nullptr;
+  Ctrl *ctrl = nullptr;
+  uint64_t *clear = nullptr;     // optional: bitmap zeroed word by word
+  // BFS epilogue
+  uint64_t *visited = nullptr;
+  int32_t *levels = nullptr;
+  int32_t lev = 0;
+  // SSSP epilogue
+  const float *dist = nullptr;
+  float *fval = nullptr;
+  float *lval = nullptr;
+};
+enum CompactMode { kCompactPlain = 0, kCompactBfs = 1, kCompactSssp = 2 };
+int compact_blocks(int64_t nw);
+void launch_compact(int mode, const CompactArgs &a, void *stream);
+
+struct TravArgs {
+  int64_t n = 0;            // vertices
+  int64_t nw = 0;           // bitmap words
+  int64_t nnz = 0;          // stored entries (for the switch rule)
+  Csr push;                 // rows = frontier vertices (out-edges)
+  Csr pull;                 // rows = candidate vertices (in-edges)
+  bool can_push = true, can_pull = true;
+  const uint64_t *visited = nullptr;  // BFS: visited | isolated; SSSP: isolated
+  const uint64_t *fcur = nullptr;
+  uint64_t *fnxt = nullptr;
+  int32_t *parents = nullptr;         // BFS, may be null
+  float *dist = nullptr;              // SSSP
+  const float *fval = nullptr;        // SSSP: frontier values by vertex
+  const float *lval = nullptr;        // SSSP: frontier values by list position
+  const float *wpush = nullptr;       // SSSP: weights of the push CSR
+  const float *wpull = nullptr;       // SSSP: weights of the pull CSR
+  const int32_t *list = nullptr;
+  const int32_t *degpre = nullptr;
+  const int32_t *tiles = nullptr;
+  Ctrl *ctrl = nullptr;
+  int64_t *stats = nullptr;
+  int32_t d = 0;
+  int32_t rule = 0, denom = 10, forced = 0;
+};
+void launch_bfs_init(const TravArgs &a, int32_t *levels, int32_t source, uint64_t *visited,
+                     uint64_t *fa, uint64_t *fb, uint64_t *status, int64_t nstatus,
+                     void *stream);
+void launch_bfs_expand(const TravArgs &a, void *stream);
+void launch_sssp_init(const TravArgs &a, int32_t source, uint64_t *iso, uint64_t *fa,
+                      uint64_t *fb, uint64_t *status, int64_t nstatus, void *stream);
+void launch_sssp_expand(const TravArgs &a, void *stream);
+
+struct PrArgs {
+  int64_t n = 0, nw = 0;
+  Csr pull;                    // CSR of A^T (in-edges)
+  const int32_t *out_rp = nullptr;  // CSR row_ptr of A (out-degrees)
+  void *p = nullptr;           // ranks (in place)
+  const void *x = nullptr;     // p / outdeg of the current iterate
+  void *xn = nullptr;          // next x
+  void *heavy_part = nullptr;  // per split piece partial sums
+  double *blk_part = nullptr;  // per workgroup {delta, dangling} partials
+  int nblk = 0;
+  Ctrl *ctrl = nullptr;
+  double alpha = 0.85;
+  double tol = 0.0;
+};
+int pr_grid(int64_t nw);
+void launch_pr_init(int is_fp64, const PrArgs &a, void *stream);
+void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream);
+
+// generic helpers
+void launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, void *stream);
+void launch_fill_bytes_pattern(void *p, int64_t count, int elem_size, const void *value,
+                               void *stream);
+void launch_popcount(const uint64_t *bm, int64_t nw, int64_t *out, void *stream);
+void launch_vector_build(uint64_t *bitmap, void *values, int elem_size, int64_t n,
+                         const int32_t *idx, const void *vals, int64_t count, uint64_t one,
+                         void *stream);
+
+// generic masked products
+struct MxvArgs {
+  int64_t n_out = 0, n_in = 0, nw_out = 0, nw_in = 0;
+  Csr push;   // rows = input indices (A'^T)
+  Csr pull;   // rows = output indices (A')
+  bool can_push = true, can_pull = true;
+  int semiring = 0;
+  int accum = 0;
+  uint32_t flags = 0;
+  bool has_mask = false;
+  bool swap_operands = false;   // vxm: multiply is u (x) A instead of A (x) u
+  // operands
+  const void *u_val = nullptr; const uint64_t *u_bm = nullptr;
+  void *w_val = nullptr; uint64_t *w_bm = nullptr;
+  const void *m_val = nullptr; const uint64_t *m_bm = nullptr; int m_type = 0;
+  // workspace
+  void *t_val = nullptr; uint64_t *t_bm = nullptr; uint64_t *t_vb = nullptr;
+  const int32_t *list = nullptr; const int32_t *degpre = nullptr; const int32_t *tiles = nullptr;
+  Ctrl *ctrl = nullptr;
+  int32_t rule = 0, denom = 10, forced = 0;
+};
+void launch_mxv(const MxvArgs &a, void *stream);
+
+}  // namespace grb

@@ -1,0 +1,234 @@
+// PageRank iteration kernels (Section 7.3 of the paper: pull form, SpMV
+// every iteration because the vector never gets sparse).
+//
+// Load balance: each wave owns one bitmap word (64 consecutive rows of the
+// CSR of A^T) and streams their in-edges as one concatenated list, 64 edges
+// per step, with a segmented sum per row (wave-level load-balanced search);
+// rows longer than kHeavyDeg are cut into fixed pieces that any wave takes,
+// and a single-workgroup fix-up kernel adds each long row's pieces in order.
+// Summation order is fixed, so fp32 and fp64 results are bitwise
+// reproducible run to run.  The dangling mass and the L1 change are reduced
+// per workgroup and then in a fixed order in the fix-up kernel, which also
+// decides convergence on the device.
+#include <hip/hip_runtime.h>
+
+#include "grb_device.h"
+#include "grb_internal.h"
+
+namespace grb {
+namespace {
+
+template <class T>
+__device__ __forceinline__ T rank_update(const PrArgs &a, T t, T dn) {
+  const T alpha = (T)a.alpha;
+  const T base = (T)((1.0 - a.alpha) / (double)a.n);
+  return base + alpha * (t + dn);
+}
+
+template <class T>
+__device__ __forceinline__ void block_partials(double delta, double dang, double *out) {
+  __shared__ double s_red[kWavesPerBlock][2];
+  delta = wave_sum_f64(delta);
+  dang = wave_sum_f64(dang);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_red[wid][0] = delta;
+    s_red[wid][1] = dang;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d0 = 0, d1 = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      d0 += s_red[i][0];
+      d1 += s_red[i][1];
+    }
+    out[2 * blockIdx.x + 0] = d0;
+    out[2 * blockIdx.x + 1] = d1;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
+  T *p = (T *)a.p;
+  T *xn = (T *)a.xn;
+  const T p0 = (T)(1.0 / (double)a.n);
+  double dang = 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < a.n;
+       v += (int64_t)gridDim.x * kBlock) {
+    p[v] = p0;
+    const int od = a.out_rp[v + 1] - a.out_rp[v];
+    if (od == 0) {
+      xn[v] = (T)0;
+      dang += (double)p0;
+    } else {
+      xn[v] = p0 / (T)od;
+    }
+  }
+  block_partials<T>(0.0, dang, a.blk_part);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
+  __shared__ int s_mark[kWavesPerBlock][64];
+  if (a.ctrl->converged) return;
+  int *mark = s_mark[threadIdx.x >> 6];
+  const int ln = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
+  const T *x = (const T *)a.x;
+  T *xn = (T *)a.xn;
+  T *p = (T *)a.p;
+  const T dn = (T)(a.ctrl->D / (double)a.n);
+  double delta = 0, dang = 0;
+  for (int64_t w = gw; w < a.nw; w += nwaves) {
+    const int64_t v = w * 64 + ln;
+    const bool inb = v < a.n;
+    int cur = 0, end = 0;
+    bool heavy = false;
+    if (inb) {
+      cur = rp[v];
+      end = rp[v + 1];
+      heavy = end - cur > kHeavyDeg;
+    }
+    const bool act = inb && !heavy;
+    T acc = (T)0;
+    for (;;) {
+      const int len = act ? end - cur : 0;
+      const int incl = wave_incl_scan(len);
+      const int total = __shfl(incl, 63);
+      if (total == 0) break;
+      const int excl = incl - len;
+      const bool starts = len > 0 && excl < 64;
+      const int r = slot_rows(mark, starts, excl);
+      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+      T val = (T)0;
+      if (ln < total) val = x[ci[rcur + (ln - rexcl)]];
+      val = seg_sum_scan<T>(val, r);
+      const int se = min(incl, 64);
+      const T seg = __shfl(val, starts ? se - 1 : 0);
+      if (starts) {
+        acc += seg;
+        cur += se - excl;
+      }
+    }
+    if (act) {
+      const T pn = rank_update<T>(a, acc, dn);
+      delta += fabs((double)pn - (double)p[v]);
+      p[v] = pn;
+      const int od = a.out_rp[v + 1] - a.out_rp[v];
+      if (od == 0) {
+        xn[v] = (T)0;
+        dang += (double)pn;
+      } else {
+        xn[v] = pn / (T)od;
+      }
+    }
+  }
+  T *hp = (T *)a.heavy_part;
+  for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
+    const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
+    const int e = min(b + kHeavyChunk, rp[r + 1]);
+    T s = (T)0;
+    for (int base = b; base < e; base += 64) {
+      const int pos = base + ln;
+      if (pos < e) s += x[ci[pos]];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (ln == 0) hp[h] = s;
+  }
+  block_partials<T>(delta, dang, a.blk_part);
+}
+
+// One workgroup: finishes long rows (their pieces added in order), reduces
+// the per-workgroup partials in a fixed order and updates the control block.
+template <class T>
+__global__ __launch_bounds__(1024) void k_pr_fixup(PrArgs a, int init) {
+  __shared__ double s_d[16], s_g[16];
+  if (!init && a.ctrl->converged) return;
+  const T dn = (T)(a.ctrl->D / (double)a.n);
+  double delta = 0, dang = 0;
+  if (!init) {
+    const T *hp = (const T *)a.heavy_part;
+    T *p = (T *)a.p;
+    T *xn = (T *)a.xn;
+    for (int64_t i = threadIdx.x; i < a.pull.nheavy_rows; i += 1024) {
+      const int r = a.pull.heavy_rows[3 * i], first = a.pull.heavy_rows[3 * i + 1],
+                cnt = a.pull.heavy_rows[3 * i + 2];
+      T acc = (T)0;
+      for (int k = 0; k < cnt; ++k) acc += hp[first + k];
+      const T pn = rank_update<T>(a, acc, dn);
+      delta += fabs((double)pn - (double)p[r]);
+      p[r] = pn;
+      const int od = a.out_rp[r + 1] - a.out_rp[r];
+      if (od == 0) {
+        xn[r] = (T)0;
+        dang += (double)pn;
+      } else {
+        xn[r] = pn / (T)od;
+      }
+    }
+  }
+  for (int i = threadIdx.x; i < a.nblk; i += 1024) {
+    delta += a.blk_part[2 * i];
+    dang += a.blk_part[2 * i + 1];
+  }
+  delta = wave_sum_f64(delta);
+  dang = wave_sum_f64(dang);
+  if ((threadIdx.x & 63) == 0) {
+    s_d[threadIdx.x >> 6] = delta;
+    s_g[threadIdx.x >> 6] = dang;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d = 0, g = 0;
+    for (int i = 0; i < 16; ++i) {
+      d += s_d[i];
+      g += s_g[i];
+    }
+    a.ctrl->D = g;
+    if (init) {
+      a.ctrl->iters = 0;
+      a.ctrl->converged = 0;
+      a.ctrl->delta = 0.0;
+    } else {
+      a.ctrl->delta = d;
+      a.ctrl->iters += 1;
+      if (d < a.tol) a.ctrl->converged = 1;
+    }
+  }
+}
+
+}  // namespace
+
+int pr_grid(int64_t nw) {
+  int64_t g = (nw + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (g < 1) g = 1;
+  if (g > kExpandGrid) g = kExpandGrid;
+  return (int)g;
+}
+
+void launch_pr_init(int is_fp64, const PrArgs &a, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (is_fp64) {
+    hipLaunchKernelGGL(k_pr_init<double>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_pr_fixup<double>, dim3(1), dim3(1024), 0, s, a, 1);
+  } else {
+    hipLaunchKernelGGL(k_pr_init<float>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_pr_fixup<float>, dim3(1), dim3(1024), 0, s, a, 1);
+  }
+}
+
+void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (is_fp64) {
+    hipLaunchKernelGGL(k_pr_iter<double>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_pr_fixup<double>, dim3(1), dim3(1024), 0, s, a, 0);
+  } else {
+    hipLaunchKernelGGL(k_pr_iter<float>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_pr_fixup<float>, dim3(1), dim3(1024), 0, s, a, 0);
+  }
+}
+
+}  // namespace grb

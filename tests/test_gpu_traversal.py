@@ -1,0 +1,187 @@
+"""GPU parity: grb_bfs / grb_sssp / grb_pagerank against the CPU oracle.
+
+BFS levels and parents and SSSP distances (integer weights, sums < 2^24)
+must match bit for bit in every direction mode; PageRank fp32 within L1
+1e-5 and fp64 within L1 1e-10 of the FP64 oracle at the same iteration
+count.  Inputs are seeded synthetic graphs of the paper's kinds (R-MAT with
+a, b, c, d = 0.57, 0.19, 0.19, 0.05 and integer weights 1..64) plus grids and
+hand-built degenerate graphs.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def grb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_01407_amd as g
+    return g
+
+
+_CACHE = {}
+
+
+def graph(name):
+    """(raw graph, oracle adjacency) by name, built once per session."""
+    if name in _CACHE:
+        return _CACHE[name]
+    if name.startswith("rmat_dir"):
+        g = graphgen.rmat(int(name.split("_")[2]), symmetric=False)
+    elif name.startswith("rmat"):
+        g = graphgen.rmat(int(name.split("_")[1]))
+    elif name.startswith("grid"):
+        r, c = name.split("_")[1].split("x")
+        g = graphgen.grid(int(r), int(c))
+    elif name == "path":
+        k = 300
+        g = graphgen.from_edges(name, k, np.arange(k - 1), np.arange(1, k),
+                                np.full(k - 1, 3.0))
+    elif name == "star":  # one row far longer than the split threshold
+        k = 5001
+        g = graphgen.from_edges(name, k, np.zeros(k - 1), np.arange(1, k),
+                                1 + np.arange(k - 1) % 64)
+    elif name == "clique":
+        iu = np.triu_indices(70, 1)
+        g = graphgen.from_edges(name, 70, iu[0], iu[1], 1 + (iu[0] + iu[1]) % 64)
+    elif name == "two_comp":
+        src = [0, 1, 2, 3, 10, 11, 12, 130]
+        dst = [1, 2, 3, 0, 11, 12, 13, 131]
+        g = graphgen.from_edges(name, 133, src, dst, [5, 1, 2, 9, 1, 1, 1, 4])
+    elif name == "empty":
+        g = graphgen.from_edges(name, 70, [], [], [])
+    elif name == "single":
+        g = graphgen.from_edges(name, 1, [], [], [])
+    else:
+        raise KeyError(name)
+    adj = oracle.Adjacency.from_raw(g)
+    _CACHE[name] = (g, adj)
+    return _CACHE[name]
+
+
+_MATS = {}
+
+
+def matrix(grb, name):
+    if name not in _MATS:
+        g, _ = graph(name)
+        _MATS[name] = grb.Matrix.from_raw(g)
+    return _MATS[name]
+
+
+MODES = [("auto_paper", 0, 0), ("auto_exact", 0, 1), ("push", 1, 0), ("pull", 2, 0)]
+SMALL = ["rmat_14", "rmat_dir_12", "grid_33x70", "path", "star", "clique", "two_comp",
+         "empty", "single"]
+
+
+def _sources(name, n):
+    if name == "two_comp":
+        return [0, 10, 132]  # 132 is isolated
+    if name in ("empty", "single"):
+        return [0]
+    rng = np.random.default_rng(7)
+    return [0] + rng.integers(0, n, 2).tolist()
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+def test_bfs_parity(grb, name, mode):
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    _, direction, rule = mode
+    for s in _sources(name, g.n):
+        d = grb.descriptor(direction=direction, rule=rule)
+        lev, par = grb.bfs(A, s, desc=d)
+        ref_lev, ref_par, nl = oracle.bfs(adj, s)
+        assert np.array_equal(lev.cpu().numpy(), ref_lev), (name, s)
+        assert np.array_equal(par.cpu().numpy(), ref_par), (name, s)
+        st = grb.last_stats()
+        assert st["iterations"] == nl
+        if direction:
+            assert set(st["direction"]) <= {direction}
+
+
+@pytest.mark.parametrize("name", ["rmat_14", "rmat_dir_12", "grid_33x70"])
+def test_bfs_direction_sequence_and_work(grb, name):
+    """Per level: frontier size, its degree sum and the direction the paper's
+    rule picks (pull iff 10 |f| > n) follow from the oracle's levels."""
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    off, _, _ = adj.arrays(weights=False)
+    deg = np.diff(off)
+    ref_lev, _, nl = oracle.bfs(adj, 0, parents=False)
+    for rule in (0, 1):
+        grb.bfs(A, 0, parents=False, desc=grb.descriptor(rule=rule))
+        st = grb.last_stats()
+        assert st["iterations"] == nl
+        for d in range(nl):
+            f = np.flatnonzero(ref_lev == d)
+            assert st["frontier"][d] == f.size
+            assert st["edges"][d] == deg[f].sum()
+            pull = (10 * f.size > g.n) if rule == 0 else (10 * deg[f].sum() > adj.nnz)
+            assert st["direction"][d] == (2 if pull else 1), (rule, d)
+
+
+@pytest.mark.parametrize("name", ["rmat_14", "grid_33x70", "star"])
+def test_bfs_repeatable(grb, name):
+    A = matrix(grb, name)
+    a = [t.cpu().numpy() for t in grb.bfs(A, 0)]
+    b = [t.cpu().numpy() for t in grb.bfs(A, 0)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+SSSP_GRAPHS = ["rmat_14", "rmat_dir_12", "grid_33x70", "path", "star", "clique", "two_comp",
+               "empty", "single"]
+
+
+@pytest.mark.parametrize("name", SSSP_GRAPHS)
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+def test_sssp_parity(grb, name, mode):
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    _, direction, rule = mode
+    for s in _sources(name, g.n):
+        dist = grb.sssp(A, s, desc=grb.descriptor(direction=direction, rule=rule))
+        ref, _, _ = oracle.sssp(adj, s)
+        assert np.array_equal(dist.cpu().numpy(), ref), (name, s)
+
+
+@pytest.mark.parametrize("name", ["rmat_dir_12", "rmat_dir_14"])
+def test_pagerank_parity(grb, name):
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    ref, it, delta = oracle.pagerank(adj, 0.85, 50, 1e-7)
+    p32, it32, d32 = grb.pagerank(A, dtype=torch.float32, max_iter=it, tol=0.0)
+    p64, it64, d64 = grb.pagerank(A, dtype=torch.float64, max_iter=it, tol=0.0)
+    assert it32 == it and it64 == it
+    assert np.abs(p32.cpu().numpy().astype(np.float64) - ref).sum() <= 1e-5
+    assert np.abs(p64.cpu().numpy() - ref).sum() <= 1e-10
+    # the device-side stopping rule stops where the oracle stops
+    _, it_auto, _ = grb.pagerank(A, dtype=torch.float64, max_iter=50, tol=1e-7)
+    assert it_auto == it
+    # bitwise repeatable
+    q32, _, _ = grb.pagerank(A, dtype=torch.float32, max_iter=it, tol=0.0)
+    assert torch.equal(p32, q32)
+
+
+def test_pagerank_closed_forms(grb):
+    n = 9
+    cyc = graphgen.from_edges("cyc", n, np.arange(n), (np.arange(n) + 1) % n, symmetric=False)
+    A = grb.Matrix.from_raw(cyc, weights=False)
+    p, it, delta = grb.pagerank(A, dtype=torch.float64, max_iter=50, tol=1e-7)
+    assert it == 1 and np.allclose(p.cpu().numpy(), 1 / n, atol=1e-15)
+    star = graph("star")[0]
+    S = grb.Matrix.from_raw(graphgen.from_edges("st", star.n, star.src, star.dst,
+                                                symmetric=False), weights=False)
+    adj = oracle.Adjacency(star.n, star.src, star.dst, symmetrise=False)
+    ref, it, _ = oracle.pagerank(adj, 0.85, 50, 1e-7)
+    p, it2, _ = grb.pagerank(S, dtype=torch.float64, max_iter=50, tol=1e-7)
+    assert it2 == it
+    assert np.abs(p.cpu().numpy() - ref).sum() <= 1e-10
