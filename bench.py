@@ -1,0 +1,394 @@
+#!/usr/bin/env python3
+"""Benchmark of the masked semiring mxv library on one MI355X.
+
+Headline (one JSON line on stdout): direction-optimised BFS from vertex 0 on
+a symmetrised R-MAT graph, scale 22, edge factor 16, (a, b, c, d) =
+(0.57, 0.19, 0.19, 0.05), int32 CSR, Boolean semiring, levels and parents.
+A step is one full BFS; value = stored entries of the symmetrised CSR per
+second of BFS (the paper's TEPS convention, Section 8), in GTEPS.
+
+The JSON line also carries:
+* roofline: HBM roofline of the BFS expand kernel (the step's dominant
+  kernel): algorithmic bytes of all its launches in the timed region divided
+  by their summed duration (HIP events recorded by the library on the launch
+  stream), against 8 TB/s;
+* cpu_baseline: the CPU oracle (single-threaded queue BFS with the
+  min-id parent pass) timed on this host on the same graph;
+* extras: SSSP on the same graph, BFS/SSSP on a 3000x3000 grid, PageRank on
+  a directed R-MAT scale 22 graph (fp32 and fp64), each with its own timing.
+
+Other modes: --rocprof-summary DIR prints a per-kernel summary of rocprofv3
+CSV output (kernel stats and FETCH_SIZE / WRITE_SIZE counters).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic byte models (what the method must move, not what the kernel did)
+# ---------------------------------------------------------------------------
+
+def first_hit_scan(rp, ci, rows_mask, hit_col):
+    """Edges a pull with early exit must read: for every row in rows_mask,
+    the position of its first neighbour with hit_col[neighbour] plus one, or
+    its full degree when there is none."""
+    deg = np.diff(rp).astype(np.int64)
+    rows = np.flatnonzero(rows_mask & (deg > 0))
+    if rows.size == 0:
+        return 0
+    total = 0
+    # process rows in slabs to bound memory
+    slab = 1 << 20
+    for lo in range(0, rows.size, slab):
+        r = rows[lo:lo + slab]
+        starts, ends = rp[r].astype(np.int64), rp[r + 1].astype(np.int64)
+        lens = ends - starts
+        idx = np.repeat(starts - np.cumsum(np.concatenate([[0], lens[:-1]])), lens) + \
+            np.arange(lens.sum())
+        h = hit_col[ci[idx]]
+        seg = np.repeat(np.arange(r.size), lens)
+        pos = np.arange(lens.sum()) - np.repeat(np.cumsum(np.concatenate([[0], lens[:-1]])), lens)
+        big = np.iinfo(np.int64).max
+        first = np.full(r.size, big, dtype=np.int64)
+        np.minimum.at(first, seg[h], pos[h])
+        total += int(np.where(first == big, lens, first + 1).sum())
+    return total
+
+
+def bfs_bytes_per_level(rp, ci, lev, directions, n):
+    """Per-level algorithmic bytes of a BFS level given the direction run.
+    push: frontier ids and row extents 12|f|, neighbour ids 4*sum deg(f),
+          visited bitmap probe n/8, next bitmap n/8, parent+level 8|next|.
+    pull: visited n/8, frontier bitmap n/8, row extents 8R of candidate rows,
+          neighbour ids 4*E_scan (early exit), next bitmap n/8, 8|next|."""
+    deg = np.diff(rp).astype(np.int64)
+    out = []
+    for d, dr in enumerate(directions):
+        f = lev == d
+        nf = int(f.sum())
+        nxt = int((lev == d + 1).sum())
+        if dr == 1:
+            b = 12 * nf + 4 * int(deg[f].sum()) + n / 8 + n / 8 + 8 * nxt
+        else:
+            cand = ((lev < 0) | (lev > d)) & (deg > 0)
+            e_scan = first_hit_scan(rp, ci, cand, f)
+            b = 3 * n / 8 + 8 * int(cand.sum()) + 4 * e_scan + 8 * nxt
+        out.append(float(b))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------
+
+def rocprof_summary(d):
+    lines = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        lines.append(f"# kernel stats: {os.path.relpath(path, d)}")
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+        lines.append(f"{'kernel':60s} {'calls':>7s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s}")
+        for r in rows:
+            name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0][:60]
+            lines.append(f"{name:60s} {int(r['Calls']):7d} {float(r['TotalDurationNs'])/1e3:11.1f} "
+                         f"{float(r['AverageNs'])/1e3:9.2f} {float(r['Percentage']):6.2f}")
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        lines.append(f"# counters: {os.path.relpath(path, d)}")
+        agg = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0][:60],
+                       r["Counter_Name"])
+                a = agg.setdefault(key, [0, 0.0, set()])
+                a[1] += float(r["Counter_Value"])
+                a[2].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+        lines.append(f"{'kernel':60s} {'counter':>12s} {'dispatches':>10s} {'KiB/dispatch':>14s}")
+        for (k, c), (_, v, ids) in sorted(agg.items(), key=lambda x: -x[1][1]):
+            nd = max(len(ids), 1)
+            lines.append(f"{k:60s} {c:>12s} {nd:10d} {v / nd:14.1f}")
+    return "\n".join(lines)
+
+
+# ---------------------------------------------------------------------------
+# measurements
+# ---------------------------------------------------------------------------
+
+def timed(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def host_info():
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": cpu, "logical_cpus": os.cpu_count()}
+
+
+def bench_extras(grb, graphgen, torch, args):
+    ex = {}
+    # SSSP on the same R-MAT graph (min-plus, weights 1..64)
+    A = args._A
+    ws = grb.workspace(grb.OP_SSSP, A)
+    for name, rule in (("paper", 0), ("exact", 1)):
+        d = grb.descriptor(rule=rule)
+        grb.sssp(A, 0, desc=d, ws=ws)
+        ms = timed(lambda: grb.sssp(A, 0, desc=d, ws=ws), args.extra_steps, torch)
+        st = grb.last_stats()
+        ex[f"sssp_rmat{args.scale}_{name}"] = {
+            "ms": round(ms, 4), "gteps": round(A.nnz / ms / 1e6, 3),
+            "rounds": st["iterations"], "pushes": st["pushes"], "pulls": st["pulls"]}
+    dp = grb.descriptor(rule=1, flags=grb.GRB_PROFILE)
+    grb.sssp(A, 0, desc=dp, ws=ws)
+    st = grb.last_stats()
+    ex[f"sssp_rmat{args.scale}_kernels"] = {
+        "expand_ms_push": round(st["expand_ms_push"], 4),
+        "expand_ms_pull": round(st["expand_ms_pull"], 4),
+        "per_round_ms": [round(x, 4) for x in st["kernel_ms"]],
+        "direction": st["direction"], "frontier": st["frontier"], "edges": st["edges"]}
+    # SSSP pull as masked SpMV over the whole graph: bytes of one full pull round
+    # (col + weight of every stored entry, row extents, frontier bitmap, distances)
+    dpull = grb.descriptor(direction=2, flags=grb.GRB_PROFILE)
+    grb.sssp(A, 0, desc=dpull, ws=ws)
+    st = grb.last_stats()
+    n = A.nrows
+    if st["kernel_ms"]:
+        rounds = len(st["kernel_ms"])
+        tot_ms = sum(st["kernel_ms"])
+        bytes_round = 4 * A.nnz + 8 * (n + 1) + n / 8 + 8 * n
+        ex[f"sssp_rmat{args.scale}_forced_pull"] = {
+            "rounds": rounds, "ms": round(tot_ms, 4),
+            "bytes_per_round_model": bytes_round,
+            "gbs": round(bytes_round * rounds / (tot_ms / 1e3) / 1e9, 1),
+            "note": "col_idx 4B/entry + row_ptr + frontier bitmap + dist read/write per round; "
+                    "weights read only for frontier neighbours (not counted)"}
+    del ws
+    # grid 3000 x 3000
+    if not args.no_grid:
+        gg = graphgen.grid(3000, 3000)
+        G = grb.Matrix.from_raw(gg)
+        wsb = grb.workspace(grb.OP_BFS, G)
+        wss = grb.workspace(grb.OP_SSSP, G)
+        grb.bfs(G, 0, ws=wsb)
+        ms = timed(lambda: grb.bfs(G, 0, ws=wsb), 2, torch)
+        st = grb.last_stats()
+        ex["bfs_grid3000"] = {"ms": round(ms, 3), "levels": st["iterations"],
+                              "us_per_level": round(ms * 1e3 / max(st["iterations"], 1), 2),
+                              "gteps": round(G.nnz / ms / 1e6, 4)}
+        grb.sssp(G, 0, ws=wss)
+        ms = timed(lambda: grb.sssp(G, 0, ws=wss), 2, torch)
+        st = grb.last_stats()
+        ex["sssp_grid3000"] = {"ms": round(ms, 3), "rounds": st["iterations"],
+                               "us_per_round": round(ms * 1e3 / max(st["iterations"], 1), 2),
+                               "gteps": round(G.nnz / ms / 1e6, 4)}
+        del G, wsb, wss
+    # PageRank on a directed R-MAT graph
+    if not args.no_pr:
+        gd = graphgen.rmat(args.scale, symmetric=False, weights=False)
+        P = grb.Matrix.from_raw(gd, weights=False)
+        res = {}
+        p64, it64, _ = grb.pagerank(P, dtype=torch.float64, max_iter=50, tol=1e-7)
+        for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            ws = grb.workspace(grb.OP_PAGERANK, P, 2 if dt == torch.float64 else 1)
+            grb.pagerank(P, dtype=dt, max_iter=50, tol=1e-7, ws=ws)
+            ms = timed(lambda: grb.pagerank(P, dtype=dt, max_iter=50, tol=1e-7, ws=ws),
+                       args.extra_steps, torch)
+            p, it, delta = grb.pagerank(P, dtype=dt, max_iter=50, tol=1e-7, ws=ws,
+                                        desc=grb.descriptor(flags=grb.GRB_PROFILE))
+            st = grb.last_stats()
+            kms = st["expand_ms_all"] / max(st["launches"], 1)
+            n = P.nrows
+            esz = 8 if dt == torch.float64 else 4
+            # per iteration: col_idx of every in-edge, row extents, x gather
+            # working set once, p read + write, out-degree row extents, x write
+            bytes_it = 4 * P.nnz + 4 * (n + 1) + esz * n + 2 * esz * n + 4 * (n + 1) + esz * n
+            res[name] = {"ms_total": round(ms, 4), "iterations": it,
+                         "ms_per_iter": round(ms / max(it, 1), 4),
+                         "spmv_kernel_ms": round(kms, 4),
+                         "spmv_kernel_gbs": round(bytes_it / (kms / 1e3) / 1e9, 1),
+                         "spmv_kernel_frac_hbm": round(bytes_it / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "gteps_per_iter": round(P.nnz / (ms / max(it, 1)) / 1e6, 3)}
+            if name == "fp32":
+                res[name]["l1_vs_gpu_fp64"] = float(
+                    (p.double() - p64).abs().sum().item())
+            del ws
+        res["nnz"] = P.nnz
+        res["iterations_fp64_reference"] = it64
+        ex[f"pagerank_rmat{args.scale}_dir"] = res
+        del P
+    return ex
+
+
+def cpu_baseline(g, A_nnz, args):
+    import oracle
+    adj = oracle.Adjacency.from_raw(g)
+    runs, t_total = 0, 0.0
+    while runs < 1 or (t_total < args.cpu_seconds and runs < 20):
+        t0 = time.perf_counter()
+        oracle.bfs(adj, 0)
+        t_total += time.perf_counter() - t0
+        runs += 1
+    per = t_total / runs
+    return {"value": round(A_nnz / per / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} full BFS runs (queue BFS + min-id parent pass) from vertex 0 on "
+                      f"the same RMAT-{args.scale} graph; {per * 1e3:.1f} ms per BFS; "
+                      f"host {host_info()['cpu']}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--extra-steps", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-pr", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device copy (counter calibration)")
+    ap.add_argument("--rocprof-summary", metavar="DIR")
+    args = ap.parse_args()
+
+    if args.rocprof_summary:
+        print(rocprof_summary(args.rocprof_summary))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU "
+              "sharding of this workload is described in DESIGN.md but not built.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import graphgen
+    import paper_1908_01407_amd as grb
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        return 1
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    log(f"[bench] generating RMAT-{args.scale}")
+    g = graphgen.rmat(args.scale)
+    log(f"[bench] building CSR ({time.perf_counter() - t_setup:.1f}s)")
+    A = grb.Matrix.from_raw(g)
+    args._A = A
+    n, nnz = A.nrows, A.nnz
+    log(f"[bench] n={n} nnz={nnz} ({time.perf_counter() - t_setup:.1f}s)")
+    ws = grb.workspace(grb.OP_BFS, A)
+
+    # pick the switch rule by measurement (results are identical either way)
+    rule_ms = {}
+    for rule in (0, 1):
+        d = grb.descriptor(rule=rule)
+        for _ in range(max(args.warmup, 1)):
+            grb.bfs(A, 0, desc=d, ws=ws)
+        rule_ms[rule] = timed(lambda: grb.bfs(A, 0, desc=d, ws=ws), 5, torch)
+    rule = min(rule_ms, key=rule_ms.get)
+    desc = grb.descriptor(rule=rule, flags=grb.GRB_PROFILE)
+    for _ in range(args.warmup):
+        grb.bfs(A, 0, desc=desc, ws=ws)
+
+    # timed region: K full BFS runs, expand kernels timed by HIP events
+    launches, exp_ms = 0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lev, par = grb.bfs(A, 0, desc=desc, ws=ws)
+        st = grb.last_stats()
+        launches += st["launches"]
+        exp_ms += st["expand_ms_all"]
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) / args.steps * 1e3
+    value = nnz / (ms_per_step / 1e3) / 1e9
+    log(f"[bench] BFS {ms_per_step:.4f} ms/step -> {value:.2f} GTEPS (rule {rule})")
+
+    # algorithmic bytes of the expand launches of one BFS
+    levels = lev.cpu().numpy()
+    rp = A.row_ptr.cpu().numpy()
+    ci = A.col_idx.cpu().numpy()
+    per_level = bfs_bytes_per_level(rp, ci, levels, st["direction"], n)
+    bytes_step = sum(per_level)
+    achieved = bytes_step * args.steps / (exp_ms / 1e3) / 1e9
+    reached = int((levels >= 0).sum())
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "kernel": "k_bfs_expand",
+        "launches_per_step": launches / args.steps,
+        "avg_launch_us": round(exp_ms / launches * 1e3, 3),
+        "algorithmic_bytes_per_step": bytes_step,
+        "per_level": [{"level": i, "dir": "push" if st["direction"][i] == 1 else "pull",
+                       "frontier": st["frontier"][i], "edges": st["edges"][i],
+                       "bytes": per_level[i], "kernel_us": round(st["kernel_ms"][i] * 1e3, 2)}
+                      for i in range(len(per_level))],
+    }
+    out = {
+        "metric": f"BFS GTEPS at RMAT-{args.scale} (direction-optimised, from vertex 0)",
+        "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"DO-BFS from vertex 0 on symmetrised RMAT scale {args.scale}, "
+                               f"edge factor 16, (a,b,c,d)=(0.57,0.19,0.19,0.05), int32 CSR, "
+                               f"levels+parents",
+                   "n": n, "nnz": nnz, "levels": st["iterations"],
+                   "switch_rule": "paper" if rule == 0 else "exact",
+                   "rule_ms": {"paper": round(rule_ms[0], 4), "exact": round(rule_ms[1], 4)},
+                   "gteps_graph500": round(
+                       (int(np.diff(rp)[levels >= 0].sum()) // 2) / (ms_per_step / 1e3) / 1e9, 3),
+                   "reached": reached},
+        "roofline": roofline,
+    }
+    if args.calibrate_copy:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 256 << 20
+    if not args.no_extras:
+        log("[bench] extras")
+        out["extras"] = bench_extras(grb, graphgen, torch, args)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, nnz, args)
+    out["host"] = host_info()
+    out["gpu"] = torch.cuda.get_device_name(0)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

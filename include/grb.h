@@ -341,10 +341,12 @@ typedef struct grb_stats {
   int32_t recorded;      /* entries filled below (min(iterations, GRB_STATS_MAX)) */
   int32_t pushes;        /* iterations that ran push */
   int32_t pulls;         /* iterations that ran pull */
-  int32_t reserved;
+  int32_t launches;      /* expand launches enqueued (the last batch may end
+                            with launches that find an empty frontier) */
   int64_t edges_push;    /* total sum of frontier degrees over push iterations */
   double expand_ms_push; /* GRB_PROFILE: summed push-expand kernel time */
   double expand_ms_pull; /* GRB_PROFILE: summed pull-expand kernel time */
+  double expand_ms_all;  /* GRB_PROFILE: time of all `launches` expand launches */
   int32_t direction[GRB_STATS_MAX]; /* 1 push, 2 pull */
   int64_t frontier[GRB_STATS_MAX];  /* frontier size entering the iteration */
   int64_t edges[GRB_STATS_MAX];     /* sum of frontier degrees */

@@ -64,9 +64,9 @@ class Descriptor(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("recorded", ctypes.c_int32), ("pushes", ctypes.c_int32),
-                ("pulls", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pulls", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("edges_push", ctypes.c_int64), ("expand_ms_push", ctypes.c_double),
-                ("expand_ms_pull", ctypes.c_double),
+                ("expand_ms_pull", ctypes.c_double), ("expand_ms_all", ctypes.c_double),
                 ("direction", ctypes.c_int32 * STATS_MAX),
                 ("frontier", ctypes.c_int64 * STATS_MAX),
                 ("edges", ctypes.c_int64 * STATS_MAX),
@@ -147,7 +147,8 @@ def last_stats() -> dict:
     return {
         "op": s.op, "iterations": s.iterations, "pushes": s.pushes, "pulls": s.pulls,
         "edges_push": s.edges_push, "expand_ms_push": s.expand_ms_push,
-        "expand_ms_pull": s.expand_ms_pull,
+        "expand_ms_pull": s.expand_ms_pull, "launches": s.launches,
+        "expand_ms_all": s.expand_ms_all,
         "direction": list(s.direction[:r]), "frontier": list(s.frontier[:r]),
         "edges": list(s.edges[:r]), "kernel_ms": list(s.kernel_ms[:r]),
     }

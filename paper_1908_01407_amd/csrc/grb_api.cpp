@@ -67,7 +67,7 @@ struct Carver {
 
 struct TravWs {
   uint64_t *visited, *fa, *fb, *status;
-  int32_t *list, *degpre, *tiles;
+  int32_t *list, *degpre, *rowstart, *tiles;
   float *lval, *fval;
   Ctrl *ctrl;
   int64_t *stats;
@@ -88,6 +88,7 @@ TravWs trav_layout(void *ws, int64_t n, int64_t nnz_push, bool sssp) {
   t.fb = c.take<uint64_t>((size_t)nw);
   t.list = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
   t.degpre = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
+  t.rowstart = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
   t.tiles = c.take<int32_t>((size_t)((n + nnz_push) / kPushTile + 3));
   if (sssp) {
     t.lval = c.take<float>((size_t)std::max<int64_t>(n, 1));
@@ -95,6 +96,25 @@ TravWs trav_layout(void *ws, int64_t n, int64_t nnz_push, bool sssp) {
   } else {
     t.lval = t.fval = nullptr;
   }
+  t.bytes = c.off;
+  return t;
+}
+
+struct BfsWs {
+  Ctrl *ctrl;
+  int64_t *stats;
+  uint64_t *visited, *F[3];
+  size_t bytes;
+};
+
+BfsWs bfs_layout(void *ws, int64_t n) {
+  Carver c(ws);
+  BfsWs t{};
+  const int64_t nw = words_of(n);
+  t.ctrl = c.take<Ctrl>(1);
+  t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
+  t.visited = c.take<uint64_t>((size_t)nw);
+  for (int i = 0; i < 3; ++i) t.F[i] = c.take<uint64_t>((size_t)nw);
   t.bytes = c.off;
   return t;
 }
@@ -123,13 +143,14 @@ PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
 struct MxvWs {
   Ctrl *ctrl;
   uint64_t *status, *t_bm, *t_vb;
-  int32_t *list, *degpre, *tiles;
-  void *t_val;
+  int32_t *list, *degpre, *rowstart, *tiles;
+  void *t_val, *hp_val;
+  uint8_t *hp_has;
   int nblk;
   size_t bytes;
 };
 
-MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz) {
+MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz, int64_t nheavy) {
   Carver c(ws);
   MxvWs t{};
   t.nblk = compact_blocks(words_of(n_in));
@@ -137,13 +158,18 @@ MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz) {
   t.status = c.take<uint64_t>((size_t)2 * t.nblk);
   t.list = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
   t.degpre = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
+  t.rowstart = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
   t.tiles = c.take<int32_t>((size_t)((n_in + nnz) / kPushTile + 3));
-  t.t_bm = c.take<uint64_t>((size_t)words_of(n_out));
-  t.t_vb = c.take<uint64_t>((size_t)words_of(n_out));
+  t.t_bm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
+  t.t_vb = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
   t.t_val = c.take<char>((size_t)std::max<int64_t>(n_out, 1) * 8);
+  t.hp_val = c.take<char>((size_t)std::max<int64_t>(nheavy, 1) * 8);
+  t.hp_has = c.take<uint8_t>((size_t)std::max<int64_t>(nheavy, 1));
   t.bytes = c.off;
   return t;
 }
+
+int64_t heavy_bound(int64_t nnz) { return nnz / kHeavyChunk + nnz / (kHeavyDeg + 1) + 2; }
 
 grb_info check_ws(void *ws, size_t have, size_t need) {
   if (need > have) return GRB_INSUFFICIENT_SPACE;
@@ -154,17 +180,19 @@ grb_info check_ws(void *ws, size_t have, size_t need) {
 
 // ---- matrix metadata ---------------------------------------------------------
 struct MetaLayout {
-  size_t heavy_off, heavy_rows_off, bytes;
-  int64_t max_pieces, max_rows;
+  size_t heavy_off, heavy_rows_off, split_off, bytes;
+  int64_t max_pieces, max_rows, max_split;
 };
 
 MetaLayout meta_layout_one(int64_t nnz, size_t base) {
   MetaLayout m{};
   m.max_rows = nnz / (kHeavyDeg + 1) + 1;
   m.max_pieces = nnz / kHeavyChunk + m.max_rows + 1;
+  m.max_split = nnz / kPushSplit + nnz / (kPushSplit + 1) + 1;
   m.heavy_off = base;
   m.heavy_rows_off = align_up(base + (size_t)m.max_pieces * 2 * sizeof(int32_t));
-  m.bytes = align_up(m.heavy_rows_off + (size_t)m.max_rows * 3 * sizeof(int32_t));
+  m.split_off = align_up(m.heavy_rows_off + (size_t)m.max_rows * 3 * sizeof(int32_t));
+  m.bytes = align_up(m.split_off + (size_t)m.max_split * 2 * sizeof(int32_t));
   return m;
 }
 
@@ -180,10 +208,16 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
       hipStreamSynchronize(s) != hipSuccess)
     return GRB_PANIC;
   if (rp[0] != 0 || rp[(size_t)c.nrows] != c.nnz) return GRB_INVALID_VALUE;
-  std::vector<int32_t> pieces, rows;
+  std::vector<int32_t> pieces, rows, split;
   for (int64_t r = 0; r < c.nrows; ++r) {
     const int32_t b = rp[(size_t)r], e = rp[(size_t)r + 1];
     if (e < b) return GRB_INVALID_VALUE;
+    if (e - b > kPushSplit) {
+      for (int32_t p = b; p < e; p += kPushSplit) {
+        split.push_back((int32_t)r);
+        split.push_back(p);
+      }
+    }
     if (e - b > kHeavyDeg) {
       rows.push_back((int32_t)r);
       rows.push_back((int32_t)(pieces.size() / 2));
@@ -195,10 +229,15 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
       rows.push_back(np);
     }
   }
-  if ((int64_t)pieces.size() / 2 > L.max_pieces || (int64_t)rows.size() / 3 > L.max_rows)
+  if ((int64_t)pieces.size() / 2 > L.max_pieces || (int64_t)rows.size() / 3 > L.max_rows ||
+      (int64_t)split.size() / 2 > L.max_split)
     return GRB_PANIC;
   int32_t *hp = (int32_t *)(meta + L.heavy_off);
   int32_t *hr = (int32_t *)(meta + L.heavy_rows_off);
+  int32_t *sp = (int32_t *)(meta + L.split_off);
+  if (!split.empty() &&
+      hipMemcpyAsync(sp, split.data(), split.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
   if (!pieces.empty() &&
       hipMemcpyAsync(hp, pieces.data(), pieces.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return GRB_PANIC;
@@ -210,6 +249,8 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
   c.nheavy = (int64_t)pieces.size() / 2;
   c.heavy_rows = hr;
   c.nheavy_rows = (int64_t)rows.size() / 3;
+  c.split = sp;
+  c.nsplit = (int64_t)split.size() / 2;
   return GRB_SUCCESS;
 }
 
@@ -231,11 +272,13 @@ struct EventPool {
 thread_local EventPool g_events;
 
 void finish_stats(int op, int iterations, const std::vector<int64_t> &rec,
-                  const std::vector<float> &kms) {
+                  const std::vector<float> &kms, int launches, double ms_all) {
   grb_stats &s = g_stats;
   std::memset(&s, 0, sizeof(s));
   s.op = op;
   s.iterations = iterations;
+  s.launches = launches;
+  s.expand_ms_all = ms_all;
   s.recorded = std::min(iterations, (int)kStatsCap);
   for (int i = 0; i < s.recorded; ++i) {
     s.frontier[i] = rec[(size_t)i * kStatFields + 0];
@@ -253,6 +296,92 @@ void finish_stats(int op, int iterations, const std::vector<int64_t> &rec,
       else s.expand_ms_pull += kms[(size_t)i];
     }
   }
+}
+
+// BFS: one kernel per level (all state on the device); the host reads the
+// frontier size back once per batch of levels to detect the end.
+grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents,
+                 const grb_descriptor &desc, void *ws, size_t ws_bytes, void *stream) {
+  const int64_t n = A->nrows;
+  const bool can_pull = A->at.valid();
+  if (!can_pull && (desc.direction == GRB_DIR_PULL || parents)) return GRB_NOT_IMPLEMENTED;
+  BfsWs w = bfs_layout(ws, n);
+  grb_info info = check_ws(ws, ws_bytes, w.bytes);
+  if (info != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+  BfsArgs ba;
+  ba.n = n;
+  ba.nw = words_of(n);
+  ba.nnz = A->nnz;
+  ba.push = A->a;
+  ba.pull = A->at;
+  ba.can_pull = can_pull;
+  ba.same_csr = A->symmetric;
+  ba.visited = w.visited;
+  ba.levels = levels;
+  ba.parents = parents;
+  ba.ctrl = w.ctrl;
+  ba.stats = w.stats;
+  ba.rule = desc.switch_rule;
+  ba.denom = desc.switch_denominator;
+  ba.forced = desc.direction;
+  int32_t *cnt = w.ctrl->lists;
+  auto at_level = [&](int64_t d) {
+    const int i = (int)(d % 3), j = (int)((d + 1) % 3), k = (int)((d + 2) % 3);
+    ba.fcur = w.F[i];
+    ba.fnxt = w.F[j];
+    ba.fclr = w.F[k];
+    ba.cnt_cur = cnt + i * kCntSlots;
+    ba.cnt_nxt = cnt + j * kCntSlots;
+    ba.cnt_clr = cnt + k * kCntSlots;
+    ba.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
+  };
+  at_level(0);
+  launch_bfs_start(ba, source, w.F[1], w.F[2], stream);
+  const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
+  int64_t d = 0;
+  int chunk = 6;
+  Ctrl hc{};
+  for (;;) {
+    for (int i = 0; i < chunk && d < cap; ++i, ++d) {
+      at_level(d);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
+      launch_bfs_level(ba, stream);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
+    }
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GRB_PANIC;
+    int64_t next = 0;
+    for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + 2 * t];
+    if (next == 0 || d >= cap) break;
+    chunk = std::min(chunk * 2, 256);
+  }
+  if (parents) {
+    launch_bfs_parents(ba, stream);
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+  }
+  const int iters = hc.nlev;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  const int nrec = std::min(iters, (int)kStatsCap);
+  if (nrec > 0 && hipMemcpyAsync(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, s) != hipSuccess)
+    return GRB_PANIC;
+  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+  std::vector<float> kms;
+  double ms_all = 0.0;
+  if (profile) {
+    for (int64_t i = 0; i < d; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
+      if (i < nrec) kms.push_back(ms);
+      ms_all += ms;
+    }
+  }
+  finish_stats(GRB_OP_BFS, iters, rec, kms, (int)std::min<int64_t>(d, INT32_MAX), ms_all);
+  return GRB_SUCCESS;
 }
 
 enum TravKind { kTravBfs, kTravSssp };
@@ -289,6 +418,7 @@ grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *lev
   ta.wpull = can_pull ? (const float *)A->at.val : nullptr;
   ta.list = w.list;
   ta.degpre = w.degpre;
+  ta.rowstart = w.rowstart;
   ta.tiles = w.tiles;
   ta.ctrl = w.ctrl;
   ta.stats = w.stats;
@@ -297,16 +427,14 @@ grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *lev
   ta.forced = desc.direction;
 
   const int64_t nstatus = 2 * (int64_t)w.nblk;
-  if (kind == kTravBfs)
-    launch_bfs_init(ta, levels, source, w.visited, w.fa, w.fb, w.status, nstatus, stream);
-  else
-    launch_sssp_init(ta, source, w.visited, w.fa, w.fb, w.status, nstatus, stream);
+  launch_sssp_init(ta, source, w.visited, w.fa, w.fb, w.status, nstatus, stream);
 
   CompactArgs ca;
   ca.nw = ta.nw;
   ca.rp = A->a.rp;
   ca.list = w.list;
   ca.degpre = w.degpre;
+  ca.rowstart = w.rowstart;
   ca.tiles = w.tiles;
   ca.ctrl = w.ctrl;
   ca.visited = w.visited;
@@ -326,10 +454,11 @@ grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *lev
     parity ^= 1;
   };
   compact(w.fb, nullptr, 0);  // level 0 = {source}
+  ca.skip_if_empty = true;
 
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
-  int chunk = 8;
+  int chunk = 6;
   Ctrl hc{};
   std::vector<int> ev_level;
   for (;;) {
@@ -339,11 +468,9 @@ grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *lev
       ta.fcur = fcur;
       ta.fnxt = fnxt;
       ta.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
-      const bool timed = profile && d < kStatsCap;
-      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
-      if (kind == kTravBfs) launch_bfs_expand(ta, stream);
-      else launch_sssp_expand(ta, stream);
-      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
+      launch_sssp_expand(ta, stream);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
       compact(fnxt, fcur, (int)std::min<int64_t>(d + 1, INT32_MAX));
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
@@ -362,14 +489,17 @@ grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *lev
       return GRB_PANIC;
   }
   std::vector<float> kms;
+  double ms_all = 0.0;
   if (profile) {
-    for (int i = 0; i < nrec; ++i) {
+    for (int64_t i = 0; i < d; ++i) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
-      kms.push_back(ms);
+      if (i < nrec) kms.push_back(ms);
+      ms_all += ms;
     }
   }
-  finish_stats(kind == kTravBfs ? GRB_OP_BFS : GRB_OP_SSSP, iters, rec, kms);
+  finish_stats(kind == kTravBfs ? GRB_OP_BFS : GRB_OP_SSSP, iters, rec, kms,
+               (int)std::min<int64_t>(d, INT32_MAX), ms_all);
   return GRB_SUCCESS;
 }
 
@@ -621,18 +751,18 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
   }
   if (!A) return GRB_UNINITIALIZED_OBJECT;
   switch (op) {
-    case GRB_OP_BFS: *bytes = trav_layout(nullptr, A->nrows, A->nnz, false).bytes; break;
+    case GRB_OP_BFS: *bytes = bfs_layout(nullptr, A->nrows).bytes; break;
     case GRB_OP_SSSP: *bytes = trav_layout(nullptr, A->nrows, A->nnz, true).bytes; break;
     case GRB_OP_PAGERANK: {
       if (k != 1 && k != 2) return GRB_INVALID_VALUE;
       Csr pull = A->at;
-      pull.nheavy = A->nnz / kHeavyChunk + A->nnz / (kHeavyDeg + 1) + 2;  // upper bound
+      pull.nheavy = heavy_bound(A->nnz);
       *bytes = pr_layout(nullptr, A->nrows, pull, k == 2 ? 8 : 4).bytes;
       break;
     }
     case GRB_OP_MXV: {
       const int64_t m = std::max(A->nrows, A->ncols);
-      *bytes = mxv_layout(nullptr, m, m, A->nnz).bytes;
+      *bytes = mxv_layout(nullptr, m, m, A->nnz, heavy_bound(A->nnz)).bytes;
       break;
     }
     default: return GRB_INVALID_VALUE;
@@ -651,7 +781,7 @@ grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source
   grb_descriptor desc;
   grb_info info = resolve_desc(d, &desc);
   if (info != GRB_SUCCESS) return info;
-  return run_traversal(kTravBfs, A, source, levels, parents, nullptr, desc, ws, ws_bytes, stream);
+  return run_bfs(A, source, levels, parents, desc, ws, ws_bytes, stream);
 }
 
 grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descriptor *d, void *ws,
@@ -708,10 +838,9 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int3
     for (; k < stop; ++k) {
       pa.x = (k % 2 == 0) ? w.x0 : w.x1;
       pa.xn = (k % 2 == 0) ? w.x1 : w.x0;
-      const bool timed = profile && k < kStatsCap;
-      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)k), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k), s);
       launch_pr_iter(is64, pa, stream);
-      if (timed) (void)hipEventRecord(g_events.get(2 * (size_t)k + 1), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
     if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -728,18 +857,138 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int3
   if (delta_out) *delta_out = hc.delta;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   std::vector<float> kms;
-  for (int i = 0; i < std::min(hc.iters, (int)kStatsCap); ++i) {
-    rec[(size_t)i * kStatFields + 0] = n;
-    rec[(size_t)i * kStatFields + 1] = A->nnz;
-    rec[(size_t)i * kStatFields + 2] = GRB_DIR_PULL;
+  double ms_all = 0.0;
+  for (int i = 0; i < k; ++i) {
+    if (i < std::min(hc.iters, (int)kStatsCap)) {
+      rec[(size_t)i * kStatFields + 0] = n;
+      rec[(size_t)i * kStatFields + 1] = A->nnz;
+      rec[(size_t)i * kStatFields + 2] = GRB_DIR_PULL;
+    }
     if (profile) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
-      kms.push_back(ms);
+      if (i < std::min(hc.iters, (int)kStatsCap)) kms.push_back(ms);
+      ms_all += ms;
     }
   }
-  finish_stats(GRB_OP_PAGERANK, hc.iters, rec, kms);
+  finish_stats(GRB_OP_PAGERANK, hc.iters, rec, kms, k, ms_all);
   return GRB_SUCCESS;
+}
+
+}  // extern "C"
+
+namespace {
+
+grb_type domain_of(grb_semiring s) {
+  switch (s) {
+    case GRB_LOR_LAND_BOOL: return GRB_BOOL;
+    case GRB_MIN_PLUS_FP32:
+    case GRB_PLUS_TIMES_FP32: return GRB_FP32;
+    case GRB_MIN_PLUS_FP64:
+    case GRB_PLUS_TIMES_FP64: return GRB_FP64;
+    default: return GRB_INT32;
+  }
+}
+
+bool accum_fits(grb_semiring s, grb_binop acc) {
+  if (acc == GRB_NOACCUM) return true;
+  switch (s) {
+    case GRB_LOR_LAND_BOOL: return acc == GRB_ACCUM_LOR;
+    case GRB_PLUS_TIMES_FP32:
+    case GRB_PLUS_TIMES_FP64: return acc == GRB_ACCUM_PLUS;
+    default: return acc == GRB_ACCUM_MIN;
+  }
+}
+
+// Shared by grb_mxv (is_vxm = false) and grb_vxm (is_vxm = true).
+grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s,
+                     grb_matrix A, grb_vector u, const grb_descriptor *d, void *ws,
+                     size_t ws_bytes, void *stream) {
+  if (!w || !u || !A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (s < GRB_LOR_LAND_BOOL || s > GRB_MIN_SECOND_INT32) return GRB_INVALID_VALUE;
+  if (accum < GRB_NOACCUM || accum > GRB_ACCUM_LOR) return GRB_INVALID_VALUE;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  if (w == u || (mask && w == mask) || (w->values && w->values == u->values) ||
+      (mask && w->bitmap == mask->bitmap))
+    return GRB_INVALID_VALUE;  // output must not alias an input
+  const grb_type dom = domain_of(s);
+  if (w->type != dom || u->type != dom) return GRB_DOMAIN_MISMATCH;
+  if (!accum_fits(s, accum)) return GRB_DOMAIN_MISMATCH;
+  // A' = A or A^T; mxv: w = A' u; vxm: w = u A' = A'^T u
+  const bool tran = (desc.flags & GRB_TRAN_A) != 0;
+  const bool out_rows_of_a = is_vxm ? tran : !tran;  // output index = row of A?
+  const grb::Csr &pull = out_rows_of_a ? A->a : A->at;
+  const grb::Csr &push = out_rows_of_a ? A->at : A->a;
+  const int64_t n_out = out_rows_of_a ? A->nrows : A->ncols;
+  const int64_t n_in = out_rows_of_a ? A->ncols : A->nrows;
+  if (w->n != n_out || u->n != n_in || (mask && mask->n != n_out)) return GRB_DIMENSION_MISMATCH;
+  const bool can_pull = pull.valid(), can_push = push.valid();
+  if ((desc.direction == GRB_DIR_PULL && !can_pull) ||
+      (desc.direction == GRB_DIR_PUSH && !can_push) || (!can_pull && !can_push))
+    return GRB_NOT_IMPLEMENTED;
+  MxvWs t = mxv_layout(ws, n_in, n_out, A->nnz, can_pull ? pull.nheavy : 0);
+  if ((info = check_ws(ws, ws_bytes, t.bytes)) != GRB_SUCCESS) return info;
+  MxvArgs a;
+  a.n_out = n_out;
+  a.n_in = n_in;
+  a.nw_out = words_of(n_out);
+  a.nw_in = words_of(n_in);
+  a.nnz = A->nnz;
+  a.push = push;
+  a.pull = pull;
+  a.can_push = can_push;
+  a.can_pull = can_pull;
+  a.semiring = s;
+  a.accum = accum;
+  // multiply operand order: mxv A(i,j) (x) u(j), vxm u(i) (x) A(i,j)
+  a.pick_vec = (s == GRB_MIN_FIRST_INT32) ? is_vxm : !is_vxm;
+  a.has_mask = mask != nullptr;
+  a.mask_comp = (desc.flags & GRB_MASK_COMP) != 0;
+  a.mask_struct = (desc.flags & GRB_MASK_STRUCT) != 0;
+  a.replace = (desc.flags & GRB_REPLACE) != 0;
+  a.u_val = u->values;
+  a.u_bm = u->bitmap;
+  a.w_val = w->values;
+  a.w_bm = w->bitmap;
+  if (mask) {
+    a.m_val = mask->values;
+    a.m_bm = mask->bitmap;
+    a.m_type = mask->type;
+  }
+  a.t_val = t.t_val;
+  a.t_bm = t.t_bm;
+  a.t_vb = t.t_vb;
+  a.hp_val = t.hp_val;
+  a.hp_has = t.hp_has;
+  a.list = t.list;
+  a.degpre = t.degpre;
+  a.rowstart = t.rowstart;
+  a.tiles = t.tiles;
+  a.status = t.status;
+  a.nblk = t.nblk;
+  a.ctrl = t.ctrl;
+  a.rule = desc.switch_rule;
+  a.denom = desc.switch_denominator;
+  a.forced = desc.direction;
+  if (n_out == 0) return GRB_SUCCESS;
+  launch_mxv(a, stream);
+  return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+grb_info grb_mxv(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s, grb_matrix A,
+                 grb_vector u, const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream) {
+  return run_product(false, w, mask, accum, s, A, u, d, ws, ws_bytes, stream);
+}
+
+grb_info grb_vxm(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s, grb_vector u,
+                 grb_matrix A, const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream) {
+  return run_product(true, w, mask, accum, s, A, u, d, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -108,12 +108,16 @@ __device__ __forceinline__ T seg_sum_scan(T x, int row) {
   return x;
 }
 
-__device__ __forceinline__ void store_release_u64(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Device-coherent atomic store / load of a 64-bit word.  Relaxed ordering:
+// the word itself carries everything the reader needs, so no other memory
+// has to be made visible with it (release/acquire at device scope would
+// write back / invalidate the per-XCD L2 caches on every call).
+__device__ __forceinline__ void store_relaxed_u64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t load_acquire_u64(uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t load_relaxed_u64(uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // atomic min for floats of either sign (returns the previous value)

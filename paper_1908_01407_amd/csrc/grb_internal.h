@@ -12,10 +12,13 @@ namespace grb {
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kPushTile = 1024;      // merge-path items (entries + edges) per push tile
-constexpr int kCompactWords = 64;    // bitmap words per compaction workgroup
+constexpr int kCompactThreads = 1024;  // threads per compaction workgroup (16 waves)
+constexpr int kCompactWords = 256;     // bitmap words per compaction workgroup
 constexpr int kHeavyDeg = 2048;      // rows longer than this are split for pull
 constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
 constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand kernels
+constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
+constexpr int kCntStripes = 32;      // BFS: striped frontier counters (count, degree sum)
 constexpr int kStatsCap = GRB_STATS_MAX;
 
 // ---- matrix ----------------------------------------------------------
@@ -32,6 +35,8 @@ struct Csr {
   int64_t nheavy = 0;                  // number of pieces
   const int32_t *heavy_rows = nullptr; // (row, first piece, piece count) triples
   int64_t nheavy_rows = 0;
+  const int32_t *split = nullptr;      // push pieces of rows longer than kPushSplit
+  int64_t nsplit = 0;
   bool valid() const { return rp != nullptr; }
 };
 
@@ -66,6 +71,7 @@ struct Ctrl {
   int32_t converged;
   double D;         // PageRank: dangling mass of the current iterate
   double delta;     // PageRank: L1 change of the last iteration
+  int32_t lists[3 * 2 * 32];  // BFS: striped counters of the three frontier buffers
   int64_t pad[4];
 };
 
@@ -83,11 +89,13 @@ struct CompactArgs {
   const int32_t *rp = nullptr;   // degrees come from this row_ptr (may be null)
   int32_t *list = nullptr;
   int32_t *degpre = nullptr;
+  int32_t *rowstart = nullptr;   // row start (in rp) of each list entry
   int32_t *tiles = nullptr;
   uint64_t *status_cur = nullptr;
   uint64_t *status_next = nullptr;
   Ctrl *ctrl = nullptr;
   uint64_t *clear = nullptr;     // optional: bitmap zeroed word by word
+  bool skip_if_empty = false;    // return at once when ctrl->count == 0
   // BFS epilogue
   uint64_t *visited = nullptr;
   int32_t *levels = nullptr;
@@ -119,16 +127,36 @@ struct TravArgs {
   const float *wpull = nullptr;       // SSSP: weights of the pull CSR
   const int32_t *list = nullptr;
   const int32_t *degpre = nullptr;
+  const int32_t *rowstart = nullptr;
   const int32_t *tiles = nullptr;
   Ctrl *ctrl = nullptr;
   int64_t *stats = nullptr;
   int32_t d = 0;
   int32_t rule = 0, denom = 10, forced = 0;
 };
-void launch_bfs_init(const TravArgs &a, int32_t *levels, int32_t source, uint64_t *visited,
-                     uint64_t *fa, uint64_t *fb, uint64_t *status, int64_t nstatus,
-                     void *stream);
-void launch_bfs_expand(const TravArgs &a, void *stream);
+
+// BFS with one kernel per level (grb_bfs.hip).  Each of the three rotating
+// frontier buffers has kCntStripes (count, degree sum) counter pairs.
+constexpr int kCntSlots = 2 * kCntStripes;
+struct BfsArgs {
+  int64_t n = 0, nw = 0, nnz = 0;
+  Csr push;   // out-edges (CSR of A)
+  Csr pull;   // in-edges (CSR of A^T)
+  bool can_pull = true;
+  bool same_csr = false;  // symmetric matrix: push and pull read one CSR
+  uint64_t *visited = nullptr;
+  uint64_t *fcur = nullptr, *fnxt = nullptr, *fclr = nullptr;
+  int32_t *levels = nullptr, *parents = nullptr;
+  int32_t *cnt_cur = nullptr, *cnt_nxt = nullptr, *cnt_clr = nullptr;
+  Ctrl *ctrl = nullptr;
+  int64_t *stats = nullptr;
+  int32_t d = 0;
+  int32_t rule = 0, denom = 10, forced = 0;
+};
+void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
+                      void *stream);
+void launch_bfs_level(const BfsArgs &a, void *stream);
+void launch_bfs_parents(const BfsArgs &a, void *stream);
 void launch_sssp_init(const TravArgs &a, int32_t source, uint64_t *iso, uint64_t *fa,
                       uint64_t *fb, uint64_t *status, int64_t nstatus, void *stream);
 void launch_sssp_expand(const TravArgs &a, void *stream);
@@ -160,24 +188,32 @@ void launch_vector_build(uint64_t *bitmap, void *values, int elem_size, int64_t 
                          const int32_t *idx, const void *vals, int64_t count, uint64_t one,
                          void *stream);
 
-// generic masked products
+// generic masked products (grb_mxv.hip)
 struct MxvArgs {
-  int64_t n_out = 0, n_in = 0, nw_out = 0, nw_in = 0;
-  Csr push;   // rows = input indices (A'^T)
-  Csr pull;   // rows = output indices (A')
+  int64_t n_out = 0, n_in = 0, nw_out = 0, nw_in = 0, nnz = 0;
+  Csr push;   // rows = input indices (CSR of A'^T)
+  Csr pull;   // rows = output indices (CSR of A')
   bool can_push = true, can_pull = true;
-  int semiring = 0;
-  int accum = 0;
-  uint32_t flags = 0;
-  bool has_mask = false;
-  bool swap_operands = false;   // vxm: multiply is u (x) A instead of A (x) u
+  int semiring = 0;        // grb_semiring
+  int accum = 0;           // grb_binop
+  bool pick_vec = false;   // MIN_FIRST / MIN_SECOND: the product is the vector operand
+  bool has_mask = false, mask_comp = false, mask_struct = false, replace = false;
   // operands
-  const void *u_val = nullptr; const uint64_t *u_bm = nullptr;
-  void *w_val = nullptr; uint64_t *w_bm = nullptr;
-  const void *m_val = nullptr; const uint64_t *m_bm = nullptr; int m_type = 0;
+  const void *u_val = nullptr;
+  const uint64_t *u_bm = nullptr;
+  void *w_val = nullptr;
+  uint64_t *w_bm = nullptr;
+  const void *m_val = nullptr;
+  const uint64_t *m_bm = nullptr;
+  int m_type = 0;
   // workspace
-  void *t_val = nullptr; uint64_t *t_bm = nullptr; uint64_t *t_vb = nullptr;
-  const int32_t *list = nullptr; const int32_t *degpre = nullptr; const int32_t *tiles = nullptr;
+  void *t_val = nullptr;
+  uint64_t *t_bm = nullptr, *t_vb = nullptr;
+  void *hp_val = nullptr;       // per pull piece partial value
+  uint8_t *hp_has = nullptr;    // per pull piece: any contribution
+  int32_t *list = nullptr, *degpre = nullptr, *rowstart = nullptr, *tiles = nullptr;
+  uint64_t *status = nullptr;
+  int nblk = 0;
   Ctrl *ctrl = nullptr;
   int32_t rule = 0, denom = 10, forced = 0;
 };

@@ -1,7 +1,7 @@
 // HIP kernels for gfx950 (CDNA4, wave64): frontier compaction, push
-// (SpMSpV) and pull (masked SpMV) expansion for BFS and SSSP, and small
-// utility kernels.  PageRank and the generic masked products live in
-// grb_spmv.hip.
+// (SpMSpV) and pull (masked SpMV) expansion for SSSP, and small utility
+// kernels.  BFS lives in grb_bfs.hip, PageRank in grb_spmv.hip and the
+// generic masked products in grb_mxv.hip.
 //
 // Design notes (prior art in the paper: Sections 4-6; the kernels below are
 // written for this hardware, not translated):
@@ -39,21 +39,28 @@ __device__ __forceinline__ uint64_t pack_status(uint64_t flag, int64_t c, int64_
 __device__ __forceinline__ int64_t status_cnt(uint64_t s) { return (int64_t)((s >> 31) & 0x7fffffffull); }
 __device__ __forceinline__ int64_t status_deg(uint64_t s) { return (int64_t)(s & 0x7fffffffull); }
 
+// Each workgroup (16 waves) compacts 256 bitmap words; its position in the
+// output comes from a decoupled look-back over the workgroups before it
+// (tickets, not blockIdx, order the workgroups, so every workgroup a
+// look-back waits on is already running).  The status word packs
+// flag (2 bits) | count (31 bits) | degree sum (31 bits).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
-  constexpr int WPW = kCompactWords / kWavesPerBlock;  // words per wave
+__global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
+  constexpr int NWV = kCompactThreads / 64;  // waves per workgroup
+  constexpr int WPW = kCompactWords / NWV;   // words per wave
   __shared__ int s_cnt[kCompactWords];
   __shared__ int s_deg[kCompactWords];
   __shared__ int s_blk;
   __shared__ int s_base_c, s_base_d;
   const int tid = threadIdx.x, wid = tid >> 6, ln = tid & 63;
+  // once a frontier is empty every later one is: nothing to compact
+  if (a.skip_if_empty && a.ctrl->count == 0) return;
   if (tid == 0) s_blk = atomicAdd(&a.ctrl->ticket, 1);
   __syncthreads();
   const int blk = s_blk;
   const int64_t w0 = (int64_t)blk * kCompactWords + wid * WPW;
   if (tid == 0) a.status_next[blk] = 0ull;
 
-  int degs[WPW];
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     const int64_t w = w0 + k;
@@ -63,7 +70,6 @@ __global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
       const int64_t v = w * 64 + ln;
       if (a.rp) deg = a.rp[v + 1] - a.rp[v];
     }
-    degs[k] = deg;
     const int ds = wave_sum(deg);
     if (ln == 0) {
       s_cnt[wid * WPW + k] = __popcll(word);
@@ -74,35 +80,52 @@ __global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
   __syncthreads();
 
   if (wid == 0) {
-    const int c = s_cnt[ln], d = s_deg[ln];
-    const int ci = wave_incl_scan(c), di = wave_incl_scan(d);
+    // block-wide exclusive scan: lane l covers words 4l .. 4l+3
+    int c[4], d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      c[i] = s_cnt[4 * ln + i];
+      d[i] = s_deg[4 * ln + i];
+    }
+    const int cl = c[0] + c[1] + c[2] + c[3], dl = d[0] + d[1] + d[2] + d[3];
+    const int ci = wave_incl_scan(cl), di = wave_incl_scan(dl);
     const int ctot = __shfl(ci, 63), dtot = __shfl(di, 63);
-    s_cnt[ln] = ci - c;
-    s_deg[ln] = di - d;
+    int ce = ci - cl, de = di - dl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s_cnt[4 * ln + i] = ce;
+      s_deg[4 * ln + i] = de;
+      ce += c[i];
+      de += d[i];
+    }
     int64_t ec = 0, ed = 0;
     if (blk > 0) {
-      if (ln == 0) store_release_u64(&a.status_cur[blk], pack_status(kFlagAgg, ctot, dtot));
+      if (ln == 0) store_relaxed_u64(&a.status_cur[blk], pack_status(kFlagAgg, ctot, dtot));
       int jhi = blk - 1;
-      for (;;) {
-        const int j = jhi - ln;
-        uint64_t s = pack_status(kFlagPre, 0, 0);
-        if (j >= 0) {
-          do {
-            s = load_acquire_u64(&a.status_cur[j]);
-          } while ((s >> 62) == 0);
+      for (;;) {  // window of 128 predecessors, nearest first
+        const int j1 = jhi - ln, j2 = jhi - 64 - ln;
+        uint64_t s1 = pack_status(kFlagPre, 0, 0), s2 = s1;
+        if (j1 >= 0) {
+          do { s1 = load_relaxed_u64(&a.status_cur[j1]); } while ((s1 >> 62) == 0);
         }
-        const uint64_t pm = __ballot((s >> 62) == kFlagPre);
-        const int fp = pm ? (__ffsll((unsigned long long)pm) - 1) : 64;
-        const int64_t c2 = ln <= fp ? status_cnt(s) : 0;
-        const int64_t d2 = ln <= fp ? status_deg(s) : 0;
-        ec += wave_sum64(c2);
-        ed += wave_sum64(d2);
-        if (pm) break;
-        jhi -= 64;
+        if (j2 >= 0) {
+          do { s2 = load_relaxed_u64(&a.status_cur[j2]); } while ((s2 >> 62) == 0);
+        }
+        const uint64_t p1 = __ballot((s1 >> 62) == kFlagPre);
+        const uint64_t p2 = __ballot((s2 >> 62) == kFlagPre);
+        const int f1 = p1 ? (__ffsll((unsigned long long)p1) - 1) : 64;
+        ec += wave_sum64(ln <= f1 ? status_cnt(s1) : 0);
+        ed += wave_sum64(ln <= f1 ? status_deg(s1) : 0);
+        if (p1) break;
+        const int f2 = p2 ? (__ffsll((unsigned long long)p2) - 1) : 64;
+        ec += wave_sum64(ln <= f2 ? status_cnt(s2) : 0);
+        ed += wave_sum64(ln <= f2 ? status_deg(s2) : 0);
+        if (p2) break;
+        jhi -= 128;
       }
     }
     if (ln == 0) {
-      store_release_u64(&a.status_cur[blk], pack_status(kFlagPre, ec + ctot, ed + dtot));
+      store_relaxed_u64(&a.status_cur[blk], pack_status(kFlagPre, ec + ctot, ed + dtot));
       s_base_c = (int)ec;
       s_base_d = (int)ed;
       if (blk == (int)gridDim.x - 1) {
@@ -127,14 +150,19 @@ __global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
     if (word == 0ull) continue;
     const bool bit = (word >> ln) & 1ull;
     const int rank = __popcll(word & mask_below(ln));
-    const int deg = degs[k];
+    const int64_t v = w * 64 + ln;
+    int deg = 0, rs = 0;
+    if (bit && a.rp) {  // second read of the same row extents: a cache hit
+      rs = a.rp[v];
+      deg = a.rp[v + 1] - rs;
+    }
     const int dinc = wave_incl_scan(deg);
     const int idx = bc + s_cnt[wid * WPW + k] + rank;
     const int dex = bd + s_deg[wid * WPW + k] + dinc - deg;
-    const int64_t v = w * 64 + ln;
     if (bit) {
       if (a.list) a.list[idx] = (int)v;
       if (a.degpre) a.degpre[idx] = dex;
+      if (a.rowstart) a.rowstart[idx] = rs;
       if (a.tiles) {
         const int64_t s0 = (int64_t)dex + idx, s1 = s0 + deg;
         for (int64_t t = (s0 + kPushTile - 1) / kPushTile; t * kPushTile <= s1; ++t)
@@ -193,7 +221,7 @@ __device__ __forceinline__ int stage_tile(PushStage &st, const TravArgs &a, int 
     const int u = a.list[i0 + k];
     st.u[k] = u;
     st.deg[k] = a.degpre[i0 + k];
-    st.rs[k] = a.push.rp[u];
+    st.rs[k] = a.rowstart[i0 + k];
     if (VAL) st.val[k] = a.lval[i0 + k];
   }
   e0 = (int64_t)t * kPushTile - i0;
@@ -216,143 +244,6 @@ __device__ __forceinline__ int find_entry(const PushStage &st, int ne, int64_t e
 __device__ __forceinline__ void set_bit_guarded(uint64_t *bm, int64_t v) {
   const uint64_t b = 1ull << (v & 63);
   if (!(bm[v >> 6] & b)) atomicOr((unsigned long long *)&bm[v >> 6], (unsigned long long)b);
-}
-
-// ---------------------------------------------------------------------------
-// BFS
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void k_bfs_init(TravArgs a, int32_t *levels, int32_t source,
-                                                     uint64_t *visited, uint64_t *fa, uint64_t *fb,
-                                                     uint64_t *status, int64_t nstatus) {
-  const int ln = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    const int64_t v = w * 64 + ln;
-    bool iso = true;
-    if (v < a.n) {
-      iso = a.can_pull ? (a.pull.rp[v + 1] == a.pull.rp[v]) : false;
-      levels[v] = -1;
-      if (a.parents) a.parents[v] = (v == source) ? source : -1;
-    }
-    const uint64_t isom = __ballot(iso);
-    if (ln == 0) {
-      visited[w] = isom;
-      fa[w] = 0ull;
-      fb[w] = (w == (source >> 6)) ? (1ull << (source & 63)) : 0ull;
-    }
-  }
-  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  for (int64_t i = gt; i < nstatus; i += (int64_t)gridDim.x * kBlock) status[i] = 0ull;
-  if (gt == 0) {
-    Ctrl c = {};
-    *a.ctrl = c;
-  }
-}
-
-__device__ void bfs_push(const TravArgs &a, PushStage &st, int sumdeg) {
-  const int ntiles = a.ctrl->ntiles;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int64_t e0, e1;
-    const int ne = stage_tile<false>(st, a, t, sumdeg, e0, e1);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      const int k = find_entry(st, ne, e);
-      const int u = st.u[k];
-      const int v = a.push.ci[st.rs[k] + (e - st.deg[k])];
-      if (!bit_of(a.visited, v)) {
-        set_bit_guarded(a.fnxt, v);
-        if (a.parents && (unsigned)a.parents[v] > (unsigned)u)
-          atomicMin((unsigned *)&a.parents[v], (unsigned)u);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-__device__ void bfs_pull(const TravArgs &a, int *mark) {
-  const int ln = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    const uint64_t cand = ~a.visited[w];
-    if (cand == 0ull) continue;
-    const int64_t v = w * 64 + ln;
-    bool act = (cand >> ln) & 1ull;
-    int cur = 0, end = 0;
-    if (act) {
-      cur = rp[v];
-      end = rp[v + 1];
-      if (end - cur > kHeavyDeg) act = false;
-    }
-    bool found = false;
-    int par = -1;
-    if (act) {  // the first two neighbours of every row, in parallel
-      const int c0 = cur < end ? ci[cur] : -1;
-      const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
-      if (c0 >= 0 && bit_of(a.fcur, c0)) { found = true; par = c0; }
-      else if (c1 >= 0 && bit_of(a.fcur, c1)) { found = true; par = c1; }
-      cur = min(cur + 2, end);
-    }
-    for (;;) {  // the rest as one concatenated stream, 64 edges per step
-      const int len = (act && !found) ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      const bool valid = ln < total;
-      const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
-      const bool hit = valid && bit_of(a.fcur, c);
-      const uint64_t hm = __ballot(hit);
-      const int se = min(incl, 64);
-      const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
-      const uint64_t h = hm & seg;
-      const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
-      const int pc = __shfl(c, fl);
-      if (h) { found = true; par = pc; }
-      if (starts) cur += se - excl;
-    }
-    const uint64_t fbits = __ballot(found);
-    if (fbits) {
-      if (ln == 0) atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)fbits);
-      if (found && a.parents) a.parents[v] = par;
-    }
-  }
-  // pieces of long rows
-  for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
-    const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
-    if (bit_of(a.visited, r)) continue;
-    const int e = min(b + kHeavyChunk, rp[r + 1]);
-    for (int base = b; base < e; base += 64) {
-      const int pos = base + ln;
-      const int c = pos < e ? ci[pos] : -1;
-      const uint64_t hm = __ballot(c >= 0 && bit_of(a.fcur, c));
-      if (hm) {
-        const int pc = __shfl(c, __ffsll((unsigned long long)hm) - 1);
-        if (ln == 0) {
-          atomicOr((unsigned long long *)&a.fnxt[r >> 6], 1ull << (r & 63));
-          if (a.parents) atomicMin((unsigned *)&a.parents[r], (unsigned)pc);
-        }
-        break;
-      }
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_bfs_expand(TravArgs a) {
-  __shared__ PushStage st;
-  __shared__ int s_mark[kWavesPerBlock][64];
-  const int count = a.ctrl->count;
-  if (count == 0) return;
-  const int sumdeg = a.ctrl->sumdeg;
-  const int dir = decide_dir(a, count, sumdeg);
-  record_stats(a, count, sumdeg, dir);
-  if (dir == GRB_DIR_PUSH) bfs_push(a, st, sumdeg);
-  else bfs_pull(a, s_mark[threadIdx.x >> 6]);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,21 +442,10 @@ int compact_blocks(int64_t nw) {
 void launch_compact(int mode, const CompactArgs &a, void *stream) {
   const int g = compact_blocks(a.nw);
   hipStream_t s = (hipStream_t)stream;
-  if (mode == kCompactBfs) hipLaunchKernelGGL(k_compact<kCompactBfs>, dim3(g), dim3(kBlock), 0, s, a);
-  else if (mode == kCompactSssp) hipLaunchKernelGGL(k_compact<kCompactSssp>, dim3(g), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_compact<kCompactPlain>, dim3(g), dim3(kBlock), 0, s, a);
-}
-
-void launch_bfs_init(const TravArgs &a, int32_t *levels, int32_t source, uint64_t *visited,
-                     uint64_t *fa, uint64_t *fb, uint64_t *status, int64_t nstatus,
-                     void *stream) {
-  const int g = grid_for(a.nw, kWavesPerBlock, 4096);
-  hipLaunchKernelGGL(k_bfs_init, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, a, levels, source,
-                     visited, fa, fb, status, nstatus);
-}
-
-void launch_bfs_expand(const TravArgs &a, void *stream) {
-  hipLaunchKernelGGL(k_bfs_expand, dim3(kExpandGrid), dim3(kBlock), 0, (hipStream_t)stream, a);
+  const dim3 blk(kCompactThreads);
+  if (mode == kCompactBfs) hipLaunchKernelGGL(k_compact<kCompactBfs>, dim3(g), blk, 0, s, a);
+  else if (mode == kCompactSssp) hipLaunchKernelGGL(k_compact<kCompactSssp>, dim3(g), blk, 0, s, a);
+  else hipLaunchKernelGGL(k_compact<kCompactPlain>, dim3(g), blk, 0, s, a);
 }
 
 void launch_sssp_init(const TravArgs &a, int32_t source, uint64_t *iso, uint64_t *fa,

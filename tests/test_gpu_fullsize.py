@@ -1,0 +1,96 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration
+bench.py times: RMAT scale 22 (edge factor 16, symmetrised, weights 1..64),
+the 3000 x 3000 grid, and PageRank on the directed RMAT scale 22 graph.
+
+The oracle computes every output in full at these sizes (a few seconds
+each), so the comparison is element by element, not sampled.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def grb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_01407_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def rmat22(grb):
+    g = graphgen.rmat(22)
+    return grb.Matrix.from_raw(g), oracle.Adjacency.from_raw(g)
+
+
+@pytest.fixture(scope="module")
+def grid3000(grb):
+    g = graphgen.grid(3000, 3000)
+    return grb.Matrix.from_raw(g), oracle.Adjacency.from_raw(g)
+
+
+MODES = [("auto_paper", 0, 0), ("auto_exact", 0, 1), ("push", 1, 0), ("pull", 2, 0)]
+
+
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+def test_bfs_rmat22(grb, rmat22, mode):
+    A, adj = rmat22
+    ref_lev, ref_par, nl = oracle.bfs(adj, 0)
+    lev, par = grb.bfs(A, 0, desc=grb.descriptor(direction=mode[1], rule=mode[2]))
+    assert np.array_equal(lev.cpu().numpy(), ref_lev)
+    assert np.array_equal(par.cpu().numpy(), ref_par)
+    assert grb.last_stats()["iterations"] == nl
+
+
+def test_bfs_rmat22_other_sources(grb, rmat22):
+    A, adj = rmat22
+    src, dst = graphgen.rmat_edges(22)
+    srcs = graphgen.sources(src, dst, 1 << 22, 3)
+    for s in srcs:
+        ref_lev, ref_par, _ = oracle.bfs(adj, int(s))
+        lev, par = grb.bfs(A, int(s), desc=grb.descriptor(rule=1))
+        assert np.array_equal(lev.cpu().numpy(), ref_lev), s
+        assert np.array_equal(par.cpu().numpy(), ref_par), s
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_sssp_rmat22(grb, rmat22, rule):
+    A, adj = rmat22
+    ref, _, _ = oracle.sssp(adj, 0)
+    dist = grb.sssp(A, 0, desc=grb.descriptor(rule=rule))
+    assert np.array_equal(dist.cpu().numpy(), ref)
+
+
+def test_grid3000_bfs_sssp(grb, grid3000):
+    A, adj = grid3000
+    ref_lev, ref_par, nl = oracle.bfs(adj, 0)
+    lev, par = grb.bfs(A, 0)
+    assert nl == 5999
+    assert np.array_equal(lev.cpu().numpy(), ref_lev)
+    assert np.array_equal(par.cpu().numpy(), ref_par)
+    ref, _, _ = oracle.sssp(adj, 0)
+    dist = grb.sssp(A, 0)
+    assert np.array_equal(dist.cpu().numpy(), ref)
+
+
+def test_pagerank_rmat22_directed(grb):
+    g = graphgen.rmat(22, symmetric=False, weights=False)
+    adj = oracle.Adjacency.from_raw(g)
+    ref, it, _ = oracle.pagerank(adj, 0.85, 50, 1e-7)
+    P = grb.Matrix.from_raw(g, weights=False)
+    p32, it32, _ = grb.pagerank(P, dtype=torch.float32, max_iter=it, tol=0.0)
+    p64, it64, _ = grb.pagerank(P, dtype=torch.float64, max_iter=it, tol=0.0)
+    assert it32 == it and it64 == it
+    err32 = np.abs(p32.cpu().numpy().astype(np.float64) - ref).sum()
+    err64 = np.abs(p64.cpu().numpy() - ref).sum()
+    assert err32 <= 1e-5, err32
+    assert err64 <= 1e-10, err64
+    _, it_auto, _ = grb.pagerank(P, dtype=torch.float64, max_iter=50, tol=1e-7)
+    assert it_auto == it

@@ -1,0 +1,227 @@
+"""GPU parity of grb_mxv / grb_vxm against the plain-loop oracle.
+
+Random small matrices (empty rows, hub rows, isolated columns) with every
+semiring x mask (none / value / structural, complemented or not) x accum x
+REPLACE x transpose x direction (push / pull / auto).  Values are small
+integers so every semiring is exact in any summation order; the results
+must match element by element.  Larger R-MAT inputs check push = pull and
+rows longer than the pull split threshold.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+from oracle import mxv as M
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def grb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_01407_amd as g
+    return g
+
+
+GRB_NAME = {"lor_land": "lor_land", "min_plus": "min_plus_fp32", "plus_times": "plus_times_fp32",
+            "min_first": "min_first_int32", "min_second": "min_second_int32"}
+ACCUM = {"lor_land": "lor", "min_plus": "min", "plus_times": "plus", "min_first": "min",
+         "min_second": "min"}
+
+
+def vec_dtype(semiring):
+    return {"lor_land": torch.uint8, "min_plus": torch.float32, "plus_times": torch.float32,
+            "min_first": torch.int32, "min_second": torch.int32}[semiring]
+
+
+def csr(n_rows, triples):
+    if not triples:
+        return np.zeros(n_rows + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32)
+    t = np.array(triples, dtype=np.float64)
+    order = np.lexsort((t[:, 1], t[:, 0]))
+    t = t[order]
+    rows = t[:, 0].astype(np.int64)
+    rp = np.zeros(n_rows + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), t[:, 1].astype(np.int32), t[:, 2].astype(np.float32)
+
+
+def device_matrix(grb, n_rows, n_cols, triples, valued=True):
+    rp, ci, v = csr(n_rows, triples)
+    trp, tci, tv = csr(n_cols, [(j, i, x) for (i, j, x) in triples])
+    return grb.Matrix(n_rows, n_cols, rp, ci, v if valued else None, trp, tci,
+                      tv if valued else None, symmetric=False)
+
+
+def rand_vec(rng, n, p, semiring):
+    out = {}
+    for i in range(n):
+        if rng.random() < p:
+            if semiring == "lor_land":
+                out[i] = bool(rng.integers(0, 2))
+            elif semiring in ("min_first", "min_second"):
+                out[i] = int(rng.integers(0, 50))
+            else:
+                out[i] = float(rng.integers(0, 20))
+    return out
+
+
+def rand_matrix(rng, n_rows, n_cols, density, semiring, hub=False):
+    triples = []
+    for i in range(n_rows):
+        for j in range(n_cols):
+            if rng.random() < density:
+                val = int(rng.integers(0, 3)) if semiring == "lor_land" else int(rng.integers(1, 9))
+                triples.append((i, j, val))
+    if hub and n_rows:
+        h = int(rng.integers(0, n_rows))
+        have = {j for (i, j, _) in triples if i == h}
+        triples += [(h, j, 1) for j in range(n_cols) if j not in have]
+    return triples
+
+
+def check_case(grb, rng, semiring, is_vxm, direction, n_rows, n_cols, trial, valued=True):
+    triples = rand_matrix(rng, n_rows, n_cols, float(rng.uniform(0.0, 0.5)), semiring,
+                          hub=trial % 5 == 0)
+    transpose = trial % 3 == 2
+    out_rows = (n_cols if not transpose else n_rows) if is_vxm else (n_rows if not transpose
+                                                                      else n_cols)
+    in_len = n_rows + n_cols - out_rows
+    A = device_matrix(grb, n_rows, n_cols, triples, valued=valued)
+    o_triples = triples if valued else [(i, j, 1) for (i, j, _) in triples]
+    u = rand_vec(rng, in_len, float(rng.uniform(0, 1)), semiring)
+    w_old = rand_vec(rng, out_rows, 0.5, semiring)
+    mask = None if trial % 4 == 0 else {i: int(rng.integers(0, 3)) for i in range(out_rows)
+                                        if rng.random() < 0.6}
+    comp = trial % 3 == 1
+    struct = trial % 5 == 3
+    accum = ACCUM[semiring] if trial % 2 else None
+    replace = trial % 7 < 3
+    dt = vec_dtype(semiring)
+    W = grb.Vector(out_rows, dt)
+    W.set(w_old)
+    U = grb.Vector(in_len, dt)
+    U.set(u)
+    Mk = None
+    if mask is not None:
+        Mk = grb.Vector(out_rows, torch.int32)
+        Mk.set(mask)
+    flags = ((grb.GRB_MASK_COMP if comp else 0) | (grb.GRB_MASK_STRUCT if struct else 0) |
+             (grb.GRB_REPLACE if replace else 0) | (grb.GRB_TRAN_A if transpose else 0))
+    d = grb.descriptor(direction=direction, flags=flags, rule=trial % 2)
+    if is_vxm:
+        grb.vxm(W, Mk, accum, GRB_NAME[semiring], U, A, desc=d)
+    else:
+        grb.mxv(W, Mk, accum, GRB_NAME[semiring], A, U, desc=d)
+    torch.cuda.synchronize()
+    fn = M.vxm if is_vxm else M.mxv
+    ref = fn(out_rows, o_triples, u, semiring=semiring, w_old=w_old, mask=mask,
+             complement=comp, structural=struct, accum=accum, replace=replace,
+             transpose=transpose)
+    got = W.to_dict()
+    assert set(got) == set(ref), (trial, sorted(got), sorted(ref))
+    for i in ref:
+        assert float(got[i]) == float(ref[i]), (trial, i, got[i], ref[i])
+
+
+@pytest.mark.parametrize("semiring", list(GRB_NAME))
+@pytest.mark.parametrize("is_vxm", [False, True], ids=["mxv", "vxm"])
+@pytest.mark.parametrize("direction", [0, 1, 2], ids=["auto", "push", "pull"])
+def test_mxv_random_small(grb, semiring, is_vxm, direction):
+    rng = np.random.default_rng(abs(hash((semiring, is_vxm, direction))) % 2**32)
+    for trial in range(24):
+        n_rows = int(rng.integers(1, 150))
+        n_cols = int(rng.integers(1, 150))
+        check_case(grb, rng, semiring, is_vxm, direction, n_rows, n_cols, trial,
+                   valued=trial % 6 != 5)
+
+
+def test_running_example(grb):
+    with open(os.path.join(GOLDEN, "running_example_bfs_step.json")) as f:
+        ex = json.load(f)
+    n = ex["n"]
+    A = device_matrix(grb, n, n, [(u, v, 1) for u, v in ex["edges"]], valued=False)
+    for direction in (0, 1, 2):
+        f_ = grb.Vector(n, torch.uint8)
+        f_.set({i: True for i in ex["frontier"]})
+        vis = grb.Vector(n, torch.uint8)
+        vis.set({i: True for i in ex["visited"]})
+        nxt = grb.Vector(n, torch.uint8)
+        d = grb.descriptor(direction=direction, flags=grb.GRB_MASK_COMP | grb.GRB_REPLACE)
+        grb.vxm(nxt, vis, None, "lor_land", f_, A, desc=d)
+        assert sorted(nxt.to_dict()) == ex["next_frontier"]
+
+
+@pytest.mark.parametrize("semiring", ["lor_land", "min_plus", "min_first", "min_second"])
+def test_push_equals_pull_rmat(grb, semiring):
+    """Exact semirings: the two directions agree bit for bit on an R-MAT graph
+    whose hub rows exceed the pull split threshold, and match the oracle."""
+    g = graphgen.rmat(13)
+    rp, ci, w = grb.csr_from_edges(g.n, g.src, g.dst, g.w, symmetrise=True)
+    A = grb.Matrix(g.n, g.n, rp, ci, w, symmetric=True)
+    assert np.diff(rp).max() > 2048
+    rng = np.random.default_rng(11)
+    triples = [(int(i), int(j), float(x)) for i, (s, e) in enumerate(zip(rp[:-1], rp[1:]))
+               for j, x in zip(ci[s:e], w[s:e])]
+    for p in (0.001, 0.05, 0.6):
+        u = rand_vec(rng, g.n, p, semiring)
+        mask = {i: 1 for i in range(g.n) if rng.random() < 0.3}
+        outs = []
+        for direction in (1, 2, 0):
+            U = grb.Vector(g.n, vec_dtype(semiring))
+            U.set(u)
+            Mk = grb.Vector(g.n, torch.int32)
+            Mk.set(mask)
+            W = grb.Vector(g.n, vec_dtype(semiring))
+            grb.mxv(W, Mk, None, GRB_NAME[semiring], A, U,
+                    desc=grb.descriptor(direction=direction, flags=grb.GRB_MASK_COMP))
+            outs.append(W.to_dict())
+        assert outs[0] == outs[1] == outs[2]
+        ref = M.mxv(g.n, triples, u, semiring=semiring, mask=mask, complement=True)
+        assert set(outs[0]) == set(ref)
+        for i in ref:
+            assert float(outs[0][i]) == float(ref[i])
+
+
+def test_plus_times_float_tolerance(grb):
+    """Real-valued plus-times: both directions within the summation bound
+    gamma_m * sum |a u| of the fp64 result; pull repeats bit for bit."""
+    g = graphgen.rmat(12, symmetric=False)
+    rng = np.random.default_rng(3)
+    rp, ci, _ = grb.csr_from_edges(g.n, g.src, g.dst, None, symmetrise=False)
+    vals = rng.standard_normal(ci.size).astype(np.float32)
+    trp, tci, tv = csr(g.n, [(int(j), int(i), float(x)) for i, (s, e) in
+                             enumerate(zip(rp[:-1], rp[1:])) for j, x in zip(ci[s:e], vals[s:e])])
+    A = grb.Matrix(g.n, g.n, rp, ci, vals, trp, tci, tv)
+    u = {i: float(rng.standard_normal()) for i in range(g.n) if rng.random() < 0.7}
+    uv = np.zeros(g.n)
+    for i, x in u.items():
+        uv[i] = np.float32(x)
+    rows = np.repeat(np.arange(g.n), np.diff(rp))
+    exact = np.zeros(g.n)
+    absum = np.zeros(g.n)
+    np.add.at(exact, rows, vals.astype(np.float64) * uv[ci])
+    np.add.at(absum, rows, np.abs(vals.astype(np.float64) * uv[ci]))
+    deg = np.diff(rp)
+    gamma = deg * 2.0**-24 / (1 - deg * 2.0**-24)
+    res = []
+    for direction in (1, 2, 2):
+        U = grb.Vector(g.n, torch.float32)
+        U.set(u)
+        W = grb.Vector(g.n, torch.float32)
+        grb.mxv(W, None, None, "plus_times_fp32", A, U, desc=grb.descriptor(direction=direction))
+        res.append(W.values.cpu().numpy().astype(np.float64)[: g.n])
+    for r in res:
+        touched = np.array([i for i in range(g.n) if any(uv[ci[rp[i]:rp[i + 1]]] != 0)])
+        if touched.size:
+            assert np.all(np.abs(r[touched] - exact[touched]) <= gamma[touched] * absum[touched]
+                          + 1e-30)
+    assert np.array_equal(res[1], res[2])

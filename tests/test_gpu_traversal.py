@@ -77,8 +77,8 @@ def matrix(grb, name):
 
 
 MODES = [("auto_paper", 0, 0), ("auto_exact", 0, 1), ("push", 1, 0), ("pull", 2, 0)]
-SMALL = ["rmat_14", "rmat_dir_12", "grid_33x70", "path", "star", "clique", "two_comp",
-         "empty", "single"]
+SMALL = ["rmat_14", "rmat_18", "rmat_dir_12", "grid_33x70", "path", "star", "clique",
+         "two_comp", "empty", "single"]
 
 
 def _sources(name, n):
@@ -137,8 +137,8 @@ def test_bfs_repeatable(grb, name):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-SSSP_GRAPHS = ["rmat_14", "rmat_dir_12", "grid_33x70", "path", "star", "clique", "two_comp",
-               "empty", "single"]
+SSSP_GRAPHS = ["rmat_14", "rmat_18", "rmat_dir_12", "grid_33x70", "path", "star", "clique",
+               "two_comp", "empty", "single"]
 
 
 @pytest.mark.parametrize("name", SSSP_GRAPHS)
