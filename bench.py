@@ -8,7 +8,7 @@ A step is one full BFS; value = stored entries of the symmetrised CSR per
 second of BFS (the paper's TEPS convention, Section 8), in GTEPS.
 
 The JSON line also carries:
-* roofline: HBM roofline of the BFS expand kernel (the step's dominant
+* roofline: HBM roofline of the BFS level kernel k_bfs_level (the step's dominant
   kernel): algorithmic bytes of all its launches in the timed region divided
   by their summed duration (HIP events recorded by the library on the launch
   stream), against 8 TB/s;
@@ -249,6 +249,102 @@ def bench_extras(grb, graphgen, torch, args):
     return ex
 
 
+def bench_msbfs(grb, graphgen, torch, args):
+    """Batched multi-source BFS (k = 64 and 512, R-MAT 20 and 22) with tiles
+    from the autotuner, against 64 sequential single-source BFS runs."""
+    from paper_1908_01407_amd import tune
+
+    res = {}
+    for scale in args.msbfs_scales:
+        if scale == args.scale:
+            g, A = args._g, args._A
+        else:
+            g = graphgen.rmat(scale, weights=False)
+            A = grb.Matrix.from_raw(g, weights=False)
+        ws1 = grb.workspace(grb.OP_BFS, A)
+        for k in args.msbfs_k:
+            src = graphgen.sources(g.src, g.dst, g.n, k, seed=3)
+            best = tune.tune_msbfs(A, src, cache_path=args.tune_cache, repeats=2, log=log)
+            wsk = grb.workspace(grb.OP_MSBFS, A, k)
+            lev = torch.empty((A.nrows, k), dtype=torch.int32, device="cuda")
+            run = lambda: grb.msbfs(A, src, words_per_pass=best["words_per_pass"],
+                                    grid=best["grid"], ws=wsk, levels=lev)
+            run()
+            ms = timed(run, args.extra_steps, torch)
+            st = grb.last_stats()
+            seq_src = src[:64]
+            ms_seq = timed(lambda: [grb.bfs(A, int(s), parents=False, ws=ws1) for s in seq_src],
+                           1, torch)
+            per_src_seq = ms_seq / len(seq_src)
+            res[f"rmat{scale}_k{k}"] = {
+                "ms": round(ms, 3), "levels": st["iterations"],
+                "sources_per_s": round(k / ms * 1e3, 1),
+                "gteps": round(k * A.nnz / ms / 1e6, 2),
+                "tile": {"words_per_pass": best["words_per_pass"], "grid": best["grid"]},
+                "sequential_ms_per_source": round(per_src_seq, 4),
+                "speedup_vs_sequential": round(per_src_seq * k / ms, 2)}
+            del wsk, lev
+        del ws1
+    return res
+
+
+def bench_serve(grb, graphgen, torch, args):
+    """Serving: six resident graphs, Poisson arrivals, 70% BFS / 30% SSSP,
+    continuous batching with HBM-footprint admission, against a
+    one-query-at-a-time FIFO server at the same arrival rates."""
+    from paper_1908_01407_amd.serve import GpuExecutor, Query, Server
+
+    raws = {f"rmat{s}": (args._g if s == args.scale else graphgen.rmat(s)) for s in (16, 18, 20, 22)}
+    raws["grid2000"] = graphgen.grid(2000, 2000)
+    raws["grid3000"] = graphgen.grid(3000, 3000)
+    graphs = {k: (args._A if k == f"rmat{args.scale}" else grb.Matrix.from_raw(g))
+              for k, g in raws.items()}
+    names = sorted(graphs)
+    cand = {k: np.flatnonzero(graphgen.touched(g.src, g.dst, g.n)) for k, g in raws.items()}
+
+    def trace(nq, rate, seed):
+        arr = graphgen.poisson_arrivals(nq, rate=rate, seed=4 + seed)
+        kind = graphgen.uniform_ints(nq, 10, seed=50 + seed)
+        gs = graphgen.uniform_ints(nq, len(names), seed=60 + seed)
+        pick = graphgen.uniform_doubles(nq, seed=70 + seed)
+        qs = []
+        for i in range(nq):
+            gname = names[int(gs[i])]
+            c = cand[gname]
+            qs.append(Query(qid=i, kind="bfs" if kind[i] < 7 else "sssp", graph=gname,
+                            source=int(c[min(int(pick[i] * c.size), c.size - 1)]),
+                            arrival=float(arr[i])))
+        return qs
+
+    out = {"graphs": {k: {"n": A.nrows, "nnz": A.nnz} for k, A in graphs.items()},
+           "mix": "70% BFS / 30% SSSP, graph and source uniform, Poisson arrivals",
+           "budget_bytes": args.serve_budget}
+    ex = GpuExecutor(graphs, slots=args.serve_slots, max_batch=64, keep_results=False)
+    fifo_ex = GpuExecutor(graphs, slots=1, max_batch=1, keep_results=False)
+    # warm up every graph and kind once
+    Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
+        trace(2 * len(names), 1e6, 99), realtime=False)
+    sat = Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
+        trace(args.serve_queries, 1e9, 0), realtime=False)
+    fifo_sat = Server(fifo_ex, budget=args.serve_budget, slots=1, max_batch=1).run(
+        trace(args.serve_queries // 2, 1e9, 0), realtime=False)
+    out["saturation"] = {"batched": sat, "fifo": fifo_sat}
+    qps = sat["qps"]
+    points = []
+    for frac in args.serve_load:
+        rate = frac * qps
+        b = Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
+            trace(args.serve_queries, rate, 1), realtime=True)
+        f = Server(fifo_ex, budget=args.serve_budget, slots=1, max_batch=1).run(
+            trace(args.serve_queries, rate, 1), realtime=True)
+        points.append({"rate_qps": round(rate, 1), "load_of_batched_saturation": frac,
+                       "batched": b, "fifo": f})
+        log(f"[bench] serve rate {rate:.1f}: batched p50 {b['p50_ms']} p99 {b['p99_ms']} | "
+            f"fifo p50 {f['p50_ms']} p99 {f['p99_ms']}")
+    out["points"] = points
+    return out
+
+
 def cpu_baseline(g, A_nnz, args):
     import oracle
     adj = oracle.Adjacency.from_raw(g)
@@ -277,6 +373,16 @@ def main():
     ap.add_argument("--no-pr", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-msbfs", action="store_true")
+    ap.add_argument("--msbfs-scales", type=int, nargs="*", default=[20, 22])
+    ap.add_argument("--msbfs-k", type=int, nargs="*", default=[64, 512])
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file caching autotuned batched-BFS tiles (default: none)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=600)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget", type=int, default=16 << 30)
+    ap.add_argument("--serve-load", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
@@ -306,6 +412,7 @@ def main():
     log(f"[bench] building CSR ({time.perf_counter() - t_setup:.1f}s)")
     A = grb.Matrix.from_raw(g)
     args._A = A
+    args._g = g
     n, nnz = A.nrows, A.nnz
     log(f"[bench] n={n} nnz={nnz} ({time.perf_counter() - t_setup:.1f}s)")
     ws = grb.workspace(grb.OP_BFS, A)
@@ -347,7 +454,7 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-        "kernel": "k_bfs_expand",
+        "kernel": "k_bfs_level",
         "launches_per_step": launches / args.steps,
         "avg_launch_us": round(exp_ms / launches * 1e3, 3),
         "algorithmic_bytes_per_step": bytes_step,
@@ -381,6 +488,12 @@ def main():
     if not args.no_extras:
         log("[bench] extras")
         out["extras"] = bench_extras(grb, graphgen, torch, args)
+    if not args.no_msbfs:
+        log("[bench] batched BFS")
+        out["batched_bfs"] = bench_msbfs(grb, graphgen, torch, args)
+    if not args.no_serve:
+        log("[bench] serving")
+        out["serving"] = bench_serve(grb, graphgen, torch, args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, nnz, args)

@@ -241,7 +241,7 @@ typedef enum grb_op {
   GRB_OP_BFS = 1,
   GRB_OP_SSSP = 2,
   GRB_OP_PAGERANK = 3, /* k = 1 for fp32, 2 for fp64 */
-  GRB_OP_MSBFS = 4,    /* k = number of sources */
+  GRB_OP_MSBFS = 4,    /* k = number of sources (batched BFS) */
   GRB_OP_NVALS = 5
 } grb_op;
 
@@ -327,6 +327,36 @@ grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descripto
 grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping,
                       int32_t max_iter, double tol, int32_t *iters, double *delta_out,
                       const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batched multi-source BFS: k traversals at once as one masked product of
+ * A^T with a bitmask block of frontiers (multi-nodeset traversal, Table 6
+ * and Section 3.3; matrix-matrix direction optimisation is the paper's
+ * future work, Section 9).  Each level pushes or pulls for the whole batch
+ * (the descriptor's switch rule on the batch's frontier; PAPER compares
+ * the frontier's (vertex, query) pairs with n*k, EXACT the out-edges of the
+ * active (vertex, 64-query word) pairs with nnz per word).
+ *   levels[n * k], VERTEX-major: levels[v * k + q] is the hop count from
+ *          sources[q] to v (0 at the source, -1 unreached), as one
+ *          single-source grb_bfs would give;
+ *   sources[k]: device int32 vertex ids, repeats allowed;
+ *   tile: query words per pass (1..ceil(k/64); each word is 64 queries)
+ *          and workgroups per pass; NULL or zero fields pick defaults (the
+ *          autotuner of the Python package writes tuned values).
+ * Needs the CSR of A^T (or a symmetric matrix) for pull.  Synchronises
+ * once per batch of levels.  Errors as grb_bfs, plus GRB_INVALID_VALUE for
+ * k < 1 or a bad tile.  Source ids are not range-checked on the host (they
+ * are device data): ids outside [0, n) are undefined behaviour.
+ */
+typedef struct grb_msbfs_tile {
+  int32_t words_per_pass; /* kt, 0 = all words of the batch in one pass */
+  int32_t grid;           /* workgroups per pass, 0 = default */
+  int32_t reserved[2];    /* must be zero */
+} grb_msbfs_tile;
+
+grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_t k,
+                   const grb_msbfs_tile *tile, const grb_descriptor *d, void *ws,
+                   size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Statistics and errors                                               */

@@ -61,6 +61,11 @@ class Descriptor(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
+class MsbfsTile(ctypes.Structure):
+    _fields_ = [("words_per_pass", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("recorded", ctypes.c_int32), ("pushes", ctypes.c_int32),
@@ -106,6 +111,8 @@ _SIGS = {
     "grb_vxm": ([_p, _p, _i32, _i32, _p, _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_bfs": ([_p, _p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_sssp": ([_p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_msbfs": ([_p, _p, _p, _i32, ctypes.POINTER(MsbfsTile), ctypes.POINTER(Descriptor), _p,
+                   _sz, _p], _i32),
     "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
                       ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
@@ -346,6 +353,24 @@ def sssp(A: Matrix, source: int, *, desc: Descriptor | None = None, ws=None, str
                         ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
                         _stream(stream)), "grb_sssp")
     return dist[: A.nrows]
+
+
+def msbfs(A: Matrix, sources, *, words_per_pass: int = 0, grid: int = 0,
+          desc: Descriptor | None = None, ws=None, levels=None, stream=None):
+    """levels int32[n, k] (vertex-major) of k BFS runs via grb_msbfs."""
+    torch = _torch()
+    if not isinstance(sources, torch.Tensor):
+        sources = torch.as_tensor(np.asarray(sources, dtype=np.int32))
+    src = sources.to(device=A.device, dtype=torch.int32).contiguous()
+    k = int(src.numel())
+    if levels is None:
+        levels = torch.empty((max(A.nrows, 1), k), dtype=torch.int32, device=A.device)
+    ws = ws if ws is not None else workspace(OP_MSBFS, A, k)
+    tile = MsbfsTile(words_per_pass, grid)
+    check(_lib.grb_msbfs(_ptr(levels), A.handle, _ptr(src), k, ctypes.byref(tile),
+                         ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
+                         _stream(stream)), "grb_msbfs")
+    return levels[: A.nrows]
 
 
 def pagerank(A: Matrix, *, dtype=None, damping: float = 0.85, max_iter: int = 50,

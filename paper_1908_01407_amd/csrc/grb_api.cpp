@@ -65,41 +65,6 @@ struct Carver {
   }
 };
 
-struct TravWs {
-  uint64_t *visited, *fa, *fb, *status;
-  int32_t *list, *degpre, *rowstart, *tiles;
-  float *lval, *fval;
-  Ctrl *ctrl;
-  int64_t *stats;
-  int nblk;
-  size_t bytes;
-};
-
-TravWs trav_layout(void *ws, int64_t n, int64_t nnz_push, bool sssp) {
-  Carver c(ws);
-  TravWs t{};
-  const int64_t nw = words_of(n);
-  t.nblk = compact_blocks(nw);
-  t.ctrl = c.take<Ctrl>(1);
-  t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
-  t.status = c.take<uint64_t>((size_t)2 * t.nblk);
-  t.visited = c.take<uint64_t>((size_t)nw);
-  t.fa = c.take<uint64_t>((size_t)nw);
-  t.fb = c.take<uint64_t>((size_t)nw);
-  t.list = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
-  t.degpre = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
-  t.rowstart = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
-  t.tiles = c.take<int32_t>((size_t)((n + nnz_push) / kPushTile + 3));
-  if (sssp) {
-    t.lval = c.take<float>((size_t)std::max<int64_t>(n, 1));
-    t.fval = c.take<float>((size_t)std::max<int64_t>(n, 1));
-  } else {
-    t.lval = t.fval = nullptr;
-  }
-  t.bytes = c.off;
-  return t;
-}
-
 struct BfsWs {
   Ctrl *ctrl;
   int64_t *stats;
@@ -115,6 +80,28 @@ BfsWs bfs_layout(void *ws, int64_t n) {
   t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
   t.visited = c.take<uint64_t>((size_t)nw);
   for (int i = 0; i < 3; ++i) t.F[i] = c.take<uint64_t>((size_t)nw);
+  t.bytes = c.off;
+  return t;
+}
+
+struct MsWs {
+  Ctrl *ctrl;
+  int64_t *stats;
+  unsigned long long *cnt;
+  uint64_t *V, *F[3], *act[3];
+  size_t bytes;
+};
+
+MsWs ms_layout(void *ws, int64_t n, int64_t k) {
+  Carver c(ws);
+  MsWs t{};
+  const int64_t W = (k + 63) / 64, nb = std::max<int64_t>(n * W, 1), nw = words_of(n);
+  t.ctrl = c.take<Ctrl>(1);
+  t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
+  t.cnt = c.take<unsigned long long>((size_t)6 * kCntStripes);
+  t.V = c.take<uint64_t>((size_t)nb);
+  for (int i = 0; i < 3; ++i) t.F[i] = c.take<uint64_t>((size_t)nb);
+  for (int i = 0; i < 3; ++i) t.act[i] = c.take<uint64_t>((size_t)std::max<int64_t>(nw, 1));
   t.bytes = c.off;
   return t;
 }
@@ -384,110 +371,73 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
   return GRB_SUCCESS;
 }
 
-enum TravKind { kTravBfs, kTravSssp };
-
-// The level loop shared by BFS and SSSP: expand + compaction per level, all
-// on the device; the host reads the frontier size back once per batch of
-// levels to detect the end.
-grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *levels,
-                       int32_t *parents, float *dist, const grb_descriptor &desc, void *ws,
-                       size_t ws_bytes, void *stream) {
+// SSSP: one kernel per round, same batching of rounds as BFS.
+grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descriptor &desc,
+                  void *ws, size_t ws_bytes, void *stream) {
   const int64_t n = A->nrows;
   const bool can_pull = A->at.valid();
-  if (desc.direction == GRB_DIR_PULL && !can_pull) return GRB_NOT_IMPLEMENTED;
-  TravWs w = trav_layout(ws, n, A->a.nnz, kind == kTravSssp);
+  if (!can_pull && desc.direction == GRB_DIR_PULL) return GRB_NOT_IMPLEMENTED;
+  BfsWs w = bfs_layout(ws, n);
   grb_info info = check_ws(ws, ws_bytes, w.bytes);
   if (info != GRB_SUCCESS) return info;
   hipStream_t s = (hipStream_t)stream;
   const bool profile = (desc.flags & GRB_PROFILE) != 0;
-
-  TravArgs ta;
-  ta.n = n;
-  ta.nw = words_of(n);
-  ta.nnz = A->nnz;
-  ta.push = A->a;
-  ta.pull = A->at;
-  ta.can_push = true;
-  ta.can_pull = can_pull;
-  ta.visited = w.visited;
-  ta.parents = parents;
-  ta.dist = dist;
-  ta.fval = w.fval;
-  ta.lval = w.lval;
-  ta.wpush = (const float *)A->a.val;
-  ta.wpull = can_pull ? (const float *)A->at.val : nullptr;
-  ta.list = w.list;
-  ta.degpre = w.degpre;
-  ta.rowstart = w.rowstart;
-  ta.tiles = w.tiles;
-  ta.ctrl = w.ctrl;
-  ta.stats = w.stats;
-  ta.rule = desc.switch_rule;
-  ta.denom = desc.switch_denominator;
-  ta.forced = desc.direction;
-
-  const int64_t nstatus = 2 * (int64_t)w.nblk;
-  launch_sssp_init(ta, source, w.visited, w.fa, w.fb, w.status, nstatus, stream);
-
-  CompactArgs ca;
-  ca.nw = ta.nw;
-  ca.rp = A->a.rp;
-  ca.list = w.list;
-  ca.degpre = w.degpre;
-  ca.rowstart = w.rowstart;
-  ca.tiles = w.tiles;
-  ca.ctrl = w.ctrl;
-  ca.visited = w.visited;
-  ca.levels = levels;
-  ca.dist = dist;
-  ca.fval = w.fval;
-  ca.lval = w.lval;
-  const int cmode = kind == kTravBfs ? kCompactBfs : kCompactSssp;
-  int parity = 0;
-  auto compact = [&](uint64_t *nb, uint64_t *clear, int lev) {
-    ca.nb = nb;
-    ca.clear = clear;
-    ca.lev = lev;
-    ca.status_cur = w.status + (size_t)parity * w.nblk;
-    ca.status_next = w.status + (size_t)(parity ^ 1) * w.nblk;
-    launch_compact(cmode, ca, stream);
-    parity ^= 1;
+  SsspArgs sa;
+  sa.n = n;
+  sa.nw = words_of(n);
+  sa.nnz = A->nnz;
+  sa.push = A->a;
+  sa.pull = A->at;
+  sa.can_pull = can_pull;
+  sa.same_csr = A->symmetric;
+  sa.wpush = (const float *)A->a.val;
+  sa.wpull = can_pull ? (const float *)A->at.val : nullptr;
+  sa.dist = dist;
+  sa.iso = w.visited;
+  sa.ctrl = w.ctrl;
+  sa.stats = w.stats;
+  sa.rule = desc.switch_rule;
+  sa.denom = desc.switch_denominator;
+  sa.forced = desc.direction;
+  int32_t *cnt = w.ctrl->lists;
+  auto at_round = [&](int64_t d) {
+    const int i = (int)(d % 3), j = (int)((d + 1) % 3), k = (int)((d + 2) % 3);
+    sa.fcur = w.F[i];
+    sa.fnxt = w.F[j];
+    sa.fclr = w.F[k];
+    sa.cnt_cur = cnt + i * kCntSlots;
+    sa.cnt_nxt = cnt + j * kCntSlots;
+    sa.cnt_clr = cnt + k * kCntSlots;
+    sa.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
   };
-  compact(w.fb, nullptr, 0);  // level 0 = {source}
-  ca.skip_if_empty = true;
-
+  at_round(0);
+  launch_sssp_start(sa, source, w.F[1], w.F[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
-  int chunk = 6;
+  int chunk = 8;
   Ctrl hc{};
-  std::vector<int> ev_level;
   for (;;) {
     for (int i = 0; i < chunk && d < cap; ++i, ++d) {
-      uint64_t *fcur = (d % 2 == 0) ? w.fb : w.fa;
-      uint64_t *fnxt = (d % 2 == 0) ? w.fa : w.fb;
-      ta.fcur = fcur;
-      ta.fnxt = fnxt;
-      ta.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
+      at_round(d);
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
-      launch_sssp_expand(ta, stream);
+      launch_sssp_round(sa, stream);
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
-      compact(fnxt, fcur, (int)std::min<int64_t>(d + 1, INT32_MAX));
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
       return GRB_PANIC;
-    if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
-    if (hc.count == 0 || d >= cap) break;
-    chunk = std::min(chunk * 2, 256);
+    int64_t next = 0;
+    for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + 2 * t];
+    if (next == 0 || d >= cap) break;
+    chunk = std::min(chunk * 2, 512);
   }
   const int iters = hc.nlev;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
-  if (nrec > 0) {
-    if (hipMemcpy(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
-                  hipMemcpyDeviceToHost) != hipSuccess)
-      return GRB_PANIC;
-  }
+  if (nrec > 0 && hipMemcpy(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
+                            hipMemcpyDeviceToHost) != hipSuccess)
+    return GRB_PANIC;
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
@@ -498,8 +448,7 @@ grb_info run_traversal(TravKind kind, grb_matrix A, int32_t source, int32_t *lev
       ms_all += ms;
     }
   }
-  finish_stats(kind == kTravBfs ? GRB_OP_BFS : GRB_OP_SSSP, iters, rec, kms,
-               (int)std::min<int64_t>(d, INT32_MAX), ms_all);
+  finish_stats(GRB_OP_SSSP, iters, rec, kms, (int)std::min<int64_t>(d, INT32_MAX), ms_all);
   return GRB_SUCCESS;
 }
 
@@ -752,7 +701,7 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
   if (!A) return GRB_UNINITIALIZED_OBJECT;
   switch (op) {
     case GRB_OP_BFS: *bytes = bfs_layout(nullptr, A->nrows).bytes; break;
-    case GRB_OP_SSSP: *bytes = trav_layout(nullptr, A->nrows, A->nnz, true).bytes; break;
+    case GRB_OP_SSSP: *bytes = bfs_layout(nullptr, A->nrows).bytes; break;
     case GRB_OP_PAGERANK: {
       if (k != 1 && k != 2) return GRB_INVALID_VALUE;
       Csr pull = A->at;
@@ -760,6 +709,10 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
       *bytes = pr_layout(nullptr, A->nrows, pull, k == 2 ? 8 : 4).bytes;
       break;
     }
+    case GRB_OP_MSBFS:
+      if (k < 1 || k > INT32_MAX) return GRB_INVALID_VALUE;
+      *bytes = ms_layout(nullptr, A->nrows, k).bytes;
+      break;
     case GRB_OP_MXV: {
       const int64_t m = std::max(A->nrows, A->ncols);
       *bytes = mxv_layout(nullptr, m, m, A->nnz, heavy_bound(A->nnz)).bytes;
@@ -794,7 +747,109 @@ grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descripto
   grb_descriptor desc;
   grb_info info = resolve_desc(d, &desc);
   if (info != GRB_SUCCESS) return info;
-  return run_traversal(kTravSssp, A, source, nullptr, nullptr, dist, desc, ws, ws_bytes, stream);
+  return run_sssp(A, source, dist, desc, ws, ws_bytes, stream);
+}
+
+grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_t k,
+                   const grb_msbfs_tile *tile, const grb_descriptor *d, void *ws, size_t ws_bytes,
+                   void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!levels || !sources) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (k < 1) return GRB_INVALID_VALUE;
+  const int W = (int)((k + 63) / 64);
+  int kt = W, grid = kExpandGrid;
+  if (tile) {
+    if (tile->reserved[0] || tile->reserved[1] || tile->words_per_pass < 0 ||
+        tile->words_per_pass > W || tile->grid < 0 || tile->grid > 65535)
+      return GRB_INVALID_VALUE;
+    if (tile->words_per_pass) kt = tile->words_per_pass;
+    if (tile->grid) grid = tile->grid;
+  }
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  const bool can_pull = A->at.valid();
+  if (desc.direction == GRB_DIR_PULL && !can_pull) return GRB_NOT_IMPLEMENTED;
+  const int64_t n = A->nrows;
+  MsWs w = ms_layout(ws, n, k);
+  if ((info = check_ws(ws, ws_bytes, w.bytes)) != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+  MsbfsArgs ma;
+  ma.n = n;
+  ma.nw = words_of(n);
+  ma.nnz = A->nnz;
+  ma.k = k;
+  ma.W = W;
+  ma.kt = kt;
+  ma.push = A->a;
+  ma.pull = A->at;
+  ma.can_pull = can_pull;
+  ma.levels = levels;
+  ma.V = w.V;
+  ma.cnt_base = w.cnt;
+  ma.ctrl = w.ctrl;
+  ma.stats = w.stats;
+  ma.rule = desc.switch_rule;
+  ma.denom = desc.switch_denominator;
+  ma.forced = desc.direction;
+  auto at_level = [&](int64_t dd) {
+    const int i = (int)(dd % 3), j = (int)((dd + 1) % 3), q = (int)((dd + 2) % 3);
+    ma.F = w.F[i];
+    ma.Fn = w.F[j];
+    ma.Fc = w.F[q];
+    ma.act = w.act[i];
+    ma.actn = w.act[j];
+    ma.actc = w.act[q];
+    ma.cnt_cur = w.cnt + (size_t)i * 2 * kCntStripes;
+    ma.cnt_nxt = w.cnt + (size_t)j * 2 * kCntStripes;
+    ma.cnt_clr = w.cnt + (size_t)q * 2 * kCntStripes;
+    ma.d = (int32_t)std::min<int64_t>(dd, INT32_MAX);
+  };
+  at_level(0);
+  launch_msbfs_start(ma, sources, w.F[1], w.F[2], w.act[1], w.act[2], stream);
+  const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
+  int64_t dlev = 0;
+  int chunk = 6;
+  std::vector<unsigned long long> hcnt((size_t)6 * kCntStripes);
+  Ctrl hc{};
+  for (;;) {
+    for (int i = 0; i < chunk && dlev < cap; ++i, ++dlev) {
+      at_level(dlev);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)dlev), s);
+      launch_msbfs_level(ma, grid, stream);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)dlev + 1), s);
+    }
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipMemcpyAsync(hcnt.data(), w.cnt, hcnt.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GRB_PANIC;
+    unsigned long long next = 0;
+    for (int t = 0; t < kCntStripes; ++t) next += hcnt[(size_t)(dlev % 3) * 2 * kCntStripes + 2 * t];
+    if (next == 0 || dlev >= cap) break;
+    chunk = std::min(chunk * 2, 256);
+  }
+  const int iters = hc.nlev;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  const int nrec = std::min(iters, (int)kStatsCap);
+  if (nrec > 0 && hipMemcpy(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
+                            hipMemcpyDeviceToHost) != hipSuccess)
+    return GRB_PANIC;
+  std::vector<float> kms;
+  double ms_all = 0.0;
+  if (profile) {
+    for (int64_t i = 0; i < dlev; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
+      if (i < nrec) kms.push_back(ms);
+      ms_all += ms;
+    }
+  }
+  finish_stats(GRB_OP_MSBFS, iters, rec, kms, (int)std::min<int64_t>(dlev, INT32_MAX), ms_all);
+  return GRB_SUCCESS;
 }
 
 grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int32_t max_iter,

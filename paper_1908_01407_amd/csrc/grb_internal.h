@@ -96,44 +96,9 @@ struct CompactArgs {
   Ctrl *ctrl = nullptr;
   uint64_t *clear = nullptr;     // optional: bitmap zeroed word by word
   bool skip_if_empty = false;    // return at once when ctrl->count == 0
-  // BFS epilogue
-  uint64_t *visited = nullptr;
-  int32_t *levels = nullptr;
-  int32_t lev = 0;
-  // SSSP epilogue
-  const float *dist = nullptr;
-  float *fval = nullptr;
-  float *lval = nullptr;
 };
-enum CompactMode { kCompactPlain = 0, kCompactBfs = 1, kCompactSssp = 2 };
 int compact_blocks(int64_t nw);
-void launch_compact(int mode, const CompactArgs &a, void *stream);
-
-struct TravArgs {
-  int64_t n = 0;            // vertices
-  int64_t nw = 0;           // bitmap words
-  int64_t nnz = 0;          // stored entries (for the switch rule)
-  Csr push;                 // rows = frontier vertices (out-edges)
-  Csr pull;                 // rows = candidate vertices (in-edges)
-  bool can_push = true, can_pull = true;
-  const uint64_t *visited = nullptr;  // BFS: visited | isolated; SSSP: isolated
-  const uint64_t *fcur = nullptr;
-  uint64_t *fnxt = nullptr;
-  int32_t *parents = nullptr;         // BFS, may be null
-  float *dist = nullptr;              // SSSP
-  const float *fval = nullptr;        // SSSP: frontier values by vertex
-  const float *lval = nullptr;        // SSSP: frontier values by list position
-  const float *wpush = nullptr;       // SSSP: weights of the push CSR
-  const float *wpull = nullptr;       // SSSP: weights of the pull CSR
-  const int32_t *list = nullptr;
-  const int32_t *degpre = nullptr;
-  const int32_t *rowstart = nullptr;
-  const int32_t *tiles = nullptr;
-  Ctrl *ctrl = nullptr;
-  int64_t *stats = nullptr;
-  int32_t d = 0;
-  int32_t rule = 0, denom = 10, forced = 0;
-};
+void launch_compact(const CompactArgs &a, void *stream);
 
 // BFS with one kernel per level (grb_bfs.hip).  Each of the three rotating
 // frontier buffers has kCntStripes (count, degree sum) counter pairs.
@@ -157,9 +122,26 @@ void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *
                       void *stream);
 void launch_bfs_level(const BfsArgs &a, void *stream);
 void launch_bfs_parents(const BfsArgs &a, void *stream);
-void launch_sssp_init(const TravArgs &a, int32_t source, uint64_t *iso, uint64_t *fa,
-                      uint64_t *fb, uint64_t *status, int64_t nstatus, void *stream);
-void launch_sssp_expand(const TravArgs &a, void *stream);
+
+// SSSP with one kernel per round (grb_sssp.hip); counters as BFS
+struct SsspArgs {
+  int64_t n = 0, nw = 0, nnz = 0;
+  Csr push, pull;
+  bool can_pull = true;
+  bool same_csr = false;
+  const float *wpush = nullptr, *wpull = nullptr;
+  float *dist = nullptr;
+  uint64_t *iso = nullptr;  // rows without in-edges (never improve in pull)
+  uint64_t *fcur = nullptr, *fnxt = nullptr, *fclr = nullptr;
+  int32_t *cnt_cur = nullptr, *cnt_nxt = nullptr, *cnt_clr = nullptr;
+  Ctrl *ctrl = nullptr;
+  int64_t *stats = nullptr;
+  int32_t d = 0;
+  int32_t rule = 0, denom = 10, forced = 0;
+};
+void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
+                       void *stream);
+void launch_sssp_round(const SsspArgs &a, void *stream);
 
 struct PrArgs {
   int64_t n = 0, nw = 0;
@@ -187,6 +169,27 @@ void launch_popcount(const uint64_t *bm, int64_t nw, int64_t *out, void *stream)
 void launch_vector_build(uint64_t *bitmap, void *values, int elem_size, int64_t n,
                          const int32_t *idx, const void *vals, int64_t count, uint64_t one,
                          void *stream);
+
+// batched multi-source BFS (grb_msbfs.hip)
+struct MsbfsArgs {
+  int64_t n = 0, nw = 0, nnz = 0, k = 0;
+  int W = 0;            // query words per vertex (k / 64 rounded up)
+  int kt = 1;           // query words per pass (tile width)
+  Csr push, pull;
+  bool can_pull = true;
+  int32_t *levels = nullptr;  // n x k, vertex-major
+  uint64_t *V = nullptr;      // visited, n x W
+  uint64_t *F = nullptr, *Fn = nullptr, *Fc = nullptr;      // frontier blocks
+  uint64_t *act = nullptr, *actn = nullptr, *actc = nullptr;  // vertex has a frontier bit
+  unsigned long long *cnt_cur = nullptr, *cnt_nxt = nullptr, *cnt_clr = nullptr, *cnt_base = nullptr;
+  Ctrl *ctrl = nullptr;
+  int64_t *stats = nullptr;
+  int32_t d = 0;
+  int32_t rule = 0, denom = 10, forced = 0;
+};
+void launch_msbfs_start(const MsbfsArgs &a, const int32_t *sources, uint64_t *F1, uint64_t *F2,
+                        uint64_t *act1, uint64_t *act2, void *stream);
+void launch_msbfs_level(const MsbfsArgs &a, int grid_x, void *stream);
 
 // generic masked products (grb_mxv.hip)
 struct MxvArgs {

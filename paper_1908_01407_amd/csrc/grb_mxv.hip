@@ -413,7 +413,7 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
     ca.status_cur = a.status;
     ca.status_next = a.status + a.nblk;
     ca.ctrl = a.ctrl;
-    launch_compact(kCompactPlain, ca, s);
+    launch_compact(ca, s);
     hipLaunchKernelGGL(k_mxv_prep<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_mxv_push<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);

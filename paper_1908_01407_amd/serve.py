@@ -1,0 +1,318 @@
+"""Query serving over resident graphs with continuous batching.
+
+Graphs stay resident in HBM.  BFS and SSSP queries arrive over time; a
+scheduler forms work items and admits them into execution slots as slots
+and memory free up:
+
+* the oldest waiting query always goes next (FIFO fairness, no starvation);
+* a BFS query takes along up to ``max_batch - 1`` later BFS queries on the
+  same graph that are already waiting, and the group runs as one batched
+  multi-source BFS (grb_msbfs): queries are batched on arrival;
+* SSSP queries run one per work item (grb_sssp);
+* a work item is admitted only if its device-memory footprint (workspace
+  plus outputs) fits in what the budget has left; slots free up the moment
+  their item finishes and the next item is admitted at once.
+
+Each slot executes on its own HIP stream, so items in different slots
+overlap on the device.  Results are bitwise what the same query gives
+alone (BFS levels exactly equal single-source BFS, SSSP is deterministic).
+
+The scheduler is pure host logic (tested on the CPU with a fake executor);
+:class:`GpuExecutor` binds it to the library.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from typing import Callable
+
+
+@dataclasses.dataclass
+class Query:
+    qid: int
+    kind: str          # "bfs" or "sssp"
+    graph: str
+    source: int
+    arrival: float     # seconds, on the server clock
+    start: float = -1.0
+    end: float = -1.0
+    result: object = None
+    error: str | None = None
+    batch: int = 0     # size of the work item it ran in
+
+
+@dataclasses.dataclass
+class WorkItem:
+    kind: str
+    graph: str
+    queries: list
+    footprint: int
+
+
+class Scheduler:
+    """Forms and admits work items; thread-safe; no GPU."""
+
+    def __init__(self, footprint: Callable[[str, str, int], int], budget: int, slots: int,
+                 max_batch: int = 64):
+        self.footprint = footprint
+        self.budget = int(budget)
+        self.slots = int(slots)
+        self.max_batch = int(max_batch)
+        self.waiting = collections.deque()
+        self.used = 0
+        self.running = 0
+        self.lock = threading.Lock()
+
+    def submit(self, q: Query) -> None:
+        with self.lock:
+            self.waiting.append(q)
+
+    def next_item(self) -> WorkItem | None:
+        """The next admissible work item, or None (no slot, no memory or
+        nothing waiting).  The oldest waiting query heads every item."""
+        with self.lock:
+            if not self.waiting or self.running >= self.slots:
+                return None
+            head = self.waiting[0]
+            group = [head]
+            if head.kind == "bfs" and self.max_batch > 1:
+                for q in list(self.waiting)[1:]:
+                    if len(group) >= self.max_batch:
+                        break
+                    if q.kind == "bfs" and q.graph == head.graph:
+                        group.append(q)
+            fp = self.footprint(head.kind, head.graph, len(group))
+            # shrink the batch until it fits, but never below the head alone
+            while fp > self.budget - self.used and len(group) > 1:
+                group.pop()
+                fp = self.footprint(head.kind, head.graph, len(group))
+            if fp > self.budget - self.used:
+                if self.running == 0 and fp > self.budget:
+                    # can never fit: fail it rather than block everything
+                    self.waiting.popleft()
+                    head.error = "footprint exceeds the memory budget"
+                    self.running += 1  # balanced by release()
+                    return WorkItem(head.kind, head.graph, [head], 0)
+                return None
+            ids = {id(q) for q in group}
+            self.waiting = collections.deque(q for q in self.waiting if id(q) not in ids)
+            self.used += fp
+            self.running += 1
+            return WorkItem(head.kind, head.graph, group, fp)
+
+    def release(self, item: WorkItem) -> None:
+        with self.lock:
+            self.used -= item.footprint
+            self.running -= 1
+
+    def idle(self) -> bool:
+        with self.lock:
+            return not self.waiting and self.running == 0
+
+
+class Server:
+    """Runs a query trace through a Scheduler with `slots` worker threads,
+    each bound to one executor slot."""
+
+    def __init__(self, executor, budget: int, slots: int, max_batch: int = 64):
+        self.executor = executor
+        self.sched = Scheduler(executor.footprint, budget, slots, max_batch)
+        self.slots = slots
+        self.cv = threading.Condition()
+        self.t0 = 0.0
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def _worker(self, slot: int, stop: threading.Event):
+        while True:
+            with self.cv:
+                item = self.sched.next_item()
+                while item is None and not stop.is_set():
+                    self.cv.wait(timeout=0.002)
+                    item = self.sched.next_item()
+                if item is None:
+                    return
+            start = self.now()
+            for q in item.queries:
+                q.start = start
+                q.batch = len(item.queries)
+            if item.queries[0].error is None:
+                try:
+                    self.executor.run(slot, item)
+                except Exception as e:  # per-item error isolation
+                    for q in item.queries:
+                        q.error = f"{type(e).__name__}: {e}"
+            end = self.now()
+            for q in item.queries:
+                q.end = end
+            self.sched.release(item)
+            with self.cv:
+                self.cv.notify_all()
+
+    def run(self, queries: list, realtime: bool = True) -> dict:
+        """Submits each query at its arrival time (realtime) or all at once,
+        waits for all to finish and returns latency statistics."""
+        stop = threading.Event()
+        self.t0 = time.perf_counter()
+        workers = [threading.Thread(target=self._worker, args=(s, stop), daemon=True)
+                   for s in range(self.slots)]
+        for w in workers:
+            w.start()
+        for q in sorted(queries, key=lambda x: x.arrival):
+            if realtime:
+                delay = q.arrival - self.now()
+                if delay > 0:
+                    time.sleep(delay)
+            else:
+                q.arrival = self.now()
+            self.sched.submit(q)
+            with self.cv:
+                self.cv.notify_all()
+        while not self.sched.idle():
+            with self.cv:
+                self.cv.wait(timeout=0.002)
+        stop.set()
+        with self.cv:
+            self.cv.notify_all()
+        for w in workers:
+            w.join()
+        makespan = max(q.end for q in queries) - min(q.arrival for q in queries)
+        return summarize(queries, makespan)
+
+
+def _pct(xs, p):
+    if not xs:
+        return None
+    xs = sorted(xs)
+    i = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def summarize(queries, makespan: float) -> dict:
+    ok = [q for q in queries if q.error is None]
+    lat = [(q.end - q.arrival) * 1e3 for q in ok]
+    out = {"queries": len(queries), "failed": len(queries) - len(ok),
+           "qps": round(len(ok) / makespan, 2) if makespan > 0 else None,
+           "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+           "mean_batch": round(sum(q.batch for q in ok) / max(len(ok), 1), 2)}
+    for kind in ("bfs", "sssp"):
+        lk = [(q.end - q.arrival) * 1e3 for q in ok if q.kind == kind]
+        out[kind] = {"n": len(lk), "p50_ms": _pct(lk, 50), "p99_ms": _pct(lk, 99)}
+    by_graph = collections.defaultdict(list)
+    for q in ok:
+        by_graph[q.graph].append((q.end - q.arrival) * 1e3)
+    out["by_graph"] = {g: {"n": len(v), "p50_ms": _pct(v, 50), "p99_ms": _pct(v, 99)}
+                       for g, v in sorted(by_graph.items())}
+    for k in ("p50_ms", "p99_ms"):
+        if out[k] is not None:
+            out[k] = round(out[k], 3)
+    return out
+
+
+class GpuExecutor:
+    """Runs work items with the library: one HIP stream and one workspace
+    region per slot; graphs are resident `Matrix` objects."""
+
+    def __init__(self, graphs: dict, slots: int, max_batch: int = 64, keep_results=True):
+        import torch
+
+        import paper_1908_01407_amd as grb
+
+        self.grb = grb
+        self.torch = torch
+        self.graphs = graphs
+        self.keep = keep_results
+        self.max_batch = max_batch
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        # per-slot workspace large enough for any item on any graph
+        need = 0
+        for A in graphs.values():
+            for op, k in ((grb.OP_BFS, 0), (grb.OP_SSSP, 0), (grb.OP_MSBFS, max_batch)):
+                need = max(need, self._ws_bytes(op, A, k))
+        self.ws = [torch.empty(need, dtype=torch.uint8, device="cuda") for _ in range(slots)]
+        self.out_bytes = max(max(A.nrows for A in graphs.values()) * max_batch * 4, 1)
+        self.outs = [torch.empty(self.out_bytes // 4, dtype=torch.int32, device="cuda")
+                     for _ in range(slots)]
+
+    def _ws_bytes(self, op, A, k):
+        import ctypes
+        n = ctypes.c_size_t()
+        self.grb.check(self.grb._lib.grb_workspace_size(op, A.handle, k, ctypes.byref(n)))
+        return n.value
+
+    def footprint(self, kind: str, graph: str, batch: int) -> int:
+        A = self.graphs[graph]
+        grb = self.grb
+        if kind == "sssp":
+            return self._ws_bytes(grb.OP_SSSP, A, 0) + 4 * A.nrows
+        if batch == 1:
+            return self._ws_bytes(grb.OP_BFS, A, 0) + 4 * A.nrows
+        return self._ws_bytes(grb.OP_MSBFS, A, batch) + 4 * A.nrows * batch
+
+    def run(self, slot: int, item: WorkItem) -> None:
+        grb, torch = self.grb, self.torch
+        A = self.graphs[item.graph]
+        s = self.streams[slot]
+        ws = self.ws[slot]
+        n = A.nrows
+        with torch.cuda.stream(s):
+            if item.kind == "sssp":
+                q = item.queries[0]
+                dist = self.outs[slot][:n].view(torch.float32)
+                grb.check(grb._lib.grb_sssp(grb._ptr(dist), A.handle, int(q.source), None,
+                                            grb._ptr(ws), ws.numel(), grb._stream(s)), "grb_sssp")
+                if self.keep:
+                    q.result = dist.cpu()
+            elif len(item.queries) == 1:
+                q = item.queries[0]
+                lev = self.outs[slot][:n]
+                grb.check(grb._lib.grb_bfs(grb._ptr(lev), None, A.handle, int(q.source), None,
+                                           grb._ptr(ws), ws.numel(), grb._stream(s)), "grb_bfs")
+                if self.keep:
+                    q.result = lev.cpu()
+            else:
+                k = len(item.queries)
+                src = torch.tensor([q.source for q in item.queries], dtype=torch.int32,
+                                   device="cuda")
+                lev = self.outs[slot][: n * k].view(n, k)
+                grb.msbfs(A, src, ws=ws, levels=lev, stream=s)
+                if self.keep:
+                    host = lev.cpu()
+                    for i, q in enumerate(item.queries):
+                        q.result = host[:, i].clone()
+            s.synchronize()
+
+
+class FakeExecutor:
+    """CPU stand-in for scheduler tests: a fixed service time per item and an
+    optional failure on chosen query ids."""
+
+    def __init__(self, sizes: dict, service_s: float = 0.002, fail_ids=()):
+        self.sizes = sizes
+        self.service_s = service_s
+        self.fail_ids = set(fail_ids)
+        self.items = []
+        self.lock = threading.Lock()
+        self.concurrent = 0
+        self.max_concurrent = 0
+
+    def footprint(self, kind, graph, batch):
+        return self.sizes[graph] * (batch if kind == "bfs" else 2)
+
+    def run(self, slot, item):
+        with self.lock:
+            self.items.append(item)
+            self.concurrent += 1
+            self.max_concurrent = max(self.max_concurrent, self.concurrent)
+        try:
+            time.sleep(self.service_s)
+            if any(q.qid in self.fail_ids for q in item.queries):
+                raise RuntimeError("injected failure")
+            for q in item.queries:
+                q.result = (q.kind, q.graph, q.source)
+        finally:
+            with self.lock:
+                self.concurrent -= 1

@@ -1,0 +1,77 @@
+"""Autotuner for the batched multi-source BFS tile shape.
+
+grb_msbfs streams every level once per pass over `words_per_pass` query
+words (64 queries each) with `grid` workgroups per pass.  Wider passes
+re-read each adjacency list fewer times; narrower passes keep the gathered
+frontier block (n x words_per_pass x 8 bytes) small enough to stay in the
+caches.  The best trade-off depends on the graph, k and the device, so it
+is measured: every candidate runs the real batch on the real graph and the
+fastest is cached in a JSON file keyed by device, graph size and k.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "grb_mi355x_tune.json")
+
+
+def candidates(k: int):
+    W = (k + 63) // 64
+    kts = sorted({w for w in (1, 2, 4, 8, W) if w <= W})
+    grids = (1024, 2048, 4096)
+    return [(kt, g) for kt in kts for g in grids]
+
+
+def _key(A, k, device_name):
+    return f"{device_name}|n={A.nrows}|nnz={A.nnz}|k={k}"
+
+
+def tune_msbfs(A, sources, *, desc=None, repeats: int = 2, cache_path: str | None = DEFAULT_CACHE,
+               force: bool = False, log=None):
+    """Returns {"words_per_pass", "grid", "ms", "table"} for this graph and
+    batch size, measuring candidates unless the cache already has them."""
+    import torch
+
+    import paper_1908_01407_amd as grb
+
+    k = len(sources)
+    dev = torch.cuda.get_device_name(A.device)
+    key = _key(A, k, dev)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if not force and key in cache:
+        return cache[key]
+    ws = grb.workspace(grb.OP_MSBFS, A, k)
+    levels = torch.empty((A.nrows, k), dtype=torch.int32, device=A.device)
+    table = []
+    for kt, g in candidates(k):
+        grb.msbfs(A, sources, words_per_pass=kt, grid=g, desc=desc, ws=ws, levels=levels)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            grb.msbfs(A, sources, words_per_pass=kt, grid=g, desc=desc, ws=ws, levels=levels)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / repeats * 1e3
+        table.append({"words_per_pass": kt, "grid": g, "ms": round(ms, 4)})
+        if log:
+            log(f"[tune] kt={kt} grid={g}: {ms:.3f} ms")
+    best = min(table, key=lambda r: r["ms"])
+    res = {"words_per_pass": best["words_per_pass"], "grid": best["grid"], "ms": best["ms"],
+           "table": table}
+    cache[key] = res
+    if cache_path:
+        try:
+            os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+            with open(cache_path + ".tmp", "w") as f:
+                json.dump(cache, f, indent=1)
+            os.replace(cache_path + ".tmp", cache_path)
+        except OSError:
+            pass
+    return res
