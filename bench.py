@@ -367,6 +367,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--rule", choices=("auto", "paper", "exact"), default="auto",
+                    help="direction switch rule of the timed BFS (auto: the faster one, "
+                         "measured; results are identical under either)")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
@@ -419,12 +422,15 @@ def main():
 
     # pick the switch rule by measurement (results are identical either way)
     rule_ms = {}
-    for rule in (0, 1):
-        d = grb.descriptor(rule=rule)
-        for _ in range(max(args.warmup, 1)):
-            grb.bfs(A, 0, desc=d, ws=ws)
-        rule_ms[rule] = timed(lambda: grb.bfs(A, 0, desc=d, ws=ws), 5, torch)
-    rule = min(rule_ms, key=rule_ms.get)
+    if args.rule == "auto":
+        for rule in (0, 1):
+            d = grb.descriptor(rule=rule)
+            for _ in range(max(args.warmup, 1)):
+                grb.bfs(A, 0, desc=d, ws=ws)
+            rule_ms[rule] = round(timed(lambda: grb.bfs(A, 0, desc=d, ws=ws), 5, torch), 4)
+        rule = min(rule_ms, key=rule_ms.get)
+    else:
+        rule = 0 if args.rule == "paper" else 1
     desc = grb.descriptor(rule=rule, flags=grb.GRB_PROFILE)
     for _ in range(args.warmup):
         grb.bfs(A, 0, desc=desc, ws=ws)
@@ -473,7 +479,7 @@ def main():
                                f"levels+parents",
                    "n": n, "nnz": nnz, "levels": st["iterations"],
                    "switch_rule": "paper" if rule == 0 else "exact",
-                   "rule_ms": {"paper": round(rule_ms[0], 4), "exact": round(rule_ms[1], 4)},
+                   "rule_ms": {("paper" if r == 0 else "exact"): v for r, v in rule_ms.items()},
                    "gteps_graph500": round(
                        (int(np.diff(rp)[levels >= 0].sum()) // 2) / (ms_per_step / 1e3) / 1e9, 3),
                    "reached": reached},

@@ -84,6 +84,24 @@ BfsWs bfs_layout(void *ws, int64_t n) {
   return t;
 }
 
+// SSSP: the BFS state plus three rotating "frontier distance" vectors
+// (dist of the frontier's vertices, +inf elsewhere)
+struct SsspWs {
+  BfsWs b;
+  float *fd[3];
+  size_t bytes;
+};
+
+SsspWs sssp_layout(void *ws, int64_t n) {
+  SsspWs t{};
+  t.b = bfs_layout(ws, n);
+  Carver c(ws);
+  c.off = t.b.bytes;
+  for (int i = 0; i < 3; ++i) t.fd[i] = c.take<float>((size_t)std::max<int64_t>(n, 1));
+  t.bytes = c.off;
+  return t;
+}
+
 struct MsWs {
   Ctrl *ctrl;
   int64_t *stats;
@@ -121,7 +139,7 @@ PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
   t.ctrl = c.take<Ctrl>(1);
   t.x0 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
   t.x1 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
-  t.heavy_part = c.take<char>((size_t)std::max<int64_t>(pull.nheavy, 1) * esize);
+  t.heavy_part = c.take<char>((size_t)std::max<int64_t>(pull.nsplit, 1) * esize);
   t.blk_part = c.take<double>((size_t)2 * t.nblk);
   t.bytes = c.off;
   return t;
@@ -157,6 +175,7 @@ MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz, int64_t nhe
 }
 
 int64_t heavy_bound(int64_t nnz) { return nnz / kHeavyChunk + nnz / (kHeavyDeg + 1) + 2; }
+int64_t split_bound(int64_t nnz) { return nnz / kPushSplit + nnz / (kPushSplit + 1) + 2; }
 
 grb_info check_ws(void *ws, size_t have, size_t need) {
   if (need > have) return GRB_INSUFFICIENT_SPACE;
@@ -167,8 +186,8 @@ grb_info check_ws(void *ws, size_t have, size_t need) {
 
 // ---- matrix metadata ---------------------------------------------------------
 struct MetaLayout {
-  size_t heavy_off, heavy_rows_off, split_off, bytes;
-  int64_t max_pieces, max_rows, max_split;
+  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, bytes;
+  int64_t max_pieces, max_rows, max_split, max_split_rows;
 };
 
 MetaLayout meta_layout_one(int64_t nnz, size_t base) {
@@ -179,7 +198,9 @@ MetaLayout meta_layout_one(int64_t nnz, size_t base) {
   m.heavy_off = base;
   m.heavy_rows_off = align_up(base + (size_t)m.max_pieces * 2 * sizeof(int32_t));
   m.split_off = align_up(m.heavy_rows_off + (size_t)m.max_rows * 3 * sizeof(int32_t));
-  m.bytes = align_up(m.split_off + (size_t)m.max_split * 2 * sizeof(int32_t));
+  m.max_split_rows = nnz / (kPushSplit + 1) + 1;
+  m.split_rows_off = align_up(m.split_off + (size_t)m.max_split * 2 * sizeof(int32_t));
+  m.bytes = align_up(m.split_rows_off + (size_t)m.max_split_rows * 3 * sizeof(int32_t));
   return m;
 }
 
@@ -195,15 +216,19 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
       hipStreamSynchronize(s) != hipSuccess)
     return GRB_PANIC;
   if (rp[0] != 0 || rp[(size_t)c.nrows] != c.nnz) return GRB_INVALID_VALUE;
-  std::vector<int32_t> pieces, rows, split;
+  std::vector<int32_t> pieces, rows, split, split_rows;
   for (int64_t r = 0; r < c.nrows; ++r) {
     const int32_t b = rp[(size_t)r], e = rp[(size_t)r + 1];
     if (e < b) return GRB_INVALID_VALUE;
     if (e - b > kPushSplit) {
-      for (int32_t p = b; p < e; p += kPushSplit) {
+      split_rows.push_back((int32_t)r);
+      split_rows.push_back((int32_t)(split.size() / 2));
+      int32_t np = 0;
+      for (int32_t p = b; p < e; p += kPushSplit, ++np) {
         split.push_back((int32_t)r);
         split.push_back(p);
       }
+      split_rows.push_back(np);
     }
     if (e - b > kHeavyDeg) {
       rows.push_back((int32_t)r);
@@ -217,11 +242,16 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
     }
   }
   if ((int64_t)pieces.size() / 2 > L.max_pieces || (int64_t)rows.size() / 3 > L.max_rows ||
-      (int64_t)split.size() / 2 > L.max_split)
+      (int64_t)split.size() / 2 > L.max_split ||
+      (int64_t)split_rows.size() / 3 > L.max_split_rows)
     return GRB_PANIC;
   int32_t *hp = (int32_t *)(meta + L.heavy_off);
   int32_t *hr = (int32_t *)(meta + L.heavy_rows_off);
   int32_t *sp = (int32_t *)(meta + L.split_off);
+  int32_t *sr = (int32_t *)(meta + L.split_rows_off);
+  if (!split_rows.empty() && hipMemcpyAsync(sr, split_rows.data(), split_rows.size() * 4,
+                                            hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
   if (!split.empty() &&
       hipMemcpyAsync(sp, split.data(), split.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return GRB_PANIC;
@@ -238,6 +268,8 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
   c.nheavy_rows = (int64_t)rows.size() / 3;
   c.split = sp;
   c.nsplit = (int64_t)split.size() / 2;
+  c.split_rows = sr;
+  c.nsplit_rows = (int64_t)split_rows.size() / 3;
   return GRB_SUCCESS;
 }
 
@@ -377,9 +409,10 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
   const int64_t n = A->nrows;
   const bool can_pull = A->at.valid();
   if (!can_pull && desc.direction == GRB_DIR_PULL) return GRB_NOT_IMPLEMENTED;
-  BfsWs w = bfs_layout(ws, n);
-  grb_info info = check_ws(ws, ws_bytes, w.bytes);
+  SsspWs sw = sssp_layout(ws, n);
+  grb_info info = check_ws(ws, ws_bytes, sw.bytes);
   if (info != GRB_SUCCESS) return info;
+  const BfsWs &w = sw.b;
   hipStream_t s = (hipStream_t)stream;
   const bool profile = (desc.flags & GRB_PROFILE) != 0;
   SsspArgs sa;
@@ -405,13 +438,16 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
     sa.fcur = w.F[i];
     sa.fnxt = w.F[j];
     sa.fclr = w.F[k];
+    sa.fd_cur = sw.fd[i];
+    sa.fd_nxt = sw.fd[j];
+    sa.fd_clr = sw.fd[k];
     sa.cnt_cur = cnt + i * kCntSlots;
     sa.cnt_nxt = cnt + j * kCntSlots;
     sa.cnt_clr = cnt + k * kCntSlots;
     sa.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
   };
   at_round(0);
-  launch_sssp_start(sa, source, w.F[1], w.F[2], stream);
+  launch_sssp_start(sa, source, w.F[1], w.F[2], sw.fd[1], sw.fd[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
   int chunk = 8;
@@ -435,9 +471,10 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
   const int iters = hc.nlev;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
-  if (nrec > 0 && hipMemcpy(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
-                            hipMemcpyDeviceToHost) != hipSuccess)
+  if (nrec > 0 && hipMemcpyAsync(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, s) != hipSuccess)
     return GRB_PANIC;
+  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
@@ -701,11 +738,11 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
   if (!A) return GRB_UNINITIALIZED_OBJECT;
   switch (op) {
     case GRB_OP_BFS: *bytes = bfs_layout(nullptr, A->nrows).bytes; break;
-    case GRB_OP_SSSP: *bytes = bfs_layout(nullptr, A->nrows).bytes; break;
+    case GRB_OP_SSSP: *bytes = sssp_layout(nullptr, A->nrows).bytes; break;
     case GRB_OP_PAGERANK: {
       if (k != 1 && k != 2) return GRB_INVALID_VALUE;
       Csr pull = A->at;
-      pull.nheavy = heavy_bound(A->nnz);
+      pull.nsplit = split_bound(A->nnz);
       *bytes = pr_layout(nullptr, A->nrows, pull, k == 2 ? 8 : 4).bytes;
       break;
     }

@@ -7,11 +7,12 @@
 // the device from the frontier's size and degree sum (the switch rule of the
 // descriptor).  The frontier is only a bitmap, and one kernel does all of a
 // level, so nothing sits between levels:
-// * push gives each wave one frontier word and streams the out-edges of its
-//   frontier rows as one concatenated list, 64 edges per step (the same
-//   wave-level load-balanced search as pull); rows longer than kPushSplit
-//   come from a static list of kPushSplit-edge pieces built by
-//   grb_matrix_prepare, each piece active when its row is in the frontier;
+// * push gives each wave a run of frontier words and streams the out-edges
+//   of its frontier rows as one concatenated list (the same wave-level
+//   load-balanced search as pull); rows longer than kPushSplit come from a
+//   static list of kPushSplit-edge pieces built by grb_matrix_prepare,
+//   spread over all waves, each piece active when its row is in the
+//   frontier;
 // * a vertex is claimed by the first atomicOr on its visited bit; the
 //   claimer writes its level and sets its bit in the next frontier bitmap;
 // * the next frontier's size and degree sum are reduced per workgroup and
@@ -37,9 +38,9 @@ __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
   return pull ? GRB_DIR_PULL : GRB_DIR_PUSH;
 }
 
-// Claims v (v < 0: nothing) for the next level; counts it in (fc, fd).
-__device__ __forceinline__ void claim(const BfsArgs &a, int v, int &fc, int &fd) {
-  if (v < 0 || bit_of(a.visited, v)) return;  // plain read: a filter, the atomic decides
+// Claims v for the next level once its visited bit was seen clear; counts
+// it in (fc, fd).
+__device__ __forceinline__ void claim_atomic(const BfsArgs &a, int v, int &fc, int &fd) {
   const uint64_t b = 1ull << (v & 63);
   const uint64_t old = atomicOr((unsigned long long *)&a.visited[v >> 6], (unsigned long long)b);
   if (old & b) return;
@@ -49,54 +50,103 @@ __device__ __forceinline__ void claim(const BfsArgs &a, int v, int &fc, int &fd)
   fd += a.push.rp[v + 1] - a.push.rp[v];
 }
 
+// Claims the targets c[0..kUnroll) (-1: none).  The visited words of all
+// of them are read first (a plain read is only a filter, the atomic
+// decides), so their latencies overlap.
+__device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
+                                            int &fd) {
+  uint64_t vw[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s)
+    if (!((vw[s] >> (c[s] & 63)) & 1ull)) claim_atomic(a, c[s], fc, fd);
+}
+
+// Each wave loads 64 bitmap words at once (one per lane) and compacts their
+// set bits into a queue of rows, taken 64 at a time (one row per lane).  The
+// edges of rows up to kPushSplit (push) or kHeavyDeg (pull) long are streamed
+// as one concatenated list; longer rows come in static pieces spread over
+// all waves, so a hub is expanded by hundreds of waves at once.
+
 __device__ void bfs_push(const BfsArgs &a, int *mark, int &fc, int &fd) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.push.rp, *ci = a.push.ci;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    if (ln == 0) a.fclr[w] = 0ull;  // the bitmap two levels ahead
-    const uint64_t fw = a.fcur[w];
-    if (fw == 0ull) continue;
-    const int64_t u = w * 64 + ln;
-    int cur = 0, end = 0;
-    if ((fw >> ln) & 1ull) {
-      cur = rp[u];
-      end = rp[u + 1];
-      if (end - cur > kPushSplit) end = cur;  // long rows: static pieces below
+  // words dealt out round-robin (wave gw takes words gw, gw + nwaves, ...)
+  // so that runs of high-degree rows spread over the waves
+  for (int64_t w0 = gw; w0 < a.nw; w0 += 64 * nwaves) {
+    const int64_t mw = w0 + (int64_t)ln * nwaves;
+    uint64_t mf = 0ull;
+    if (mw < a.nw) {
+      a.fclr[mw] = 0ull;  // the bitmap two levels ahead
+      mf = a.fcur[mw];
     }
-    for (;;) {
-      const int len = end - cur;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      claim(a, ln < total ? ci[rcur + (ln - rexcl)] : -1, fc, fd);
-      if (starts) cur += min(incl, 64) - excl;
+    const int cnt = __popcll(mf);
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, 63);
+    for (int b = 0; b < total; b += 64) {
+      const int64_t u = queue_slot(mark, mf, cnt, incl, total, b, mw);
+      int cur = 0, end = 0;
+      if (u >= 0) {
+        cur = rp[u];
+        end = rp[u + 1];
+        if (end - cur > kPushSplit) end = cur;  // long rows: static pieces below
+      }
+      // the rows' out-edges as one concatenated stream, kUnroll x 64 edges
+      // per step
+      for (bool more = true; more;) {
+        int c[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          c[s] = -1;
+          if (!more) continue;
+          const int len = end - cur;
+          const int incl2 = wave_incl_scan(len);
+          const int tot2 = __shfl(incl2, 63);
+          if (tot2 == 0) {
+            more = false;
+            continue;
+          }
+          const int excl = incl2 - len;
+          const bool starts = len > 0 && excl < 64;
+          const int r = slot_rows(mark, starts, excl);
+          const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+          if (ln < tot2) c[s] = rcur + (ln - rexcl);
+          if (starts) cur += min(incl2, 64) - excl;
+        }
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) c[s] = c[s] >= 0 ? ci[c[s]] : -1;
+        claim_batch(a, c, fc, fd);
+      }
     }
   }
-  // static pieces of long rows: 64 pieces tested per step (one per lane),
-  // then the wave streams the pieces whose row is in the frontier
-  for (int64_t h0 = gw * 64; h0 < a.push.nsplit; h0 += nwaves * 64) {
-    const int64_t h = h0 + ln;
-    int u = -1, b = 0;
+  // static pieces of long rows, spread over the waves (wave gw owns pieces
+  // gw, gw + nwaves, ...), 64 tested per step; a piece whose row is in the
+  // frontier is streamed by the whole wave, kUnroll x 64 edges at once
+  static_assert(kPushSplit == 64 * kUnroll, "a push piece is one unrolled step");
+  for (int64_t hb = gw; hb < a.push.nsplit; hb += 64 * nwaves) {
+    const int64_t h = hb + (int64_t)ln * nwaves;
+    int u = -1, b = 0, e = 0;
     if (h < a.push.nsplit) {
       u = a.push.split[2 * h];
       b = a.push.split[2 * h + 1];
+      if (bit_of(a.fcur, u)) e = min(b + kPushSplit, rp[u + 1]);
+      else u = -1;
     }
-    uint64_t act = __ballot(u >= 0 && bit_of(a.fcur, u));
+    uint64_t act = __ballot(u >= 0);
     while (act) {
       const int k = __ffsll((unsigned long long)act) - 1;
       act &= act - 1;
-      const int pu = __shfl(u, k), pb = __shfl(b, k);
-      const int e = min(pb + kPushSplit, rp[pu + 1]);
-      for (int base = pb; base < e; base += 64) {
-        const int pos = base + ln;
-        claim(a, pos < e ? ci[pos] : -1, fc, fd);
+      const int pb = __shfl(b, k), pe = __shfl(e, k);
+      int c[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const int pos = pb + s * 64 + ln;
+        c[s] = pos < pe ? ci[pos] : -1;
       }
+      claim_batch(a, c, fc, fd);
     }
   }
 }
@@ -106,74 +156,128 @@ __device__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd) {
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    if (ln == 0) a.fclr[w] = 0ull;
-    const uint64_t cand = ~a.visited[w];
-    if (cand == 0ull) continue;
-    const int64_t v = w * 64 + ln;
-    bool act = (cand >> ln) & 1ull;
-    int cur = 0, end = 0;
-    if (act) {
-      cur = rp[v];
-      end = rp[v + 1];
-      if (end - cur > kHeavyDeg) act = false;  // long rows: split pieces below
+  int64_t lo, hi;
+  wave_words(a.nw, gw, nwaves, lo, hi);
+  for (int64_t w0 = lo; w0 < hi; w0 += 64) {
+    const int64_t mw = w0 + ln;
+    uint64_t mc = 0ull;  // candidate rows: not visited
+    if (mw < hi) {
+      a.fclr[mw] = 0ull;
+      mc = ~a.visited[mw];
     }
-    const int deg0 = end - cur;  // push degree when both orientations share one CSR
-    bool found = false;
-    int par = -1;
-    if (act) {  // the first two neighbours of every row, in parallel
-      const int c0 = cur < end ? ci[cur] : -1;
-      const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
-      if (c0 >= 0 && bit_of(a.fcur, c0)) { found = true; par = c0; }
-      else if (c1 >= 0 && bit_of(a.fcur, c1)) { found = true; par = c1; }
-      cur = min(cur + 2, end);
-    }
-    for (;;) {  // the rest as one concatenated stream, 64 edges per step
-      const int len = (act && !found) ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      const bool valid = ln < total;
-      const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
-      const uint64_t hm = __ballot(valid && bit_of(a.fcur, c));
-      const int se = min(incl, 64);
-      const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
-      const uint64_t h = hm & seg;
-      const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
-      const int pc = __shfl(c, fl);
-      if (h) { found = true; par = pc; }
-      if (starts) cur += se - excl;
-    }
-    const uint64_t fbits = __ballot(found);
-    if (fbits == 0ull) continue;
-    if (ln == 0) {
-      atomicOr((unsigned long long *)&a.visited[w], (unsigned long long)fbits);
-      atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)fbits);
-    }
-    if (found) {
-      a.levels[v] = a.d + 1;
-      if (a.parents) a.parents[v] = par;
-      fc += 1;
-      fd += a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
+    const int cnt = __popcll(mc);
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, 63);
+    // kPullRows rows per lane: the loads of their first two neighbours are
+    // issued together
+    for (int b = 0; b < total; b += 64 * kPullRows) {
+      int64_t v[kPullRows];
+      int cur[kPullRows], end[kPullRows];
+      bool act[kPullRows];
+#pragma unroll
+      for (int q = 0; q < kPullRows; ++q) {
+        v[q] = b + q * 64 < total ? queue_slot(mark, mc, cnt, incl, total, b + q * 64, mw) : -1;
+        act[q] = v[q] >= 0;
+      }
+#pragma unroll
+      for (int q = 0; q < kPullRows; ++q) {
+        cur[q] = act[q] ? rp[v[q]] : 0;
+        end[q] = act[q] ? rp[v[q] + 1] : 0;
+        if (end[q] - cur[q] > kHeavyDeg || end[q] == cur[q]) act[q] = false;  // pieces / empty
+      }
+      int c0[kPullRows], c1[kPullRows];
+#pragma unroll
+      for (int q = 0; q < kPullRows; ++q) {
+        c0[q] = act[q] ? ci[cur[q]] : -1;
+        c1[q] = act[q] && cur[q] + 1 < end[q] ? ci[cur[q] + 1] : -1;
+      }
+      uint64_t b0[kPullRows], b1[kPullRows];
+#pragma unroll
+      for (int q = 0; q < kPullRows; ++q) {
+        b0[q] = c0[q] >= 0 ? a.fcur[c0[q] >> 6] : 0ull;
+        b1[q] = c1[q] >= 0 ? a.fcur[c1[q] >> 6] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < kPullRows; ++q) {
+        const int deg0 = end[q] - cur[q];
+        bool found = false;
+        int par = -1;
+        if (c0[q] >= 0 && ((b0[q] >> (c0[q] & 63)) & 1ull)) {
+          found = true;
+          par = c0[q];
+        } else if (c1[q] >= 0 && ((b1[q] >> (c1[q] & 63)) & 1ull)) {
+          found = true;
+          par = c1[q];
+        }
+        int cq = act[q] ? min(cur[q] + 2, end[q]) : 0, eq = act[q] ? end[q] : 0;
+        for (;;) {  // the rest as one concatenated stream, 64 edges per step
+          const int len = (act[q] && !found) ? eq - cq : 0;
+          const int incl2 = wave_incl_scan(len);
+          const int tot2 = __shfl(incl2, 63);
+          if (tot2 == 0) break;
+          const int excl = incl2 - len;
+          const bool starts = len > 0 && excl < 64;
+          const int r = slot_rows(mark, starts, excl);
+          const int rcur = __shfl(cq, r), rexcl = __shfl(excl, r);
+          const bool valid = ln < tot2;
+          const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
+          const uint64_t hm = __ballot(valid && bit_of(a.fcur, c));
+          const int se = min(incl2, 64);
+          const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
+          const uint64_t h = hm & seg;
+          const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
+          const int pc = __shfl(c, fl);
+          if (h) {
+            found = true;
+            par = pc;
+          }
+          if (starts) cq += se - excl;
+        }
+        // rows of one bitmap word sit in consecutive lanes: one atomicOr per
+        // word and bitmap
+        const int64_t vw = found ? (v[q] >> 6) : -1;
+        const uint64_t hb = run_head_or(vw, found ? (1ull << (v[q] & 63)) : 0ull);
+        if (hb && vw >= 0) {
+          atomicOr((unsigned long long *)&a.visited[vw], (unsigned long long)hb);
+          atomicOr((unsigned long long *)&a.fnxt[vw], (unsigned long long)hb);
+        }
+        if (found) {
+          a.levels[v[q]] = a.d + 1;
+          if (a.parents) a.parents[v[q]] = par;
+          fc += 1;
+          fd += a.same_csr ? deg0 : a.push.rp[v[q] + 1] - a.push.rp[v[q]];
+        }
+      }
     }
   }
   // pieces of long rows; a row counts as a candidate unless it was reached
-  // before this level (its level is then 0..d)
+  // before this level (its level is then 0..d): a piece's claim must not
+  // hide the row from its other pieces, whose first frontier neighbour may
+  // have a smaller id.  kUnroll x 64 edges are loaded at once and searched
+  // for the first frontier neighbour in order; the parent is the minimum
+  // over the pieces.
   for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
     const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
     const int lr = a.levels[r];
     if (lr >= 0 && lr <= a.d) continue;
     const int e = min(b + kHeavyChunk, rp[r + 1]);
-    for (int base = b; base < e; base += 64) {
-      const int pos = base + ln;
-      const int c = pos < e ? ci[pos] : -1;
-      const uint64_t hm = __ballot(c >= 0 && bit_of(a.fcur, c));
-      if (hm) {
-        const int pc = __shfl(c, __ffsll((unsigned long long)hm) - 1);
+    for (int base = b; base < e; base += 64 * kUnroll) {
+      int c[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const int pos = base + s * 64 + ln;
+        c[s] = pos < e ? ci[pos] : -1;
+      }
+      uint64_t fwd[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) fwd[s] = c[s] >= 0 ? a.fcur[c[s] >> 6] : 0ull;
+      int pc = -1;
+#pragma unroll
+      for (int s = kUnroll - 1; s >= 0; --s) {
+        const uint64_t hm = __ballot(c[s] >= 0 && ((fwd[s] >> (c[s] & 63)) & 1ull));
+        if (hm) pc = __shfl(c[s], __ffsll((unsigned long long)hm) - 1);
+      }
+      if (pc >= 0) {
         if (ln == 0) {
           const uint64_t bit = 1ull << (r & 63);
           const uint64_t old =
@@ -281,7 +385,9 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
 }
 
 // Smallest-id parent of every vertex reached by a push: the first
-// in-neighbour (ascending) whose level is one less.
+// in-neighbour (ascending) whose level is one less.  One wave per bitmap
+// word of vertices; the first two in-neighbours of every row are tested in
+// parallel, the rest streamed as one concatenated list.
 __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   int *mark = s_mark[threadIdx.x >> 6];
@@ -298,10 +404,20 @@ __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
       need = lv > 0 && a.parents[v] < 0;
     }
     if (__ballot(need) == 0ull) continue;
-    int cur = need ? rp[v] : 0, end = need ? rp[v + 1] : 0;
+    int cur = need ? rp[v] : 0;
+    const int end = need ? rp[v + 1] : 0;
     const int tgt = lv - 1;
     bool found = false;
     int par = -1;
+    if (need) {
+      const int c0 = cur < end ? ci[cur] : -1;
+      const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
+      const int l0 = c0 >= 0 ? a.levels[c0] : -2;
+      const int l1 = c1 >= 0 ? a.levels[c1] : -2;
+      if (l0 == tgt) { found = true; par = c0; }
+      else if (l1 == tgt) { found = true; par = c1; }
+      cur = min(cur + 2, end);
+    }
     for (;;) {
       const int len = (need && !found) ? end - cur : 0;
       const int incl = wave_incl_scan(len);
@@ -341,7 +457,10 @@ void launch_bfs_level(const BfsArgs &a, void *stream) {
 }
 
 void launch_bfs_parents(const BfsArgs &a, void *stream) {
-  hipLaunchKernelGGL(k_bfs_parents, dim3(kExpandGrid), dim3(kBlock), 0, (hipStream_t)stream, a);
+  // one wave per bitmap word
+  int64_t g = (a.nw + kWavesPerBlock - 1) / kWavesPerBlock;
+  g = g < 1 ? 1 : (g > (1 << 20) ? (1 << 20) : g);
+  hipLaunchKernelGGL(k_bfs_parents, dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a);
 }
 
 }  // namespace grb

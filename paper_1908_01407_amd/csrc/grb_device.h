@@ -68,6 +68,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The bitmap words [lo, hi) a wave owns in a grid-wide sweep: one
+// contiguous run per wave, so lanes can load 64 of them at once.
+__device__ __forceinline__ void wave_words(int64_t nw, int64_t gw, int64_t nwaves, int64_t &lo,
+                                           int64_t &hi) {
+  const int64_t per = (nw + nwaves - 1) / nwaves;
+  lo = gw * per;
+  hi = lo + per < nw ? lo + per : nw;
+}
+
 // Wave-level load-balanced search: lane `l` owns a row whose remaining
 // edges occupy slots [excl, excl + len) of a concatenated stream.  For every
 // slot s in [0, 64) this returns the lane whose row covers s (the row that
@@ -82,6 +91,56 @@ __device__ __forceinline__ int slot_rows(int *mark, bool starts, int excl) {
   const int r = wave_max_scan(mark[ln]);
   wave_lds_sync();
   return r;
+}
+
+// Position of the n-th (0-based) set bit of x, found by halving the window
+// with popcounts; x must have more than n set bits.
+__device__ __forceinline__ int nth_set_bit(uint64_t x, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const int c = __popcll((x >> pos) & mask_below(w));
+    if (n >= c) {
+      n -= c;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// Wave-local compaction of a bitmap: lane l holds word m (bitmap word index
+// `word`), its popcount `cnt` and the inclusive scan `incl` of the counts.
+// Returns the vertex of slot b + lane of the enumeration of all set bits in
+// lane order (-1 past the end, `total` = the last lane's incl).
+__device__ __forceinline__ int64_t queue_slot(int *mark, uint64_t m, int cnt, int incl, int total,
+                                              int b, int64_t word) {
+  const int ln = threadIdx.x & 63;
+  const int excl = incl - cnt;
+  const bool starts = cnt > 0 && incl > b && excl < b + 64;
+  const int k = slot_rows(mark, starts, excl > b ? excl - b : 0);
+  const uint64_t mk = __shfl(m, k);
+  const int ek = __shfl(excl, k);
+  const int64_t wk = __shfl(word, k);
+  const int sl = b + ln;
+  return sl < total ? wk * 64 + nth_set_bit(mk, sl - ek) : -1;
+}
+
+// Lanes hold (word, bits) where lanes with equal words are contiguous.
+// Returns to the first lane of each run of equal words the OR of the run's
+// bits, to every other lane 0.
+__device__ __forceinline__ uint64_t run_head_or(int64_t word, uint64_t bits) {
+  const int ln = threadIdx.x & 63;
+  const int64_t prev = __shfl_up(word, 1);
+  const bool head = ln == 0 || prev != word;
+  const int rid = wave_max_scan(head ? ln : -1);
+  uint64_t x = bits;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_down(x, off);
+    const int ry = __shfl_down(rid, off);
+    if (ln + off < 64 && ry == rid) x |= y;
+  }
+  return head ? x : 0ull;
 }
 
 // Inclusive min-scan over slots restricted to runs of equal row id.

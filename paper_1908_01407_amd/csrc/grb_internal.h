@@ -18,6 +18,8 @@ constexpr int kHeavyDeg = 2048;      // rows longer than this are split for pull
 constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
 constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand kernels
 constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
+constexpr int kUnroll = 4;         // 64-edge steps whose loads are issued together
+constexpr int kPullRows = 2;       // BFS pull: rows per lane whose first loads overlap
 constexpr int kCntStripes = 32;      // BFS: striped frontier counters (count, degree sum)
 constexpr int kStatsCap = GRB_STATS_MAX;
 
@@ -35,8 +37,10 @@ struct Csr {
   int64_t nheavy = 0;                  // number of pieces
   const int32_t *heavy_rows = nullptr; // (row, first piece, piece count) triples
   int64_t nheavy_rows = 0;
-  const int32_t *split = nullptr;      // push pieces of rows longer than kPushSplit
+  const int32_t *split = nullptr;      // (row, begin) pieces of rows longer than kPushSplit
   int64_t nsplit = 0;
+  const int32_t *split_rows = nullptr; // (row, first piece, piece count) triples
+  int64_t nsplit_rows = 0;
   bool valid() const { return rp != nullptr; }
 };
 
@@ -133,14 +137,17 @@ struct SsspArgs {
   float *dist = nullptr;
   uint64_t *iso = nullptr;  // rows without in-edges (never improve in pull)
   uint64_t *fcur = nullptr, *fnxt = nullptr, *fclr = nullptr;
+  // frontier distances: dist of the buffer's frontier vertices, +inf
+  // elsewhere (the improved value of each vertex, for the next round)
+  float *fd_cur = nullptr, *fd_nxt = nullptr, *fd_clr = nullptr;
   int32_t *cnt_cur = nullptr, *cnt_nxt = nullptr, *cnt_clr = nullptr;
   Ctrl *ctrl = nullptr;
   int64_t *stats = nullptr;
   int32_t d = 0;
   int32_t rule = 0, denom = 10, forced = 0;
 };
-void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
-                       void *stream);
+void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2, float *fd1,
+                       float *fd2, void *stream);
 void launch_sssp_round(const SsspArgs &a, void *stream);
 
 struct PrArgs {
@@ -150,7 +157,7 @@ struct PrArgs {
   void *p = nullptr;           // ranks (in place)
   const void *x = nullptr;     // p / outdeg of the current iterate
   void *xn = nullptr;          // next x
-  void *heavy_part = nullptr;  // per split piece partial sums
+  void *heavy_part = nullptr;  // partial sums of the pieces of long rows
   double *blk_part = nullptr;  // per workgroup {delta, dangling} partials
   int nblk = 0;
   Ctrl *ctrl = nullptr;

@@ -192,30 +192,32 @@ __device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t
       }
     }
   }
-  // static pieces of long rows (one wave per active piece)
-  for (int64_t h0 = gw * 64; h0 < a.push.nsplit; h0 += nwaves * 64) {
-    const int64_t h = h0 + ln;
-    int u = -1, b = 0;
+  // static pieces of long rows, spread over the waves (wave gw owns pieces
+  // gw, gw + nwaves, ...), 64 tested per step
+  for (int64_t hb = gw; hb < a.push.nsplit; hb += 64 * nwaves) {
+    const int64_t h = hb + (int64_t)ln * nwaves;
+    int u = -1, b = 0, e = 0;
     if (h < a.push.nsplit) {
       u = a.push.split[2 * h];
       b = a.push.split[2 * h + 1];
+      if (bit_of(a.act, u)) e = min(b + kPushSplit, rp[u + 1]);
+      else u = -1;
     }
-    uint64_t act = __ballot(u >= 0 && bit_of(a.act, u));
+    uint64_t act = __ballot(u >= 0);
     while (act) {
       const int kk = __ffsll((unsigned long long)act) - 1;
       act &= act - 1;
-      const int pu = __shfl(u, kk), pb = __shfl(b, kk);
-      const int e = min(pb + kPushSplit, rp[pu + 1]);
+      const int pu = __shfl(u, kk), pb = __shfl(b, kk), pe = __shfl(e, kk);
       for (int jj = 0; jj < a.kt; ++jj) {
         const int j = j0 + jj;
         if (j >= a.W) break;
         const uint64_t fu = a.F[(int64_t)pu * a.W + j];
         if (fu == 0ull) continue;
-        for (int base = pb; base < e; base += 64) {
+        for (int base = pb; base < pe; base += 64) {
           const int pos = base + ln;
           int64_t tv = -1;
           uint64_t nb = 0ull;
-          if (pos < e) {
+          if (pos < pe) {
             tv = ci[pos];
             nb = claim_bits(a, tv, j, fu, edges_acc);
             act_acc += __popcll(nb);

@@ -1,12 +1,13 @@
 // PageRank iteration kernels (Section 7.3 of the paper: pull form, SpMV
 // every iteration because the vector never gets sparse).
 //
-// Load balance: each wave owns one bitmap word (64 consecutive rows of the
-// CSR of A^T) and streams their in-edges as one concatenated list, 64 edges
-// per step, with a segmented sum per row (wave-level load-balanced search);
-// rows longer than kHeavyDeg are cut into fixed pieces that any wave takes,
-// and a single-workgroup fix-up kernel adds each long row's pieces in order.
-// Summation order is fixed, so fp32 and fp64 results are bitwise
+// Load balance: each wave takes one bitmap word of rows (64 consecutive
+// rows of the CSR of A^T) per step, words dealt out round-robin, and
+// streams their in-edges as one concatenated list, kUnroll x 64 edges per
+// step, with a segmented sum per row (wave-level load-balanced search);
+// rows longer than kPushSplit are cut into fixed pieces that any wave
+// takes, and a single-workgroup fix-up kernel adds each long row's pieces
+// in order.  Summation order is fixed, so fp32 and fp64 results are bitwise
 // reproducible run to run.  The dangling mass and the L1 change are reduced
 // per workgroup and then in a fixed order in the fix-up kernel, which also
 // decides convergence on the device.
@@ -81,35 +82,60 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   T *p = (T *)a.p;
   const T dn = (T)(a.ctrl->D / (double)a.n);
   double delta = 0, dang = 0;
+  // rows up to kPushSplit long: one word of rows per wave and step, words
+  // dealt out round-robin; kUnroll x 64 edges per step (slot positions
+  // first, then all gathers, then the segmented sums in slot order)
   for (int64_t w = gw; w < a.nw; w += nwaves) {
     const int64_t v = w * 64 + ln;
     const bool inb = v < a.n;
     int cur = 0, end = 0;
-    bool heavy = false;
+    bool split = false;
     if (inb) {
       cur = rp[v];
       end = rp[v + 1];
-      heavy = end - cur > kHeavyDeg;
+      split = end - cur > kPushSplit;
     }
-    const bool act = inb && !heavy;
+    const bool act = inb && !split;
+    if (!act) end = cur;
     T acc = (T)0;
-    for (;;) {
-      const int len = act ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      T val = (T)0;
-      if (ln < total) val = x[ci[rcur + (ln - rexcl)]];
-      val = seg_sum_scan<T>(val, r);
-      const int se = min(incl, 64);
-      const T seg = __shfl(val, starts ? se - 1 : 0);
-      if (starts) {
-        acc += seg;
-        cur += se - excl;
+    for (bool more = true; more;) {
+      int pos[kUnroll], row[kUnroll], se[kUnroll];
+      bool st[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        pos[s] = -1;
+        row[s] = 0;
+        se[s] = 0;
+        st[s] = false;
+        if (!more) continue;
+        const int len = end - cur;
+        const int incl = wave_incl_scan(len);
+        const int total = __shfl(incl, 63);
+        if (total == 0) {
+          more = false;
+          continue;
+        }
+        const int excl = incl - len;
+        const bool starts = len > 0 && excl < 64;
+        const int r = slot_rows(mark, starts, excl);
+        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+        if (ln < total) pos[s] = rcur + (ln - rexcl);
+        row[s] = r;
+        st[s] = starts;
+        se[s] = min(incl, 64);
+        if (starts) cur += se[s] - excl;
+      }
+      int c[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) c[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+      T val[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) val[s] = c[s] >= 0 ? x[c[s]] : (T)0;
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const T y = seg_sum_scan<T>(val[s], row[s]);
+        const T seg = __shfl(y, st[s] ? se[s] - 1 : 0);
+        if (st[s]) acc += seg;
       }
     }
     if (act) {
@@ -125,18 +151,43 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
       }
     }
   }
+  // pieces of long rows (kPushSplit edges each), spread over the waves and
+  // two at a time; each piece's sum goes to its slot for the fix-up kernel
+  static_assert(kPushSplit == 64 * kUnroll, "a piece is one unrolled step");
   T *hp = (T *)a.heavy_part;
-  for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
-    const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
-    const int e = min(b + kHeavyChunk, rp[r + 1]);
-    T s = (T)0;
-    for (int base = b; base < e; base += 64) {
-      const int pos = base + ln;
-      if (pos < e) s += x[ci[pos]];
-    }
+  for (int64_t h0 = gw; h0 < a.pull.nsplit; h0 += 2 * nwaves) {
+    int pb[2], pe[2];
+    int64_t ph[2];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (ln == 0) hp[h] = s;
+    for (int q = 0; q < 2; ++q) {
+      ph[q] = h0 + q * nwaves;
+      pb[q] = pe[q] = 0;
+      if (ph[q] < a.pull.nsplit) {
+        const int r = a.pull.split[2 * ph[q]];
+        pb[q] = a.pull.split[2 * ph[q] + 1];
+        pe[q] = min(pb[q] + kPushSplit, rp[r + 1]);
+      }
+    }
+    int c[2][kUnroll];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const int pos = pb[q] + s * 64 + ln;
+        c[q][s] = pos < pe[q] ? ci[pos] : -1;
+      }
+    T val[2][kUnroll];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) val[q][s] = c[q][s] >= 0 ? x[c[q][s]] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T sum = (val[q][0] + val[q][1]) + (val[q][2] + val[q][3]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      if (ln == 0 && ph[q] < a.pull.nsplit) hp[ph[q]] = sum;
+    }
   }
   block_partials<T>(delta, dang, a.blk_part);
 }
@@ -153,9 +204,9 @@ __global__ __launch_bounds__(1024) void k_pr_fixup(PrArgs a, int init) {
     const T *hp = (const T *)a.heavy_part;
     T *p = (T *)a.p;
     T *xn = (T *)a.xn;
-    for (int64_t i = threadIdx.x; i < a.pull.nheavy_rows; i += 1024) {
-      const int r = a.pull.heavy_rows[3 * i], first = a.pull.heavy_rows[3 * i + 1],
-                cnt = a.pull.heavy_rows[3 * i + 2];
+    for (int64_t i = threadIdx.x; i < a.pull.nsplit_rows; i += 1024) {
+      const int r = a.pull.split_rows[3 * i], first = a.pull.split_rows[3 * i + 1],
+                cnt = a.pull.split_rows[3 * i + 2];
       T acc = (T)0;
       for (int k = 0; k < cnt; ++k) acc += hp[first + k];
       const T pn = rank_update<T>(a, acc, dn);

@@ -2,16 +2,18 @@
 // with the frontier sparsified to the vertices whose distance improved in
 // the previous round; stop when no distance improves.  One kernel per
 // round, like the BFS levels:
-// * push: one wave per frontier word streams the frontier rows' out-edges
-//   (concatenated, 64 per step) and relaxes dist[v] with an atomicMin on
-//   the float's bits (distances are >= 0, so the bit patterns order like
-//   the values); rows longer than kPushSplit use the static pieces;
-// * pull: one wave per word of candidate rows (rows with in-edges) streams
-//   their in-edges and takes a segmented minimum of dist[u] + w(u,v) over
-//   frontier neighbours u; a row's owner writes its own distance; rows
-//   longer than kHeavyDeg are split into pieces that use atomicMin;
-// * every improved vertex sets its bit in the next frontier; the first
-//   setter counts it (size and degree sum for the direction choice).
+// * push streams the out-edges of the frontier rows and relaxes dist[v]
+//   with an atomicMin on the float's bits (distances are >= 0, so the bit
+//   patterns order like the values);
+// * pull streams the in-edges of every row that has any and takes a
+//   segmented minimum of fd[u] + w(u,v), where fd holds the distances of
+//   the frontier's vertices and +inf elsewhere (one gather per edge, no
+//   bitmap test); the row's wave writes it with a plain store, and pieces
+//   of long rows combine their minima with atomicMin;
+// * every improved vertex sets its bit in the next frontier and its new
+//   distance in the next fd vector (atomicMin); the first setter counts it
+//   (size and degree sum for the direction choice).  fd vectors rotate with
+//   the bitmaps; a round resets the entries of the buffer it clears.
 // Relaxations read the current distances in place, so a round may already
 // use a distance lowered earlier in the same round; any such order reaches
 // the same fixed point, the exact shortest distances.
@@ -41,10 +43,53 @@ __device__ __forceinline__ void mark_improved(const SsspArgs &a, int v, int &fc,
   fd += a.push.rp[v + 1] - a.push.rp[v];
 }
 
-__device__ __forceinline__ void relax(const SsspArgs &a, int v, float nd, int &fc, int &fd) {
-  if (!(nd < a.dist[v])) return;  // plain read: a filter, the atomic decides
-  const int old = atomicMin((int *)&a.dist[v], __float_as_int(nd));
-  if (nd < __int_as_float(old)) mark_improved(a, v, fc, fd);
+// Relaxes dist[c[s]] with nd[s] for s < kUnroll (c < 0: none).  The
+// current distances are read first, all at once (a plain read is only a
+// filter, the atomic decides).
+__device__ __forceinline__ void relax_batch(const SsspArgs &a, const int (&c)[kUnroll],
+                                            const float (&nd)[kUnroll], int &fc, int &fd) {
+  float cd[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) cd[s] = c[s] >= 0 ? a.dist[c[s]] : 0.0f;
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    if (c[s] >= 0 && nd[s] < cd[s]) {
+      const int old = atomicMin((int *)&a.dist[c[s]], __float_as_int(nd[s]));
+      if (nd[s] < __int_as_float(old)) {
+        atomicMin((int *)&a.fd_nxt[c[s]], __float_as_int(nd[s]));
+        mark_improved(a, c[s], fc, fd);
+      }
+    }
+  }
+}
+
+// Bitmap words are dealt out to the waves round-robin.  Push compacts the
+// frontier bits of a wave's words into a queue of rows, pull takes the
+// candidate rows one word at a time (lanes = the word's 64 rows).  Rows up
+// to kPushSplit edges long are streamed by the wave as one concatenated
+// list, kUnroll x 64 edges per step; longer rows come in static
+// kPushSplit-edge pieces spread over all waves (both directions), so no
+// wave is left with a hub.
+
+// Clears the frontier bitmap two rounds ahead, word `mw` per lane, and
+// resets the frontier distances of its vertices to +inf (coalesced: the
+// wave writes one word's 64 entries at a time).
+__device__ __forceinline__ void clear_behind(const SsspArgs &a, int64_t mw, bool valid) {
+  const int ln = threadIdx.x & 63;
+  uint64_t old = 0ull;
+  if (valid) {
+    old = a.fclr[mw];
+    if (old) a.fclr[mw] = 0ull;
+  }
+  uint64_t nz = __ballot(old != 0ull);
+  const float inf = __int_as_float(0x7f800000);
+  while (nz) {
+    const int k = __ffsll((unsigned long long)nz) - 1;
+    nz &= nz - 1;
+    const int64_t w = __shfl(mw, k);
+    const uint64_t bits = __shfl(old, k);
+    if ((bits >> ln) & 1ull) a.fd_clr[w * 64 + ln] = inf;
+  }
 }
 
 __device__ void sssp_push(const SsspArgs &a, int *mark, int &fc, int &fd) {
@@ -52,54 +97,94 @@ __device__ void sssp_push(const SsspArgs &a, int *mark, int &fc, int &fd) {
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.push.rp, *ci = a.push.ci;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    if (ln == 0) a.fclr[w] = 0ull;
-    const uint64_t fw = a.fcur[w];
-    if (fw == 0ull) continue;
-    const int64_t u = w * 64 + ln;
-    int cur = 0, end = 0;
-    float du = 0.0f;
-    if ((fw >> ln) & 1ull) {
-      cur = rp[u];
-      end = rp[u + 1];
-      du = a.dist[u];
-      if (end - cur > kPushSplit) end = cur;  // long rows: static pieces below
-    }
-    for (;;) {
-      const int len = end - cur;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      const float rdu = __shfl(du, r);
-      if (ln < total) {
-        const int pos = rcur + (ln - rexcl);
-        relax(a, ci[pos], rdu + a.wpush[pos], fc, fd);
+  // words dealt out round-robin (wave gw takes words gw, gw + nwaves, ...);
+  // their set bits are compacted into a queue of rows, 64 at a time
+  for (int64_t w0 = gw; w0 < a.nw; w0 += 64 * nwaves) {
+    const int64_t mw = w0 + (int64_t)ln * nwaves;
+    clear_behind(a, mw, mw < a.nw);
+    const uint64_t mf = mw < a.nw ? a.fcur[mw] : 0ull;
+    const int cnt = __popcll(mf);
+    const int qincl = wave_incl_scan(cnt);
+    const int qtotal = __shfl(qincl, 63);
+    for (int b = 0; b < qtotal; b += 64) {
+      const int64_t u = queue_slot(mark, mf, cnt, qincl, qtotal, b, mw);
+      int cur = 0, end = 0;
+      float du = 0.0f;
+      if (u >= 0) {
+        cur = rp[u];
+        end = rp[u + 1];
+        du = a.dist[u];
+        if (end - cur > kPushSplit) end = cur;  // long rows: static pieces below
       }
-      if (starts) cur += min(incl, 64) - excl;
+      for (bool more = true; more;) {
+        int cc[kUnroll];
+        float nd[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          cc[s] = -1;
+          nd[s] = 0.0f;
+          if (!more) continue;
+          const int len = end - cur;
+          const int incl = wave_incl_scan(len);
+          const int total = __shfl(incl, 63);
+          if (total == 0) {
+            more = false;
+            continue;
+          }
+          const int excl = incl - len;
+          const bool starts = len > 0 && excl < 64;
+          const int r = slot_rows(mark, starts, excl);
+          const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+          const float rdu = __shfl(du, r);
+          if (ln < total) {
+            cc[s] = rcur + (ln - rexcl);
+            nd[s] = rdu;
+          }
+          if (starts) cur += min(incl, 64) - excl;
+        }
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          if (cc[s] >= 0) {
+            const int pos = cc[s];
+            cc[s] = ci[pos];
+            nd[s] += a.wpush[pos];
+          }
+        }
+        relax_batch(a, cc, nd, fc, fd);
+      }
     }
   }
-  for (int64_t h0 = gw * 64; h0 < a.push.nsplit; h0 += nwaves * 64) {
-    const int64_t h = h0 + ln;
-    int u = -1, b = 0;
+  // static pieces of long rows, spread over the waves, 64 tested per step
+  static_assert(kPushSplit == 64 * kUnroll, "a piece is one unrolled step");
+  for (int64_t hb = gw; hb < a.push.nsplit; hb += 64 * nwaves) {
+    const int64_t h = hb + (int64_t)ln * nwaves;
+    int u = -1, b = 0, e = 0;
+    float du = 0.0f;
     if (h < a.push.nsplit) {
       u = a.push.split[2 * h];
       b = a.push.split[2 * h + 1];
+      if (bit_of(a.fcur, u)) {
+        e = min(b + kPushSplit, rp[u + 1]);
+        du = a.dist[u];
+      } else {
+        u = -1;
+      }
     }
-    uint64_t act = __ballot(u >= 0 && bit_of(a.fcur, u));
+    uint64_t act = __ballot(u >= 0);
     while (act) {
       const int k = __ffsll((unsigned long long)act) - 1;
       act &= act - 1;
-      const int pu = __shfl(u, k), pb = __shfl(b, k);
-      const float du = a.dist[pu];
-      const int e = min(pb + kPushSplit, rp[pu + 1]);
-      for (int base = pb; base < e; base += 64) {
-        const int pos = base + ln;
-        if (pos < e) relax(a, ci[pos], du + a.wpush[pos], fc, fd);
+      const int pb = __shfl(b, k), pe = __shfl(e, k);
+      const float pdu = __shfl(du, k);
+      int cc[kUnroll];
+      float nd[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const int pos = pb + s * 64 + ln;
+        cc[s] = pos < pe ? ci[pos] : -1;
+        nd[s] = pos < pe ? pdu + a.wpush[pos] : 0.0f;
       }
+      relax_batch(a, cc, nd, fc, fd);
     }
   }
 }
@@ -110,66 +195,151 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd) {
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
   const float inf = __int_as_float(0x7f800000);
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    if (ln == 0) a.fclr[w] = 0ull;
-    const uint64_t cand = ~a.iso[w];
-    if (cand == 0ull) continue;
-    const int64_t v = w * 64 + ln;
-    bool act = (cand >> ln) & 1ull;
-    int cur = 0, end = 0;
-    if (act) {
-      cur = rp[v];
-      end = rp[v + 1];
-      if (end - cur > kHeavyDeg) act = false;  // long rows: split pieces below
-    }
-    const int deg0 = end - cur;
-    float best = inf;
-    for (;;) {
-      const int len = act ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      float x = inf;
-      if (ln < total) {
-        const int pos = rcur + (ln - rexcl);
-        const int c = ci[pos];
-        if (bit_of(a.fcur, c)) x = a.dist[c] + a.wpull[pos];
+  // words are dealt out round-robin (wave gw takes words gw, gw + nwaves,
+  // ...): rows of similar degree have nearby ids, so neighbouring heavy
+  // words go to different waves
+  for (int64_t w0 = gw; w0 < a.nw; w0 += 64 * nwaves) {
+    const int64_t mw = w0 + (int64_t)ln * nwaves;
+    clear_behind(a, mw, mw < a.nw);
+    const uint64_t mc = mw < a.nw ? ~a.iso[mw] : 0ull;  // candidate rows: rows with in-edges
+    uint64_t nzw = __ballot(mc != 0ull);
+    while (nzw) {
+      const int k = __ffsll((unsigned long long)nzw) - 1;
+      nzw &= nzw - 1;
+      const int64_t w = w0 + (int64_t)k * nwaves;
+      const uint64_t cand = __shfl(mc, k);
+      const int64_t v = w * 64 + ln;
+      bool act = (cand >> ln) & 1ull;
+      int cur = 0, end = 0;
+      if (act) {
+        cur = rp[v];
+        end = rp[v + 1];
+        if (end - cur > kPushSplit) act = false;  // long rows: pieces below
       }
-      x = seg_min_scan(x, r);
-      const int se = min(incl, 64);
-      const float segmin = __shfl(x, starts ? se - 1 : 0);
-      if (starts) {
-        best = fminf(best, segmin);
-        cur += se - excl;
+      if (!act) end = cur;
+      const int deg0 = end - cur;
+      float best = inf;
+      // slot positions of kUnroll x 64 edges first, then their loads, then
+      // the segmented minima over frontier neighbours (a distance is read
+      // only for neighbours in the frontier)
+      for (bool more = true; more;) {
+        int pos[kUnroll], row[kUnroll], se[kUnroll];
+        bool st[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          pos[s] = -1;
+          row[s] = 0;
+          se[s] = 0;
+          st[s] = false;
+          if (!more) continue;
+          const int len = end - cur;
+          const int incl = wave_incl_scan(len);
+          const int total = __shfl(incl, 63);
+          if (total == 0) {
+            more = false;
+            continue;
+          }
+          const int excl = incl - len;
+          const bool starts = len > 0 && excl < 64;
+          const int r = slot_rows(mark, starts, excl);
+          const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+          if (ln < total) pos[s] = rcur + (ln - rexcl);
+          row[s] = r;
+          st[s] = starts;
+          se[s] = min(incl, 64);
+          if (starts) cur += se[s] - excl;
+        }
+        int cv[kUnroll];
+        float wt[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          cv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+          wt[s] = pos[s] >= 0 ? a.wpull[pos[s]] : 0.0f;
+        }
+        // one gather per edge: the frontier distance is +inf off the
+        // frontier
+        float dc[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) dc[s] = cv[s] >= 0 ? a.fd_cur[cv[s]] : inf;
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          const float y = seg_min_scan(dc[s] + wt[s], row[s]);
+          const float segmin = __shfl(y, st[s] ? se[s] - 1 : 0);
+          if (st[s]) best = fminf(best, segmin);
+        }
       }
+      bool improved = false;
+      if (act && best < a.dist[v]) {  // only this wave writes row v in a pull round
+        a.dist[v] = best;
+        a.fd_nxt[v] = best;
+        improved = true;
+        fc += 1;
+        fd += a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
+      }
+      const uint64_t ib = __ballot(improved);
+      if (ib && ln == 0) atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)ib);
     }
-    bool improved = false;
-    if (act && best < a.dist[v]) {
-      a.dist[v] = best;
-      improved = true;
-      fc += 1;
-      fd += a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
-    }
-    const uint64_t ib = __ballot(improved);
-    if (ib && ln == 0) atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)ib);
   }
-  for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
-    const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
-    const int e = min(b + kHeavyChunk, rp[r + 1]);
-    float best = inf;
-    for (int base = b; base < e; base += 64) {
-      const int pos = base + ln;
-      if (pos < e) {
-        const int c = ci[pos];
-        if (bit_of(a.fcur, c)) best = fminf(best, a.dist[c] + a.wpull[pos]);
+  // pieces of long rows: each piece's minimum is combined with atomicMin;
+  // two active pieces are loaded at once so their latencies overlap
+  for (int64_t hb = gw; hb < a.pull.nsplit; hb += 64 * nwaves) {
+    const int64_t h = hb + (int64_t)ln * nwaves;
+    int r = -1, b = 0, e = 0;
+    if (h < a.pull.nsplit) {
+      r = a.pull.split[2 * h];
+      b = a.pull.split[2 * h + 1];
+      e = min(b + kPushSplit, rp[r + 1]);
+    }
+    uint64_t act = __ballot(r >= 0);
+    while (act) {
+      int pr[2], pb[2], pe[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        pr[q] = -1;
+        pb[q] = pe[q] = 0;
+        if (act) {
+          const int k = __ffsll((unsigned long long)act) - 1;
+          act &= act - 1;
+          pr[q] = __shfl(r, k);
+          pb[q] = __shfl(b, k);
+          pe[q] = __shfl(e, k);
+        }
+      }
+      int cv[2][kUnroll];
+      float wt[2][kUnroll];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          const int pos = pb[q] + s * 64 + ln;
+          cv[q][s] = pos < pe[q] ? ci[pos] : -1;
+          wt[q][s] = pos < pe[q] ? a.wpull[pos] : 0.0f;
+        }
+      float dc[2][kUnroll];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) dc[q][s] = cv[q][s] >= 0 ? a.fd_cur[cv[q][s]] : inf;
+      float best[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        best[q] = inf;
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) best[q] = fminf(best[q], dc[q][s] + wt[q][s]);
+      }
+      best[0] = wave_min(best[0]);
+      best[1] = wave_min(best[1]);
+      // lane q relaxes piece q's row
+      const int myr = ln == 0 ? pr[0] : (ln == 1 ? pr[1] : -1);
+      const float myb = ln == 0 ? best[0] : best[1];
+      if (myr >= 0 && myb < inf) {
+        const int old = atomicMin((int *)&a.dist[myr], __float_as_int(myb));
+        if (myb < __int_as_float(old)) {
+          atomicMin((int *)&a.fd_nxt[myr], __float_as_int(myb));
+          mark_improved(a, myr, fc, fd);
+        }
       }
     }
-    best = wave_min(best);
-    if (ln == 0) relax(a, r, best, fc, fd);
   }
 }
 
@@ -225,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_sssp_round(SsspArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_sssp_start(SsspArgs a, int32_t source, uint64_t *f1,
-                                                       uint64_t *f2) {
+                                                       uint64_t *f2, float *fd1, float *fd2) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -234,7 +404,11 @@ __global__ __launch_bounds__(kBlock) void k_sssp_start(SsspArgs a, int32_t sourc
     bool iso = true;
     if (v < a.n) {
       iso = a.can_pull ? (a.pull.rp[v + 1] == a.pull.rp[v]) : false;
-      a.dist[v] = (v == source) ? 0.0f : __int_as_float(0x7f800000);
+      const float inf = __int_as_float(0x7f800000);
+      a.dist[v] = (v == source) ? 0.0f : inf;
+      a.fd_cur[v] = (v == source) ? 0.0f : inf;
+      fd1[v] = inf;
+      fd2[v] = inf;
     }
     const uint64_t isom = __ballot(iso);
     if (ln == 0) {
@@ -258,12 +432,12 @@ __global__ __launch_bounds__(kBlock) void k_sssp_start(SsspArgs a, int32_t sourc
 
 }  // namespace
 
-void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
-                       void *stream) {
+void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2, float *fd1,
+                       float *fd2, void *stream) {
   int64_t g = (a.nw + kWavesPerBlock - 1) / kWavesPerBlock;
   g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
   hipLaunchKernelGGL(k_sssp_start, dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a,
-                     source, f1, f2);
+                     source, f1, f2, fd1, fd2);
 }
 
 void launch_sssp_round(const SsspArgs &a, void *stream) {
