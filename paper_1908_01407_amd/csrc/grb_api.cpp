@@ -360,8 +360,15 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
   launch_bfs_start(ba, source, w.F[1], w.F[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
-  int chunk = 6;
+  // The first batch covers six levels and the empty one that ends most
+  // small-world searches (it also runs the parents pass); later batches
+  // double.  Control block and level records come back in one copy.
+  int chunk = 7;
+  const size_t rec_bytes = (size_t)kStatsCap * kStatFields * sizeof(int64_t);
+  const size_t head = (size_t)((char *)w.stats - (char *)w.ctrl);
+  std::vector<char> host(head + rec_bytes);
   Ctrl hc{};
+  bool empty_seen = false;
   for (;;) {
     for (int i = 0; i < chunk && d < cap; ++i, ++d) {
       at_level(d);
@@ -370,25 +377,26 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(host.data(), w.ctrl, host.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return GRB_PANIC;
-    int64_t next = 0;
-    for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + 2 * t];
-    if (next == 0 || d >= cap) break;
+    std::memcpy(&hc, host.data(), sizeof(Ctrl));
+    if (hc.nlev < d) {  // a launched level found the frontier empty
+      empty_seen = true;
+      break;
+    }
+    if (d >= cap) break;
     chunk = std::min(chunk * 2, 256);
   }
-  if (parents) {
+  if (parents && !empty_seen) {  // stopped by the level cap
     launch_bfs_parents(ba, stream);
     if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
   }
   const int iters = hc.nlev;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
-  if (nrec > 0 && hipMemcpyAsync(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
-                                 hipMemcpyDeviceToHost, s) != hipSuccess)
-    return GRB_PANIC;
-  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+  std::memcpy(rec.data(), host.data() + head, rec_bytes);
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {

@@ -21,7 +21,9 @@
 //   buffer d, fills buffer d+1 and clears buffer d+2.
 // Pull finds the smallest-id parent directly (ascending adjacency, first
 // hit).  Push-discovered vertices get theirs from one pass after the last
-// level: the first in-neighbour one level up in ascending order.
+// level, run by the first level kernel that finds the frontier empty (or by
+// its own kernel when the level cap stops the search first): the first
+// in-neighbour one level up in ascending order.
 #include <hip/hip_runtime.h>
 
 #include "grb_device.h"
@@ -69,7 +71,7 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
 // as one concatenated list; longer rows come in static pieces spread over
 // all waves, so a hub is expanded by hundreds of waves at once.
 
-__device__ void bfs_push(const BfsArgs &a, int *mark, int &fc, int &fd) {
+__device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, int &fc, int &fd) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -151,7 +153,7 @@ __device__ void bfs_push(const BfsArgs &a, int *mark, int &fc, int &fd) {
   }
 }
 
-__device__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd) {
+__device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -296,6 +298,67 @@ __device__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd) {
   }
 }
 
+// Smallest-id parent of every vertex reached by a push: the first
+// in-neighbour (ascending) whose level is one less.  A wave takes one bitmap
+// word of vertices at a time; the first two in-neighbours of every row are
+// tested in parallel, the rest streamed as one concatenated list.
+__device__ __forceinline__ void parents_pass(const BfsArgs &a, int *mark) {
+  const int ln = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
+  for (int64_t w = gw; w < a.nw; w += nwaves) {
+    const int64_t v = w * 64 + ln;
+    int lv = -1;
+    bool need = false;
+    if (v < a.n) {
+      lv = a.levels[v];
+      need = lv > 0 && a.parents[v] < 0;
+    }
+    if (__ballot(need) == 0ull) continue;
+    int cur = need ? rp[v] : 0;
+    const int end = need ? rp[v + 1] : 0;
+    const int tgt = lv - 1;
+    bool found = false;
+    int par = -1;
+    if (need) {
+      const int c0 = cur < end ? ci[cur] : -1;
+      const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
+      const int l0 = c0 >= 0 ? a.levels[c0] : -2;
+      const int l1 = c1 >= 0 ? a.levels[c1] : -2;
+      if (l0 == tgt) { found = true; par = c0; }
+      else if (l1 == tgt) { found = true; par = c1; }
+      cur = min(cur + 2, end);
+    }
+    for (;;) {
+      const int len = (need && !found) ? end - cur : 0;
+      const int incl = wave_incl_scan(len);
+      const int total = __shfl(incl, 63);
+      if (total == 0) break;
+      const int excl = incl - len;
+      const bool starts = len > 0 && excl < 64;
+      const int r = slot_rows(mark, starts, excl);
+      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r), rt = __shfl(tgt, r);
+      const bool valid = ln < total;
+      const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
+      const uint64_t hm = __ballot(valid && a.levels[c] == rt);
+      const int se = min(incl, 64);
+      const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
+      const uint64_t h = hm & seg;
+      const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
+      const int pc = __shfl(c, fl);
+      if (h) { found = true; par = pc; }
+      if (starts) cur += se - excl;
+    }
+    if (found) a.parents[v] = par;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
+  __shared__ int s_mark[kWavesPerBlock][64];
+  parents_pass(a, s_mark[threadIdx.x >> 6]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   __shared__ int s_count, s_sumdeg;
@@ -324,7 +387,12 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   }
   __syncthreads();
   const int count = s_count;
-  if (count == 0) return;
+  if (count == 0) {
+    // the first empty level (the last level with a frontier was d - 1)
+    // finds the parents of the push-discovered vertices
+    if (a.parents && a.ctrl->nlev == a.d) parents_pass(a, s_mark[threadIdx.x >> 6]);
+    return;
+  }
   const int dir = decide(a, count, s_sumdeg);
   int fc = 0, fd = 0;
   if (dir == GRB_DIR_PUSH) bfs_push(a, s_mark[threadIdx.x >> 6], fc, fd);
@@ -381,64 +449,6 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
     a.ctrl->nlev = 0;
     a.cnt_cur[0] = 1;  // level 0 = {source}
     a.cnt_cur[1] = a.push.rp[source + 1] - a.push.rp[source];
-  }
-}
-
-// Smallest-id parent of every vertex reached by a push: the first
-// in-neighbour (ascending) whose level is one less.  One wave per bitmap
-// word of vertices; the first two in-neighbours of every row are tested in
-// parallel, the rest streamed as one concatenated list.
-__global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
-  __shared__ int s_mark[kWavesPerBlock][64];
-  int *mark = s_mark[threadIdx.x >> 6];
-  const int ln = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    const int64_t v = w * 64 + ln;
-    int lv = -1;
-    bool need = false;
-    if (v < a.n) {
-      lv = a.levels[v];
-      need = lv > 0 && a.parents[v] < 0;
-    }
-    if (__ballot(need) == 0ull) continue;
-    int cur = need ? rp[v] : 0;
-    const int end = need ? rp[v + 1] : 0;
-    const int tgt = lv - 1;
-    bool found = false;
-    int par = -1;
-    if (need) {
-      const int c0 = cur < end ? ci[cur] : -1;
-      const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
-      const int l0 = c0 >= 0 ? a.levels[c0] : -2;
-      const int l1 = c1 >= 0 ? a.levels[c1] : -2;
-      if (l0 == tgt) { found = true; par = c0; }
-      else if (l1 == tgt) { found = true; par = c1; }
-      cur = min(cur + 2, end);
-    }
-    for (;;) {
-      const int len = (need && !found) ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r), rt = __shfl(tgt, r);
-      const bool valid = ln < total;
-      const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
-      const uint64_t hm = __ballot(valid && a.levels[c] == rt);
-      const int se = min(incl, 64);
-      const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
-      const uint64_t h = hm & seg;
-      const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
-      const int pc = __shfl(c, fl);
-      if (h) { found = true; par = pc; }
-      if (starts) cur += se - excl;
-    }
-    if (found) a.parents[v] = par;
   }
 }
 
