@@ -185,13 +185,15 @@ def bench_extras(grb, graphgen, torch, args):
     if st["kernel_ms"]:
         rounds = len(st["kernel_ms"])
         tot_ms = sum(st["kernel_ms"])
-        bytes_round = 4 * A.nnz + 8 * (n + 1) + n / 8 + 8 * n
+        bytes_round = 8 * A.nnz + 4 * (n + 1) + 4 * n + 4 * n + n / 4
         ex[f"sssp_rmat{args.scale}_forced_pull"] = {
             "rounds": rounds, "ms": round(tot_ms, 4),
             "bytes_per_round_model": bytes_round,
             "gbs": round(bytes_round * rounds / (tot_ms / 1e3) / 1e9, 1),
-            "note": "col_idx 4B/entry + row_ptr + frontier bitmap + dist read/write per round; "
-                    "weights read only for frontier neighbours (not counted)"}
+            "frac_hbm": round(bytes_round * rounds / (tot_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "per round: col_idx + weight of every stored entry (8 B), row extents, "
+                    "frontier distances (gathered, counted once), distances read, candidate "
+                    "and next-frontier bitmaps"}
     del ws
     # grid 3000 x 3000
     if not args.no_grid:

@@ -40,29 +40,83 @@ __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
   return pull ? GRB_DIR_PULL : GRB_DIR_PUSH;
 }
 
-// Claims v for the next level once its visited bit was seen clear; counts
-// it in (fc, fd).
-__device__ __forceinline__ void claim_atomic(const BfsArgs &a, int v, int &fc, int &fd) {
-  const uint64_t b = 1ull << (v & 63);
-  const uint64_t old = atomicOr((unsigned long long *)&a.visited[v >> 6], (unsigned long long)b);
-  if (old & b) return;
-  a.levels[v] = a.d + 1;
-  atomicOr((unsigned long long *)&a.fnxt[v >> 6], (unsigned long long)b);
-  fc += 1;
-  fd += a.push.rp[v + 1] - a.push.rp[v];
+// Finishes the claims won by this lane: level, next-frontier bit, counts.
+// The degree loads of all won targets are issued together.
+__device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnroll],
+                                          const bool (&won)[kUnroll], int &fc, int &fd) {
+  int d0[kUnroll], d1[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    d0[s] = 0;
+    d1[s] = 0;
+    if (won[s]) {
+      a.levels[c[s]] = a.d + 1;
+      atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], 1ull << (c[s] & 63));
+      d0[s] = a.push.rp[c[s]];
+      d1[s] = a.push.rp[c[s] + 1];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    fc += won[s] ? 1 : 0;
+    fd += d1[s] - d0[s];
+  }
 }
 
-// Claims the targets c[0..kUnroll) (-1: none).  The visited words of all
-// of them are read first (a plain read is only a filter, the atomic
-// decides), so their latencies overlap.
+// Claims the targets c[0..kUnroll) (-1: none) from a stream that may hold
+// one target twice.  The visited words of all of them are read first (a
+// plain read is only a filter, the atomic decides) and all atomics are
+// issued before any result is used, so their latencies overlap.
 __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
                                             int &fd) {
   uint64_t vw[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+  uint64_t old[kUnroll];
 #pragma unroll
-  for (int s = 0; s < kUnroll; ++s)
-    if (!((vw[s] >> (c[s] & 63)) & 1ull)) claim_atomic(a, c[s], fc, fd);
+  for (int s = 0; s < kUnroll; ++s) {
+    old[s] = ~0ull;
+    if (!((vw[s] >> (c[s] & 63)) & 1ull))
+      old[s] = atomicOr((unsigned long long *)&a.visited[c[s] >> 6], 1ull << (c[s] & 63));
+  }
+  bool won[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) won[s] = c[s] >= 0 && !((old[s] >> (c[s] & 63)) & 1ull);
+  claim_won(a, c, won, fc, fd);
+}
+
+// Claims the targets of one piece of a row: ascending and distinct, so the
+// lanes whose targets share a visited word sit side by side and one atomicOr
+// per word serves them all.
+__device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
+                                            int &fd) {
+  uint64_t vw[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+  bool want[kUnroll];
+  uint64_t old[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    want[s] = c[s] >= 0 && !((vw[s] >> (c[s] & 63)) & 1ull);
+    const int64_t wd = want[s] ? (int64_t)(c[s] >> 6) : -1;
+    const uint64_t run = run_head_or(wd, want[s] ? (1ull << (c[s] & 63)) : 0ull);
+    old[s] = 0ull;
+    if (run && wd >= 0)
+      old[s] = atomicOr((unsigned long long *)&a.visited[wd], (unsigned long long)run);
+  }
+  bool won[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    // the run's head holds the word's previous value; hand it to the run
+    const int64_t wd = want[s] ? (int64_t)(c[s] >> 6) : -1;
+    const int64_t prev = __shfl_up(wd, 1);
+    const int ln = threadIdx.x & 63;
+    const bool head = ln == 0 || prev != wd;
+    const int rid = wave_max_scan(head ? ln : -1);
+    const uint64_t ow = __shfl(old[s], rid);
+    won[s] = want[s] && !((ow >> (c[s] & 63)) & 1ull);
+  }
+  claim_won(a, c, won, fc, fd);
 }
 
 // Each wave loads 64 bitmap words at once (one per lane) and compacts their
@@ -148,7 +202,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, int &fc, i
         const int pos = pb + s * 64 + ln;
         c[s] = pos < pe ? ci[pos] : -1;
       }
-      claim_batch(a, c, fc, fd);
+      claim_piece(a, c, fc, fd);
     }
   }
 }
