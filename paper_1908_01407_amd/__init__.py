@@ -272,8 +272,11 @@ class Matrix:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            _lib.grb_matrix_free(ctypes.byref(h))
+        try:
+            if h is not None and h.value:
+                _lib.grb_matrix_free(ctypes.byref(h))
+        except (AttributeError, TypeError):
+            pass  # module globals already torn down at interpreter exit
 
 
 _TYPE_OF = {}
@@ -304,8 +307,11 @@ class Vector:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            _lib.grb_vector_free(ctypes.byref(h))
+        try:
+            if h is not None and h.value:
+                _lib.grb_vector_free(ctypes.byref(h))
+        except (AttributeError, TypeError):
+            pass  # module globals already torn down at interpreter exit
 
     def set(self, entries: dict, stream=None):
         """Clears, then sets the given {index: value} entries (via grb_vector_build)."""
@@ -333,11 +339,19 @@ class Vector:
 # ---- drivers and products --------------------------------------------------------
 
 def bfs(A: Matrix, source: int, *, parents: bool = True, desc: Descriptor | None = None,
-        ws=None, stream=None):
-    """(levels int32[n], parents int32[n] or None) via grb_bfs."""
+        ws=None, stream=None, out=None):
+    """(levels int32[n], parents int32[n] or None) via grb_bfs.  `out` may
+    pass (levels, parents) device tensors of at least n entries to fill."""
     torch = _torch()
-    lev = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device)
-    par = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device) if parents else None
+    if out is not None:
+        lev, par = out
+        if lev.numel() < A.nrows or (parents and (par is None or par.numel() < A.nrows)):
+            raise ValueError("bfs: output tensors hold fewer than n entries")
+        if not parents:
+            par = None
+    else:
+        lev = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device)
+        par = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device) if parents else None
     ws = ws if ws is not None else workspace(OP_BFS, A)
     check(_lib.grb_bfs(_ptr(lev), _ptr(par), A.handle, int(source),
                        ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),

@@ -1,0 +1,54 @@
+"""Byte models of bench.py (host-side arithmetic, no GPU): the early-exit
+scan length against brute force, and the BFS byte model on a path graph
+where every term can be counted by hand."""
+import numpy as np
+
+import bench
+import graphgen
+import oracle
+
+
+def brute_first_hit(rp, ci, rows_mask, hit_col):
+    total = 0
+    for r in np.flatnonzero(rows_mask):
+        nb = ci[rp[r]:rp[r + 1]]
+        if nb.size == 0:
+            continue
+        hits = np.flatnonzero(hit_col[nb])
+        total += int(hits[0]) + 1 if hits.size else int(nb.size)
+    return total
+
+
+def csr_of(raw):
+    adj = oracle.Adjacency.from_raw(raw)
+    rp, ci = adj.arrays()[:2]
+    return np.asarray(rp, dtype=np.int64), np.asarray(ci, dtype=np.int64)
+
+
+def test_first_hit_scan_matches_brute_force():
+    g = graphgen.rmat(9)
+    rp, ci = csr_of(g)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        rows = rng.random(g.n) < 0.4
+        hit = rng.random(g.n) < 0.1
+        assert bench.first_hit_scan(rp, ci, rows, hit) == brute_first_hit(rp, ci, rows, hit)
+
+
+def test_path_graph_byte_model():
+    # path 0-1-2-3: levels 0,1,2,3 from vertex 0, every level a push
+    n = 4
+    raw = graphgen.from_edges("path4", n, np.array([0, 1, 2]), np.array([1, 2, 3]))
+    rp, ci = csr_of(raw)
+    lev = np.array([0, 1, 2, 3])
+    dirs = [1, 1, 1, 1]
+    per = bench.bfs_bytes_per_level(rp, ci, lev, dirs, n)
+    deg = np.diff(rp)
+    for d in range(4):
+        nxt = 1 if d < 3 else 0
+        assert per[d] == 12 * 1 + 4 * deg[d] + n / 8 + n / 8 + 8 * nxt
+    # parents pass: 4n + 4 per reached vertex (levels > 0: 3), and for each
+    # push-discovered vertex 12 + 8 x (scan to its first neighbour a level up)
+    # vertex 1: neighbours [0, 2] -> 0 hits first (1 edge); vertex 2: [1, 3]
+    # -> 1 edge; vertex 3: [2] -> 1 edge
+    assert bench.parents_pass_bytes(rp, ci, lev, dirs, n) == 4 * n + 4 * 3 + 3 * 12 + 8 * 3
