@@ -472,7 +472,7 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
         hipStreamSynchronize(s) != hipSuccess)
       return GRB_PANIC;
     int64_t next = 0;
-    for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + 2 * t];
+    for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + kCntFields * t];
     if (next == 0 || d >= cap) break;
     chunk = std::min(chunk * 2, 512);
   }

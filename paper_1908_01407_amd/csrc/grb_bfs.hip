@@ -43,7 +43,8 @@ __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
 // Finishes the claims won by this lane: level, next-frontier bit, counts.
 // The degree loads of all won targets are issued together.
 __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnroll],
-                                          const bool (&won)[kUnroll], int &fc, int &fd) {
+                                          const bool (&won)[kUnroll], int &fc, int &fd,
+                                          int &fl) {
   int d0[kUnroll], d1[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
@@ -60,6 +61,7 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
   for (int s = 0; s < kUnroll; ++s) {
     fc += won[s] ? 1 : 0;
     fd += d1[s] - d0[s];
+    fl += d1[s] - d0[s] > kPushSplit ? 1 : 0;
   }
 }
 
@@ -68,7 +70,7 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
 // plain read is only a filter, the atomic decides) and all atomics are
 // issued before any result is used, so their latencies overlap.
 __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
-                                            int &fd) {
+                                            int &fd, int &fl) {
   uint64_t vw[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
@@ -82,14 +84,14 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
   bool won[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) won[s] = c[s] >= 0 && !((old[s] >> (c[s] & 63)) & 1ull);
-  claim_won(a, c, won, fc, fd);
+  claim_won(a, c, won, fc, fd, fl);
 }
 
 // Claims the targets of one piece of a row: ascending and distinct, so the
 // lanes whose targets share a visited word sit side by side and one atomicOr
 // per word serves them all.
 __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
-                                            int &fd) {
+                                            int &fd, int &fl) {
   uint64_t vw[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
@@ -116,7 +118,7 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
     const uint64_t ow = __shfl(old[s], rid);
     won[s] = want[s] && !((ow >> (c[s] & 63)) & 1ull);
   }
-  claim_won(a, c, won, fc, fd);
+  claim_won(a, c, won, fc, fd, fl);
 }
 
 // Each wave loads 64 bitmap words at once (one per lane) and compacts their
@@ -125,7 +127,8 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
 // as one concatenated list; longer rows come in static pieces spread over
 // all waves, so a hub is expanded by hundreds of waves at once.
 
-__device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, int &fc, int &fd) {
+__device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_rows, int &fc,
+                                         int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -174,7 +177,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, int &fc, i
         }
 #pragma unroll
         for (int s = 0; s < kUnroll; ++s) c[s] = c[s] >= 0 ? ci[c[s]] : -1;
-        claim_batch(a, c, fc, fd);
+        claim_batch(a, c, fc, fd, fl);
       }
     }
   }
@@ -182,6 +185,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, int &fc, i
   // gw, gw + nwaves, ...), 64 tested per step; a piece whose row is in the
   // frontier is streamed by the whole wave, kUnroll x 64 edges at once
   static_assert(kPushSplit == 64 * kUnroll, "a push piece is one unrolled step");
+  if (!long_rows) return;  // no row of the frontier has pieces
   for (int64_t hb = gw; hb < a.push.nsplit; hb += 64 * nwaves) {
     const int64_t h = hb + (int64_t)ln * nwaves;
     int u = -1, b = 0, e = 0;
@@ -202,12 +206,32 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, int &fc, i
         const int pos = pb + s * 64 + ln;
         c[s] = pos < pe ? ci[pos] : -1;
       }
-      claim_piece(a, c, fc, fd);
+      claim_piece(a, c, fc, fd, fl);
     }
   }
 }
 
-__device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd) {
+// Records rows found in a pull: rows of one bitmap word sit in consecutive
+// lanes (ascending ids), so one atomicOr per word and bitmap serves them.
+__device__ __forceinline__ void pull_found(const BfsArgs &a, bool found, int64_t v, int par,
+                                           int deg, int &fc, int &fd, int &fl) {
+  const int64_t vw = found ? (v >> 6) : -1;
+  const uint64_t hb = run_head_or(vw, found ? (1ull << (v & 63)) : 0ull);
+  if (hb && vw >= 0) {
+    atomicOr((unsigned long long *)&a.visited[vw], (unsigned long long)hb);
+    atomicOr((unsigned long long *)&a.fnxt[vw], (unsigned long long)hb);
+  }
+  if (found) {
+    a.levels[v] = a.d + 1;
+    if (a.parents) a.parents[v] = par;
+    const int pd = a.same_csr ? deg : a.push.rp[v + 1] - a.push.rp[v];
+    fc += 1;
+    fd += pd;
+    fl += pd > kPushSplit ? 1 : 0;
+  }
+}
+
+__device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -224,8 +248,8 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
     const int cnt = __popcll(mc);
     const int incl = wave_incl_scan(cnt);
     const int total = __shfl(incl, 63);
-    // kPullRows rows per lane: the loads of their first two neighbours are
-    // issued together
+    // kPullRows queued rows per lane: the loads of their first two
+    // neighbours are issued together
     for (int b = 0; b < total; b += 64 * kPullRows) {
       int64_t v[kPullRows];
       int cur[kPullRows], end[kPullRows];
@@ -253,9 +277,12 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
         b0[q] = c0[q] >= 0 ? a.fcur[c0[q] >> 6] : 0ull;
         b1[q] = c1[q] >= 0 ? a.fcur[c1[q] >> 6] : 0ull;
       }
+      // rows settled by their first two neighbours; the others (with more
+      // edges left) are counted per batch for the stream below
+      uint64_t rest[kPullRows];
+      int nrest = 0;
 #pragma unroll
       for (int q = 0; q < kPullRows; ++q) {
-        const int deg0 = end[q] - cur[q];
         bool found = false;
         int par = -1;
         if (c0[q] >= 0 && ((b0[q] >> (c0[q] & 63)) & 1ull)) {
@@ -265,16 +292,43 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
           found = true;
           par = c1[q];
         }
-        int cq = act[q] ? min(cur[q] + 2, end[q]) : 0, eq = act[q] ? end[q] : 0;
-        for (;;) {  // the rest as one concatenated stream, 64 edges per step
-          const int len = (act[q] && !found) ? eq - cq : 0;
+        pull_found(a, found, v[q], par, end[q] - cur[q], fc, fd, fl);
+        rest[q] = __ballot(act[q] && !found && end[q] - cur[q] > 2);
+        nrest += __popcll(rest[q]);
+      }
+      // the unsettled rows of all batches, compacted 64 at a time, stream
+      // their remaining edges as one concatenated list with early exit
+      for (int sb = 0; sb < nrest; sb += 64) {
+        const int j = sb + ln;  // this lane's place among the unsettled rows
+        int64_t rv = -1;
+        int rc = 0, re = 0;
+        int before = 0;
+#pragma unroll
+        for (int q = 0; q < kPullRows; ++q) {
+          const int cq = __popcll(rest[q]);
+          const int li = (j >= before && j < before + cq) ? nth_set_bit(rest[q], j - before) : 0;
+          const int64_t sv = __shfl(v[q], li);
+          const int sc = __shfl(cur[q], li), se_ = __shfl(end[q], li);
+          if (j >= before && j < before + cq) {
+            rv = sv;
+            rc = sc + 2;
+            re = se_;
+          }
+          before += cq;
+        }
+        const bool act2 = rv >= 0;
+        const int deg2 = re - (rc - 2);
+        bool found = false;
+        int par = -1;
+        for (;;) {
+          const int len = (act2 && !found) ? re - rc : 0;
           const int incl2 = wave_incl_scan(len);
           const int tot2 = __shfl(incl2, 63);
           if (tot2 == 0) break;
           const int excl = incl2 - len;
           const bool starts = len > 0 && excl < 64;
           const int r = slot_rows(mark, starts, excl);
-          const int rcur = __shfl(cq, r), rexcl = __shfl(excl, r);
+          const int rcur = __shfl(rc, r), rexcl = __shfl(excl, r);
           const bool valid = ln < tot2;
           const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
           const uint64_t hm = __ballot(valid && bit_of(a.fcur, c));
@@ -287,22 +341,9 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
             found = true;
             par = pc;
           }
-          if (starts) cq += se - excl;
+          if (starts) rc += se - excl;
         }
-        // rows of one bitmap word sit in consecutive lanes: one atomicOr per
-        // word and bitmap
-        const int64_t vw = found ? (v[q] >> 6) : -1;
-        const uint64_t hb = run_head_or(vw, found ? (1ull << (v[q] & 63)) : 0ull);
-        if (hb && vw >= 0) {
-          atomicOr((unsigned long long *)&a.visited[vw], (unsigned long long)hb);
-          atomicOr((unsigned long long *)&a.fnxt[vw], (unsigned long long)hb);
-        }
-        if (found) {
-          a.levels[v[q]] = a.d + 1;
-          if (a.parents) a.parents[v[q]] = par;
-          fc += 1;
-          fd += a.same_csr ? deg0 : a.push.rp[v[q] + 1] - a.push.rp[v[q]];
-        }
+        pull_found(a, found, rv, par, deg2, fc, fd, fl);
       }
     }
   }
@@ -312,99 +353,131 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
   // have a smaller id.  kUnroll x 64 edges are loaded at once and searched
   // for the first frontier neighbour in order; the parent is the minimum
   // over the pieces.
-  for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
-    const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
-    const int lr = a.levels[r];
-    if (lr >= 0 && lr <= a.d) continue;
-    const int e = min(b + kHeavyChunk, rp[r + 1]);
-    for (int base = b; base < e; base += 64 * kUnroll) {
-      int c[kUnroll];
+  // Wave gw owns pieces gw, gw + nwaves, ...: 64 of them are tested at once
+  // (one per lane), then the wave streams the live ones.
+  for (int64_t hb = gw; hb < a.pull.nheavy; hb += 64 * nwaves) {
+    const int64_t hh = hb + (int64_t)ln * nwaves;
+    int hr = -1, hbeg = 0, hend = 0;
+    if (hh < a.pull.nheavy) {
+      hr = a.pull.heavy[2 * hh];
+      hbeg = a.pull.heavy[2 * hh + 1];
+      const int lr = a.levels[hr];
+      if (lr >= 0 && lr <= a.d) hr = -1;
+      else hend = min(hbeg + kHeavyChunk, rp[hr + 1]);
+    }
+    uint64_t live = __ballot(hr >= 0);
+    while (live) {
+      const int k = __ffsll((unsigned long long)live) - 1;
+      live &= live - 1;
+      const int r = __shfl(hr, k), b = __shfl(hbeg, k), e = __shfl(hend, k);
+      for (int base = b; base < e; base += 64 * kUnroll) {
+        int c[kUnroll];
 #pragma unroll
-      for (int s = 0; s < kUnroll; ++s) {
-        const int pos = base + s * 64 + ln;
-        c[s] = pos < e ? ci[pos] : -1;
-      }
-      uint64_t fwd[kUnroll];
-#pragma unroll
-      for (int s = 0; s < kUnroll; ++s) fwd[s] = c[s] >= 0 ? a.fcur[c[s] >> 6] : 0ull;
-      int pc = -1;
-#pragma unroll
-      for (int s = kUnroll - 1; s >= 0; --s) {
-        const uint64_t hm = __ballot(c[s] >= 0 && ((fwd[s] >> (c[s] & 63)) & 1ull));
-        if (hm) pc = __shfl(c[s], __ffsll((unsigned long long)hm) - 1);
-      }
-      if (pc >= 0) {
-        if (ln == 0) {
-          const uint64_t bit = 1ull << (r & 63);
-          const uint64_t old =
-              atomicOr((unsigned long long *)&a.visited[r >> 6], (unsigned long long)bit);
-          if (a.parents) atomicMin((unsigned *)&a.parents[r], (unsigned)pc);
-          if (!(old & bit)) {
-            a.levels[r] = a.d + 1;
-            atomicOr((unsigned long long *)&a.fnxt[r >> 6], (unsigned long long)bit);
-            fc += 1;
-            fd += a.push.rp[r + 1] - a.push.rp[r];
-          }
+        for (int s = 0; s < kUnroll; ++s) {
+          const int pos = base + s * 64 + ln;
+          c[s] = pos < e ? ci[pos] : -1;
         }
-        break;
+        uint64_t fwd[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) fwd[s] = c[s] >= 0 ? a.fcur[c[s] >> 6] : 0ull;
+        int pc = -1;
+#pragma unroll
+        for (int s = kUnroll - 1; s >= 0; --s) {
+          const uint64_t hm = __ballot(c[s] >= 0 && ((fwd[s] >> (c[s] & 63)) & 1ull));
+          if (hm) pc = __shfl(c[s], __ffsll((unsigned long long)hm) - 1);
+        }
+        if (pc >= 0) {
+          if (ln == 0) {
+            const uint64_t bit = 1ull << (r & 63);
+            const uint64_t old =
+                atomicOr((unsigned long long *)&a.visited[r >> 6], (unsigned long long)bit);
+            if (a.parents) atomicMin((unsigned *)&a.parents[r], (unsigned)pc);
+            if (!(old & bit)) {
+              a.levels[r] = a.d + 1;
+              atomicOr((unsigned long long *)&a.fnxt[r >> 6], (unsigned long long)bit);
+              const int pd = a.push.rp[r + 1] - a.push.rp[r];
+              fc += 1;
+              fd += pd;
+              fl += pd > kPushSplit ? 1 : 0;
+            }
+          }
+          break;
+        }
       }
     }
   }
 }
 
 // Smallest-id parent of every vertex reached by a push: the first
-// in-neighbour (ascending) whose level is one less.  A wave takes one bitmap
-// word of vertices at a time; the first two in-neighbours of every row are
-// tested in parallel, the rest streamed as one concatenated list.
+// in-neighbour (ascending) whose level is one less.  A wave compacts the
+// vertices that need a parent in 8 words of its run into a queue, 64 at a
+// time; the first two in-neighbours of every queued row are tested in
+// parallel, the rest streamed as one concatenated list.
 __device__ __forceinline__ void parents_pass(const BfsArgs &a, int *mark) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    const int64_t v = w * 64 + ln;
-    int lv = -1;
-    bool need = false;
-    if (v < a.n) {
-      lv = a.levels[v];
-      need = lv > 0 && a.parents[v] < 0;
+  int64_t lo, hi;
+  wave_words(a.nw, gw, nwaves, lo, hi);
+  for (int64_t w0 = lo; w0 < hi; w0 += 8) {
+    // the vertices of 8 words that still need a parent: reached (level > 0)
+    // and without one; all 16 loads per lane are issued together
+    uint64_t nm[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t v = (w0 + k) * 64 + ln;
+      const bool inb = w0 + k < hi && v < a.n;
+      const int lv = inb ? a.levels[v] : -1;
+      const int pv = inb ? a.parents[v] : 0;
+      nm[k] = __ballot(lv > 0 && pv < 0);
     }
-    if (__ballot(need) == 0ull) continue;
-    int cur = need ? rp[v] : 0;
-    const int end = need ? rp[v + 1] : 0;
-    const int tgt = lv - 1;
-    bool found = false;
-    int par = -1;
-    if (need) {
-      const int c0 = cur < end ? ci[cur] : -1;
-      const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
-      const int l0 = c0 >= 0 ? a.levels[c0] : -2;
-      const int l1 = c1 >= 0 ? a.levels[c1] : -2;
-      if (l0 == tgt) { found = true; par = c0; }
-      else if (l1 == tgt) { found = true; par = c1; }
-      cur = min(cur + 2, end);
+    uint64_t mq = 0ull;  // lane k < 8 holds word w0 + k's mask
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (ln == k) mq = nm[k];
+    const int cnt = __popcll(mq);
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, 63);
+    for (int b = 0; b < total; b += 64) {
+      const int64_t v = queue_slot(mark, mq, cnt, incl, total, b, w0 + ln);
+      const bool need = v >= 0;
+      int cur = need ? rp[v] : 0;
+      const int end = need ? rp[v + 1] : 0;
+      const int tgt = need ? a.levels[v] - 1 : -3;
+      bool found = false;
+      int par = -1;
+      if (need) {
+        const int c0 = cur < end ? ci[cur] : -1;
+        const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
+        const int l0 = c0 >= 0 ? a.levels[c0] : -2;
+        const int l1 = c1 >= 0 ? a.levels[c1] : -2;
+        if (l0 == tgt) { found = true; par = c0; }
+        else if (l1 == tgt) { found = true; par = c1; }
+        cur = min(cur + 2, end);
+      }
+      for (;;) {
+        const int len = (need && !found) ? end - cur : 0;
+        const int incl2 = wave_incl_scan(len);
+        const int tot2 = __shfl(incl2, 63);
+        if (tot2 == 0) break;
+        const int excl = incl2 - len;
+        const bool starts = len > 0 && excl < 64;
+        const int r = slot_rows(mark, starts, excl);
+        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r), rt = __shfl(tgt, r);
+        const bool valid = ln < tot2;
+        const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
+        const uint64_t hm = __ballot(valid && a.levels[c] == rt);
+        const int se = min(incl2, 64);
+        const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
+        const uint64_t h = hm & seg;
+        const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
+        const int pc = __shfl(c, fl);
+        if (h) { found = true; par = pc; }
+        if (starts) cur += se - excl;
+      }
+      if (found) a.parents[v] = par;
     }
-    for (;;) {
-      const int len = (need && !found) ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r), rt = __shfl(tgt, r);
-      const bool valid = ln < total;
-      const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
-      const uint64_t hm = __ballot(valid && a.levels[c] == rt);
-      const int se = min(incl, 64);
-      const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
-      const uint64_t h = hm & seg;
-      const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
-      const int pc = __shfl(c, fl);
-      if (h) { found = true; par = pc; }
-      if (starts) cur += se - excl;
-    }
-    if (found) a.parents[v] = par;
   }
 }
 
@@ -415,16 +488,18 @@ __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
-  __shared__ int s_count, s_sumdeg;
-  __shared__ int s_red[kWavesPerBlock][2];
+  __shared__ int s_count, s_sumdeg, s_long;
+  __shared__ int s_red[kWavesPerBlock][kCntFields];
   if (threadIdx.x == 0) {
-    int c = 0, sd = 0;
+    int c = 0, sd = 0, lr = 0;
     for (int t = 0; t < kCntStripes; ++t) {
-      c += a.cnt_cur[2 * t];
-      sd += a.cnt_cur[2 * t + 1];
+      c += a.cnt_cur[kCntFields * t];
+      sd += a.cnt_cur[kCntFields * t + 1];
+      lr += a.cnt_cur[kCntFields * t + 2];
     }
     s_count = c;
     s_sumdeg = sd;
+    s_long = lr;
     if (blockIdx.x == 0) {
       // the buffer two levels ahead is cleared even when this level is
       // empty: it still holds the counts of the previous level
@@ -448,26 +523,30 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
     return;
   }
   const int dir = decide(a, count, s_sumdeg);
-  int fc = 0, fd = 0;
-  if (dir == GRB_DIR_PUSH) bfs_push(a, s_mark[threadIdx.x >> 6], fc, fd);
-  else bfs_pull(a, s_mark[threadIdx.x >> 6], fc, fd);
+  int fc = 0, fd = 0, fl = 0;
+  if (dir == GRB_DIR_PUSH) bfs_push(a, s_mark[threadIdx.x >> 6], s_long > 0, fc, fd, fl);
+  else bfs_pull(a, s_mark[threadIdx.x >> 6], fc, fd, fl);
   fc = wave_sum(fc);
   fd = wave_sum(fd);
+  fl = wave_sum(fl);
   if ((threadIdx.x & 63) == 0) {
     s_red[threadIdx.x >> 6][0] = fc;
     s_red[threadIdx.x >> 6][1] = fd;
+    s_red[threadIdx.x >> 6][2] = fl;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int c = 0, sd = 0;
+    int c = 0, sd = 0, lr = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) {
       c += s_red[i][0];
       sd += s_red[i][1];
+      lr += s_red[i][2];
     }
     if (c) {
       const int t = blockIdx.x % kCntStripes;
-      atomicAdd(&a.cnt_nxt[2 * t], c);
-      atomicAdd(&a.cnt_nxt[2 * t + 1], sd);
+      atomicAdd(&a.cnt_nxt[kCntFields * t], c);
+      atomicAdd(&a.cnt_nxt[kCntFields * t + 1], sd);
+      if (lr) atomicAdd(&a.cnt_nxt[kCntFields * t + 2], lr);
     }
   }
 }
@@ -501,8 +580,10 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
       a.cnt_clr[i] = 0;
     }
     a.ctrl->nlev = 0;
+    const int ds = a.push.rp[source + 1] - a.push.rp[source];
     a.cnt_cur[0] = 1;  // level 0 = {source}
-    a.cnt_cur[1] = a.push.rp[source + 1] - a.push.rp[source];
+    a.cnt_cur[1] = ds;
+    a.cnt_cur[2] = ds > kPushSplit ? 1 : 0;
   }
 }
 

@@ -19,7 +19,7 @@ constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
 constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand kernels
 constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
 constexpr int kUnroll = 4;         // 64-edge steps whose loads are issued together
-constexpr int kPullRows = 2;       // BFS pull: rows per lane whose first loads overlap
+constexpr int kPullRows = 4;       // BFS pull: rows per lane whose first loads overlap
 constexpr int kCntStripes = 32;      // BFS: striped frontier counters (count, degree sum)
 constexpr int kStatsCap = GRB_STATS_MAX;
 
@@ -75,7 +75,7 @@ struct Ctrl {
   int32_t converged;
   double D;         // PageRank: dangling mass of the current iterate
   double delta;     // PageRank: L1 change of the last iteration
-  int32_t lists[3 * 2 * 32];  // BFS: striped counters of the three frontier buffers
+  int32_t lists[3 * 3 * 32];  // BFS / SSSP: striped counters of the three frontier buffers
   int64_t pad[4];
 };
 
@@ -106,7 +106,9 @@ void launch_compact(const CompactArgs &a, void *stream);
 
 // BFS with one kernel per level (grb_bfs.hip).  Each of the three rotating
 // frontier buffers has kCntStripes (count, degree sum) counter pairs.
-constexpr int kCntSlots = 2 * kCntStripes;
+// per stripe: frontier size, its degree sum, its rows longer than kPushSplit
+constexpr int kCntFields = 3;
+constexpr int kCntSlots = kCntFields * kCntStripes;
 struct BfsArgs {
   int64_t n = 0, nw = 0, nnz = 0;
   Csr push;   // out-edges (CSR of A)

@@ -34,20 +34,24 @@ __device__ __forceinline__ int decide(const SsspArgs &a, int count, int sumdeg) 
 }
 
 // Marks v improved for the next round; the first marker counts it.
-__device__ __forceinline__ void mark_improved(const SsspArgs &a, int v, int &fc, int &fd) {
+__device__ __forceinline__ void mark_improved(const SsspArgs &a, int v, int &fc, int &fd,
+                                              int &fl) {
   const uint64_t b = 1ull << (v & 63);
   if (a.fnxt[v >> 6] & b) return;
   const uint64_t old = atomicOr((unsigned long long *)&a.fnxt[v >> 6], (unsigned long long)b);
   if (old & b) return;
+  const int pd = a.push.rp[v + 1] - a.push.rp[v];
   fc += 1;
-  fd += a.push.rp[v + 1] - a.push.rp[v];
+  fd += pd;
+  fl += pd > kPushSplit ? 1 : 0;
 }
 
 // Relaxes dist[c[s]] with nd[s] for s < kUnroll (c < 0: none).  The
 // current distances are read first, all at once (a plain read is only a
 // filter, the atomic decides).
 __device__ __forceinline__ void relax_batch(const SsspArgs &a, const int (&c)[kUnroll],
-                                            const float (&nd)[kUnroll], int &fc, int &fd) {
+                                            const float (&nd)[kUnroll], int &fc, int &fd,
+                                            int &fl) {
   float cd[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) cd[s] = c[s] >= 0 ? a.dist[c[s]] : 0.0f;
@@ -57,7 +61,7 @@ __device__ __forceinline__ void relax_batch(const SsspArgs &a, const int (&c)[kU
       const int old = atomicMin((int *)&a.dist[c[s]], __float_as_int(nd[s]));
       if (nd[s] < __int_as_float(old)) {
         atomicMin((int *)&a.fd_nxt[c[s]], __float_as_int(nd[s]));
-        mark_improved(a, c[s], fc, fd);
+        mark_improved(a, c[s], fc, fd, fl);
       }
     }
   }
@@ -92,7 +96,8 @@ __device__ __forceinline__ void clear_behind(const SsspArgs &a, int64_t mw, bool
   }
 }
 
-__device__ void sssp_push(const SsspArgs &a, int *mark, int &fc, int &fd) {
+__device__ void sssp_push(const SsspArgs &a, int *mark, bool long_rows, int &fc, int &fd,
+                          int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -150,12 +155,13 @@ __device__ void sssp_push(const SsspArgs &a, int *mark, int &fc, int &fd) {
             nd[s] += a.wpush[pos];
           }
         }
-        relax_batch(a, cc, nd, fc, fd);
+        relax_batch(a, cc, nd, fc, fd, fl);
       }
     }
   }
   // static pieces of long rows, spread over the waves, 64 tested per step
   static_assert(kPushSplit == 64 * kUnroll, "a piece is one unrolled step");
+  if (!long_rows) return;  // no row of the frontier has pieces
   for (int64_t hb = gw; hb < a.push.nsplit; hb += 64 * nwaves) {
     const int64_t h = hb + (int64_t)ln * nwaves;
     int u = -1, b = 0, e = 0;
@@ -184,12 +190,12 @@ __device__ void sssp_push(const SsspArgs &a, int *mark, int &fc, int &fd) {
         cc[s] = pos < pe ? ci[pos] : -1;
         nd[s] = pos < pe ? pdu + a.wpush[pos] : 0.0f;
       }
-      relax_batch(a, cc, nd, fc, fd);
+      relax_batch(a, cc, nd, fc, fd, fl);
     }
   }
 }
 
-__device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd) {
+__device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -273,8 +279,10 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd) {
         a.dist[v] = best;
         a.fd_nxt[v] = best;
         improved = true;
+        const int pd = a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
         fc += 1;
-        fd += a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
+        fd += pd;
+        fl += pd > kPushSplit ? 1 : 0;
       }
       const uint64_t ib = __ballot(improved);
       if (ib && ln == 0) atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)ib);
@@ -336,7 +344,7 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd) {
         const int old = atomicMin((int *)&a.dist[myr], __float_as_int(myb));
         if (myb < __int_as_float(old)) {
           atomicMin((int *)&a.fd_nxt[myr], __float_as_int(myb));
-          mark_improved(a, myr, fc, fd);
+          mark_improved(a, myr, fc, fd, fl);
         }
       }
     }
@@ -345,16 +353,18 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd) {
 
 __global__ __launch_bounds__(kBlock) void k_sssp_round(SsspArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
-  __shared__ int s_count, s_sumdeg;
-  __shared__ int s_red[kWavesPerBlock][2];
+  __shared__ int s_count, s_sumdeg, s_long;
+  __shared__ int s_red[kWavesPerBlock][kCntFields];
   if (threadIdx.x == 0) {
-    int c = 0, sd = 0;
+    int c = 0, sd = 0, lr = 0;
     for (int t = 0; t < kCntStripes; ++t) {
-      c += a.cnt_cur[2 * t];
-      sd += a.cnt_cur[2 * t + 1];
+      c += a.cnt_cur[kCntFields * t];
+      sd += a.cnt_cur[kCntFields * t + 1];
+      lr += a.cnt_cur[kCntFields * t + 2];
     }
     s_count = c;
     s_sumdeg = sd;
+    s_long = lr;
     if (blockIdx.x == 0) {
       for (int i = 0; i < kCntSlots; ++i) a.cnt_clr[i] = 0;
       if (c > 0) {
@@ -370,26 +380,30 @@ __global__ __launch_bounds__(kBlock) void k_sssp_round(SsspArgs a) {
   __syncthreads();
   if (s_count == 0) return;
   const int dir = decide(a, s_count, s_sumdeg);
-  int fc = 0, fd = 0;
-  if (dir == GRB_DIR_PUSH) sssp_push(a, s_mark[threadIdx.x >> 6], fc, fd);
-  else sssp_pull(a, s_mark[threadIdx.x >> 6], fc, fd);
+  int fc = 0, fd = 0, fl = 0;
+  if (dir == GRB_DIR_PUSH) sssp_push(a, s_mark[threadIdx.x >> 6], s_long > 0, fc, fd, fl);
+  else sssp_pull(a, s_mark[threadIdx.x >> 6], fc, fd, fl);
   fc = wave_sum(fc);
   fd = wave_sum(fd);
+  fl = wave_sum(fl);
   if ((threadIdx.x & 63) == 0) {
     s_red[threadIdx.x >> 6][0] = fc;
     s_red[threadIdx.x >> 6][1] = fd;
+    s_red[threadIdx.x >> 6][2] = fl;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int c = 0, sd = 0;
+    int c = 0, sd = 0, lr = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) {
       c += s_red[i][0];
       sd += s_red[i][1];
+      lr += s_red[i][2];
     }
     if (c) {
       const int t = blockIdx.x % kCntStripes;
-      atomicAdd(&a.cnt_nxt[2 * t], c);
-      atomicAdd(&a.cnt_nxt[2 * t + 1], sd);
+      atomicAdd(&a.cnt_nxt[kCntFields * t], c);
+      atomicAdd(&a.cnt_nxt[kCntFields * t + 1], sd);
+      if (lr) atomicAdd(&a.cnt_nxt[kCntFields * t + 2], lr);
     }
   }
 }
@@ -425,8 +439,10 @@ __global__ __launch_bounds__(kBlock) void k_sssp_start(SsspArgs a, int32_t sourc
       a.cnt_clr[i] = 0;
     }
     a.ctrl->nlev = 0;
+    const int ds = a.push.rp[source + 1] - a.push.rp[source];
     a.cnt_cur[0] = 1;
-    a.cnt_cur[1] = a.push.rp[source + 1] - a.push.rp[source];
+    a.cnt_cur[1] = ds;
+    a.cnt_cur[2] = ds > kPushSplit ? 1 : 0;
   }
 }
 
