@@ -128,19 +128,20 @@ struct PrWs {
   Ctrl *ctrl;
   void *x0, *x1, *heavy_part;
   double *blk_part;
-  int nblk;
+  int nblk, nblk_long;
   size_t bytes;
 };
 
 PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
   Carver c(ws);
   PrWs t{};
-  t.nblk = pr_grid(words_of(n));
+  t.nblk = kExpandGrid;
+  t.nblk_long = pr_long_grid(pull.nsplit_rows);
   t.ctrl = c.take<Ctrl>(1);
   t.x0 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
   t.x1 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
   t.heavy_part = c.take<char>((size_t)std::max<int64_t>(pull.nsplit, 1) * esize);
-  t.blk_part = c.take<double>((size_t)2 * t.nblk);
+  t.blk_part = c.take<double>((size_t)2 * (t.nblk + t.nblk_long));
   t.bytes = c.off;
   return t;
 }
@@ -186,7 +187,7 @@ grb_info check_ws(void *ws, size_t have, size_t need) {
 
 // ---- matrix metadata ---------------------------------------------------------
 struct MetaLayout {
-  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, bytes;
+  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, wpart_off, bytes;
   int64_t max_pieces, max_rows, max_split, max_split_rows;
 };
 
@@ -200,7 +201,8 @@ MetaLayout meta_layout_one(int64_t nnz, size_t base) {
   m.split_off = align_up(m.heavy_rows_off + (size_t)m.max_rows * 3 * sizeof(int32_t));
   m.max_split_rows = nnz / (kPushSplit + 1) + 1;
   m.split_rows_off = align_up(m.split_off + (size_t)m.max_split * 2 * sizeof(int32_t));
-  m.bytes = align_up(m.split_rows_off + (size_t)m.max_split_rows * 3 * sizeof(int32_t));
+  m.wpart_off = align_up(m.split_rows_off + (size_t)m.max_split_rows * 3 * sizeof(int32_t));
+  m.bytes = align_up(m.wpart_off + (size_t)(kWaveParts + 1) * sizeof(int32_t));
   return m;
 }
 
@@ -247,6 +249,32 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
     return GRB_PANIC;
   int32_t *hp = (int32_t *)(meta + L.heavy_off);
   int32_t *hr = (int32_t *)(meta + L.heavy_rows_off);
+  // word runs of about equal work for the full sweeps
+  const int64_t nw = words_of(c.nrows);
+  std::vector<int64_t> wcost((size_t)nw + 1, 0);
+  for (int64_t w = 0; w < nw; ++w) {
+    int64_t e = 256;  // fixed cost of a word: about one step of the stream
+    const int64_t r1 = std::min<int64_t>(c.nrows, (w + 1) * 64);
+    for (int64_t r = w * 64; r < r1; ++r) {
+      const int64_t d = rp[(size_t)r + 1] - rp[(size_t)r];
+      if (d <= kPushSplit) e += d;
+    }
+    wcost[(size_t)w + 1] = wcost[(size_t)w] + e;
+  }
+  std::vector<int32_t> wpart((size_t)kWaveParts + 1);
+  {
+    const int64_t tot = wcost[(size_t)nw];
+    int64_t w = 0;
+    for (int64_t p = 0; p <= kWaveParts; ++p) {
+      const int64_t goal = (int64_t)((__int128)tot * p / kWaveParts);
+      while (w < nw && wcost[(size_t)w] < goal) ++w;
+      wpart[(size_t)p] = (int32_t)w;
+    }
+    wpart[(size_t)kWaveParts] = (int32_t)nw;
+  }
+  int32_t *wp = (int32_t *)(meta + L.wpart_off);
+  if (hipMemcpyAsync(wp, wpart.data(), wpart.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
   int32_t *sp = (int32_t *)(meta + L.split_off);
   int32_t *sr = (int32_t *)(meta + L.split_rows_off);
   if (!split_rows.empty() && hipMemcpyAsync(sr, split_rows.data(), split_rows.size() * 4,
@@ -270,6 +298,7 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
   c.nsplit = (int64_t)split.size() / 2;
   c.split_rows = sr;
   c.nsplit_rows = (int64_t)split_rows.size() / 3;
+  c.wpart = wp;
   return GRB_SUCCESS;
 }
 
@@ -751,6 +780,7 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
       if (k != 1 && k != 2) return GRB_INVALID_VALUE;
       Csr pull = A->at;
       pull.nsplit = split_bound(A->nnz);
+      pull.nsplit_rows = A->nnz / (kPushSplit + 1) + 1;
       *bytes = pr_layout(nullptr, A->nrows, pull, k == 2 ? 8 : 4).bytes;
       break;
     }
@@ -927,6 +957,7 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int3
   pa.heavy_part = w.heavy_part;
   pa.blk_part = w.blk_part;
   pa.nblk = w.nblk;
+  pa.nblk_long = w.nblk_long;
   pa.ctrl = w.ctrl;
   pa.alpha = damping;
   pa.tol = tol;

@@ -89,7 +89,8 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
 
 // Claims the targets of one piece of a row: ascending and distinct, so the
 // lanes whose targets share a visited word sit side by side and one atomicOr
-// per word serves them all.
+// per word serves them all (issued by the run's last lane, whose previous
+// value of the word every lane of the run then reads).
 __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
                                             int &fd, int &fl) {
   uint64_t vw[kUnroll];
@@ -97,11 +98,12 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
   for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
   bool want[kUnroll];
   uint64_t old[kUnroll];
+  int tail[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     want[s] = c[s] >= 0 && !((vw[s] >> (c[s] & 63)) & 1ull);
     const int64_t wd = want[s] ? (int64_t)(c[s] >> 6) : -1;
-    const uint64_t run = run_head_or(wd, want[s] ? (1ull << (c[s] & 63)) : 0ull);
+    const uint64_t run = run_tail_or(wd, want[s] ? (1ull << (c[s] & 63)) : 0ull, tail[s]);
     old[s] = 0ull;
     if (run && wd >= 0)
       old[s] = atomicOr((unsigned long long *)&a.visited[wd], (unsigned long long)run);
@@ -109,13 +111,7 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
   bool won[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
-    // the run's head holds the word's previous value; hand it to the run
-    const int64_t wd = want[s] ? (int64_t)(c[s] >> 6) : -1;
-    const int64_t prev = __shfl_up(wd, 1);
-    const int ln = threadIdx.x & 63;
-    const bool head = ln == 0 || prev != wd;
-    const int rid = wave_max_scan(head ? ln : -1);
-    const uint64_t ow = __shfl(old[s], rid);
+    const uint64_t ow = __shfl(old[s], tail[s]);
     won[s] = want[s] && !((ow >> (c[s] & 63)) & 1ull);
   }
   claim_won(a, c, won, fc, fd, fl);
@@ -144,7 +140,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
     }
     const int cnt = __popcll(mf);
     const int incl = wave_incl_scan(cnt);
-    const int total = __shfl(incl, 63);
+    const int total = lane_last(incl);
     for (int b = 0; b < total; b += 64) {
       const int64_t u = queue_slot(mark, mf, cnt, incl, total, b, mw);
       int cur = 0, end = 0;
@@ -163,7 +159,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
           if (!more) continue;
           const int len = end - cur;
           const int incl2 = wave_incl_scan(len);
-          const int tot2 = __shfl(incl2, 63);
+          const int tot2 = lane_last(incl2);
           if (tot2 == 0) {
             more = false;
             continue;
@@ -216,7 +212,8 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
 __device__ __forceinline__ void pull_found(const BfsArgs &a, bool found, int64_t v, int par,
                                            int deg, int &fc, int &fd, int &fl) {
   const int64_t vw = found ? (v >> 6) : -1;
-  const uint64_t hb = run_head_or(vw, found ? (1ull << (v & 63)) : 0ull);
+  int tail;
+  const uint64_t hb = run_tail_or(vw, found ? (1ull << (v & 63)) : 0ull, tail);
   if (hb && vw >= 0) {
     atomicOr((unsigned long long *)&a.visited[vw], (unsigned long long)hb);
     atomicOr((unsigned long long *)&a.fnxt[vw], (unsigned long long)hb);
@@ -247,7 +244,7 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
     }
     const int cnt = __popcll(mc);
     const int incl = wave_incl_scan(cnt);
-    const int total = __shfl(incl, 63);
+    const int total = lane_last(incl);
     // kPullRows queued rows per lane: the loads of their first two
     // neighbours are issued together
     for (int b = 0; b < total; b += 64 * kPullRows) {
@@ -323,7 +320,7 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
         for (;;) {
           const int len = (act2 && !found) ? re - rc : 0;
           const int incl2 = wave_incl_scan(len);
-          const int tot2 = __shfl(incl2, 63);
+          const int tot2 = lane_last(incl2);
           if (tot2 == 0) break;
           const int excl = incl2 - len;
           const bool starts = len > 0 && excl < 64;
@@ -438,7 +435,7 @@ __device__ __forceinline__ void parents_pass(const BfsArgs &a, int *mark) {
       if (ln == k) mq = nm[k];
     const int cnt = __popcll(mq);
     const int incl = wave_incl_scan(cnt);
-    const int total = __shfl(incl, 63);
+    const int total = lane_last(incl);
     for (int b = 0; b < total; b += 64) {
       const int64_t v = queue_slot(mark, mq, cnt, incl, total, b, w0 + ln);
       const bool need = v >= 0;
@@ -459,7 +456,7 @@ __device__ __forceinline__ void parents_pass(const BfsArgs &a, int *mark) {
       for (;;) {
         const int len = (need && !found) ? end - cur : 0;
         const int incl2 = wave_incl_scan(len);
-        const int tot2 = __shfl(incl2, 63);
+        const int tot2 = lane_last(incl2);
         if (tot2 == 0) break;
         const int excl = incl2 - len;
         const bool starts = len > 0 && excl < 64;

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 
 namespace grb {
@@ -17,25 +18,103 @@ __device__ __forceinline__ bool bit_of(const uint64_t *bm, int64_t v) {
   return (bm[v >> 6] >> (v & 63)) & 1ull;
 }
 
-__device__ __forceinline__ int wave_incl_scan(int x) {
-  const int ln = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off);
-    if (ln >= off) x += y;
-  }
+// ---- lane movement with DPP ---------------------------------------------
+// Inclusive scans run Hillis-Steele over the wave with DPP moves instead of
+// LDS shuffles: row_shr:1,2,4,8 within each row of 16 lanes, then
+// row_bcast:15 (lane 15 of a row into the next row, rows 1 and 3) and
+// row_bcast:31 (lane 31 into rows 2 and 3).  A lane whose source is outside
+// its row, or whose row is masked off, receives `old` (the operation's
+// identity).  All 64 lanes must be active.
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1
+constexpr int kDppWaveShr1 = 0x138;  // lane i receives lane i - 1
+
+template <int C, int R>
+__device__ __forceinline__ int dpp_move(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, C, R, 0xf, false);
+}
+template <int C, int R>
+__device__ __forceinline__ float dpp_move(float old, float v) {
+  return __int_as_float(dpp_move<C, R>(__float_as_int(old), __float_as_int(v)));
+}
+template <int C, int R>
+__device__ __forceinline__ uint64_t dpp_move(uint64_t old, uint64_t v) {
+  const int lo = dpp_move<C, R>((int)(uint32_t)old, (int)(uint32_t)v);
+  const int hi = dpp_move<C, R>((int)(uint32_t)(old >> 32), (int)(uint32_t)(v >> 32));
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+template <int C, int R>
+__device__ __forceinline__ int64_t dpp_move(int64_t old, int64_t v) {
+  return (int64_t)dpp_move<C, R>((uint64_t)old, (uint64_t)v);
+}
+template <int C, int R>
+__device__ __forceinline__ double dpp_move(double old, double v) {
+  return __longlong_as_double(
+      (long long)dpp_move<C, R>((uint64_t)__double_as_longlong(old), (uint64_t)__double_as_longlong(v)));
+}
+
+// inclusive scan of `op` (identity `id`) over the 64 lanes
+template <class T, class Op>
+__device__ __forceinline__ T wave_scan(T x, T id, Op op) {
+  x = op(x, dpp_move<kDppShr1, 0xf>(id, x));
+  x = op(x, dpp_move<kDppShr2, 0xf>(id, x));
+  x = op(x, dpp_move<kDppShr4, 0xf>(id, x));
+  x = op(x, dpp_move<kDppShr8, 0xf>(id, x));
+  x = op(x, dpp_move<kDppBcast15, 0xa>(id, x));
+  x = op(x, dpp_move<kDppBcast31, 0xc>(id, x));
   return x;
 }
 
-__device__ __forceinline__ int wave_max_scan(int x) {
-  const int ln = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off);
-    if (ln >= off) x = max(x, y);
+// inclusive scan restricted to runs of equal `seg` (runs must be contiguous
+// and seg >= 0)
+template <class T, class Op>
+__device__ __forceinline__ T wave_seg_scan(T x, int seg, T id, Op op) {
+#define GRB_SEG_STEP(C, R)                          \
+  {                                                 \
+    const T y = dpp_move<C, R>(id, x);              \
+    const int sy = dpp_move<C, R>(-1, seg);         \
+    if (sy == seg) x = op(x, y);                    \
   }
+  GRB_SEG_STEP(kDppShr1, 0xf)
+  GRB_SEG_STEP(kDppShr2, 0xf)
+  GRB_SEG_STEP(kDppShr4, 0xf)
+  GRB_SEG_STEP(kDppShr8, 0xf)
+  GRB_SEG_STEP(kDppBcast15, 0xa)
+  GRB_SEG_STEP(kDppBcast31, 0xc)
+#undef GRB_SEG_STEP
   return x;
 }
+
+// value of lane 63 (uniform)
+__device__ __forceinline__ int lane_last(int x) { return __builtin_amdgcn_readlane(x, 63); }
+__device__ __forceinline__ float lane_last(float x) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+__device__ __forceinline__ double lane_last(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((unsigned long long)b >> 32), 63);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+struct OpAdd {
+  template <class T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+  __device__ __forceinline__ int operator()(int a, int b) const { return a > b ? a : b; }
+};
+struct OpMinF {
+  __device__ __forceinline__ float operator()(float a, float b) const { return fminf(a, b); }
+};
+struct OpOr {
+  __device__ __forceinline__ uint64_t operator()(uint64_t a, uint64_t b) const { return a | b; }
+};
+
+__device__ __forceinline__ int wave_incl_scan(int x) { return wave_scan(x, 0, OpAdd()); }
+
+__device__ __forceinline__ int wave_max_scan(int x) { return wave_scan(x, INT_MIN, OpMax()); }
 
 __device__ __forceinline__ int wave_sum(int x) {
 #pragma unroll
@@ -55,10 +134,9 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
   return x;
 }
 
+// minimum over the wave, returned to every lane
 __device__ __forceinline__ float wave_min(float x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off));
-  return x;
+  return lane_last(wave_scan(x, __int_as_float(0x7f800000), OpMinF()));
 }
 
 // Orders this wave's LDS traffic (lanes of one wave exchange data through LDS).
@@ -125,46 +203,31 @@ __device__ __forceinline__ int64_t queue_slot(int *mark, uint64_t m, int cnt, in
   return sl < total ? wk * 64 + nth_set_bit(mk, sl - ek) : -1;
 }
 
-// Lanes hold (word, bits) where lanes with equal words are contiguous.
-// Returns to the first lane of each run of equal words the OR of the run's
-// bits, to every other lane 0.
-__device__ __forceinline__ uint64_t run_head_or(int64_t word, uint64_t bits) {
+// Lanes hold (word, bits) where lanes with equal words are contiguous
+// (word < 0: no bits).  Returns to the last lane of each run of equal words
+// the OR of the run's bits (0 elsewhere) and sets `tail` to the index of the
+// last lane of this lane's run.
+__device__ __forceinline__ uint64_t run_tail_or(int64_t word, uint64_t bits, int &tail) {
   const int ln = threadIdx.x & 63;
-  const int64_t prev = __shfl_up(word, 1);
-  const bool head = ln == 0 || prev != word;
-  const int rid = wave_max_scan(head ? ln : -1);
-  uint64_t x = bits;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint64_t y = __shfl_down(x, off);
-    const int ry = __shfl_down(rid, off);
-    if (ln + off < 64 && ry == rid) x |= y;
-  }
-  return head ? x : 0ull;
+  const int64_t prev = dpp_move<kDppWaveShr1, 0xf>(word ^ 1, word);
+  const int64_t next = dpp_move<kDppWaveShl1, 0xf>(word ^ 1, word);
+  const bool head = prev != word;
+  const bool last = next != word;
+  const int rid = wave_max_scan(head ? ln : -1);  // first lane of the run
+  const uint64_t x = wave_seg_scan(bits, rid, (uint64_t)0, OpOr());
+  const uint64_t tails = __ballot(last);
+  tail = __ffsll((unsigned long long)(tails & ~mask_below(ln))) - 1;
+  return last ? x : 0ull;
 }
 
 // Inclusive min-scan over slots restricted to runs of equal row id.
 __device__ __forceinline__ float seg_min_scan(float x, int row) {
-  const int ln = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const float y = __shfl_up(x, off);
-    const int ry = __shfl_up(row, off);
-    if (ln >= off && ry == row) x = fminf(x, y);
-  }
-  return x;
+  return wave_seg_scan(x, row, __int_as_float(0x7f800000), OpMinF());
 }
 
 template <class T>
 __device__ __forceinline__ T seg_sum_scan(T x, int row) {
-  const int ln = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T y = __shfl_up(x, off);
-    const int ry = __shfl_up(row, off);
-    if (ln >= off && ry == row) x += y;
-  }
-  return x;
+  return wave_seg_scan(x, row, (T)0, OpAdd());
 }
 
 // Device-coherent atomic store / load of a 64-bit word.  Relaxed ordering:

@@ -18,6 +18,7 @@ constexpr int kHeavyDeg = 2048;      // rows longer than this are split for pull
 constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
 constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand kernels
 constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
+constexpr int kWaveParts = kExpandGrid * kWavesPerBlock;  // waves of a full-sweep kernel
 constexpr int kUnroll = 4;         // 64-edge steps whose loads are issued together
 constexpr int kPullRows = 4;       // BFS pull: rows per lane whose first loads overlap
 constexpr int kCntStripes = 32;      // BFS: striped frontier counters (count, degree sum)
@@ -41,6 +42,10 @@ struct Csr {
   int64_t nsplit = 0;
   const int32_t *split_rows = nullptr; // (row, first piece, piece count) triples
   int64_t nsplit_rows = 0;
+  // bitmap words cut into kWaveParts contiguous runs of about equal work
+  // (edges of rows up to kPushSplit long plus a fixed cost per word), for
+  // kernels that sweep every row: run p is words [wpart[p], wpart[p + 1])
+  const int32_t *wpart = nullptr;
   bool valid() const { return rp != nullptr; }
 };
 
@@ -161,12 +166,13 @@ struct PrArgs {
   void *xn = nullptr;          // next x
   void *heavy_part = nullptr;  // partial sums of the pieces of long rows
   double *blk_part = nullptr;  // per workgroup {delta, dangling} partials
-  int nblk = 0;
+  int nblk = 0;                // workgroups of the SpMV kernel (kExpandGrid)
+  int nblk_long = 0;           // workgroups of the long-row kernel
   Ctrl *ctrl = nullptr;
   double alpha = 0.85;
   double tol = 0.0;
 };
-int pr_grid(int64_t nw);
+int pr_long_grid(int64_t nsplit_rows);  // workgroups of the long-row kernel
 void launch_pr_init(int is_fp64, const PrArgs &a, void *stream);
 void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream);
 

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
     }
     const int cl = c[0] + c[1] + c[2] + c[3], dl = d[0] + d[1] + d[2] + d[3];
     const int ci = wave_incl_scan(cl), di = wave_incl_scan(dl);
-    const int ctot = __shfl(ci, 63), dtot = __shfl(di, 63);
+    const int ctot = lane_last(ci), dtot = lane_last(di);
     int ce = ci - cl, de = di - dl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

@@ -29,14 +29,7 @@ namespace grb {
 namespace {
 
 __device__ __forceinline__ uint64_t wave_seg_or(uint64_t x, int row) {
-  const int ln = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint64_t y = __shfl_up(x, off);
-    const int ry = __shfl_up(row, off);
-    if (ln >= off && ry == row) x |= y;
-  }
-  return x;
+  return wave_seg_scan(x, row, (uint64_t)0, OpOr());
 }
 
 // valid queries of word j (the last word may be partial)
@@ -118,7 +111,7 @@ __device__ void ms_pull(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t
         const bool live = need != 0ull && (acc & need) != need && cur < re;
         const int len = live ? re - cur : 0;
         const int incl = wave_incl_scan(len);
-        const int total = __shfl(incl, 63);
+        const int total = lane_last(incl);
         if (total == 0) break;
         const int excl = incl - len;
         const bool starts = len > 0 && excl < 64;
@@ -173,7 +166,7 @@ __device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t
       for (;;) {
         const int len = end - cur;
         const int incl = wave_incl_scan(len);
-        const int total = __shfl(incl, 63);
+        const int total = lane_last(incl);
         if (total == 0) break;
         const int excl = incl - len;
         const bool starts = len > 0 && excl < 64;

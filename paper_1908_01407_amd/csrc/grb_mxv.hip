@@ -55,6 +55,13 @@ struct SrMinSel {
 template <> struct Sr<GRB_MIN_FIRST_INT32> : SrMinSel {};
 template <> struct Sr<GRB_MIN_SECOND_INT32> : SrMinSel {};
 
+template <int SR> struct SrAdd {
+  __device__ __forceinline__ typename Sr<SR>::T operator()(typename Sr<SR>::T a,
+                                                           typename Sr<SR>::T b) const {
+    return Sr<SR>::add(a, b);
+  }
+};
+
 template <int SR>
 __device__ __forceinline__ typename Sr<SR>::T atomic_add_sr(typename Sr<SR>::T *p,
                                                             typename Sr<SR>::T v) {
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
       if constexpr (Sr<SR>::lor) live = live && acc == 0;  // OR saturates at true
       const int len = live ? end - cur : 0;
       const int incl = wave_incl_scan(len);
-      const int total = __shfl(incl, 63);
+      const int total = lane_last(incl);
       if (total == 0) break;
       const int excl = incl - len;
       const bool starts = len > 0 && excl < 64;
@@ -292,13 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
         if (pm & seg) has = true;
         if (tm & seg) acc = 1;
       } else {
-        T x = prod;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {  // segmented inclusive scan
-          const T y = __shfl_up(x, off);
-          const int ry = __shfl_up(r, off);
-          if (ln >= off && ry == r) x = Sr<SR>::add(x, y);
-        }
+        const T x = wave_seg_scan(prod, r, Sr<SR>::identity(), SrAdd<SR>());
         const T segv = __shfl(x, starts ? se - 1 : 0);
         if (pm & seg) {
           has = true;

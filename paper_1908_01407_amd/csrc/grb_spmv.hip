@@ -1,13 +1,14 @@
 // PageRank iteration kernels (Section 7.3 of the paper: pull form, SpMV
 // every iteration because the vector never gets sparse).
 //
-// Load balance: each wave takes one bitmap word of rows (64 consecutive
-// rows of the CSR of A^T) per step, words dealt out round-robin, and
+// Load balance: each wave takes a run of bitmap words of rows (64
+// consecutive rows of the CSR of A^T each), runs of about equal work built
+// by grb_matrix_prepare, one word per step, and
 // streams their in-edges as one concatenated list, kUnroll x 64 edges per
 // step, with a segmented sum per row (wave-level load-balanced search);
 // rows longer than kPushSplit are cut into fixed pieces that any wave
-// takes, and a single-workgroup fix-up kernel adds each long row's pieces
-// in order.  Summation order is fixed, so fp32 and fp64 results are bitwise
+// takes, and a second kernel (one thread per long row) adds each long
+// row's pieces in order.  Summation order is fixed, so fp32 and fp64 results are bitwise
 // reproducible run to run.  The dangling mass and the L1 change are reduced
 // per workgroup and then in a fixed order in the fix-up kernel, which also
 // decides convergence on the device.
@@ -82,10 +83,12 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   T *p = (T *)a.p;
   const T dn = (T)(a.ctrl->D / (double)a.n);
   double delta = 0, dang = 0;
-  // rows up to kPushSplit long: one word of rows per wave and step, words
-  // dealt out round-robin; kUnroll x 64 edges per step (slot positions
-  // first, then all gathers, then the segmented sums in slot order)
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
+  // rows up to kPushSplit long: the wave's run of words (about equal work
+  // per run), one word of rows per step; kUnroll x 64 edges per step (slot
+  // positions first, then all gathers, then the segmented sums in slot order)
+  const int64_t wlo = gw < kWaveParts ? a.pull.wpart[gw] : 0;
+  const int64_t whi = gw < kWaveParts ? a.pull.wpart[gw + 1] : 0;
+  for (int64_t w = wlo; w < whi; ++w) {
     const int64_t v = w * 64 + ln;
     const bool inb = v < a.n;
     int cur = 0, end = 0;
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
         if (!more) continue;
         const int len = end - cur;
         const int incl = wave_incl_scan(len);
-        const int total = __shfl(incl, 63);
+        const int total = lane_last(incl);
         if (total == 0) {
           more = false;
           continue;
@@ -184,44 +187,52 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       T sum = (val[q][0] + val[q][1]) + (val[q][2] + val[q][3]);
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      sum = lane_last(wave_scan(sum, (T)0, OpAdd()));  // fixed order
       if (ln == 0 && ph[q] < a.pull.nsplit) hp[ph[q]] = sum;
     }
   }
   block_partials<T>(delta, dang, a.blk_part);
 }
 
-// One workgroup: finishes long rows (their pieces added in order), reduces
-// the per-workgroup partials in a fixed order and updates the control block.
+// Long rows: one thread per row adds the row's pieces in order and updates
+// its rank; per-workgroup partials follow those of the SpMV kernel.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pr_long(PrArgs a) {
+  if (a.ctrl->converged) return;
+  const T dn = (T)(a.ctrl->D / (double)a.n);
+  const T *hp = (const T *)a.heavy_part;
+  T *p = (T *)a.p;
+  T *xn = (T *)a.xn;
+  double delta = 0, dang = 0;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < a.pull.nsplit_rows) {
+    const int r = a.pull.split_rows[3 * i], first = a.pull.split_rows[3 * i + 1],
+              cnt = a.pull.split_rows[3 * i + 2];
+    T acc = (T)0;
+    for (int k = 0; k < cnt; ++k) acc += hp[first + k];
+    const T pn = rank_update<T>(a, acc, dn);
+    delta = fabs((double)pn - (double)p[r]);
+    p[r] = pn;
+    const int od = a.out_rp[r + 1] - a.out_rp[r];
+    if (od == 0) {
+      xn[r] = (T)0;
+      dang = (double)pn;
+    } else {
+      xn[r] = pn / (T)od;
+    }
+  }
+  block_partials<T>(delta, dang, a.blk_part + 2 * a.nblk);
+}
+
+// One workgroup: reduces the per-workgroup partials in a fixed order and
+// updates the control block (dangling mass, L1 change, convergence).
 template <class T>
 __global__ __launch_bounds__(1024) void k_pr_fixup(PrArgs a, int init) {
   __shared__ double s_d[16], s_g[16];
   if (!init && a.ctrl->converged) return;
-  const T dn = (T)(a.ctrl->D / (double)a.n);
   double delta = 0, dang = 0;
-  if (!init) {
-    const T *hp = (const T *)a.heavy_part;
-    T *p = (T *)a.p;
-    T *xn = (T *)a.xn;
-    for (int64_t i = threadIdx.x; i < a.pull.nsplit_rows; i += 1024) {
-      const int r = a.pull.split_rows[3 * i], first = a.pull.split_rows[3 * i + 1],
-                cnt = a.pull.split_rows[3 * i + 2];
-      T acc = (T)0;
-      for (int k = 0; k < cnt; ++k) acc += hp[first + k];
-      const T pn = rank_update<T>(a, acc, dn);
-      delta += fabs((double)pn - (double)p[r]);
-      p[r] = pn;
-      const int od = a.out_rp[r + 1] - a.out_rp[r];
-      if (od == 0) {
-        xn[r] = (T)0;
-        dang += (double)pn;
-      } else {
-        xn[r] = pn / (T)od;
-      }
-    }
-  }
-  for (int i = threadIdx.x; i < a.nblk; i += 1024) {
+  const int nparts = init ? a.nblk : a.nblk + a.nblk_long;
+  for (int i = threadIdx.x; i < nparts; i += 1024) {
     delta += a.blk_part[2 * i];
     dang += a.blk_part[2 * i + 1];
   }
@@ -253,11 +264,8 @@ __global__ __launch_bounds__(1024) void k_pr_fixup(PrArgs a, int init) {
 
 }  // namespace
 
-int pr_grid(int64_t nw) {
-  int64_t g = (nw + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (g < 1) g = 1;
-  if (g > kExpandGrid) g = kExpandGrid;
-  return (int)g;
+int pr_long_grid(int64_t nsplit_rows) {
+  return (int)((nsplit_rows + kBlock - 1) / kBlock);
 }
 
 void launch_pr_init(int is_fp64, const PrArgs &a, void *stream) {
@@ -275,9 +283,13 @@ void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   if (is_fp64) {
     hipLaunchKernelGGL(k_pr_iter<double>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    if (a.nblk_long > 0)
+      hipLaunchKernelGGL(k_pr_long<double>, dim3(a.nblk_long), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_pr_fixup<double>, dim3(1), dim3(1024), 0, s, a, 0);
   } else {
     hipLaunchKernelGGL(k_pr_iter<float>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    if (a.nblk_long > 0)
+      hipLaunchKernelGGL(k_pr_long<float>, dim3(a.nblk_long), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_pr_fixup<float>, dim3(1), dim3(1024), 0, s, a, 0);
   }
 }

@@ -110,7 +110,7 @@ __device__ void sssp_push(const SsspArgs &a, int *mark, bool long_rows, int &fc,
     const uint64_t mf = mw < a.nw ? a.fcur[mw] : 0ull;
     const int cnt = __popcll(mf);
     const int qincl = wave_incl_scan(cnt);
-    const int qtotal = __shfl(qincl, 63);
+    const int qtotal = lane_last(qincl);
     for (int b = 0; b < qtotal; b += 64) {
       const int64_t u = queue_slot(mark, mf, cnt, qincl, qtotal, b, mw);
       int cur = 0, end = 0;
@@ -131,7 +131,7 @@ __device__ void sssp_push(const SsspArgs &a, int *mark, bool long_rows, int &fc,
           if (!more) continue;
           const int len = end - cur;
           const int incl = wave_incl_scan(len);
-          const int total = __shfl(incl, 63);
+          const int total = lane_last(incl);
           if (total == 0) {
             more = false;
             continue;
@@ -201,18 +201,19 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &f
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
   const float inf = __int_as_float(0x7f800000);
-  // words are dealt out round-robin (wave gw takes words gw, gw + nwaves,
-  // ...): rows of similar degree have nearby ids, so neighbouring heavy
-  // words go to different waves
-  for (int64_t w0 = gw; w0 < a.nw; w0 += 64 * nwaves) {
-    const int64_t mw = w0 + (int64_t)ln * nwaves;
-    clear_behind(a, mw, mw < a.nw);
-    const uint64_t mc = mw < a.nw ? ~a.iso[mw] : 0ull;  // candidate rows: rows with in-edges
+  // the wave's run of words (runs of about equal work, built by
+  // grb_matrix_prepare: rows of similar degree have nearby ids)
+  const int64_t wlo = gw < kWaveParts ? a.pull.wpart[gw] : 0;
+  const int64_t whi = gw < kWaveParts ? a.pull.wpart[gw + 1] : 0;
+  for (int64_t w0 = wlo; w0 < whi; w0 += 64) {
+    const int64_t mw = w0 + ln;
+    clear_behind(a, mw, mw < whi);
+    const uint64_t mc = mw < whi ? ~a.iso[mw] : 0ull;  // candidate rows: rows with in-edges
     uint64_t nzw = __ballot(mc != 0ull);
     while (nzw) {
       const int k = __ffsll((unsigned long long)nzw) - 1;
       nzw &= nzw - 1;
-      const int64_t w = w0 + (int64_t)k * nwaves;
+      const int64_t w = w0 + k;
       const uint64_t cand = __shfl(mc, k);
       const int64_t v = w * 64 + ln;
       bool act = (cand >> ln) & 1ull;
@@ -240,7 +241,7 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &f
           if (!more) continue;
           const int len = end - cur;
           const int incl = wave_incl_scan(len);
-          const int total = __shfl(incl, 63);
+          const int total = lane_last(incl);
           if (total == 0) {
             more = false;
             continue;
