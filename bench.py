@@ -321,8 +321,9 @@ def bench_msbfs(grb, graphgen, torch, args):
             best = tune.tune_msbfs(A, src, cache_path=args.tune_cache, repeats=2, log=log)
             wsk = grb.workspace(grb.OP_MSBFS, A, k)
             lev = torch.empty((A.nrows, k), dtype=torch.int32, device="cuda")
+            dbest = grb.descriptor(rule=tune.RULES[best.get("rule", "paper")])
             run = lambda: grb.msbfs(A, src, words_per_pass=best["words_per_pass"],
-                                    grid=best["grid"], ws=wsk, levels=lev)
+                                    grid=best["grid"], desc=dbest, ws=wsk, levels=lev)
             run()
             ms = timed(run, args.extra_steps, torch)
             st = grb.last_stats()
@@ -334,7 +335,8 @@ def bench_msbfs(grb, graphgen, torch, args):
                 "ms": round(ms, 3), "levels": st["iterations"],
                 "sources_per_s": round(k / ms * 1e3, 1),
                 "gteps": round(k * A.nnz / ms / 1e6, 2),
-                "tile": {"words_per_pass": best["words_per_pass"], "grid": best["grid"]},
+                "tile": {"words_per_pass": best["words_per_pass"], "grid": best["grid"],
+                         "rule": best.get("rule", "paper")},
                 "sequential_ms_per_source": round(per_src_seq, 4),
                 "speedup_vs_sequential": round(per_src_seq * k / ms, 2)}
             del wsk, lev

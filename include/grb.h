@@ -349,7 +349,8 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping,
  * are device data): ids outside [0, n) are undefined behaviour.
  */
 typedef struct grb_msbfs_tile {
-  int32_t words_per_pass; /* kt, 0 = all words of the batch in one pass */
+  int32_t words_per_pass; /* kt, 0 = all words of the batch; at most 8 words are
+                             taken per pass (larger values act as 8) */
   int32_t grid;           /* workgroups per pass, 0 = default */
   int32_t reserved[2];    /* must be zero */
 } grb_msbfs_tile;

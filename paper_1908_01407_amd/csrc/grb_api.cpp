@@ -841,6 +841,7 @@ grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_
     if (tile->words_per_pass) kt = tile->words_per_pass;
     if (tile->grid) grid = tile->grid;
   }
+  kt = std::min(kt, kMsMaxWordsPerPass);
   grb_descriptor desc;
   grb_info info = resolve_desc(d, &desc);
   if (info != GRB_SUCCESS) return info;
@@ -910,9 +911,10 @@ grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_
   const int iters = hc.nlev;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
-  if (nrec > 0 && hipMemcpy(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
-                            hipMemcpyDeviceToHost) != hipSuccess)
+  if (nrec > 0 && hipMemcpyAsync(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, s) != hipSuccess)
     return GRB_PANIC;
+  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {

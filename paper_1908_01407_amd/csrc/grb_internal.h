@@ -20,6 +20,7 @@ constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand ker
 constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
 constexpr int kWaveParts = kExpandGrid * kWavesPerBlock;  // waves of a full-sweep kernel
 constexpr int kUnroll = 4;         // 64-edge steps whose loads are issued together
+constexpr int kMsMaxWordsPerPass = 8;  // batched BFS: query words (of 64) per pass, at most
 constexpr int kPullRows = 4;       // BFS pull: rows per lane whose first loads overlap
 constexpr int kCntStripes = 32;      // BFS: striped frontier counters (count, degree sum)
 constexpr int kStatsCap = GRB_STATS_MAX;

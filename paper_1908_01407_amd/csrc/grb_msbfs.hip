@@ -85,60 +85,166 @@ __device__ __forceinline__ uint64_t claim_bits(const MsbfsArgs &a, int64_t v, in
   return nb;
 }
 
-__device__ void ms_pull(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc) {
+// Pull over the pass's query words j0 .. j0 + nj - 1 (nj <= L <= 8): an edge
+// occupies L consecutive lanes, one per query word, so the frontier words of
+// a neighbour (consecutive in the vertex-major block) come in one coalesced
+// load; S = 64 / L edges per sub-step, kUnroll sub-steps per step.  Rows
+// (lanes of the row layout, 64 per bitmap word) keep their unvisited and
+// found bits per word and stop once every unvisited query of the pass is
+// found.  Rows longer than kPushSplit are left to the pieces below, which
+// claim with atomics like push.
+template <int L>
+__device__ void ms_pull_rows(const MsbfsArgs &a, int *mark, int64_t &act_acc,
+                             int64_t &edges_acc) {
+  constexpr int S = 64 / L;
   const int ln = threadIdx.x & 63;
+  const int sl = ln / L, jl = ln % L;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
   const int j0 = blockIdx.y * a.kt;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    const int64_t v = w * 64 + ln;
-    const bool inb = v < a.n;
-    int rs = 0, re = 0;
-    if (inb) {
-      rs = rp[v];
-      re = rp[v + 1];
-    }
-    for (int jj = 0; jj < a.kt; ++jj) {
-      const int j = j0 + jj;
-      if (j >= a.W) break;
-      uint64_t need = 0ull;  // unvisited queries of this word
-      if (inb && re > rs) need = ~a.V[v * a.W + j] & qmask(a, j);
-      if (__ballot(need != 0ull) == 0ull) continue;
-      uint64_t acc = 0ull;
+  const int nj = min(a.kt, a.W - j0);
+  const bool jv = jl < nj;
+  for (int64_t part = gw; part < kWaveParts; part += nwaves) {
+    const int64_t wlo = a.pull.wpart[part], whi = a.pull.wpart[part + 1];
+    for (int64_t w = wlo; w < whi; ++w) {
+      const int64_t v = w * 64 + ln;
+      const bool inb = v < a.n;
+      int rs = 0, re = 0;
+      if (inb) {
+        rs = rp[v];
+        re = rp[v + 1];
+        if (re - rs > kPushSplit) re = rs;  // pieces
+      }
+      uint64_t need[L], acc[L];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        need[q] = 0ull;
+        acc[q] = 0ull;
+        if (q < nj && re > rs) need[q] = ~a.V[v * a.W + j0 + q] & qmask(a, j0 + q);
+        any |= need[q] != 0ull;
+      }
+      if (__ballot(any) == 0ull) continue;
       int cur = rs;
-      for (;;) {
-        const bool live = need != 0ull && (acc & need) != need && cur < re;
-        const int len = live ? re - cur : 0;
-        const int incl = wave_incl_scan(len);
-        const int total = lane_last(incl);
-        if (total == 0) break;
-        const int excl = incl - len;
-        const bool starts = len > 0 && excl < 64;
-        const int r = slot_rows(mark, starts, excl);
-        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-        uint64_t f = 0ull;
-        if (ln < total) f = a.F[(int64_t)ci[rcur + (ln - rexcl)] * a.W + j];
-        f = wave_seg_or(f, r);
-        const int se = min(incl, 64);
-        const uint64_t segv = __shfl(f, starts ? se - 1 : 0);
-        if (starts) {
-          acc |= segv;
-          cur += se - excl;
+      const int end = any ? re : rs;
+      bool done = !any;
+      for (bool more = true; more;) {
+        // slot positions of kUnroll sub-steps (S edges each)
+        int pos[kUnroll], row[kUnroll], se[kUnroll];
+        bool st[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          pos[u] = -1;
+          row[u] = 0;
+          se[u] = 0;
+          st[u] = false;
+          if (!more) continue;
+          const int len = done ? 0 : end - cur;
+          const int incl = wave_incl_scan(len);
+          const int total = lane_last(incl);
+          if (total == 0) {
+            more = false;
+            continue;
+          }
+          const int excl = incl - len;
+          const bool starts = len > 0 && excl < S;
+          const int rr = slot_rows(mark, starts, excl);  // row of slot ln (ln < S used)
+          const int r = __shfl(rr, sl);                 // row of this lane's slot
+          const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+          if (sl < total) pos[u] = rcur + (sl - rexcl);
+          row[u] = r;
+          st[u] = starts;
+          se[u] = min(incl, S);
+          if (starts) cur += se[u] - excl;
         }
+        uint64_t f[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int c = pos[u] >= 0 ? ci[pos[u]] : -1;
+          f[u] = (c >= 0 && jv) ? a.F[(int64_t)c * a.W + j0 + jl] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          // OR over the slots of each row, per query word (lanes L apart)
+          uint64_t x = f[u];
+#pragma unroll
+          for (int off = L; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(x, off);
+            const int ry = __shfl_up(row[u], off);
+            if (ln >= off && ry == row[u]) x |= y;
+          }
+          // the row's lane takes the OR from the last slot of its segment
+          const int last = st[u] ? se[u] - 1 : 0;
+#pragma unroll
+          for (int q = 0; q < L; ++q) {
+            const uint64_t segv = __shfl(x, last * L + q);
+            if (st[u]) acc[q] |= segv;
+          }
+        }
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < L; ++q) all &= (acc[q] & need[q]) == need[q];
+        done = done || all;
       }
-      const uint64_t nb = acc & need;
-      if (nb) {
-        a.V[v * a.W + j] |= nb;  // this lane owns (v, j) in pull
-        a.Fn[v * a.W + j] = nb;
-        act_acc += __popcll(nb);
-        edges_acc += a.push.rp[v + 1] - a.push.rp[v];
+      // found bits: this wave owns row v in pull
+      bool anyb = false;
+      int64_t e_add = 0;
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        const uint64_t nb = acc[q] & need[q];
+        if (nb) {
+          a.V[v * a.W + j0 + q] |= nb;
+          a.Fn[v * a.W + j0 + q] = nb;
+          act_acc += __popcll(nb);
+          anyb = true;
+          e_add += a.push.rp[v + 1] - a.push.rp[v];
+        }
+        write_levels(a, v, j0 + q, nb);
       }
-      const uint64_t anyb = __ballot(nb != 0ull);
-      if (anyb && ln == 0) atomicOr((unsigned long long *)&a.actn[w], (unsigned long long)anyb);
-      write_levels(a, v, j, nb);
+      edges_acc += e_add;
+      const uint64_t ab = __ballot(anyb);
+      if (ab && ln == 0) atomicOr((unsigned long long *)&a.actn[w], (unsigned long long)ab);
     }
   }
+  // pieces of long rows: OR of the piece's neighbours' frontier words, then
+  // claims like push (kPushSplit edges: S per sub-step)
+  for (int64_t h = gw; h < a.pull.nsplit; h += nwaves) {
+    const int r = a.pull.split[2 * h], b = a.pull.split[2 * h + 1];
+    const int e = min(b + kPushSplit, rp[r + 1]);
+    uint64_t need = 0ull;
+    if (jv) need = ~a.V[(int64_t)r * a.W + j0 + jl] & qmask(a, j0 + jl);
+    if (__ballot(need != 0ull) == 0ull) continue;
+    uint64_t acc = 0ull;
+    for (int base = b; base < e; base += S * kUnroll) {
+      uint64_t f[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int p = base + u * S + sl;
+        const int c = p < e ? ci[p] : -1;
+        f[u] = (c >= 0 && jv) ? a.F[(int64_t)c * a.W + j0 + jl] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) acc |= f[u];
+      if (__ballot((acc & need) != need) == 0ull) break;  // every word complete
+    }
+    // OR over the slots (lanes L apart) and claim in lanes 0 .. L-1
+#pragma unroll
+    for (int off = L; off < 64; off <<= 1) acc |= __shfl_xor(acc, off);
+    int64_t ea = 0;
+    uint64_t nb = 0ull;
+    if (sl == 0 && jv) nb = claim_bits(a, r, j0 + jl, acc & need, ea);
+    act_acc += sl == 0 ? __popcll(nb) : 0;
+    edges_acc += ea;
+    write_levels(a, sl == 0 ? (int64_t)r : -1, j0 + jl, sl == 0 ? nb : 0ull);
+  }
+}
+
+__device__ void ms_pull(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc) {
+  if (a.kt <= 1) ms_pull_rows<1>(a, mark, act_acc, edges_acc);
+  else if (a.kt <= 2) ms_pull_rows<2>(a, mark, act_acc, edges_acc);
+  else if (a.kt <= 4) ms_pull_rows<4>(a, mark, act_acc, edges_acc);
+  else ms_pull_rows<8>(a, mark, act_acc, edges_acc);
 }
 
 __device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc) {

@@ -23,6 +23,7 @@ The scheduler is pure host logic (tested on the CPU with a fake executor);
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import threading
 import time
@@ -227,6 +228,9 @@ class GpuExecutor:
         self.keep = keep_results
         self.max_batch = max_batch
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        # the exact switch rule (frontier degree sum against nnz): results are
+        # the same under either rule, and on these graphs it is the faster
+        self.desc = grb.descriptor(rule=grb.SWITCH_EXACT)
         # per-slot workspace large enough for any item on any graph
         need = 0
         for A in graphs.values():
@@ -262,15 +266,17 @@ class GpuExecutor:
             if item.kind == "sssp":
                 q = item.queries[0]
                 dist = self.outs[slot][:n].view(torch.float32)
-                grb.check(grb._lib.grb_sssp(grb._ptr(dist), A.handle, int(q.source), None,
-                                            grb._ptr(ws), ws.numel(), grb._stream(s)), "grb_sssp")
+                grb.check(grb._lib.grb_sssp(grb._ptr(dist), A.handle, int(q.source),
+                                            ctypes.byref(self.desc), grb._ptr(ws), ws.numel(),
+                                            grb._stream(s)), "grb_sssp")
                 if self.keep:
                     q.result = dist.cpu()
             elif len(item.queries) == 1:
                 q = item.queries[0]
                 lev = self.outs[slot][:n]
-                grb.check(grb._lib.grb_bfs(grb._ptr(lev), None, A.handle, int(q.source), None,
-                                           grb._ptr(ws), ws.numel(), grb._stream(s)), "grb_bfs")
+                grb.check(grb._lib.grb_bfs(grb._ptr(lev), None, A.handle, int(q.source),
+                                           ctypes.byref(self.desc), grb._ptr(ws), ws.numel(),
+                                           grb._stream(s)), "grb_bfs")
                 if self.keep:
                     q.result = lev.cpu()
             else:
@@ -278,7 +284,7 @@ class GpuExecutor:
                 src = torch.tensor([q.source for q in item.queries], dtype=torch.int32,
                                    device="cuda")
                 lev = self.outs[slot][: n * k].view(n, k)
-                grb.msbfs(A, src, ws=ws, levels=lev, stream=s)
+                grb.msbfs(A, src, desc=self.desc, ws=ws, levels=lev, stream=s)
                 if self.keep:
                     host = lev.cpu()
                     for i, q in enumerate(item.queries):

@@ -1,12 +1,14 @@
 """Autotuner for the batched multi-source BFS tile shape.
 
 grb_msbfs streams every level once per pass over `words_per_pass` query
-words (64 queries each) with `grid` workgroups per pass.  Wider passes
-re-read each adjacency list fewer times; narrower passes keep the gathered
-frontier block (n x words_per_pass x 8 bytes) small enough to stay in the
-caches.  The best trade-off depends on the graph, k and the device, so it
-is measured: every candidate runs the real batch on the real graph and the
-fastest is cached in a JSON file keyed by device, graph size and k.
+words (64 queries each, at most 8 per pass) with `grid` workgroups per pass,
+and picks push or pull per level with the descriptor's switch rule.  Wider
+passes re-read each adjacency list fewer times and gather whole frontier
+rows per edge; narrower passes keep the gathered frontier block (n x
+words_per_pass x 8 bytes) small enough to stay in the caches.  The best
+shape and rule depend on the graph, k and the device, so they are measured:
+every candidate runs the real batch on the real graph and the fastest is
+cached in a JSON file keyed by device, graph size and k.
 """
 from __future__ import annotations
 
@@ -17,21 +19,25 @@ import time
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "grb_mi355x_tune.json")
 
 
+RULES = {"paper": 0, "exact": 1}
+
+
 def candidates(k: int):
     W = (k + 63) // 64
-    kts = sorted({w for w in (1, 2, 4, 8, W) if w <= W})
+    kts = sorted({w for w in (1, 2, 4, 8, min(W, 8)) if w <= W})
     grids = (1024, 2048, 4096)
-    return [(kt, g) for kt in kts for g in grids]
+    return [(kt, g, r) for kt in kts for g in grids for r in RULES]
 
 
 def _key(A, k, device_name):
     return f"{device_name}|n={A.nrows}|nnz={A.nnz}|k={k}"
 
 
-def tune_msbfs(A, sources, *, desc=None, repeats: int = 2, cache_path: str | None = DEFAULT_CACHE,
+def tune_msbfs(A, sources, *, repeats: int = 2, cache_path: str | None = DEFAULT_CACHE,
                force: bool = False, log=None):
-    """Returns {"words_per_pass", "grid", "ms", "table"} for this graph and
-    batch size, measuring candidates unless the cache already has them."""
+    """Returns {"words_per_pass", "grid", "rule", "ms", "table"} for this
+    graph and batch size ("rule": "paper" or "exact"), measuring candidates
+    unless the cache already has them."""
     import torch
 
     import paper_1908_01407_amd as grb
@@ -51,7 +57,8 @@ def tune_msbfs(A, sources, *, desc=None, repeats: int = 2, cache_path: str | Non
     ws = grb.workspace(grb.OP_MSBFS, A, k)
     levels = torch.empty((A.nrows, k), dtype=torch.int32, device=A.device)
     table = []
-    for kt, g in candidates(k):
+    for kt, g, rule in candidates(k):
+        desc = grb.descriptor(rule=RULES[rule])
         grb.msbfs(A, sources, words_per_pass=kt, grid=g, desc=desc, ws=ws, levels=levels)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -59,12 +66,12 @@ def tune_msbfs(A, sources, *, desc=None, repeats: int = 2, cache_path: str | Non
             grb.msbfs(A, sources, words_per_pass=kt, grid=g, desc=desc, ws=ws, levels=levels)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / repeats * 1e3
-        table.append({"words_per_pass": kt, "grid": g, "ms": round(ms, 4)})
+        table.append({"words_per_pass": kt, "grid": g, "rule": rule, "ms": round(ms, 4)})
         if log:
-            log(f"[tune] kt={kt} grid={g}: {ms:.3f} ms")
+            log(f"[tune] kt={kt} grid={g} rule={rule}: {ms:.3f} ms")
     best = min(table, key=lambda r: r["ms"])
-    res = {"words_per_pass": best["words_per_pass"], "grid": best["grid"], "ms": best["ms"],
-           "table": table}
+    res = {"words_per_pass": best["words_per_pass"], "grid": best["grid"], "rule": best["rule"],
+           "ms": best["ms"], "table": table}
     cache[key] = res
     if cache_path:
         try:
