@@ -328,8 +328,9 @@ def bench_msbfs(grb, graphgen, torch, args):
             ms = timed(run, args.extra_steps, torch)
             st = grb.last_stats()
             seq_src = src[:64]
-            ms_seq = timed(lambda: [grb.bfs(A, int(s), parents=False, ws=ws1) for s in seq_src],
-                           1, torch)
+            dseq = grb.descriptor(rule=grb.SWITCH_EXACT)  # the faster rule for one source
+            ms_seq = timed(lambda: [grb.bfs(A, int(s), parents=False, desc=dseq, ws=ws1)
+                                    for s in seq_src], 1, torch)
             per_src_seq = ms_seq / len(seq_src)
             res[f"rmat{scale}_k{k}"] = {
                 "ms": round(ms, 3), "levels": st["iterations"],
