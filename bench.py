@@ -265,6 +265,15 @@ def bench_extras(grb, graphgen, torch, args):
         ex["sssp_grid3000"] = {"ms": round(ms, 3), "rounds": st["iterations"],
                                "us_per_round": round(ms * 1e3 / max(st["iterations"], 1), 2),
                                "gteps": round(G.nnz / ms / 1e6, 4)}
+        # bucketed rounds (grb_sssp_delta), same distances
+        for delta in (256.0, 2048.0):
+            grb.sssp(G, 0, ws=wss, delta=delta)
+            ms = timed(lambda: grb.sssp(G, 0, ws=wss, delta=delta), 2, torch)
+            st = grb.last_stats()
+            ex[f"sssp_grid3000_delta{int(delta)}"] = {
+                "ms": round(ms, 3), "rounds": st["iterations"],
+                "us_per_round": round(ms * 1e3 / max(st["iterations"], 1), 2),
+                "gteps": round(G.nnz / ms / 1e6, 4)}
         del G, wsb, wss
     # PageRank on a directed R-MAT graph
     if not args.no_pr:
@@ -376,8 +385,11 @@ def bench_serve(grb, graphgen, torch, args):
     out = {"graphs": {k: {"n": A.nrows, "nnz": A.nnz} for k, A in graphs.items()},
            "mix": "70% BFS / 30% SSSP, graph and source uniform, Poisson arrivals",
            "budget_bytes": args.serve_budget}
-    ex = GpuExecutor(graphs, slots=args.serve_slots, max_batch=64, keep_results=False)
-    fifo_ex = GpuExecutor(graphs, slots=1, max_batch=1, keep_results=False)
+    # high-diameter graphs answer SSSP with bucketed rounds
+    deltas = {"grid2000": 2048.0, "grid3000": 2048.0}
+    ex = GpuExecutor(graphs, slots=args.serve_slots, max_batch=64, keep_results=False,
+                     sssp_delta=deltas)
+    fifo_ex = GpuExecutor(graphs, slots=1, max_batch=1, keep_results=False, sssp_delta=deltas)
     # warm up every graph and kind once
     Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
         trace(2 * len(names), 1e6, 99), realtime=False)

@@ -111,6 +111,8 @@ _SIGS = {
     "grb_vxm": ([_p, _p, _i32, _i32, _p, _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_bfs": ([_p, _p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_sssp": ([_p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_sssp_delta": ([_p, _p, _i32, ctypes.c_float, ctypes.POINTER(Descriptor), _p, _sz, _p],
+                       _i32),
     "grb_msbfs": ([_p, _p, _p, _i32, ctypes.POINTER(MsbfsTile), ctypes.POINTER(Descriptor), _p,
                    _sz, _p], _i32),
     "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
@@ -359,13 +361,20 @@ def bfs(A: Matrix, source: int, *, parents: bool = True, desc: Descriptor | None
     return lev[: A.nrows], (par[: A.nrows] if par is not None else None)
 
 
-def sssp(A: Matrix, source: int, *, desc: Descriptor | None = None, ws=None, stream=None):
+def sssp(A: Matrix, source: int, *, delta: float | None = None, desc: Descriptor | None = None,
+         ws=None, stream=None):
+    """dist fp32[n] via grb_sssp, or via grb_sssp_delta when `delta` (the
+    bucket width) is given."""
     torch = _torch()
     dist = torch.empty(max(A.nrows, 1), dtype=torch.float32, device=A.device)
     ws = ws if ws is not None else workspace(OP_SSSP, A)
-    check(_lib.grb_sssp(_ptr(dist), A.handle, int(source),
-                        ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
-                        _stream(stream)), "grb_sssp")
+    dp = ctypes.byref(desc) if desc is not None else None
+    if delta is None:
+        check(_lib.grb_sssp(_ptr(dist), A.handle, int(source), dp, _ptr(ws), ws.numel(),
+                            _stream(stream)), "grb_sssp")
+    else:
+        check(_lib.grb_sssp_delta(_ptr(dist), A.handle, int(source), float(delta), dp, _ptr(ws),
+                                  ws.numel(), _stream(stream)), "grb_sssp_delta")
     return dist[: A.nrows]
 
 

@@ -526,6 +526,83 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
   return GRB_SUCCESS;
 }
 
+// Bucketed SSSP: one push kernel per round over the pending set, the host
+// reads the counters back once per batch of rounds.
+grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
+                        const grb_descriptor &desc, void *ws, size_t ws_bytes, void *stream) {
+  const int64_t n = A->nrows;
+  SsspWs sw = sssp_layout(ws, n);
+  grb_info info = check_ws(ws, ws_bytes, sw.bytes);
+  if (info != GRB_SUCCESS) return info;
+  const BfsWs &w = sw.b;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+  SsspArgs sa;
+  sa.n = n;
+  sa.nw = words_of(n);
+  sa.nnz = A->nnz;
+  sa.push = A->a;
+  sa.pull = A->at;
+  sa.can_pull = false;
+  sa.same_csr = A->symmetric;
+  sa.wpush = (const float *)A->a.val;
+  sa.dist = dist;
+  sa.ctrl = w.ctrl;
+  sa.stats = w.stats;
+  sa.delta = delta;
+  int32_t *cnt = w.ctrl->lists;
+  auto at_round = [&](int64_t d) {
+    const int i = (int)(d % 3), j = (int)((d + 1) % 3), k = (int)((d + 2) % 3);
+    sa.fcur = w.F[i];
+    sa.fnxt = w.F[j];
+    sa.fclr = w.F[k];
+    sa.cnt_cur = cnt + i * kDeltaSlots;
+    sa.cnt_nxt = cnt + j * kDeltaSlots;
+    sa.cnt_clr = cnt + k * kDeltaSlots;
+    sa.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
+  };
+  at_round(0);
+  launch_sssp_delta_start(sa, source, w.F[1], w.F[2], stream);
+  const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
+  int64_t d = 0;
+  int chunk = 16;
+  const size_t rec_bytes = (size_t)kStatsCap * kStatFields * sizeof(int64_t);
+  const size_t head = (size_t)((char *)w.stats - (char *)w.ctrl);
+  std::vector<char> host(head + rec_bytes);
+  Ctrl hc{};
+  for (;;) {
+    for (int i = 0; i < chunk && d < cap; ++i, ++d) {
+      at_round(d);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
+      launch_sssp_delta_round(sa, stream);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
+    }
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipMemcpyAsync(host.data(), w.ctrl, host.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GRB_PANIC;
+    std::memcpy(&hc, host.data(), sizeof(Ctrl));
+    if (hc.nlev < d || d >= cap) break;  // a launched round found nothing pending
+    chunk = std::min(chunk * 2, 512);
+  }
+  const int iters = hc.nlev;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  std::memcpy(rec.data(), host.data() + head, rec_bytes);
+  const int nrec = std::min(iters, (int)kStatsCap);
+  std::vector<float> kms;
+  double ms_all = 0.0;
+  if (profile) {
+    for (int64_t i = 0; i < d; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
+      if (i < nrec) kms.push_back(ms);
+      ms_all += ms;
+    }
+  }
+  finish_stats(GRB_OP_SSSP, iters, rec, kms, (int)std::min<int64_t>(d, INT32_MAX), ms_all);
+  return GRB_SUCCESS;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -823,6 +900,21 @@ grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descripto
   grb_info info = resolve_desc(d, &desc);
   if (info != GRB_SUCCESS) return info;
   return run_sssp(A, source, dist, desc, ws, ws_bytes, stream);
+}
+
+grb_info grb_sssp_delta(float *dist, grb_matrix A, int32_t source, float delta,
+                        const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!dist) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (source < 0 || source >= A->nrows) return GRB_INVALID_INDEX;
+  if (A->a.vtype != GRB_FP32) return GRB_DOMAIN_MISMATCH;
+  if (!(delta > 0.0f) || !(delta < 3.0e38f)) return GRB_INVALID_VALUE;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  if (desc.direction == GRB_DIR_PULL) return GRB_NOT_IMPLEMENTED;
+  return run_sssp_delta(A, source, dist, delta, desc, ws, ws_bytes, stream);
 }
 
 grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_t k,

@@ -81,7 +81,9 @@ struct Ctrl {
   int32_t converged;
   double D;         // PageRank: dangling mass of the current iterate
   double delta;     // PageRank: L1 change of the last iteration
-  int32_t lists[3 * 3 * 32];  // BFS / SSSP: striped counters of the three frontier buffers
+  int32_t lists[3 * 5 * 32];  // BFS / SSSP: striped counters of the three frontier buffers
+  int32_t bucket;             // bucketed SSSP: the bucket of the last round
+  int32_t pad2[3];
   int64_t pad[4];
 };
 
@@ -148,6 +150,7 @@ struct SsspArgs {
   // frontier distances: dist of the buffer's frontier vertices, +inf
   // elsewhere (the improved value of each vertex, for the next round)
   float *fd_cur = nullptr, *fd_nxt = nullptr, *fd_clr = nullptr;
+  float delta = 0.0f;  // bucketed rounds: bucket width
   int32_t *cnt_cur = nullptr, *cnt_nxt = nullptr, *cnt_clr = nullptr;
   Ctrl *ctrl = nullptr;
   int64_t *stats = nullptr;
@@ -157,6 +160,15 @@ struct SsspArgs {
 void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2, float *fd1,
                        float *fd2, void *stream);
 void launch_sssp_round(const SsspArgs &a, void *stream);
+
+// Bucketed SSSP (near-far rounds, push only): per stripe the next round's
+// near count, its degree sum, its rows with pieces, the smallest far bucket
+// and the pending count
+constexpr int kDeltaFields = 5;
+constexpr int kDeltaSlots = kDeltaFields * kCntStripes;
+void launch_sssp_delta_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
+                             void *stream);
+void launch_sssp_delta_round(const SsspArgs &a, void *stream);
 
 struct PrArgs {
   int64_t n = 0, nw = 0;

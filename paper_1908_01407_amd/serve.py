@@ -8,7 +8,8 @@ and memory free up:
 * a BFS query takes along up to ``max_batch - 1`` later BFS queries on the
   same graph that are already waiting, and the group runs as one batched
   multi-source BFS (grb_msbfs): queries are batched on arrival;
-* SSSP queries run one per work item (grb_sssp);
+* SSSP queries run one per work item (grb_sssp, or grb_sssp_delta on the
+  graphs given a bucket width);
 * a work item is admitted only if its device-memory footprint (workspace
   plus outputs) fits in what the budget has left; slots free up the moment
   their item finishes and the next item is admitted at once.
@@ -217,7 +218,8 @@ class GpuExecutor:
     """Runs work items with the library: one HIP stream and one workspace
     region per slot; graphs are resident `Matrix` objects."""
 
-    def __init__(self, graphs: dict, slots: int, max_batch: int = 64, keep_results=True):
+    def __init__(self, graphs: dict, slots: int, max_batch: int = 64, keep_results=True,
+                 sssp_delta: dict | None = None):
         import torch
 
         import paper_1908_01407_amd as grb
@@ -226,6 +228,8 @@ class GpuExecutor:
         self.torch = torch
         self.graphs = graphs
         self.keep = keep_results
+        # graph -> bucket width: SSSP on these graphs uses grb_sssp_delta
+        self.sssp_delta = dict(sssp_delta or {})
         self.max_batch = max_batch
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         # the exact switch rule (frontier degree sum against nnz): results are
@@ -266,9 +270,16 @@ class GpuExecutor:
             if item.kind == "sssp":
                 q = item.queries[0]
                 dist = self.outs[slot][:n].view(torch.float32)
-                grb.check(grb._lib.grb_sssp(grb._ptr(dist), A.handle, int(q.source),
-                                            ctypes.byref(self.desc), grb._ptr(ws), ws.numel(),
-                                            grb._stream(s)), "grb_sssp")
+                delta = self.sssp_delta.get(item.graph)
+                if delta is None:
+                    grb.check(grb._lib.grb_sssp(grb._ptr(dist), A.handle, int(q.source),
+                                                ctypes.byref(self.desc), grb._ptr(ws), ws.numel(),
+                                                grb._stream(s)), "grb_sssp")
+                else:
+                    grb.check(grb._lib.grb_sssp_delta(grb._ptr(dist), A.handle, int(q.source),
+                                                      float(delta), ctypes.byref(self.desc),
+                                                      grb._ptr(ws), ws.numel(), grb._stream(s)),
+                              "grb_sssp_delta")
                 if self.keep:
                     q.result = dist.cpu()
             elif len(item.queries) == 1:

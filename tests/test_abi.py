@@ -77,6 +77,7 @@ def test_matrix_create_validation(grb):
     # products and drivers refuse an unprepared matrix before touching the GPU
     assert grb.grb_bfs(FAKE, None, h, 0, None, FAKE, 1 << 20, None) == 2
     assert grb.grb_sssp(FAKE, h, 0, None, FAKE, 1 << 20, None) == 2
+    assert grb.grb_sssp_delta(FAKE, h, 0, 64.0, None, FAKE, 1 << 20, None) == 2
     it = ctypes.c_int32()
     assert grb.grb_pagerank(FAKE, 2, h, 0.85, 5, 0.0, ctypes.byref(it), None, None, FAKE,
                             1 << 20, None) == 2

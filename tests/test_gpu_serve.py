@@ -37,7 +37,7 @@ def test_results_same_alone_and_in_mix(grb):
         srcs = graphgen.sources(raws[g].src, raws[g].dst, raws[g].n, 1, seed=100 + i)
         qs.append(Query(qid=i, kind="bfs" if kind[i] < 7 else "sssp", graph=g,
                         source=int(srcs[0]), arrival=float(arr[i])))
-    ex = GpuExecutor(graphs, slots=4, max_batch=16)
+    ex = GpuExecutor(graphs, slots=4, max_batch=16, sssp_delta={"g60": 64.0})
     srv = Server(ex, budget=1 << 34, slots=4, max_batch=16)
     st = srv.run(qs, realtime=True)
     assert st["failed"] == 0

@@ -153,6 +153,27 @@ def test_sssp_parity(grb, name, mode):
         assert np.array_equal(dist.cpu().numpy(), ref), (name, s)
 
 
+@pytest.mark.parametrize("name", SSSP_GRAPHS)
+@pytest.mark.parametrize("delta", [1.0, 7.5, 64.0, 1e6])
+def test_sssp_delta_parity(grb, name, delta):
+    # bucketed rounds reach the same exact distances for any bucket width
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    for s in _sources(name, g.n):
+        dist = grb.sssp(A, s, delta=delta)
+        ref, _, _ = oracle.sssp(adj, s)
+        assert np.array_equal(dist.cpu().numpy(), ref), (name, s, delta)
+
+
+def test_sssp_delta_argument_errors(grb):
+    A = matrix(grb, "rmat_14")
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(grb.GrbError):
+            grb.sssp(A, 0, delta=bad)
+    with pytest.raises(grb.GrbError):
+        grb.sssp(A, 0, delta=64.0, desc=grb.descriptor(direction=grb.DIR_PULL))
+
+
 @pytest.mark.parametrize("name", ["rmat_dir_12", "rmat_dir_14"])
 def test_pagerank_parity(grb, name):
     g, adj = graph(name)
