@@ -20,10 +20,11 @@
 // * bitmaps and counters rotate through three buffers: the level reads
 //   buffer d, fills buffer d+1 and clears buffer d+2.
 // Pull finds the smallest-id parent directly (ascending adjacency, first
-// hit).  Push-discovered vertices get theirs from one pass after the last
-// level, run by the first level kernel that finds the frontier empty (or by
-// its own kernel when the level cap stops the search first): the first
-// in-neighbour one level up in ascending order.
+// hit).  A push from a one-vertex frontier writes that vertex as parent.
+// Vertices found by a push of several vertices get theirs in the next
+// level's kernel, where they are the frontier: the first in-neighbour one
+// level up in ascending order (a standalone pass covers the last level
+// when the level cap stops the search).
 #include <hip/hip_runtime.h>
 
 #include "grb_device.h"
@@ -42,9 +43,11 @@ __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
 
 // Finishes the claims won by this lane: level, next-frontier bit, counts.
 // The degree loads of all won targets are issued together.
+// With a one-vertex frontier (`single`) that vertex, par[s], is the only
+// parent a target can have, and it is written at once.
 __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnroll],
-                                          const bool (&won)[kUnroll], int &fc, int &fd,
-                                          int &fl) {
+                                          const bool (&won)[kUnroll], const int (&par)[kUnroll],
+                                          bool single, int &fc, int &fd, int &fl) {
   int d0[kUnroll], d1[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
@@ -52,6 +55,7 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
     d1[s] = 0;
     if (won[s]) {
       a.levels[c[s]] = a.d + 1;
+      if (single && a.parents) a.parents[c[s]] = par[s];
       atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], 1ull << (c[s] & 63));
       d0[s] = a.push.rp[c[s]];
       d1[s] = a.push.rp[c[s] + 1];
@@ -69,7 +73,8 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
 // one target twice.  The visited words of all of them are read first (a
 // plain read is only a filter, the atomic decides) and all atomics are
 // issued before any result is used, so their latencies overlap.
-__device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
+__device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll],
+                                            const int (&par)[kUnroll], bool single, int &fc,
                                             int &fd, int &fl) {
   uint64_t vw[kUnroll];
 #pragma unroll
@@ -84,14 +89,15 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
   bool won[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) won[s] = c[s] >= 0 && !((old[s] >> (c[s] & 63)) & 1ull);
-  claim_won(a, c, won, fc, fd, fl);
+  claim_won(a, c, won, par, single, fc, fd, fl);
 }
 
 // Claims the targets of one piece of a row: ascending and distinct, so the
 // lanes whose targets share a visited word sit side by side and one atomicOr
 // per word serves them all (issued by the run's last lane, whose previous
 // value of the word every lane of the run then reads).
-__device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUnroll], int &fc,
+__device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUnroll],
+                                            const int (&par)[kUnroll], bool single, int &fc,
                                             int &fd, int &fl) {
   uint64_t vw[kUnroll];
 #pragma unroll
@@ -114,7 +120,7 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
     const uint64_t ow = __shfl(old[s], tail[s]);
     won[s] = want[s] && !((ow >> (c[s] & 63)) & 1ull);
   }
-  claim_won(a, c, won, fc, fd, fl);
+  claim_won(a, c, won, par, single, fc, fd, fl);
 }
 
 // Each wave loads 64 bitmap words at once (one per lane) and compacts their
@@ -123,8 +129,8 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
 // as one concatenated list; longer rows come in static pieces spread over
 // all waves, so a hub is expanded by hundreds of waves at once.
 
-__device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_rows, int &fc,
-                                         int &fd, int &fl) {
+__device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_rows, bool single,
+                                         int &fc, int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -151,11 +157,13 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
       }
       // the rows' out-edges as one concatenated stream, kUnroll x 64 edges
       // per step
+      const int uid = (int)u;
       for (bool more = true; more;) {
-        int c[kUnroll];
+        int c[kUnroll], par[kUnroll];
 #pragma unroll
         for (int s = 0; s < kUnroll; ++s) {
           c[s] = -1;
+          par[s] = -1;
           if (!more) continue;
           const int len = end - cur;
           const int incl2 = wave_incl_scan(len);
@@ -168,12 +176,13 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
           const bool starts = len > 0 && excl < 64;
           const int r = slot_rows(mark, starts, excl);
           const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+          par[s] = __shfl(uid, r);
           if (ln < tot2) c[s] = rcur + (ln - rexcl);
           if (starts) cur += min(incl2, 64) - excl;
         }
 #pragma unroll
         for (int s = 0; s < kUnroll; ++s) c[s] = c[s] >= 0 ? ci[c[s]] : -1;
-        claim_batch(a, c, fc, fd, fl);
+        claim_batch(a, c, par, single, fc, fd, fl);
       }
     }
   }
@@ -195,14 +204,15 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
     while (act) {
       const int k = __ffsll((unsigned long long)act) - 1;
       act &= act - 1;
-      const int pb = __shfl(b, k), pe = __shfl(e, k);
-      int c[kUnroll];
+      const int pb = __shfl(b, k), pe = __shfl(e, k), pu = __shfl(u, k);
+      int c[kUnroll], par[kUnroll];
 #pragma unroll
       for (int s = 0; s < kUnroll; ++s) {
         const int pos = pb + s * 64 + ln;
         c[s] = pos < pe ? ci[pos] : -1;
+        par[s] = pu;
       }
-      claim_piece(a, c, fc, fd, fl);
+      claim_piece(a, c, par, single, fc, fd, fl);
     }
   }
 }
@@ -478,6 +488,62 @@ __device__ __forceinline__ void parents_pass(const BfsArgs &a, int *mark) {
   }
 }
 
+// Parents of this level's frontier when a push of more than one vertex
+// found it: for each frontier vertex v (queued from the frontier words, dealt
+// out round-robin), the first in-neighbour one level up in ascending order.
+__device__ __forceinline__ void frontier_parents(const BfsArgs &a, int *mark) {
+  const int ln = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
+  const int tgt = a.d - 1;
+  for (int64_t w0 = gw; w0 < a.nw; w0 += 64 * nwaves) {
+    const int64_t mw = w0 + (int64_t)ln * nwaves;
+    const uint64_t mf = mw < a.nw ? a.fcur[mw] : 0ull;
+    const int cnt = __popcll(mf);
+    const int incl = wave_incl_scan(cnt);
+    const int total = lane_last(incl);
+    for (int b = 0; b < total; b += 64) {
+      const int64_t v = queue_slot(mark, mf, cnt, incl, total, b, mw);
+      const bool need = v >= 0;
+      int cur = need ? rp[v] : 0;
+      const int end = need ? rp[v + 1] : 0;
+      bool found = false;
+      int par = -1;
+      if (need) {
+        const int c0 = cur < end ? ci[cur] : -1;
+        const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
+        const int l0 = c0 >= 0 ? a.levels[c0] : -2;
+        const int l1 = c1 >= 0 ? a.levels[c1] : -2;
+        if (l0 == tgt) { found = true; par = c0; }
+        else if (l1 == tgt) { found = true; par = c1; }
+        cur = min(cur + 2, end);
+      }
+      for (;;) {
+        const int len = (need && !found) ? end - cur : 0;
+        const int incl2 = wave_incl_scan(len);
+        const int tot2 = lane_last(incl2);
+        if (tot2 == 0) break;
+        const int excl = incl2 - len;
+        const bool starts = len > 0 && excl < 64;
+        const int r = slot_rows(mark, starts, excl);
+        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+        const bool valid = ln < tot2;
+        const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
+        const uint64_t hm = __ballot(valid && a.levels[c] == tgt);
+        const int se = min(incl2, 64);
+        const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
+        const uint64_t h = hm & seg;
+        const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
+        const int pc = __shfl(c, fl);
+        if (h) { found = true; par = pc; }
+        if (starts) cur += se - excl;
+      }
+      if (found) a.parents[v] = par;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   parents_pass(a, s_mark[threadIdx.x >> 6]);
@@ -485,9 +551,10 @@ __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
-  __shared__ int s_count, s_sumdeg, s_long;
+  __shared__ int s_count, s_sumdeg, s_long, s_open;
   __shared__ int s_red[kWavesPerBlock][kCntFields];
   if (threadIdx.x == 0) {
+    s_open = a.parents ? a.ctrl->pushed[a.d % 3] : 0;
     int c = 0, sd = 0, lr = 0;
     for (int t = 0; t < kCntStripes; ++t) {
       c += a.cnt_cur[kCntFields * t];
@@ -503,6 +570,9 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
       for (int i = 0; i < kCntSlots; ++i) a.cnt_clr[i] = 0;
       if (c > 0) {
         a.ctrl->nlev = a.d + 1;
+        // the next frontier's parents stay open when a push of several
+        // vertices finds it
+        a.ctrl->pushed[(a.d + 1) % 3] = (decide(a, c, sd) == GRB_DIR_PUSH && c > 1) ? 1 : 0;
         if (a.stats && a.d < kStatsCap) {
           a.stats[a.d * kStatFields + 0] = c;
           a.stats[a.d * kStatFields + 1] = sd;
@@ -513,16 +583,15 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   }
   __syncthreads();
   const int count = s_count;
-  if (count == 0) {
-    // the first empty level (the last level with a frontier was d - 1)
-    // finds the parents of the push-discovered vertices
-    if (a.parents && a.ctrl->nlev == a.d) parents_pass(a, s_mark[threadIdx.x >> 6]);
-    return;
-  }
+  if (count == 0) return;
   const int dir = decide(a, count, s_sumdeg);
   int fc = 0, fd = 0, fl = 0;
-  if (dir == GRB_DIR_PUSH) bfs_push(a, s_mark[threadIdx.x >> 6], s_long > 0, fc, fd, fl);
-  else bfs_pull(a, s_mark[threadIdx.x >> 6], fc, fd, fl);
+  // parents of this frontier, when a push of several vertices found it
+  if (s_open) frontier_parents(a, s_mark[threadIdx.x >> 6]);
+  if (dir == GRB_DIR_PUSH)
+    bfs_push(a, s_mark[threadIdx.x >> 6], s_long > 0, count == 1, fc, fd, fl);
+  else
+    bfs_pull(a, s_mark[threadIdx.x >> 6], fc, fd, fl);
   fc = wave_sum(fc);
   fd = wave_sum(fd);
   fl = wave_sum(fl);
@@ -577,6 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
       a.cnt_clr[i] = 0;
     }
     a.ctrl->nlev = 0;
+    a.ctrl->pushed[0] = a.ctrl->pushed[1] = a.ctrl->pushed[2] = 0;
     const int ds = a.push.rp[source + 1] - a.push.rp[source];
     a.cnt_cur[0] = 1;  // level 0 = {source}
     a.cnt_cur[1] = ds;

@@ -83,7 +83,8 @@ struct Ctrl {
   double delta;     // PageRank: L1 change of the last iteration
   int32_t lists[3 * 5 * 32];  // BFS / SSSP: striped counters of the three frontier buffers
   int32_t bucket;             // bucketed SSSP: the bucket of the last round
-  int32_t pad2[3];
+  int32_t pushed[3];          // BFS: buffer's frontier came from a push of > 1 vertex
+                              // (its vertices' parents are still open)
   int64_t pad[4];
 };
 
