@@ -187,11 +187,11 @@ grb_info check_ws(void *ws, size_t have, size_t need) {
 
 // ---- matrix metadata ---------------------------------------------------------
 struct MetaLayout {
-  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, wpart_off, bytes;
+  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, wpart_off, iso_off, bytes;
   int64_t max_pieces, max_rows, max_split, max_split_rows;
 };
 
-MetaLayout meta_layout_one(int64_t nnz, size_t base) {
+MetaLayout meta_layout_one(int64_t nnz, int64_t nrows, size_t base) {
   MetaLayout m{};
   m.max_rows = nnz / (kHeavyDeg + 1) + 1;
   m.max_pieces = nnz / kHeavyChunk + m.max_rows + 1;
@@ -202,7 +202,8 @@ MetaLayout meta_layout_one(int64_t nnz, size_t base) {
   m.max_split_rows = nnz / (kPushSplit + 1) + 1;
   m.split_rows_off = align_up(m.split_off + (size_t)m.max_split * 2 * sizeof(int32_t));
   m.wpart_off = align_up(m.split_rows_off + (size_t)m.max_split_rows * 3 * sizeof(int32_t));
-  m.bytes = align_up(m.wpart_off + (size_t)(kWaveParts + 1) * sizeof(int32_t));
+  m.iso_off = align_up(m.wpart_off + (size_t)(kWaveParts + 1) * sizeof(int32_t));
+  m.bytes = align_up(m.iso_off + (size_t)words_of(nrows) * sizeof(uint64_t));
   return m;
 }
 
@@ -272,6 +273,20 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
     }
     wpart[(size_t)kWaveParts] = (int32_t)nw;
   }
+  // rows without entries; padding bits past nrows count as such
+  std::vector<uint64_t> iso((size_t)nw, 0ull);
+  for (int64_t w = 0; w < nw; ++w) {
+    uint64_t bits = 0ull;
+    for (int b = 0; b < 64; ++b) {
+      const int64_t r = w * 64 + b;
+      if (r >= c.nrows || rp[(size_t)r + 1] == rp[(size_t)r]) bits |= 1ull << b;
+    }
+    iso[(size_t)w] = bits;
+  }
+  uint64_t *isop = (uint64_t *)(meta + L.iso_off);
+  if (nw > 0 &&
+      hipMemcpyAsync(isop, iso.data(), iso.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
   int32_t *wp = (int32_t *)(meta + L.wpart_off);
   if (hipMemcpyAsync(wp, wpart.data(), wpart.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return GRB_PANIC;
@@ -299,6 +314,7 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
   c.split_rows = sr;
   c.nsplit_rows = (int64_t)split_rows.size() / 3;
   c.wpart = wp;
+  c.iso = isop;
   return GRB_SUCCESS;
 }
 
@@ -731,9 +747,9 @@ grb_info grb_matrix_nvals(grb_matrix A, int64_t *nnz) {
 grb_info grb_matrix_meta_size(grb_matrix A, size_t *bytes) {
   if (!A) return GRB_UNINITIALIZED_OBJECT;
   if (!bytes) return GRB_NULL_POINTER;
-  MetaLayout la = meta_layout_one(A->nnz, 0);
+  MetaLayout la = meta_layout_one(A->nnz, A->nrows, 0);
   size_t total = la.bytes;
-  if (!A->symmetric && A->at.valid()) total = meta_layout_one(A->nnz, total).bytes;
+  if (!A->symmetric && A->at.valid()) total = meta_layout_one(A->nnz, A->ncols, total).bytes;
   *bytes = total;
   return GRB_SUCCESS;
 }
@@ -746,13 +762,13 @@ grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *s
   if (!meta) return GRB_NULL_POINTER;
   if (((uintptr_t)meta) % 256 != 0) return GRB_INVALID_VALUE;
   hipStream_t s = (hipStream_t)stream;
-  MetaLayout la = meta_layout_one(A->nnz, 0);
+  MetaLayout la = meta_layout_one(A->nnz, A->nrows, 0);
   grb_info info = build_meta(A->a, (char *)meta, la, s);
   if (info != GRB_SUCCESS) return info;
   if (A->symmetric) {
     A->at = A->a;
   } else if (A->at.valid()) {
-    MetaLayout lt = meta_layout_one(A->nnz, la.bytes);
+    MetaLayout lt = meta_layout_one(A->nnz, A->ncols, la.bytes);
     info = build_meta(A->at, (char *)meta, lt, s);
     if (info != GRB_SUCCESS) return info;
   }

@@ -619,27 +619,46 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source, uint64_t *f1,
                                                       uint64_t *f2) {
-  const int ln = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t w = gw; w < a.nw; w += nwaves) {
-    const int64_t v = w * 64 + ln;
-    bool iso = true;
-    if (v < a.n) {
-      // no in-edges: a pull can never reach it (a push cannot either)
-      iso = a.can_pull ? (a.pull.rp[v + 1] == a.pull.rp[v]) : false;
-      a.levels[v] = (v == source) ? 0 : -1;
-      if (a.parents) a.parents[v] = (v == source) ? source : -1;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * kBlock;
+  // levels and parents: -1 (source: 0 and itself), four vertices per
+  // 16-byte store when both arrays allow it
+  const bool vec = ((uintptr_t)a.levels % 16 == 0) &&
+                   (!a.parents || (uintptr_t)a.parents % 16 == 0);
+  const int64_t n4 = vec ? a.n / 4 : 0;
+  for (int64_t i = tid; i < n4; i += nt) {
+    int4 l = make_int4(-1, -1, -1, -1), p = l;
+    if ((source >> 2) == i) {
+      const int k = source & 3;
+      if (k == 0) { l.x = 0; p.x = source; }
+      else if (k == 1) { l.y = 0; p.y = source; }
+      else if (k == 2) { l.z = 0; p.z = source; }
+      else { l.w = 0; p.w = source; }
     }
-    const uint64_t isom = __ballot(iso || v == source);
-    if (ln == 0) {
-      a.visited[w] = isom;
-      a.fcur[w] = (w == (source >> 6)) ? (1ull << (source & 63)) : 0ull;
-      f1[w] = 0ull;
-      f2[w] = 0ull;
-    }
+    reinterpret_cast<int4 *>(a.levels)[i] = l;
+    if (a.parents) reinterpret_cast<int4 *>(a.parents)[i] = p;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  for (int64_t v = n4 * 4 + tid; v < a.n; v += nt) {
+    a.levels[v] = (v == source) ? 0 : -1;
+    if (a.parents) a.parents[v] = (v == source) ? source : -1;
+  }
+  // visited = rows a pull can never reach (no in-edges; padding) + source
+  const int64_t sw = source >> 6;
+  const uint64_t sb = 1ull << (source & 63);
+  for (int64_t w = tid; w < a.nw; w += nt) {
+    uint64_t vis;
+    if (a.can_pull) {
+      vis = a.pull.iso[w];
+    } else {
+      const int64_t valid = a.n - w * 64;  // bits past n are padding
+      vis = valid >= 64 ? 0ull : ~mask_below((int)valid);
+    }
+    a.visited[w] = vis | (w == sw ? sb : 0ull);
+    a.fcur[w] = w == sw ? sb : 0ull;
+    f1[w] = 0ull;
+    f2[w] = 0ull;
+  }
+  if (tid == 0) {
     for (int i = 0; i < kCntSlots; ++i) {
       a.cnt_cur[i] = 0;
       a.cnt_nxt[i] = 0;
@@ -658,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
 
 void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                       void *stream) {
-  int64_t g = (a.nw + kWavesPerBlock - 1) / kWavesPerBlock;
+  int64_t g = (a.n / 4 + kBlock - 1) / kBlock;
   g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
   hipLaunchKernelGGL(k_bfs_start, dim3((unsigned)g), dim3(kBlock), 0, (hipStream_t)stream, a,
                      source, f1, f2);

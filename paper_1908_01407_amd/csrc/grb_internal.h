@@ -47,6 +47,8 @@ struct Csr {
   // (edges of rows up to kPushSplit long plus a fixed cost per word), for
   // kernels that sweep every row: run p is words [wpart[p], wpart[p + 1])
   const int32_t *wpart = nullptr;
+  // rows without entries (and the padding bits past nrows), one bit each
+  const uint64_t *iso = nullptr;
   bool valid() const { return rp != nullptr; }
 };
 
