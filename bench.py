@@ -67,27 +67,34 @@ def first_hit_scan(rp, ci, rows_mask, hit_col):
     return total
 
 
-def parents_pass_bytes(rp, ci, lev, directions, n):
-    """Bytes of the parents pass (run by the first empty level kernel): the
-    level of every vertex (4n), the parent slot of every reached vertex
-    (4 each), and for every vertex a push discovered: its row extents (8),
-    the in-neighbours scanned up to the first one a level up (id and level,
-    8 each) and the parent it writes (4)."""
-    total = 4.0 * n + 4.0 * int((lev > 0).sum())
+def parents_bytes(rp, ci, lev, directions, frontier, n):
+    """Bytes of the parent work per level kernel.  A push from a one-vertex
+    frontier writes each found vertex's parent with its level (4 bytes each,
+    charged to that level).  After a push from several vertices the next
+    level's kernel searches, for each of its frontier vertices, the
+    in-neighbours up to the first one a level up: row extents (8), ids and
+    levels of the scanned neighbours (8 each) and the parent written (4),
+    charged to that next level.  Pull levels find parents while they scan."""
+    out = [0.0] * len(directions)
     for d, dr in enumerate(directions):
         if dr != 1:
             continue
-        rows = lev == d + 1
-        cnt = int(rows.sum())
-        if cnt:
-            total += 12.0 * cnt + 8.0 * first_hit_scan(rp, ci, rows, lev == d)
-    return total
+        nxt = lev == d + 1
+        cnt = int(nxt.sum())
+        if not cnt:
+            continue
+        if frontier[d] == 1:
+            out[d] += 4.0 * cnt
+        elif d + 1 < len(out):
+            out[d + 1] += 12.0 * cnt + 8.0 * first_hit_scan(rp, ci, nxt, lev == d)
+    return out
 
 
 def bfs_bytes_per_level(rp, ci, lev, directions, n):
     """Per-level algorithmic bytes of a BFS level given the direction run.
     push: frontier ids and row extents 12|f|, neighbour ids 4*sum deg(f),
-          visited bitmap probe n/8, next bitmap n/8, parent+level 8|next|.
+          visited bitmap probe n/8, next bitmap n/8, level 4|next| (parents
+          in parents_bytes).
     pull: visited n/8, frontier bitmap n/8, row extents 8R of candidate rows,
           neighbour ids 4*E_scan (early exit), next bitmap n/8, 8|next|."""
     deg = np.diff(rp).astype(np.int64)
@@ -97,7 +104,7 @@ def bfs_bytes_per_level(rp, ci, lev, directions, n):
         nf = int(f.sum())
         nxt = int((lev == d + 1).sum())
         if dr == 1:
-            b = 12 * nf + 4 * int(deg[f].sum()) + n / 8 + n / 8 + 8 * nxt
+            b = 12 * nf + 4 * int(deg[f].sum()) + n / 8 + n / 8 + 4 * nxt
         else:
             cand = ((lev < 0) | (lev > d)) & (deg > 0)
             e_scan = first_hit_scan(rp, ci, cand, f)
@@ -536,8 +543,9 @@ def main():
     rp = A.row_ptr.cpu().numpy()
     ci = A.col_idx.cpu().numpy()
     per_level = bfs_bytes_per_level(rp, ci, levels, st["direction"], n)
-    par_bytes = parents_pass_bytes(rp, ci, levels, st["direction"], n)
-    bytes_step = sum(per_level) + par_bytes
+    par = parents_bytes(rp, ci, levels, st["direction"], st["frontier"], n)
+    per_level = [b + p for b, p in zip(per_level, par)]
+    bytes_step = sum(per_level)
     achieved = bytes_step * args.steps / (exp_ms / 1e3) / 1e9
     reached = int((levels >= 0).sum())
     roofline = {
@@ -556,7 +564,7 @@ def main():
                        "frontier": st["frontier"][i], "edges": st["edges"][i],
                        "bytes": per_level[i], "kernel_us": round(st["kernel_ms"][i] * 1e3, 2)}
                       for i in range(len(per_level))] + [
-            {"level": len(per_level), "dir": "empty level: parents pass", "bytes": par_bytes,
+            {"level": len(per_level), "dir": "empty level (ends the search)", "bytes": 0.0,
              "kernel_us": round((st["expand_ms_all"] - sum(st["kernel_ms"])) * 1e3, 2)}],
     }
     out = {

@@ -46,9 +46,13 @@ def test_path_graph_byte_model():
     deg = np.diff(rp)
     for d in range(4):
         nxt = 1 if d < 3 else 0
-        assert per[d] == 12 * 1 + 4 * deg[d] + n / 8 + n / 8 + 8 * nxt
-    # parents pass: 4n + 4 per reached vertex (levels > 0: 3), and for each
-    # push-discovered vertex 12 + 8 x (scan to its first neighbour a level up)
-    # vertex 1: neighbours [0, 2] -> 0 hits first (1 edge); vertex 2: [1, 3]
-    # -> 1 edge; vertex 3: [2] -> 1 edge
-    assert bench.parents_pass_bytes(rp, ci, lev, dirs, n) == 4 * n + 4 * 3 + 3 * 12 + 8 * 3
+        assert per[d] == 12 * 1 + 4 * deg[d] + n / 8 + n / 8 + 4 * nxt
+    # parents: level 0's frontier is one vertex, so vertex 1's parent is
+    # written with its level (4 bytes); levels 1 and 2 push from one vertex
+    # each too (the path), so every parent is written at claim
+    assert bench.parents_bytes(rp, ci, lev, dirs, [1, 1, 1, 1], n) == [4.0, 4.0, 4.0, 0.0]
+    # with a frontier of several vertices at level 1, level 2's kernel finds
+    # vertex 2's parent: 12 + 8 x (neighbours [1, 3] -> 1 hits first: 1 edge);
+    # level 2 (one vertex) still writes vertex 3's parent at claim (4)
+    assert bench.parents_bytes(rp, ci, lev, dirs, [1, 2, 1, 1], n) == [4.0, 0.0, 12.0 + 8.0 + 4.0,
+                                                                        0.0]
