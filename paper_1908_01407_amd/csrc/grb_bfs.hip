@@ -45,9 +45,10 @@ __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
 // The degree loads of all won targets are issued together.
 // With a one-vertex frontier (`single`) that vertex, par[s], is the only
 // parent a target can have, and it is written at once.
+// `next_set`: the caller has already set the targets' next-frontier bits.
 __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnroll],
                                           const bool (&won)[kUnroll], const int (&par)[kUnroll],
-                                          bool single, int &fc, int &fd, int &fl) {
+                                          bool single, bool next_set, int &fc, int &fd, int &fl) {
   int d0[kUnroll], d1[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
@@ -56,7 +57,8 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
     if (won[s]) {
       a.levels[c[s]] = a.d + 1;
       if (single && a.parents) a.parents[c[s]] = par[s];
-      atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], 1ull << (c[s] & 63));
+      if (!next_set)
+        atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], 1ull << (c[s] & 63));
       d0[s] = a.push.rp[c[s]];
       d1[s] = a.push.rp[c[s] + 1];
     }
@@ -89,7 +91,7 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
   bool won[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) won[s] = c[s] >= 0 && !((old[s] >> (c[s] & 63)) & 1ull);
-  claim_won(a, c, won, par, single, fc, fd, fl);
+  claim_won(a, c, won, par, single, false, fc, fd, fl);
 }
 
 // Claims the targets of one piece of a row: ascending and distinct, so the
@@ -103,24 +105,28 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
   bool want[kUnroll];
-  uint64_t old[kUnroll];
+  uint64_t old[kUnroll], run[kUnroll];
+  int64_t wd[kUnroll];
   int tail[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     want[s] = c[s] >= 0 && !((vw[s] >> (c[s] & 63)) & 1ull);
-    const int64_t wd = want[s] ? (int64_t)(c[s] >> 6) : -1;
-    const uint64_t run = run_tail_or(wd, want[s] ? (1ull << (c[s] & 63)) : 0ull, tail[s]);
+    wd[s] = want[s] ? (int64_t)(c[s] >> 6) : -1;
+    run[s] = run_tail_or(wd[s], want[s] ? (1ull << (c[s] & 63)) : 0ull, tail[s]);
     old[s] = 0ull;
-    if (run && wd >= 0)
-      old[s] = atomicOr((unsigned long long *)&a.visited[wd], (unsigned long long)run);
+    if (run[s] && wd[s] >= 0)
+      old[s] = atomicOr((unsigned long long *)&a.visited[wd[s]], (unsigned long long)run[s]);
   }
   bool won[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     const uint64_t ow = __shfl(old[s], tail[s]);
     won[s] = want[s] && !((ow >> (c[s] & 63)) & 1ull);
+    // the run's tail also sets the won bits of the next frontier at once
+    if (run[s] && wd[s] >= 0 && (run[s] & ~old[s]))
+      atomicOr((unsigned long long *)&a.fnxt[wd[s]], (unsigned long long)(run[s] & ~old[s]));
   }
-  claim_won(a, c, won, par, single, fc, fd, fl);
+  claim_won(a, c, won, par, single, true, fc, fd, fl);
 }
 
 // Each wave loads 64 bitmap words at once (one per lane) and compacts their
