@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -335,6 +336,63 @@ struct EventPool {
 };
 thread_local EventPool g_events;
 
+// ---- control-block readback ----------------------------------------------------
+// The drivers read their control block back once per batch of launches.  A
+// device-to-host copy into pageable memory goes through the runtime's bounce
+// buffer and takes about twice the round trip of one into pinned memory, so
+// the copies land in a pinned staging buffer (one per host thread, grown on
+// demand, kept for the thread's lifetime) and are then copied on the host.
+struct Staging {
+  char *buf = nullptr;
+  size_t cap = 0;
+  char *get(size_t bytes) {
+    if (bytes <= cap) return buf;
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    if (hipHostMalloc((void **)&buf, bytes, hipHostMallocDefault) != hipSuccess) {
+      buf = nullptr;
+      return nullptr;
+    }
+    cap = bytes;
+    return buf;
+  }
+};
+thread_local Staging g_staging;
+
+struct Region {
+  void *dst;        // host destination
+  const void *src;  // device source
+  size_t bytes;
+};
+
+// Copies every region device-to-host on stream s and waits for the stream.
+// Falls back to direct copies if no pinned memory can be had.  False on any
+// HIP error.
+bool read_back(std::initializer_list<Region> regs, hipStream_t s) {
+  auto slot = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t total = 0;
+  for (const Region &r : regs) total += slot(r.bytes);
+  char *st = g_staging.get(total);
+  size_t off = 0;
+  for (const Region &r : regs) {
+    if (r.bytes == 0) continue;
+    void *to = st ? (void *)(st + off) : r.dst;
+    if (hipMemcpyAsync(to, r.src, r.bytes, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+    off += slot(r.bytes);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  if (st) {
+    off = 0;
+    for (const Region &r : regs) {
+      if (r.bytes == 0) continue;
+      std::memcpy(r.dst, st + off, r.bytes);
+      off += slot(r.bytes);
+    }
+  }
+  return true;
+}
+
 void finish_stats(int op, int iterations, const std::vector<int64_t> &rec,
                   const std::vector<float> &kms, int launches, double ms_all) {
   grb_stats &s = g_stats;
@@ -422,9 +480,8 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(host.data(), w.ctrl, host.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return GRB_PANIC;
+    const size_t recs = (size_t)std::min<int64_t>(d, kStatsCap) * kStatFields * sizeof(int64_t);
+    if (!read_back({{host.data(), w.ctrl, head + recs}}, s)) return GRB_PANIC;
     std::memcpy(&hc, host.data(), sizeof(Ctrl));
     if (hc.nlev < d) {  // a launched level found the frontier empty
       empty_seen = true;
@@ -513,9 +570,7 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return GRB_PANIC;
+    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
     int64_t next = 0;
     for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + kCntFields * t];
     if (next == 0 || d >= cap) break;
@@ -524,10 +579,8 @@ grb_info run_sssp(grb_matrix A, int32_t source, float *dist, const grb_descripto
   const int iters = hc.nlev;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
-  if (nrec > 0 && hipMemcpyAsync(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
-                                 hipMemcpyDeviceToHost, s) != hipSuccess)
+  if (!read_back({{rec.data(), w.stats, (size_t)std::max(nrec, 0) * kStatFields * sizeof(int64_t)}}, s))
     return GRB_PANIC;
-  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
@@ -594,9 +647,8 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(host.data(), w.ctrl, host.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return GRB_PANIC;
+    const size_t recs = (size_t)std::min<int64_t>(d, kStatsCap) * kStatFields * sizeof(int64_t);
+    if (!read_back({{host.data(), w.ctrl, head + recs}}, s)) return GRB_PANIC;
     std::memcpy(&hc, host.data(), sizeof(Ctrl));
     if (hc.nlev < d || d >= cap) break;  // a launched round found nothing pending
     chunk = std::min(chunk * 2, 512);
@@ -850,9 +902,7 @@ grb_info grb_vector_nvals(grb_vector v, int64_t *nvals, void *ws, size_t ws_byte
   launch_popcount(v->bitmap, words_of(v->n), (int64_t *)ws, stream);
   if ((info = check_launch()) != GRB_SUCCESS) return info;
   int64_t h = 0;
-  if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return GRB_PANIC;
+  if (!read_back({{&h, ws, sizeof(h)}}, s)) return GRB_PANIC;
   *nvals = h;
   return GRB_SUCCESS;
 }
@@ -1006,10 +1056,9 @@ grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)dlev + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(hcnt.data(), w.cnt, hcnt.size() * sizeof(unsigned long long),
-                       hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+    if (!read_back({{hcnt.data(), w.cnt, hcnt.size() * sizeof(unsigned long long)},
+                    {&hc, w.ctrl, sizeof(Ctrl)}},
+                   s))
       return GRB_PANIC;
     unsigned long long next = 0;
     for (int t = 0; t < kCntStripes; ++t) next += hcnt[(size_t)(dlev % 3) * 2 * kCntStripes + 2 * t];
@@ -1019,10 +1068,8 @@ grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_
   const int iters = hc.nlev;
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
-  if (nrec > 0 && hipMemcpyAsync(rec.data(), w.stats, (size_t)nrec * kStatFields * sizeof(int64_t),
-                                 hipMemcpyDeviceToHost, s) != hipSuccess)
+  if (!read_back({{rec.data(), w.stats, (size_t)std::max(nrec, 0) * kStatFields * sizeof(int64_t)}}, s))
     return GRB_PANIC;
-  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
@@ -1084,15 +1131,11 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int3
       if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k + 1), s);
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return GRB_PANIC;
+    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
     if (hc.converged) break;
   }
   if (max_iter == 0) {
-    if (hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return GRB_PANIC;
+    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
   }
   *iters = hc.iters;
   if (delta_out) *delta_out = hc.delta;
