@@ -13,6 +13,9 @@ computes, written from the paper (GraphBLAST, Yang, Buluc and Owens):
   the paper's Bellman-Ford variant (Section 7.2) converges to.
 * :func:`pagerank` — FP64 power iteration (Section 7.3) with uniform
   redistribution of dangling mass and an L1 stopping rule.
+* :func:`pagerank_adaptive` — adaptive PageRank (PageRankDelta): the same
+  iteration with converged vertices frozen (the masked form named in
+  Sections 3.2 and 7.3).
 * :func:`msbfs` — k independent BFS runs (multi-nodeset traversal).
 * :mod:`oracle.mxv` — the plain-loop masked semiring mxv / vxm.
 
@@ -73,6 +76,8 @@ def _load():
         lib.oracle_sssp.restype = i64
         lib.oracle_pagerank.argtypes = [p, f64, i32, f64, p, p]
         lib.oracle_pagerank.restype = i32
+        lib.oracle_pagerank_adaptive.argtypes = [p, f64, i32, f64, f64, p, p, p, p]
+        lib.oracle_pagerank_adaptive.restype = i32
         lib.oracle_msbfs.argtypes = [p, i64, p, p, i32]
         lib.oracle_msbfs.restype = i32
         _lib = lib
@@ -157,6 +162,22 @@ def pagerank(adj_out: Adjacency, alpha=0.85, max_iter=50, tol=1e-7):
     if it < 0:
         raise ValueError("oracle_pagerank: bad input")
     return p, int(it), float(delta.value)
+
+
+def pagerank_adaptive(adj_out: Adjacency, eps: float, alpha=0.85, max_iter=50, tol=1e-7):
+    """Adaptive PageRank (PageRankDelta): (p float64[n], iterations run, last
+    L1 delta, vertices still active, frozen_at int32[n] = iteration at which
+    each vertex froze, 0 if never)."""
+    p = np.empty(adj_out.n, dtype=np.float64)
+    fz = np.empty(adj_out.n, dtype=np.int32)
+    delta = ctypes.c_double(0.0)
+    active = ctypes.c_int64(0)
+    it = _load().oracle_pagerank_adaptive(adj_out._h, float(alpha), int(max_iter), float(tol),
+                                          float(eps), _ptr(p), _ptr(fz), ctypes.byref(delta),
+                                          ctypes.byref(active))
+    if it < 0:
+        raise ValueError("oracle_pagerank_adaptive: bad input")
+    return p, int(it), float(delta.value), int(active.value), fz
 
 
 def msbfs(adj: Adjacency, sources, nthreads: int = 1):

@@ -325,6 +325,68 @@ int32_t oracle_pagerank(const oracle_adj *a, double alpha, int32_t max_iter,
   return it;
 }
 
+/*
+ * Adaptive PageRank (PageRankDelta, named in Sections 3.2 and 7.3 as the
+ * masked form of PageRank: the mask holds the vertices that have already
+ * converged, whose values are no longer updated; Kamvar, Haveliwala and
+ * Golub's adaptive method).  Starting from p = 1/n with every vertex
+ * active, each iteration
+ *   D      = sum of p(u) over all vertices u without out-edges (frozen ones
+ *            included),
+ *   p'(v)  = (1-alpha)/n + alpha * (sum_{u->v} p(u)/outdeg(u) + D/n)
+ *            for active v;  p'(v) = p(v) for frozen v,
+ *   delta  = ||p' - p||_1,
+ * and then freezes every active v with |p'(v) - p(v)| <= eps * p(v) (its
+ * change relative to the previous iterate); a frozen vertex stays frozen.
+ * Stops after max_iter iterations, as soon as delta < tol, or when no
+ * vertex is left active.  p receives the values, frozen_at (may be NULL)
+ * the iteration (1-based) at which each vertex froze or 0 if it never
+ * did, *active_out (may be NULL) the count still active.  Returns the
+ * iterations run, or -1 on bad input.
+ */
+int32_t oracle_pagerank_adaptive(const oracle_adj *a, double alpha, int32_t max_iter,
+                                 double tol, double eps, double *p, int32_t *frozen_at,
+                                 double *delta_out, int64_t *active_out) {
+  const int64_t n = a->n;
+  if (n <= 0 || max_iter < 0 || !(eps >= 0.0)) return -1;
+  double *q = (double *)malloc((size_t)n * sizeof(double));
+  int32_t *fz = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!q || !fz) { free(q); free(fz); return -1; }
+  for (int64_t v = 0; v < n; ++v) { p[v] = 1.0 / (double)n; fz[v] = 0; }
+  int64_t active = n;
+  int32_t it = 0;
+  double delta = INFINITY;
+  while (it < max_iter && active > 0) {
+    double dangling = 0.0;
+    for (int64_t u = 0; u < n; ++u)
+      if (a->off[u + 1] == a->off[u]) dangling += p[u];
+    for (int64_t v = 0; v < n; ++v) q[v] = 0.0;
+    for (int64_t u = 0; u < n; ++u) {
+      const int64_t deg = a->off[u + 1] - a->off[u];
+      if (deg == 0) continue;
+      const double share = p[u] / (double)deg;
+      for (int64_t e = a->off[u]; e < a->off[u + 1]; ++e) q[a->nbr[e]] += share;
+    }
+    ++it;
+    delta = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+      if (fz[v]) continue;  /* frozen: p'(v) = p(v) */
+      const double nv = (1.0 - alpha) / (double)n + alpha * (q[v] + dangling / (double)n);
+      const double ch = fabs(nv - p[v]);
+      delta += ch;
+      if (ch <= eps * p[v]) { fz[v] = it; --active; }
+      p[v] = nv;
+    }
+    if (delta < tol) break;
+  }
+  if (frozen_at) memcpy(frozen_at, fz, (size_t)n * sizeof(int32_t));
+  free(q);
+  free(fz);
+  if (delta_out) *delta_out = delta;
+  if (active_out) *active_out = active;
+  return it;
+}
+
 /* ------------------------------------------------------------------ */
 /* batched BFS: k independent single-source runs                       */
 /* ------------------------------------------------------------------ */
