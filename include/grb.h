@@ -345,6 +345,27 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping,
                       const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Adaptive PageRank (PageRankDelta, the masked PageRank of Sections 3.2
+ * and 7.3: the mask holds the vertices that have converged, which are no
+ * longer updated, so an iteration touches only the in-edges of the active
+ * rows).  As grb_pagerank, except that each iteration updates only the
+ * active vertices (a frozen vertex keeps its value, and D still sums the
+ * frozen dangling ones) and then freezes every active v whose change
+ * satisfies |p'(v) - p(v)| <= eps * p(v), p(v) being the previous iterate.
+ * Stops after max_iter iterations, once delta < tol, or when no vertex is
+ * left active.  *active_out (may be NULL) receives the count still active.
+ * Stats record per iteration the active vertices, their in-edges, direction
+ * pull and the count active after it.  Same workspace as grb_pagerank
+ * (GRB_OP_PAGERANK).  eps negative or not finite: GRB_INVALID_VALUE; other
+ * errors as grb_pagerank.
+ */
+grb_info grb_pagerank_adaptive(void *p, grb_type type, grb_matrix A, double damping,
+                               int32_t max_iter, double tol, double eps, int32_t *iters,
+                               double *delta_out, int64_t *active_out,
+                               const grb_descriptor *d, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/*
  * Batched multi-source BFS: k traversals at once as one masked product of
  * A^T with a bitmask block of frontiers (multi-nodeset traversal, Table 6
  * and Section 3.3; matrix-matrix direction optimisation is the paper's

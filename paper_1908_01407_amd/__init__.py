@@ -118,6 +118,10 @@ _SIGS = {
     "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
                       ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_pagerank_adaptive": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
+                               ctypes.c_double, ctypes.POINTER(_i32),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
 }
 
 #: every C symbol this binding exposes, with its ctypes function
@@ -411,6 +415,28 @@ def pagerank(A: Matrix, *, dtype=None, damping: float = 0.85, max_iter: int = 50
                             ctypes.byref(desc) if desc is not None else None, _ptr(ws),
                             ws.numel(), _stream(stream)), "grb_pagerank")
     return p[: A.nrows], iters.value, delta.value
+
+
+def pagerank_adaptive(A: Matrix, eps: float, *, dtype=None, damping: float = 0.85,
+                      max_iter: int = 50, tol: float = 1e-7, desc: Descriptor | None = None,
+                      ws=None, stream=None):
+    """(p[n], iterations, last L1 delta, vertices still active) via
+    grb_pagerank_adaptive (converged vertices frozen once their relative
+    change is at most eps)."""
+    torch = _torch()
+    dtype = dtype if dtype is not None else torch.float32
+    t = GRB_FP64 if dtype == torch.float64 else GRB_FP32
+    p = torch.empty(max(A.nrows, 1), dtype=dtype, device=A.device)
+    ws = ws if ws is not None else workspace(OP_PAGERANK, A, 2 if t == GRB_FP64 else 1)
+    iters = ctypes.c_int32()
+    delta = ctypes.c_double()
+    active = ctypes.c_int64()
+    check(_lib.grb_pagerank_adaptive(_ptr(p), t, A.handle, float(damping), int(max_iter),
+                                     float(tol), float(eps), ctypes.byref(iters),
+                                     ctypes.byref(delta), ctypes.byref(active),
+                                     ctypes.byref(desc) if desc is not None else None, _ptr(ws),
+                                     ws.numel(), _stream(stream)), "grb_pagerank_adaptive")
+    return p[: A.nrows], iters.value, delta.value, active.value
 
 
 def mxv(w: Vector, mask: Vector | None, accum, semiring: str, A: Matrix, u: Vector, *,

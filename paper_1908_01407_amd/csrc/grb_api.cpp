@@ -127,8 +127,10 @@ MsWs ms_layout(void *ws, int64_t n, int64_t k) {
 
 struct PrWs {
   Ctrl *ctrl;
+  int64_t *stats;
   void *x0, *x1, *heavy_part;
   double *blk_part;
+  uint64_t *act[3];  // adaptive PageRank: rotating activity bitmaps
   int nblk, nblk_long;
   size_t bytes;
 };
@@ -139,10 +141,12 @@ PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
   t.nblk = kExpandGrid;
   t.nblk_long = pr_long_grid(pull.nsplit_rows);
   t.ctrl = c.take<Ctrl>(1);
+  t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
   t.x0 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
   t.x1 = c.take<char>((size_t)std::max<int64_t>(n, 1) * esize);
   t.heavy_part = c.take<char>((size_t)std::max<int64_t>(pull.nsplit, 1) * esize);
-  t.blk_part = c.take<double>((size_t)2 * (t.nblk + t.nblk_long));
+  t.blk_part = c.take<double>((size_t)kPrFields * (t.nblk + t.nblk_long));
+  for (int i = 0; i < 3; ++i) t.act[i] = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n), 1));
   t.bytes = c.off;
   return t;
 }
@@ -671,6 +675,102 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
   return GRB_SUCCESS;
 }
 
+// PageRank and adaptive PageRank: batches of 8 iterations, the host reads
+// the control block back after each batch (the device decides convergence).
+grb_info run_pagerank(void *p, grb_type type, grb_matrix A, double damping, int32_t max_iter,
+                      double tol, bool adaptive, double eps, int32_t *iters, double *delta_out,
+                      int64_t *active_out, const grb_descriptor *d, void *ws, size_t ws_bytes,
+                      void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!p || !iters) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (type != GRB_FP32 && type != GRB_FP64) return GRB_DOMAIN_MISMATCH;
+  if (A->nrows == 0 || max_iter < 0 || !(damping >= 0.0 && damping <= 1.0) || !(tol >= 0.0))
+    return GRB_INVALID_VALUE;
+  if (!A->at.valid()) return GRB_NOT_IMPLEMENTED;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  const int is64 = type == GRB_FP64;
+  const int64_t n = A->nrows;
+  PrWs w = pr_layout(ws, n, A->at, is64 ? 8 : 4);
+  if ((info = check_ws(ws, ws_bytes, w.bytes)) != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+  PrArgs pa;
+  pa.n = n;
+  pa.nw = words_of(n);
+  pa.pull = A->at;
+  pa.out_rp = A->a.rp;
+  pa.p = p;
+  pa.x = w.x0;
+  pa.xn = w.x0;
+  pa.heavy_part = w.heavy_part;
+  pa.blk_part = w.blk_part;
+  pa.nblk = w.nblk;
+  pa.nblk_long = w.nblk_long;
+  pa.ctrl = w.ctrl;
+  pa.stats = w.stats;
+  pa.alpha = damping;
+  pa.tol = tol;
+  pa.eps = eps;
+  auto at_iter = [&](int k) {
+    if (!adaptive) return;
+    pa.act_cur = w.act[k % 3];
+    pa.act_nxt = w.act[(k + 1) % 3];
+    pa.act_prev = w.act[(k + 2) % 3];
+  };
+  at_iter(0);
+  launch_pr_init(is64, pa, stream);
+  Ctrl hc{};
+  int k = 0;
+  while (k < max_iter) {
+    const int stop = std::min(max_iter, k + 8);
+    for (; k < stop; ++k) {
+      pa.x = (k % 2 == 0) ? w.x0 : w.x1;
+      pa.xn = (k % 2 == 0) ? w.x1 : w.x0;
+      at_iter(k);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k), s);
+      launch_pr_iter(is64, pa, stream);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k + 1), s);
+    }
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
+    if (hc.converged) break;
+  }
+  if (max_iter == 0) {
+    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
+  }
+  *iters = hc.iters;
+  if (delta_out) *delta_out = hc.delta;
+  if (active_out) *active_out = adaptive ? hc.active : 0;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  const int nrec = std::min(hc.iters, (int)kStatsCap);
+  if (adaptive) {
+    if (!read_back({{rec.data(), w.stats, (size_t)std::max(nrec, 0) * kStatFields * sizeof(int64_t)}},
+                   s))
+      return GRB_PANIC;
+  } else {
+    for (int i = 0; i < nrec; ++i) {
+      rec[(size_t)i * kStatFields + 0] = n;
+      rec[(size_t)i * kStatFields + 1] = A->nnz;
+      rec[(size_t)i * kStatFields + 2] = GRB_DIR_PULL;
+    }
+  }
+  std::vector<float> kms;
+  double ms_all = 0.0;
+  if (profile) {
+    for (int i = 0; i < k; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
+      if (i < nrec) kms.push_back(ms);
+      ms_all += ms;
+    }
+  }
+  finish_stats(GRB_OP_PAGERANK, hc.iters, rec, kms, k, ms_all);
+  return GRB_SUCCESS;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1087,76 +1187,17 @@ grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_
 grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping, int32_t max_iter,
                       double tol, int32_t *iters, double *delta_out, const grb_descriptor *d,
                       void *ws, size_t ws_bytes, void *stream) {
-  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
-  if (!p || !iters) return GRB_NULL_POINTER;
-  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
-  if (type != GRB_FP32 && type != GRB_FP64) return GRB_DOMAIN_MISMATCH;
-  if (A->nrows == 0 || max_iter < 0 || !(damping >= 0.0 && damping <= 1.0) || !(tol >= 0.0))
-    return GRB_INVALID_VALUE;
-  if (!A->at.valid()) return GRB_NOT_IMPLEMENTED;
-  grb_descriptor desc;
-  grb_info info = resolve_desc(d, &desc);
-  if (info != GRB_SUCCESS) return info;
-  const int is64 = type == GRB_FP64;
-  const int64_t n = A->nrows;
-  PrWs w = pr_layout(ws, n, A->at, is64 ? 8 : 4);
-  if ((info = check_ws(ws, ws_bytes, w.bytes)) != GRB_SUCCESS) return info;
-  hipStream_t s = (hipStream_t)stream;
-  const bool profile = (desc.flags & GRB_PROFILE) != 0;
-  PrArgs pa;
-  pa.n = n;
-  pa.nw = words_of(n);
-  pa.pull = A->at;
-  pa.out_rp = A->a.rp;
-  pa.p = p;
-  pa.x = w.x0;
-  pa.xn = w.x0;
-  pa.heavy_part = w.heavy_part;
-  pa.blk_part = w.blk_part;
-  pa.nblk = w.nblk;
-  pa.nblk_long = w.nblk_long;
-  pa.ctrl = w.ctrl;
-  pa.alpha = damping;
-  pa.tol = tol;
-  launch_pr_init(is64, pa, stream);
-  Ctrl hc{};
-  int k = 0;
-  while (k < max_iter) {
-    const int stop = std::min(max_iter, k + 8);
-    for (; k < stop; ++k) {
-      pa.x = (k % 2 == 0) ? w.x0 : w.x1;
-      pa.xn = (k % 2 == 0) ? w.x1 : w.x0;
-      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k), s);
-      launch_pr_iter(is64, pa, stream);
-      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)k + 1), s);
-    }
-    if ((info = check_launch()) != GRB_SUCCESS) return info;
-    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
-    if (hc.converged) break;
-  }
-  if (max_iter == 0) {
-    if (!read_back({{&hc, w.ctrl, sizeof(Ctrl)}}, s)) return GRB_PANIC;
-  }
-  *iters = hc.iters;
-  if (delta_out) *delta_out = hc.delta;
-  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
-  std::vector<float> kms;
-  double ms_all = 0.0;
-  for (int i = 0; i < k; ++i) {
-    if (i < std::min(hc.iters, (int)kStatsCap)) {
-      rec[(size_t)i * kStatFields + 0] = n;
-      rec[(size_t)i * kStatFields + 1] = A->nnz;
-      rec[(size_t)i * kStatFields + 2] = GRB_DIR_PULL;
-    }
-    if (profile) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
-      if (i < std::min(hc.iters, (int)kStatsCap)) kms.push_back(ms);
-      ms_all += ms;
-    }
-  }
-  finish_stats(GRB_OP_PAGERANK, hc.iters, rec, kms, k, ms_all);
-  return GRB_SUCCESS;
+  return run_pagerank(p, type, A, damping, max_iter, tol, false, 0.0, iters, delta_out, nullptr,
+                      d, ws, ws_bytes, stream);
+}
+
+grb_info grb_pagerank_adaptive(void *p, grb_type type, grb_matrix A, double damping,
+                               int32_t max_iter, double tol, double eps, int32_t *iters,
+                               double *delta_out, int64_t *active_out, const grb_descriptor *d,
+                               void *ws, size_t ws_bytes, void *stream) {
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return GRB_INVALID_VALUE;
+  return run_pagerank(p, type, A, damping, max_iter, tol, true, eps, iters, delta_out,
+                      active_out, d, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

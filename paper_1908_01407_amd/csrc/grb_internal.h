@@ -87,6 +87,8 @@ struct Ctrl {
   int32_t bucket;             // bucketed SSSP: the bucket of the last round
   int32_t pushed[3];          // BFS: buffer's frontier came from a push of > 1 vertex
                               // (its vertices' parents are still open)
+  double Dfz;                 // adaptive PageRank: dangling mass of the frozen vertices
+  int64_t active;             // adaptive PageRank: vertices still active
   int64_t pad[4];
 };
 
@@ -181,16 +183,26 @@ struct PrArgs {
   const void *x = nullptr;     // p / outdeg of the current iterate
   void *xn = nullptr;          // next x
   void *heavy_part = nullptr;  // partial sums of the pieces of long rows
-  double *blk_part = nullptr;  // per workgroup {delta, dangling} partials
+  double *blk_part = nullptr;  // per workgroup partials, kPrFields each
   int nblk = 0;                // workgroups of the SpMV kernel (kExpandGrid)
   int nblk_long = 0;           // workgroups of the long-row kernel
   Ctrl *ctrl = nullptr;
+  int64_t *stats = nullptr;    // adaptive: per-iteration {active rows, their in-edges, pull}
   double alpha = 0.85;
   double tol = 0.0;
+  // adaptive PageRank: bit v of act_cur = vertex v still updated in this
+  // iteration, act_prev = in the previous one, act_nxt = in the next one
+  // (written here); nullptr for plain PageRank
+  uint64_t *act_cur = nullptr, *act_prev = nullptr, *act_nxt = nullptr;
+  double eps = 0.0;  // freeze when |p' - p| <= eps * p
 };
+// per-workgroup partials of a PageRank iteration: L1 change, dangling mass
+// of the updated vertices, dangling mass of the vertices frozen now,
+// vertices active after the iteration, vertices and in-edges updated
+constexpr int kPrFields = 6;
 int pr_long_grid(int64_t nsplit_rows);  // workgroups of the long-row kernel
 void launch_pr_init(int is_fp64, const PrArgs &a, void *stream);
-void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream);
+void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream);  // adaptive iff a.act_cur
 
 // generic helpers
 void launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, void *stream);

@@ -1,5 +1,9 @@
 // PageRank iteration kernels (Section 7.3 of the paper: pull form, SpMV
-// every iteration because the vector never gets sparse).
+// every iteration because the vector never gets sparse), and the adaptive
+// form (PageRankDelta, named in Sections 3.2 and 7.3): the mask holds the
+// vertices that have converged, whose values stay frozen, so only the rows
+// of the others are computed and the work of an iteration is the in-edges
+// of its active rows.
 //
 // Load balance: each wave takes a run of bitmap words of rows (64
 // consecutive rows of the CSR of A^T each), runs of about equal work built
@@ -12,6 +16,14 @@
 // reproducible run to run.  The dangling mass and the L1 change are reduced
 // per workgroup and then in a fixed order in the fix-up kernel, which also
 // decides convergence on the device.
+//
+// Adaptive: three rotating activity bitmaps (this iteration, the previous
+// one, the next one).  A wave owns the words of its run, so it writes each
+// word of the next bitmap with one store (long rows stay set there and
+// their kernel clears the bit of a row that freezes).  A vertex frozen in
+// the previous iteration copies its x into the other buffer once; from
+// then on both buffers hold it.  The dangling mass of frozen vertices is
+// kept as a running sum on the device.
 #include <hip/hip_runtime.h>
 
 #include "grb_device.h"
@@ -27,25 +39,24 @@ __device__ __forceinline__ T rank_update(const PrArgs &a, T t, T dn) {
   return base + alpha * (t + dn);
 }
 
-template <class T>
-__device__ __forceinline__ void block_partials(double delta, double dang, double *out) {
-  __shared__ double s_red[kWavesPerBlock][2];
-  delta = wave_sum_f64(delta);
-  dang = wave_sum_f64(dang);
+// Sums each of the kPrFields partials over the workgroup (fixed order);
+// thread 0 writes them to out[kPrFields * blockIdx.x + f].
+__device__ __forceinline__ void block_partials(double (&v)[kPrFields], double *out) {
+  __shared__ double s_red[kWavesPerBlock][kPrFields];
   const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    s_red[wid][0] = delta;
-    s_red[wid][1] = dang;
+#pragma unroll
+  for (int f = 0; f < kPrFields; ++f) {
+    v[f] = wave_sum_f64(v[f]);
+    if ((threadIdx.x & 63) == 0) s_red[wid][f] = v[f];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double d0 = 0, d1 = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) {
-      d0 += s_red[i][0];
-      d1 += s_red[i][1];
+#pragma unroll
+    for (int f = 0; f < kPrFields; ++f) {
+      double t = 0;
+      for (int i = 0; i < kWavesPerBlock; ++i) t += s_red[i][f];
+      out[kPrFields * blockIdx.x + f] = t;
     }
-    out[2 * blockIdx.x + 0] = d0;
-    out[2 * blockIdx.x + 1] = d1;
   }
 }
 
@@ -55,8 +66,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
   T *xn = (T *)a.xn;
   const T p0 = (T)(1.0 / (double)a.n);
   double dang = 0;
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < a.n;
-       v += (int64_t)gridDim.x * kBlock) {
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * kBlock;
+  for (int64_t v = tid; v < a.n; v += nt) {
     p[v] = p0;
     const int od = a.out_rp[v + 1] - a.out_rp[v];
     if (od == 0) {
@@ -66,10 +78,21 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
       xn[v] = p0 / (T)od;
     }
   }
-  block_partials<T>(0.0, dang, a.blk_part);
+  // adaptive: every vertex is active in the first iteration and counts as
+  // active in the one before it (so nothing is carried over)
+  if (a.act_cur) {
+    for (int64_t w = tid; w < a.nw; w += nt) {
+      const int64_t valid = a.n - w * 64;
+      const uint64_t m = valid >= 64 ? ~0ull : mask_below((int)valid);
+      a.act_cur[w] = m;
+      a.act_prev[w] = m;
+    }
+  }
+  double v[kPrFields] = {0.0, dang, 0.0, 0.0, 0.0, 0.0};
+  block_partials(v, a.blk_part);
 }
 
-template <class T>
+template <class T, bool AD>
 __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   if (a.ctrl->converged) return;
@@ -82,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   T *xn = (T *)a.xn;
   T *p = (T *)a.p;
   const T dn = (T)(a.ctrl->D / (double)a.n);
-  double delta = 0, dang = 0;
+  double delta = 0, dang = 0, dfz = 0, after = 0, upd = 0, edges = 0;
   // rows up to kPushSplit long: the wave's run of words (about equal work
   // per run), one word of rows per step; kUnroll x 64 edges per step (slot
   // positions first, then all gathers, then the segmented sums in slot order)
@@ -91,14 +114,30 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   for (int64_t w = wlo; w < whi; ++w) {
     const int64_t v = w * 64 + ln;
     const bool inb = v < a.n;
+    uint64_t on_m = ~0ull;
+    if (AD) {
+      on_m = a.act_cur[w];
+      const uint64_t was = a.act_prev[w];
+      // frozen in the previous iteration: x enters the other buffer once
+      if (inb && (((was & ~on_m) >> ln) & 1ull)) xn[v] = x[v];
+      if (!on_m) {  // the word's rows are all frozen
+        if (ln == 0) a.act_nxt[w] = 0ull;
+        continue;
+      }
+    }
+    const bool on = inb && ((on_m >> ln) & 1ull);
     int cur = 0, end = 0;
     bool split = false;
-    if (inb) {
+    if (on) {
       cur = rp[v];
       end = rp[v + 1];
       split = end - cur > kPushSplit;
+      if (AD) {
+        upd += 1.0;
+        edges += (double)(end - cur);
+      }
     }
-    const bool act = inb && !split;
+    const bool act = on && !split;
     if (!act) end = cur;
     T acc = (T)0;
     for (bool more = true; more;) {
@@ -141,9 +180,12 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
         if (st[s]) acc += seg;
       }
     }
+    bool keep = false;
     if (act) {
+      const T po = p[v];
       const T pn = rank_update<T>(a, acc, dn);
-      delta += fabs((double)pn - (double)p[v]);
+      const double ch = fabs((double)pn - (double)po);
+      delta += ch;
       p[v] = pn;
       const int od = a.out_rp[v + 1] - a.out_rp[v];
       if (od == 0) {
@@ -151,6 +193,18 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
         dang += (double)pn;
       } else {
         xn[v] = pn / (T)od;
+      }
+      if (AD) {
+        keep = !(ch <= a.eps * (double)po);
+        if (!keep && od == 0) dfz += (double)pn;
+      }
+    }
+    if (AD) {
+      // long rows stay set; their kernel clears the bit if they freeze
+      const uint64_t nx = __ballot(keep || (on && split));
+      if (ln == 0) {
+        a.act_nxt[w] = nx;
+        after += (double)__popcll(nx);
       }
     }
   }
@@ -167,8 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
       pb[q] = pe[q] = 0;
       if (ph[q] < a.pull.nsplit) {
         const int r = a.pull.split[2 * ph[q]];
-        pb[q] = a.pull.split[2 * ph[q] + 1];
-        pe[q] = min(pb[q] + kPushSplit, rp[r + 1]);
+        if (!AD || bit_of(a.act_cur, r)) {  // frozen rows: no work
+          pb[q] = a.pull.split[2 * ph[q] + 1];
+          pe[q] = min(pb[q] + kPushSplit, rp[r + 1]);
+        }
       }
     }
     int c[2][kUnroll];
@@ -191,73 +247,100 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
       if (ln == 0 && ph[q] < a.pull.nsplit) hp[ph[q]] = sum;
     }
   }
-  block_partials<T>(delta, dang, a.blk_part);
+  double pv[kPrFields] = {delta, dang, dfz, after, upd, edges};
+  block_partials(pv, a.blk_part);
 }
 
 // Long rows: one thread per row adds the row's pieces in order and updates
 // its rank; per-workgroup partials follow those of the SpMV kernel.
-template <class T>
+template <class T, bool AD>
 __global__ __launch_bounds__(kBlock) void k_pr_long(PrArgs a) {
   if (a.ctrl->converged) return;
   const T dn = (T)(a.ctrl->D / (double)a.n);
   const T *hp = (const T *)a.heavy_part;
   T *p = (T *)a.p;
   T *xn = (T *)a.xn;
-  double delta = 0, dang = 0;
+  double delta = 0, dang = 0, dfz = 0, after = 0;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < a.pull.nsplit_rows) {
     const int r = a.pull.split_rows[3 * i], first = a.pull.split_rows[3 * i + 1],
               cnt = a.pull.split_rows[3 * i + 2];
-    T acc = (T)0;
-    for (int k = 0; k < cnt; ++k) acc += hp[first + k];
-    const T pn = rank_update<T>(a, acc, dn);
-    delta = fabs((double)pn - (double)p[r]);
-    p[r] = pn;
-    const int od = a.out_rp[r + 1] - a.out_rp[r];
-    if (od == 0) {
-      xn[r] = (T)0;
-      dang = (double)pn;
-    } else {
-      xn[r] = pn / (T)od;
+    if (!AD || bit_of(a.act_cur, r)) {
+      T acc = (T)0;
+      for (int k = 0; k < cnt; ++k) acc += hp[first + k];
+      const T po = p[r];
+      const T pn = rank_update<T>(a, acc, dn);
+      const double ch = fabs((double)pn - (double)po);
+      delta = ch;
+      p[r] = pn;
+      const int od = a.out_rp[r + 1] - a.out_rp[r];
+      if (od == 0) {
+        xn[r] = (T)0;
+        dang = (double)pn;
+      } else {
+        xn[r] = pn / (T)od;
+      }
+      if (AD && ch <= a.eps * (double)po) {  // freezes: clear its bit
+        atomicAnd((unsigned long long *)&a.act_nxt[r >> 6], ~(1ull << (r & 63)));
+        after = -1.0;
+        if (od == 0) dfz = (double)pn;
+      }
     }
   }
-  block_partials<T>(delta, dang, a.blk_part + 2 * a.nblk);
+  double pv[kPrFields] = {delta, dang, dfz, after, 0.0, 0.0};
+  block_partials(pv, a.blk_part + kPrFields * a.nblk);
 }
 
 // One workgroup: reduces the per-workgroup partials in a fixed order and
-// updates the control block (dangling mass, L1 change, convergence).
+// updates the control block (dangling mass, L1 change, convergence; for
+// the adaptive form also the frozen dangling mass, the active count and the
+// iteration's record).
 template <class T>
 __global__ __launch_bounds__(1024) void k_pr_fixup(PrArgs a, int init) {
-  __shared__ double s_d[16], s_g[16];
+  __shared__ double s_v[16][kPrFields];
   if (!init && a.ctrl->converged) return;
-  double delta = 0, dang = 0;
+  double v[kPrFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int nparts = init ? a.nblk : a.nblk + a.nblk_long;
-  for (int i = threadIdx.x; i < nparts; i += 1024) {
-    delta += a.blk_part[2 * i];
-    dang += a.blk_part[2 * i + 1];
-  }
-  delta = wave_sum_f64(delta);
-  dang = wave_sum_f64(dang);
-  if ((threadIdx.x & 63) == 0) {
-    s_d[threadIdx.x >> 6] = delta;
-    s_g[threadIdx.x >> 6] = dang;
+  for (int i = threadIdx.x; i < nparts; i += 1024)
+#pragma unroll
+    for (int f = 0; f < kPrFields; ++f) v[f] += a.blk_part[kPrFields * i + f];
+#pragma unroll
+  for (int f = 0; f < kPrFields; ++f) {
+    v[f] = wave_sum_f64(v[f]);
+    if ((threadIdx.x & 63) == 0) s_v[threadIdx.x >> 6][f] = v[f];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double d = 0, g = 0;
-    for (int i = 0; i < 16; ++i) {
-      d += s_d[i];
-      g += s_g[i];
-    }
-    a.ctrl->D = g;
+    double t[kPrFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int f = 0; f < kPrFields; ++f) t[f] += s_v[i][f];
+    Ctrl *c = a.ctrl;
     if (init) {
-      a.ctrl->iters = 0;
-      a.ctrl->converged = 0;
-      a.ctrl->delta = 0.0;
+      c->D = t[1];
+      c->Dfz = 0.0;
+      c->active = a.act_cur ? a.n : 0;
+      c->iters = 0;
+      c->converged = 0;
+      c->delta = 0.0;
     } else {
-      a.ctrl->delta = d;
-      a.ctrl->iters += 1;
-      if (d < a.tol) a.ctrl->converged = 1;
+      const double dfz_old = a.act_cur ? c->Dfz : 0.0;
+      c->D = t[1] + dfz_old;
+      c->delta = t[0];
+      if (a.act_cur) {
+        c->Dfz = dfz_old + t[2];
+        c->active = (int64_t)t[3];
+        if (a.stats && c->iters < kStatsCap) {
+          int64_t *r = a.stats + (size_t)c->iters * kStatFields;
+          r[0] = (int64_t)t[4];
+          r[1] = (int64_t)t[5];
+          r[2] = GRB_DIR_PULL;
+          r[3] = (int64_t)t[3];
+        }
+      }
+      c->iters += 1;
+      if (t[0] < a.tol) c->converged = 1;
+      if (a.act_cur && c->active == 0) c->converged = 1;
     }
   }
 }
@@ -279,18 +362,23 @@ void launch_pr_init(int is_fp64, const PrArgs &a, void *stream) {
   }
 }
 
+template <class T, bool AD>
+static void pr_iter_launch(const PrArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_pr_iter<T, AD>), dim3(a.nblk), dim3(kBlock), 0, s, a);
+  if (a.nblk_long > 0)
+    hipLaunchKernelGGL((k_pr_long<T, AD>), dim3(a.nblk_long), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_pr_fixup<T>, dim3(1), dim3(1024), 0, s, a, 0);
+}
+
 void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream) {
   hipStream_t s = (hipStream_t)stream;
+  const bool ad = a.act_cur != nullptr;
   if (is_fp64) {
-    hipLaunchKernelGGL(k_pr_iter<double>, dim3(a.nblk), dim3(kBlock), 0, s, a);
-    if (a.nblk_long > 0)
-      hipLaunchKernelGGL(k_pr_long<double>, dim3(a.nblk_long), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_pr_fixup<double>, dim3(1), dim3(1024), 0, s, a, 0);
+    if (ad) pr_iter_launch<double, true>(a, s);
+    else pr_iter_launch<double, false>(a, s);
   } else {
-    hipLaunchKernelGGL(k_pr_iter<float>, dim3(a.nblk), dim3(kBlock), 0, s, a);
-    if (a.nblk_long > 0)
-      hipLaunchKernelGGL(k_pr_long<float>, dim3(a.nblk_long), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_pr_fixup<float>, dim3(1), dim3(1024), 0, s, a, 0);
+    if (ad) pr_iter_launch<float, true>(a, s);
+    else pr_iter_launch<float, false>(a, s);
   }
 }
 

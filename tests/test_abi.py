@@ -81,6 +81,11 @@ def test_matrix_create_validation(grb):
     it = ctypes.c_int32()
     assert grb.grb_pagerank(FAKE, 2, h, 0.85, 5, 0.0, ctypes.byref(it), None, None, FAKE,
                             1 << 20, None) == 2
+    assert grb.grb_pagerank_adaptive(FAKE, 2, h, 0.85, 5, 0.0, 1e-3, ctypes.byref(it), None,
+                                     None, None, FAKE, 1 << 20, None) == 2
+    for bad in (-1e-3, float("nan"), float("inf")):  # bad threshold: refused first
+        assert grb.grb_pagerank_adaptive(FAKE, 2, h, 0.85, 5, 0.0, bad, ctypes.byref(it), None,
+                                         None, None, FAKE, 1 << 20, None) == 4
     assert grb.grb_matrix_free(ctypes.byref(h)) == 0 and not h.value
     assert grb.grb_bfs(FAKE, None, None, 0, None, FAKE, 1 << 20, None) == 2
 

@@ -94,3 +94,14 @@ def test_pagerank_rmat22_directed(grb):
     assert err64 <= 1e-10, err64
     _, it_auto, _ = grb.pagerank(P, dtype=torch.float64, max_iter=50, tol=1e-7)
     assert it_auto == it
+    # adaptive form (converged vertices frozen), as the benchmark runs it
+    aref, ait, _, aact, _ = oracle.pagerank_adaptive(adj, 1e-4, 0.85, 50, 1e-7)
+    a32, it32, _, act32 = grb.pagerank_adaptive(P, 1e-4, dtype=torch.float32, max_iter=ait,
+                                                tol=0.0)
+    a64, it64, _, act64 = grb.pagerank_adaptive(P, 1e-4, dtype=torch.float64, max_iter=ait,
+                                                tol=0.0)
+    assert it64 == ait and act64 == aact
+    err32 = np.abs(a32.cpu().numpy().astype(np.float64) - aref).sum()
+    err64 = np.abs(a64.cpu().numpy() - aref).sum()
+    assert err32 <= 1e-5, err32
+    assert err64 <= 1e-10, err64

@@ -192,6 +192,83 @@ def test_pagerank_parity(grb, name):
     assert torch.equal(p32, q32)
 
 
+def _adaptive_schedule(adj, fz, it):
+    """per iteration j = 1..it: (vertices active entering it, their in-edges,
+    vertices active after it), from the oracle's freeze iterations"""
+    _, nbr, _ = adj.arrays(weights=False)
+    indeg = np.bincount(nbr, minlength=adj.n)
+    rows = []
+    for j in range(1, it + 1):
+        live = (fz == 0) | (fz >= j)
+        after = (fz == 0) | (fz > j)
+        rows.append((int(live.sum()), int(indeg[live].sum()), int(after.sum())))
+    return rows
+
+
+def _directed_star():
+    star = graph("star")[0]
+    g = graphgen.from_edges("dstar", star.n, star.src, star.dst, symmetric=False)
+    return g, oracle.Adjacency(star.n, star.src, star.dst, symmetrise=False)
+
+
+@pytest.mark.parametrize("name", ["rmat_dir_12", "rmat_dir_14", "star_dir"])
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_pagerank_adaptive_parity(grb, name, eps):
+    if name == "star_dir":  # in-rows far longer than the piece size
+        g, adj = _directed_star()
+        A = grb.Matrix.from_raw(g, weights=False)
+    else:
+        g, adj = graph(name)
+        A = matrix(grb, name)
+    ref, it, delta, active, fz = oracle.pagerank_adaptive(adj, eps, 0.85, 50, 1e-7)
+    p64, it64, d64, a64 = grb.pagerank_adaptive(A, eps, dtype=torch.float64, max_iter=it,
+                                                tol=0.0)
+    st = grb.last_stats()
+    p32, it32, d32, a32 = grb.pagerank_adaptive(A, eps, dtype=torch.float32, max_iter=it,
+                                                tol=0.0)
+    assert it64 == it and a64 == active
+    assert np.abs(p64.cpu().numpy() - ref).sum() <= 1e-10
+    assert np.abs(p32.cpu().numpy().astype(np.float64) - ref).sum() <= 1e-5
+    # per iteration: active rows, their in-edges, active after (fp64 run)
+    sched = _adaptive_schedule(adj, fz, it)
+    assert st["iterations"] == it
+    assert [(f, e) for f, e, _ in sched] == list(zip(st["frontier"], st["edges"]))
+    assert all(d == 2 for d in st["direction"])
+    # the device-side stopping rule stops where the oracle stops
+    _, it_auto, _, a_auto = grb.pagerank_adaptive(A, eps, dtype=torch.float64, max_iter=50,
+                                                  tol=1e-7)
+    assert it_auto == it and a_auto == active
+    # bitwise repeatable
+    q32, _, _, _ = grb.pagerank_adaptive(A, eps, dtype=torch.float32, max_iter=it, tol=0.0)
+    assert torch.equal(p32, q32)
+
+
+def test_pagerank_adaptive_edge_cases(grb):
+    n = 9
+    cyc = graphgen.from_edges("cyc", n, np.arange(n), (np.arange(n) + 1) % n, symmetric=False)
+    A = grb.Matrix.from_raw(cyc, weights=False)
+    for dt in (torch.float32, torch.float64):
+        p, it, delta, active = grb.pagerank_adaptive(A, 1e-6, dtype=dt, max_iter=50, tol=0.0)
+        assert it == 1 and active == 0
+        assert np.allclose(p.cpu().numpy(), 1 / n, atol=1e-7)
+    # eps = 0 on a graph that never stands still: every iteration is plain PageRank
+    g, adj = graph("rmat_dir_12")
+    B = matrix(grb, "rmat_dir_12")
+    ref, it, _ = oracle.pagerank(adj, 0.85, 6, 0.0)
+    p, it2, _, active = grb.pagerank_adaptive(B, 0.0, dtype=torch.float64, max_iter=6, tol=0.0)
+    _, _, _, oact, _ = oracle.pagerank_adaptive(adj, 0.0, 0.85, 6, 0.0)
+    assert it2 == 6 and active == oact
+    if oact == adj.n:
+        assert np.abs(p.cpu().numpy() - ref).sum() <= 1e-12
+    # max_iter = 0: no iteration, p = 1/n
+    p, it3, _, active = grb.pagerank_adaptive(B, 1e-3, dtype=torch.float64, max_iter=0)
+    assert it3 == 0 and active == adj.n
+    assert np.allclose(p.cpu().numpy(), 1 / adj.n, atol=1e-18)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(grb.GrbError):
+            grb.pagerank_adaptive(B, bad)
+
+
 def test_pagerank_closed_forms(grb):
     n = 9
     cyc = graphgen.from_edges("cyc", n, np.arange(n), (np.arange(n) + 1) % n, symmetric=False)
