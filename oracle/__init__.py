@@ -15,8 +15,10 @@ computes, written from the paper (GraphBLAST, Yang, Buluc and Owens):
   redistribution of dangling mass and an L1 stopping rule.
 * :func:`pagerank_adaptive` — adaptive PageRank (PageRankDelta): the same
   iteration with converged vertices frozen (the masked form named in
-  Sections 3.2 and 7.3).
+  Sections 5.1 and 7.3).
 * :func:`msbfs` — k independent BFS runs (multi-nodeset traversal).
+* :func:`triangles` — triangle count and per-vertex counts by definition
+  (Section 7.4), each triangle found once from its lowest edge.
 * :mod:`oracle.mxv` — the plain-loop masked semiring mxv / vxm.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
@@ -78,6 +80,8 @@ def _load():
         lib.oracle_pagerank.restype = i32
         lib.oracle_pagerank_adaptive.argtypes = [p, f64, i32, f64, f64, p, p, p, p]
         lib.oracle_pagerank_adaptive.restype = i32
+        lib.oracle_triangles.argtypes = [p, p]
+        lib.oracle_triangles.restype = i64
         lib.oracle_msbfs.argtypes = [p, i64, p, p, i32]
         lib.oracle_msbfs.restype = i32
         _lib = lib
@@ -178,6 +182,15 @@ def pagerank_adaptive(adj_out: Adjacency, eps: float, alpha=0.85, max_iter=50, t
     if it < 0:
         raise ValueError("oracle_pagerank_adaptive: bad input")
     return p, int(it), float(delta.value), int(active.value), fz
+
+
+def triangles(adj: Adjacency):
+    """(triangle count, per-vertex counts int64[n]) of a symmetric adjacency."""
+    pv = np.empty(adj.n, dtype=np.int64)
+    t = _load().oracle_triangles(adj._h, _ptr(pv))
+    if t < 0:
+        raise ValueError("oracle_triangles: bad input")
+    return int(t), pv
 
 
 def msbfs(adj: Adjacency, sources, nthreads: int = 1):

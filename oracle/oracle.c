@@ -16,7 +16,10 @@
  *   oracle_sssp        Dijkstra with a binary heap in double precision
  *   oracle_pagerank    FP64 power iteration with uniform redistribution of
  *                      dangling mass, L1 stopping rule
+ *   oracle_pagerank_adaptive  the same iteration with converged vertices
+ *                      frozen (PageRankDelta)
  *   oracle_msbfs       k independent oracle_bfs runs (optionally on threads)
+ *   oracle_triangles   triangle count (and per-vertex counts) by definition
  *
  * parity pins: see tests/test_oracle_*.py (brute force, closed forms,
  * invariants, library special cases).
@@ -326,7 +329,7 @@ int32_t oracle_pagerank(const oracle_adj *a, double alpha, int32_t max_iter,
 }
 
 /*
- * Adaptive PageRank (PageRankDelta, named in Sections 3.2 and 7.3 as the
+ * Adaptive PageRank (PageRankDelta, named in Sections 5.1 and 7.3 as the
  * masked form of PageRank: the mask holds the vertices that have already
  * converged, whose values are no longer updated; Kamvar, Haveliwala and
  * Golub's adaptive method).  Starting from p = 1/n with every vertex
@@ -427,4 +430,61 @@ int32_t oracle_msbfs(const oracle_adj *a, int64_t k, const int32_t *sources,
   for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
   free(th);
   return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* triangle counting                                                   */
+/* ------------------------------------------------------------------ */
+
+/* first position in nbr[lo, hi) holding a value > x (ascending list) */
+static int64_t upper_pos(const int32_t *nbr, int64_t lo, int64_t hi, int32_t x) {
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (nbr[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+/* whether x occurs in nbr[lo, hi) (ascending list) */
+static int has_entry(const int32_t *nbr, int64_t lo, int64_t hi, int32_t x) {
+  const int64_t p = upper_pos(nbr, lo, hi, x);
+  return p > lo && nbr[p - 1] == x;
+}
+
+/*
+ * Triangle count of an undirected graph (Section 7.4: the number of vertex
+ * triples that are pairwise adjacent), by its definition: each triangle
+ * u < v < w is found exactly once, from its edge (u, v), as a common
+ * neighbour w > v of u and v (the shorter of the two sorted tails above v
+ * is walked and each of its entries looked up in the other).  The
+ * adjacency must be symmetric.  per_vertex (n entries, may be NULL)
+ * receives the number of triangles containing each vertex.  Returns the
+ * count, or -1 on bad input.
+ */
+int64_t oracle_triangles(const oracle_adj *a, int64_t *per_vertex) {
+  if (!a || a->n < 0) return -1;
+  if (per_vertex)
+    for (int64_t v = 0; v < a->n; ++v) per_vertex[v] = 0;
+  int64_t total = 0;
+  for (int64_t u = 0; u < a->n; ++u) {
+    const int64_t ub = a->off[u], ue = a->off[u + 1];
+    for (int64_t e = upper_pos(a->nbr, ub, ue, (int32_t)u); e < ue; ++e) {
+      const int32_t v = a->nbr[e];  /* v > u */
+      const int64_t tu = e + 1;     /* N(u) above v: [tu, ue) */
+      const int64_t tv = upper_pos(a->nbr, a->off[v], a->off[v + 1], v);
+      const int64_t ve = a->off[v + 1];
+      const int walk_u = (ue - tu) <= (ve - tv);
+      const int64_t wb = walk_u ? tu : tv, we = walk_u ? ue : ve;
+      const int64_t ob = walk_u ? tv : tu, oe = walk_u ? ve : ue;
+      for (int64_t k = wb; k < we; ++k) {
+        const int32_t w = a->nbr[k];
+        if (has_entry(a->nbr, ob, oe, w)) {
+          ++total;
+          if (per_vertex) { per_vertex[u]++; per_vertex[v]++; per_vertex[w]++; }
+        }
+      }
+    }
+  }
+  return total;
 }
