@@ -311,6 +311,20 @@ def bench_extras(grb, graphgen, torch, args):
             if name == "fp32":
                 res[name]["l1_vs_gpu_fp64"] = float(
                     (p.double() - p64).abs().sum().item())
+            # adaptive form: converged vertices frozen (relative change <= eps)
+            for eps in (1e-4, 1e-5):
+                grb.pagerank_adaptive(P, eps, dtype=dt, max_iter=50, tol=1e-7, ws=ws)
+                ms_a = timed(lambda: grb.pagerank_adaptive(P, eps, dtype=dt, max_iter=50,
+                                                           tol=1e-7, ws=ws),
+                             args.extra_steps, torch)
+                q, it_a, _, act = grb.pagerank_adaptive(P, eps, dtype=dt, max_iter=50, tol=1e-7,
+                                                        ws=ws)
+                st = grb.last_stats()
+                res[f"{name}_adaptive_eps{eps:g}"] = {
+                    "ms_total": round(ms_a, 4), "iterations": it_a, "active_left": act,
+                    "edges_touched": int(sum(st["edges"])),
+                    "edges_touched_vs_plain": round(sum(st["edges"]) / (P.nnz * it), 4),
+                    "l1_vs_gpu_fp64_plain": float((q.double() - p64).abs().sum().item())}
             del ws
         res["nnz"] = P.nnz
         res["iterations_fp64_reference"] = it64

@@ -66,6 +66,7 @@ typedef enum grb_type {
  *   PLUS_TIMES  (+, *, R, 0)                 classical products (PageRank)
  *   MIN_FIRST   (min, first, int32, INT32_MAX)
  *   MIN_SECOND  (min, second, int32, INT32_MAX)
+ *   PLUS_PAIR   (+, pair = 1, int32, 0)       common-index counts (masked SpGEMM)
  * For mxv the multiply is A(i,j) (x) u(j); for vxm it is u(i) (x) A(i,j).
  * So vxm with MIN_FIRST, or mxv with MIN_SECOND, returns the smallest
  * vector value among the contributing neighbours: with u(j) = j on the
@@ -78,7 +79,9 @@ typedef enum grb_semiring {
   GRB_PLUS_TIMES_FP32 = 3,
   GRB_PLUS_TIMES_FP64 = 4,
   GRB_MIN_FIRST_INT32 = 5,
-  GRB_MIN_SECOND_INT32 = 6
+  GRB_MIN_SECOND_INT32 = 6,
+  GRB_PLUS_PAIR_INT32 = 7 /* structure only: each common index counts 1
+                             (grb_mxm_masked only) */
 } grb_semiring;
 
 /* Optional accumulator applied between the old output and the product
@@ -159,6 +162,19 @@ grb_info grb_csr_nnz(grb_csr_builder b, int64_t *nnz);
  * (nnz floats; may be NULL, must be NULL if built without weights). */
 grb_info grb_csr_copy(grb_csr_builder b, int32_t *row_ptr, int32_t *col_idx, float *values);
 grb_info grb_csr_free(grb_csr_builder *b);
+
+/*
+ * Triangle-counting input (Section 7.4 counts triangles as the sum of
+ * L L^T .* L, L the strict lower triangle, rows ordered by degree): from a
+ * built symmetric CSR `src`, renumbers the vertices by decreasing degree
+ * (ties by increasing id) and keeps, in row i, the neighbours numbered
+ * below i (so every row holds at most sqrt(2 nnz) entries), rows sorted.
+ * *out receives a new builder (structure only; read it with grb_csr_nnz /
+ * grb_csr_copy, release it with grb_csr_free); rank (n entries, may be
+ * NULL) the new number of each vertex.  Errors: GRB_NULL_POINTER,
+ * GRB_OUT_OF_MEMORY.
+ */
+grb_info grb_csr_lower_by_degree(grb_csr_builder src, grb_csr_builder *out, int32_t *rank);
 
 /* ------------------------------------------------------------------ */
 /* Matrix                                                              */
@@ -242,7 +258,8 @@ typedef enum grb_op {
   GRB_OP_SSSP = 2,
   GRB_OP_PAGERANK = 3, /* k = 1 for fp32, 2 for fp64 */
   GRB_OP_MSBFS = 4,    /* k = number of sources (batched BFS) */
-  GRB_OP_NVALS = 5
+  GRB_OP_NVALS = 5,
+  GRB_OP_MXM = 6       /* grb_mxm_masked and grb_tricount (A unused) */
 } grb_op;
 
 /* Bytes of device workspace the operation needs on matrix A.  Workspace
@@ -345,7 +362,7 @@ grb_info grb_pagerank(void *p, grb_type type, grb_matrix A, double damping,
                       const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Adaptive PageRank (PageRankDelta, the masked PageRank of Sections 3.2
+ * Adaptive PageRank (PageRankDelta, the masked PageRank of Sections 5.1
  * and 7.3: the mask holds the vertices that have converged, which are no
  * longer updated, so an iteration touches only the in-edges of the active
  * rows).  As grb_pagerank, except that each iteration updates only the
@@ -364,6 +381,37 @@ grb_info grb_pagerank_adaptive(void *p, grb_type type, grb_matrix A, double damp
                                double *delta_out, int64_t *active_out,
                                const grb_descriptor *d, void *ws, size_t ws_bytes,
                                void *stream);
+
+/*
+ * Masked sparse matrix-matrix product in the dot-product form (Section 6.2.4,
+ * masked SpGEMM): for every entry (i, j) of the mask M,
+ *   c[e] = sum over k of A(i, k) * B(j, k)    (e = the entry's position
+ *                                              in M's CSR arrays),
+ * i.e. C = (A B^T) .* M with B given by its rows, the form triangle
+ * counting uses (A = B = M = L).  Only the mask's entries are computed; an
+ * entry whose rows share no index gets 0.  Semirings: GRB_PLUS_TIMES_FP32
+ * and _FP64 (A and B carry values of that type; c is float / double) and
+ * GRB_PLUS_PAIR_INT32 (structure only, every common index counts 1; c is
+ * int32); others GRB_NOT_IMPLEMENTED.  Needs M.nrows = A.nrows,
+ * M.ncols = B.nrows, A.ncols = B.ncols (else GRB_DIMENSION_MISMATCH); rows
+ * of A and B sorted by column; the mask is structural, so the descriptor
+ * may only carry GRB_PROFILE (other flags GRB_NOT_IMPLEMENTED).  The
+ * matrices need not be prepared.  Workspace: GRB_OP_MXM.  Asynchronous.
+ */
+grb_info grb_mxm_masked(void *c, grb_matrix M, grb_matrix A, grb_matrix B, grb_semiring s,
+                        const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Triangle count (Section 7.4): *count (host) receives the sum of
+ * (L L^T) .* L over the structure of L, which is the number of triangles
+ * when L is the strict lower triangle of a symmetric adjacency under any
+ * numbering (grb_csr_lower_by_degree builds the one that bounds the work).
+ * The product and the reduction run fused in one kernel; nothing of the
+ * product is stored.  L: square, rows sorted (else the result is undefined);
+ * need not be prepared.  Workspace: GRB_OP_MXM.  Synchronises the stream.
+ */
+grb_info grb_tricount(int64_t *count, grb_matrix L, const grb_descriptor *d, void *ws,
+                      size_t ws_bytes, void *stream);
 
 /*
  * Batched multi-source BFS: k traversals at once as one masked product of

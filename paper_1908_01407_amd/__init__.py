@@ -37,14 +37,14 @@ ERRORS = {
 GRB_BOOL, GRB_INT32, GRB_FP32, GRB_FP64 = 0, 1, 2, 3
 SEMIRINGS = {
     "lor_land": 0, "min_plus_fp32": 1, "min_plus_fp64": 2, "plus_times_fp32": 3,
-    "plus_times_fp64": 4, "min_first_int32": 5, "min_second_int32": 6,
+    "plus_times_fp64": 4, "min_first_int32": 5, "min_second_int32": 6, "plus_pair_int32": 7,
 }
 ACCUMS = {None: 0, "min": 1, "plus": 2, "lor": 3}
 GRB_MASK_COMP, GRB_MASK_STRUCT, GRB_TRAN_A, GRB_REPLACE, GRB_PROFILE = 0x1, 0x2, 0x4, 0x8, 0x10
 DIR_AUTO, DIR_PUSH, DIR_PULL = 0, 1, 2
 SWITCH_PAPER, SWITCH_EXACT = 0, 1
 GRB_MATRIX_SYMMETRIC = 0x1
-OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS = 0, 1, 2, 3, 4, 5
+OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS, OP_MXM = 0, 1, 2, 3, 4, 5, 6
 STATS_MAX = 256
 
 
@@ -92,6 +92,9 @@ _SIGS = {
     "grb_csr_nnz": ([_p, ctypes.POINTER(_i64)], _i32),
     "grb_csr_copy": ([_p, _p, _p, _p], _i32),
     "grb_csr_free": ([_PP], _i32),
+    "grb_csr_lower_by_degree": ([_p, _PP, _p], _i32),
+    "grb_mxm_masked": ([_p, _p, _p, _p, _i32, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_tricount": ([ctypes.POINTER(_i64), _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_matrix_create": ([_PP, _i64, _i64, _i64, _p, _p, _p, _i32, _p, _p, _p, _u32], _i32),
     "grb_matrix_free": ([_PP], _i32),
     "grb_matrix_nrows": ([_p, ctypes.POINTER(_i64)], _i32),
@@ -192,6 +195,39 @@ def csr_from_edges(n: int, src, dst, w=None, symmetrise: bool = True):
     finally:
         _lib.grb_csr_free(ctypes.byref(h))
     return rp, ci, vals
+
+
+def _csr_out(h, n):
+    nnz = ctypes.c_int64()
+    check(_lib.grb_csr_nnz(h, ctypes.byref(nnz)), "grb_csr_nnz")
+    rp = np.empty(n + 1, dtype=np.int32)
+    ci = np.empty(max(nnz.value, 0), dtype=np.int32)
+    check(_lib.grb_csr_copy(h, rp.ctypes.data, ci.ctypes.data if nnz.value else None, None),
+          "grb_csr_copy")
+    return rp, ci
+
+
+def lower_by_degree(n: int, src, dst):
+    """Triangle-counting input via grb_csr_lower_by_degree: the symmetrised,
+    cleaned graph renumbered by decreasing degree, strict lower triangle.
+    Returns (row_ptr, col_idx, rank) as numpy arrays."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    h = ctypes.c_void_p()
+    lo = ctypes.c_void_p()
+    check(_lib.grb_csr_build(ctypes.byref(h), n, src.shape[0], src.ctypes.data, dst.ctypes.data,
+                             None, 1), "grb_csr_build")
+    try:
+        rank = np.empty(max(n, 1), dtype=np.int32)
+        check(_lib.grb_csr_lower_by_degree(h, ctypes.byref(lo), rank.ctypes.data),
+              "grb_csr_lower_by_degree")
+        try:
+            rp, ci = _csr_out(lo, n)
+        finally:
+            _lib.grb_csr_free(ctypes.byref(lo))
+    finally:
+        _lib.grb_csr_free(ctypes.byref(h))
+    return rp, ci, rank[:n]
 
 
 # ---- torch-backed objects ---------------------------------------------------------
@@ -437,6 +473,32 @@ def pagerank_adaptive(A: Matrix, eps: float, *, dtype=None, damping: float = 0.8
                                      ctypes.byref(desc) if desc is not None else None, _ptr(ws),
                                      ws.numel(), _stream(stream)), "grb_pagerank_adaptive")
     return p[: A.nrows], iters.value, delta.value, active.value
+
+
+def mxm_masked(M: Matrix, A: Matrix, B: Matrix, semiring: str = "plus_pair_int32", *,
+               desc: Descriptor | None = None, ws=None, stream=None):
+    """C = (A B^T) .* M via grb_mxm_masked: one value per entry of M, in M's
+    CSR order (int32 for plus_pair_int32, float / double for plus_times)."""
+    torch = _torch()
+    dt = {"plus_pair_int32": torch.int32, "plus_times_fp32": torch.float32,
+          "plus_times_fp64": torch.float64}.get(semiring, torch.int32)
+    c = torch.empty(max(M.nnz, 1), dtype=dt, device=M.device)
+    ws = ws if ws is not None else workspace(OP_MXM, None, device=M.device)
+    check(_lib.grb_mxm_masked(_ptr(c), M.handle, A.handle, B.handle, SEMIRINGS[semiring],
+                              ctypes.byref(desc) if desc is not None else None, _ptr(ws),
+                              ws.numel(), _stream(stream)), "grb_mxm_masked")
+    return c[: M.nnz]
+
+
+def tricount(L: Matrix, *, desc: Descriptor | None = None, ws=None, stream=None) -> int:
+    """Sum of (L L^T) .* L via grb_tricount: the triangle count when L is a
+    strict lower triangle of a symmetric graph (see lower_by_degree)."""
+    ws = ws if ws is not None else workspace(OP_MXM, None, device=L.device)
+    out = ctypes.c_int64()
+    check(_lib.grb_tricount(ctypes.byref(out), L.handle,
+                            ctypes.byref(desc) if desc is not None else None, _ptr(ws),
+                            ws.numel(), _stream(stream)), "grb_tricount")
+    return out.value
 
 
 def mxv(w: Vector, mask: Vector | None, accum, semiring: str, A: Matrix, u: Vector, *,

@@ -1015,6 +1015,10 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
     *bytes = 256;
     return GRB_SUCCESS;
   }
+  if (op == GRB_OP_MXM) {
+    *bytes = kMxmWs;
+    return GRB_SUCCESS;
+  }
   if (!A) return GRB_UNINITIALIZED_OBJECT;
   switch (op) {
     case GRB_OP_BFS: *bytes = bfs_layout(nullptr, A->nrows).bytes; break;
@@ -1200,6 +1204,79 @@ grb_info grb_pagerank_adaptive(void *p, grb_type type, grb_matrix A, double damp
                       active_out, d, ws, ws_bytes, stream);
 }
 
+grb_info grb_mxm_masked(void *c, grb_matrix M, grb_matrix A, grb_matrix B, grb_semiring s,
+                        const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream) {
+  if (!M || !A || !B) return GRB_UNINITIALIZED_OBJECT;
+  if (M->nrows != A->nrows || M->ncols != B->nrows || A->ncols != B->ncols)
+    return GRB_DIMENSION_MISMATCH;
+  int vt = GRB_INT32;
+  if (s == GRB_PLUS_TIMES_FP32 || s == GRB_PLUS_TIMES_FP64) {
+    vt = s == GRB_PLUS_TIMES_FP32 ? GRB_FP32 : GRB_FP64;
+    if (A->a.vtype != vt || B->a.vtype != vt) return GRB_DOMAIN_MISMATCH;
+  } else if (s != GRB_PLUS_PAIR_INT32) {
+    return (s >= GRB_LOR_LAND_BOOL && s <= GRB_MIN_SECOND_INT32) ? GRB_NOT_IMPLEMENTED
+                                                                 : GRB_INVALID_VALUE;
+  }
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  if (desc.flags & ~GRB_PROFILE) return GRB_NOT_IMPLEMENTED;
+  if (!c && M->nnz > 0) return GRB_NULL_POINTER;
+  if ((info = check_ws(ws, ws_bytes, kMxmWs)) != GRB_SUCCESS) return info;
+  if (M->nnz == 0 || M->nrows == 0) return GRB_SUCCESS;
+  MxmArgs ma;
+  ma.nrows = M->nrows;
+  ma.M = M->a;
+  ma.A = A->a;
+  ma.B = B->a;
+  ma.c = c;
+  ma.vt = vt;
+  launch_mxm_dot(ma, false, stream);
+  return check_launch();
+}
+
+grb_info grb_tricount(int64_t *count, grb_matrix L, const grb_descriptor *d, void *ws,
+                      size_t ws_bytes, void *stream) {
+  if (!L) return GRB_UNINITIALIZED_OBJECT;
+  if (!count) return GRB_NULL_POINTER;
+  if (L->nrows != L->ncols) return GRB_DIMENSION_MISMATCH;
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  if (desc.flags & ~GRB_PROFILE) return GRB_NOT_IMPLEMENTED;
+  if ((info = check_ws(ws, ws_bytes, kMxmWs)) != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  const bool profile = (desc.flags & GRB_PROFILE) != 0;
+  unsigned long long *cnt = (unsigned long long *)ws;
+  launch_fill_u64((uint64_t *)cnt, 1, 0ull, stream);
+  MxmArgs ma;
+  ma.nrows = L->nrows;
+  ma.M = L->a;
+  ma.A = L->a;
+  ma.B = L->a;
+  ma.count = cnt;
+  if (profile) (void)hipEventRecord(g_events.get(0), s);
+  if (L->nnz > 0) launch_mxm_dot(ma, true, stream);
+  if (profile) (void)hipEventRecord(g_events.get(1), s);
+  if ((info = check_launch()) != GRB_SUCCESS) return info;
+  unsigned long long h = 0;
+  if (!read_back({{&h, cnt, sizeof(h)}}, s)) return GRB_PANIC;
+  *count = (int64_t)h;
+  std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+  rec[0] = L->nnz;
+  rec[2] = GRB_DIR_PULL;
+  std::vector<float> kms;
+  double ms_all = 0.0;
+  if (profile) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, g_events.get(0), g_events.get(1));
+    kms.push_back(ms);
+    ms_all = ms;
+  }
+  finish_stats(GRB_OP_MXM, 1, rec, kms, 1, ms_all);
+  return GRB_SUCCESS;
+}
+
 }  // extern "C"
 
 namespace {
@@ -1230,6 +1307,7 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
                      grb_matrix A, grb_vector u, const grb_descriptor *d, void *ws,
                      size_t ws_bytes, void *stream) {
   if (!w || !u || !A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (s == GRB_PLUS_PAIR_INT32) return GRB_NOT_IMPLEMENTED;  // masked SpGEMM only
   if (s < GRB_LOR_LAND_BOOL || s > GRB_MIN_SECOND_INT32) return GRB_INVALID_VALUE;
   if (accum < GRB_NOACCUM || accum > GRB_ACCUM_LOR) return GRB_INVALID_VALUE;
   grb_descriptor desc;

@@ -161,3 +161,51 @@ extern "C" grb_info grb_csr_free(grb_csr_builder *b) {
   *b = nullptr;
   return GRB_SUCCESS;
 }
+
+// Degree-ordered strict lower triangle for triangle counting (Section 7.4:
+// the count is the reduction of L L^T .* L).  Vertices are renumbered by
+// decreasing degree (ties by increasing id), so row i of L holds the
+// neighbours of i that come earlier in that order, i.e. have at least its
+// degree: at most sqrt(2 * nnz) of them.  The result is a new builder
+// (structure only, rows sorted); rank[v] (may be NULL) receives the new id
+// of vertex v.
+extern "C" grb_info grb_csr_lower_by_degree(grb_csr_builder src, grb_csr_builder *out,
+                                           int32_t *rank) {
+  if (!src || !out) return GRB_NULL_POINTER;
+  *out = nullptr;
+  const int64_t n = src->n;
+  grb_csr_builder_s *b = new (std::nothrow) grb_csr_builder_s;
+  if (!b) return GRB_OUT_OF_MEMORY;
+  try {
+    std::vector<int32_t> order((size_t)n), rk((size_t)n);
+    for (int64_t v = 0; v < n; ++v) order[(size_t)v] = (int32_t)v;
+    const std::vector<int32_t> &rp = src->row_ptr;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+      return rp[(size_t)a + 1] - rp[(size_t)a] > rp[(size_t)c + 1] - rp[(size_t)c];
+    });
+    for (int64_t i = 0; i < n; ++i) rk[(size_t)order[(size_t)i]] = (int32_t)i;
+    b->n = n;
+    b->weighted = false;
+    b->row_ptr.assign((size_t)n + 1, 0);
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e)
+        if (rk[(size_t)src->col[(size_t)e]] < rk[(size_t)v]) b->row_ptr[(size_t)rk[(size_t)v] + 1]++;
+    for (int64_t i = 0; i < n; ++i) b->row_ptr[(size_t)i + 1] += b->row_ptr[(size_t)i];
+    b->nnz = b->row_ptr[(size_t)n];
+    b->col.resize((size_t)b->nnz);
+    std::vector<int32_t> pos(b->row_ptr.begin(), b->row_ptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v)
+      for (int32_t e = rp[(size_t)v]; e < rp[(size_t)v + 1]; ++e) {
+        const int32_t c = rk[(size_t)src->col[(size_t)e]];
+        if (c < rk[(size_t)v]) b->col[(size_t)pos[(size_t)rk[(size_t)v]]++] = c;
+      }
+    for (int64_t i = 0; i < n; ++i)
+      std::sort(b->col.begin() + b->row_ptr[(size_t)i], b->col.begin() + b->row_ptr[(size_t)i + 1]);
+    if (rank) std::memcpy(rank, rk.data(), (size_t)n * sizeof(int32_t));
+  } catch (const std::bad_alloc &) {
+    delete b;
+    return GRB_OUT_OF_MEMORY;
+  }
+  *out = b;
+  return GRB_SUCCESS;
+}

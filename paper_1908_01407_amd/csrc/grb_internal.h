@@ -204,6 +204,18 @@ int pr_long_grid(int64_t nsplit_rows);  // workgroups of the long-row kernel
 void launch_pr_init(int is_fp64, const PrArgs &a, void *stream);
 void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream);  // adaptive iff a.act_cur
 
+// masked SpGEMM in the dot-product form, C = (A B^T) .* M (grb_mxm.hip)
+constexpr int kMxmLds = 1024;  // entries of a row of A a wave keeps in LDS
+constexpr size_t kMxmWs = 256; // workspace: the triangle counter
+struct MxmArgs {
+  int64_t nrows = 0;  // rows of M (and of A)
+  Csr M, A, B;        // B is given by its rows (the columns of B^T)
+  void *c = nullptr;  // nnz(M) results in M's entry order (write mode)
+  unsigned long long *count = nullptr;  // count mode: the sum of all results
+  int vt = 0;         // GRB_FP32 / GRB_FP64 (PLUS_TIMES), else PLUS_PAIR
+};
+void launch_mxm_dot(const MxmArgs &a, bool count, void *stream);
+
 // generic helpers
 void launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, void *stream);
 void launch_fill_bytes_pattern(void *p, int64_t count, int elem_size, const void *value,

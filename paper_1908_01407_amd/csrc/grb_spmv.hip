@@ -1,6 +1,6 @@
 // PageRank iteration kernels (Section 7.3 of the paper: pull form, SpMV
 // every iteration because the vector never gets sparse), and the adaptive
-// form (PageRankDelta, named in Sections 3.2 and 7.3): the mask holds the
+// form (PageRankDelta, named in Sections 5.1 and 7.3): the mask holds the
 // vertices that have converged, whose values stay frozen, so only the rows
 // of the others are computed and the work of an iteration is the in-edges
 // of its active rows.

@@ -135,3 +135,44 @@ def test_csr_builder_errors(grb):
     assert e.value.code == 5
     rp, ci, w = grb.csr_from_edges(3, [], [], None)
     assert rp.tolist() == [0, 0, 0, 0] and ci.size == 0 and w is None
+
+
+@pytest.mark.parametrize("kind", ["rmat10", "rmat12", "grid", "clique", "empty"])
+def test_lower_by_degree_matches_oracle(grb, kind):
+    """grb_csr_lower_by_degree (host setup of triangle counting) gives the
+    oracle's degree-ordered strict lower triangle exactly."""
+    from oracle import mxm as omxm
+    if kind.startswith("rmat"):
+        g = graphgen.rmat(int(kind[4:]), weights=False)
+    elif kind == "grid":
+        g = graphgen.grid(9, 11, weights=False)
+    elif kind == "clique":
+        iu = np.triu_indices(40, 1)
+        g = graphgen.from_edges("clique", 40, iu[0], iu[1])
+    else:
+        g = graphgen.from_edges("empty", 5, [], [])
+    adj = oracle.Adjacency.from_raw(g)
+    off, nbr, _ = adj.arrays(weights=False)
+    rp, ci, rank = grb.lower_by_degree(g.n, g.src, g.dst)
+    orp, oci, orank = omxm.lower_by_degree(g.n, off, nbr)
+    assert np.array_equal(rank, orank)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+
+
+def test_mxm_argument_errors(grb):
+    rc, h = _create(grb, flags=1)
+    assert rc == 0
+    it = ctypes.c_int64()
+    # masked products refuse semirings they do not provide, before any launch
+    assert grb.grb_mxm_masked(FAKE, h, h, h, 1, None, FAKE, 1 << 20, None) == 8
+    assert grb.grb_mxm_masked(FAKE, h, h, h, 99, None, FAKE, 1 << 20, None) == 4
+    assert grb.grb_mxm_masked(FAKE, h, h, h, 3, None, FAKE, 1 << 20, None) == 6  # no fp32 values
+    assert grb.grb_mxm_masked(FAKE, None, h, h, 7, None, FAKE, 1 << 20, None) == 2
+    assert grb.grb_mxm_masked(FAKE, h, h, h, 7, None, FAKE, 16, None) == 9  # workspace too small
+    assert grb.grb_tricount(None, h, None, FAKE, 1 << 20, None) == 3
+    assert grb.grb_tricount(ctypes.byref(it), None, None, FAKE, 1 << 20, None) == 2
+    d = grb.descriptor(flags=grb.GRB_MASK_COMP)
+    assert grb.grb_tricount(ctypes.byref(it), h, ctypes.byref(d), FAKE, 1 << 20, None) == 8
+    sz = ctypes.c_size_t()
+    assert grb.grb_workspace_size(6, None, 0, ctypes.byref(sz)) == 0 and sz.value >= 8
+    assert grb.grb_matrix_free(ctypes.byref(h)) == 0
