@@ -40,6 +40,8 @@ def mxm_masked(M, A, B, semiring: str):
     n_rows, _, mrp, mci = M[:4]
     mrp = np.asarray(mrp, dtype=np.int64)
     rows = np.repeat(np.arange(n_rows), np.diff(mrp))
+    if rows.shape[0] == 0:
+        return np.zeros(0, dtype=np.float64)
     return np.asarray(prod[rows, np.asarray(mci, dtype=np.int64)]).ravel().astype(np.float64)
 
 
@@ -54,6 +56,8 @@ def mxm_abs_bound(M, A, B):
     mrp = np.asarray(mrp, dtype=np.int64)
     rows = np.repeat(np.arange(n_rows), np.diff(mrp))
     cols = np.asarray(mci, dtype=np.int64)
+    if rows.shape[0] == 0:
+        return np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.float64)
     cnt = np.asarray((Ap @ Bp.T).tocsr()[rows, cols]).ravel()
     mag = np.asarray((Aa @ Ba.T).tocsr()[rows, cols]).ravel()
     return cnt, mag

@@ -105,3 +105,26 @@ def test_pagerank_rmat22_directed(grb):
     err64 = np.abs(a64.cpu().numpy() - aref).sum()
     assert err32 <= 1e-5, err32
     assert err64 <= 1e-10, err64
+
+
+def test_tricount_rmat22(grb):
+    """Triangle count of RMAT-22: the degree-ordered operand equals the
+    oracle's, sampled per-edge counts (row intersections) match the
+    oracle's one by one, and the fused count equals the sum of the product."""
+    from oracle import mxm as omxm
+    g = graphgen.rmat(22, weights=False)
+    adj = oracle.Adjacency.from_raw(g)
+    off, nbr, _ = adj.arrays(weights=False)
+    rp, ci, rank = grb.lower_by_degree(g.n, g.src, g.dst)
+    orp, oci, orank = omxm.lower_by_degree(g.n, off, nbr)
+    assert np.array_equal(rank, orank)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    del off, nbr, orp, oci
+    L = grb.Matrix(g.n, g.n, rp, ci, None, symmetric=False)
+    t = grb.tricount(L)
+    c = grb.mxm_masked(L, L, L, "plus_pair_int32")
+    assert int(c.to(torch.int64).sum()) == t
+    rng = np.random.default_rng(11)
+    ent = rng.choice(ci.shape[0], 3000, replace=False)
+    got = c[torch.from_numpy(ent).to(c.device)].cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, omxm.edge_counts(rp, ci, ent))

@@ -115,3 +115,11 @@ def test_lower_by_degree_and_tricount_identity(scale):
     assert int(c.sum()) == t
     ent = np.arange(0, ci.shape[0], max(1, ci.shape[0] // 300))
     assert np.array_equal(omxm.edge_counts(rp, ci, ent), c[ent].astype(np.int64))
+
+
+def test_mxm_masked_empty_mask():
+    A = (3, 4, np.array([0, 1, 1, 2]), np.array([0, 3]), np.array([1.0, 2.0]))
+    M = (3, 3, np.zeros(4, np.int64), np.zeros(0, np.int64), None)
+    assert omxm.mxm_masked(M, A, A, "plus_times_fp64").shape == (0,)
+    cnt, mag = omxm.mxm_abs_bound(M, A, A)
+    assert cnt.shape == (0,) and mag.shape == (0,)
