@@ -207,6 +207,9 @@ void launch_pr_iter(int is_fp64, const PrArgs &a, void *stream);  // adaptive if
 // masked SpGEMM in the dot-product form, C = (A B^T) .* M (grb_mxm.hip)
 constexpr int kMxmLds = 1024;  // entries of a row of A a wave keeps in LDS
 constexpr size_t kMxmWs = 256; // workspace: the triangle counter
+constexpr int kPairBits = 1 << 16;  // structure-only product: LDS bitmap columns per wave
+constexpr int kPairTail = 256;      // ... and LDS entries of a row's part above them
+constexpr int kPairLong = 128;      // rows of B streamed one at a time from this length
 struct MxmArgs {
   int64_t nrows = 0;  // rows of M (and of A)
   Csr M, A, B;        // B is given by its rows (the columns of B^T)
