@@ -15,8 +15,10 @@ The JSON line also carries:
   headline pass), against 8 TB/s;
 * cpu_baseline: the CPU oracle (single-threaded queue BFS with the
   min-id parent pass) timed on this host on the same graph;
-* extras: SSSP on the same graph, BFS/SSSP on a 3000x3000 grid, PageRank on
-  a directed R-MAT scale 22 graph (fp32 and fp64), each with its own timing.
+* extras: SSSP on the same graph (Bellman-Ford rounds and bucketed), BFS/SSSP
+  on a 3000x3000 grid, PageRank and adaptive PageRank on a directed R-MAT
+  scale 22 graph (fp32 and fp64), triangle counting on R-MAT scales 18 and
+  22, batched BFS and the serving loop, each with its own timing.
 
 Other modes: --rocprof-summary DIR prints a per-kernel summary of rocprofv3
 CSV output (kernel stats and FETCH_SIZE / WRITE_SIZE counters).
@@ -330,6 +332,27 @@ def bench_extras(grb, graphgen, torch, args):
         res["iterations_fp64_reference"] = it64
         ex[f"pagerank_rmat{args.scale}_dir"] = res
         del P
+    # triangle counting: the sum of L L^T .* L (degree-ordered lower triangle)
+    if not args.no_tc:
+        for sc in sorted({18, args.scale}):
+            g = graphgen.rmat(sc, weights=False)
+            rp, ci, _ = grb.lower_by_degree(g.n, g.src, g.dst)  # setup, untimed
+            L = grb.Matrix(g.n, g.n, rp, ci, None, symmetric=False)
+            ws = grb.workspace(grb.OP_MXM, None)
+            t = grb.tricount(L, ws=ws)
+            ms = timed(lambda: grb.tricount(L, ws=ws), args.extra_steps, torch)
+            grb.tricount(L, ws=ws, desc=grb.descriptor(flags=grb.GRB_PROFILE))
+            kms = grb.last_stats()["expand_ms_all"]
+            # membership probes: every entry of row j of L, once per row i
+            # holding j (entries of L equal to j)
+            lr = np.diff(rp).astype(np.int64)
+            probes = int(np.sum(lr * np.bincount(ci, minlength=g.n)))
+            ex[f"tricount_rmat{sc}"] = {
+                "ms": round(ms, 3), "kernel_ms": round(kms, 3), "triangles": t,
+                "nnz_lower": int(ci.shape[0]), "probes": probes,
+                "gprobes_per_s": round(probes / (kms / 1e3) / 1e9, 1),
+                "edges_per_s_g": round(2 * ci.shape[0] / (ms / 1e3) / 1e9, 3)}
+            del L, ws
     return ex
 
 
@@ -464,6 +487,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-pr", action="store_true")
+    ap.add_argument("--no-tc", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-msbfs", action="store_true")
