@@ -69,14 +69,18 @@ def first_hit_scan(rp, ci, rows_mask, hit_col):
     return total
 
 
-def parents_bytes(rp, ci, lev, directions, frontier, n):
+def parents_bytes(rp, ci, lev, directions, frontier, n, symmetric=True):
     """Bytes of the parent work per level kernel.  A push from a one-vertex
     frontier writes each found vertex's parent with its level (4 bytes each,
     charged to that level).  After a push from several vertices the next
-    level's kernel searches, for each of its frontier vertices, the
-    in-neighbours up to the first one a level up: row extents (8), ids and
-    levels of the scanned neighbours (8 each) and the parent written (4),
-    charged to that next level.  Pull levels find parents while they scan."""
+    level's kernel finds the parents of its frontier: when it pushes over the
+    same CSR (symmetric graph), from the edges it expands anyway, reading the
+    level of every expanded neighbour (4 per edge) and writing the parent
+    (4); otherwise by scanning each vertex's in-neighbours up to the first
+    one a level up: row extents (8), ids and levels of the scanned
+    neighbours (8 each) and the parent (4).  Charged to that next level.
+    Pull levels find parents while they scan."""
+    deg = np.diff(rp).astype(np.int64)
     out = [0.0] * len(directions)
     for d, dr in enumerate(directions):
         if dr != 1:
@@ -88,7 +92,10 @@ def parents_bytes(rp, ci, lev, directions, frontier, n):
         if frontier[d] == 1:
             out[d] += 4.0 * cnt
         elif d + 1 < len(out):
-            out[d + 1] += 12.0 * cnt + 8.0 * first_hit_scan(rp, ci, nxt, lev == d)
+            if symmetric and directions[d + 1] == 1:
+                out[d + 1] += 4.0 * int(deg[nxt].sum()) + 4.0 * cnt
+            else:
+                out[d + 1] += 12.0 * cnt + 8.0 * first_hit_scan(rp, ci, nxt, lev == d)
     return out
 
 

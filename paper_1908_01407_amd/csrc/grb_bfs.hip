@@ -22,9 +22,11 @@
 // Pull finds the smallest-id parent directly (ascending adjacency, first
 // hit).  A push from a one-vertex frontier writes that vertex as parent.
 // Vertices found by a push of several vertices get theirs in the next
-// level's kernel, where they are the frontier: the first in-neighbour one
-// level up in ascending order (a standalone pass covers the last level
-// when the level cap stops the search).
+// level's kernel, where they are the frontier: the smallest in-neighbour
+// one level up, offered edge by edge while that level pushes over the same
+// CSR, else found by a pass over their in-edges (first hit in ascending
+// order); a standalone pass covers the last level when the level cap stops
+// the search.
 #include <hip/hip_runtime.h>
 
 #include "grb_device.h"
@@ -71,16 +73,34 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
   }
 }
 
+// Parents of the frontier while a push expands it (symmetric graphs, whose
+// out-edges are the in-edges): an expanded edge (u, v) with v one level
+// above u offers v as u's parent, and the smallest offer wins (parents[u]
+// is -1 until then, the largest value as unsigned).  lv[s]: level of c[s],
+// loaded by the caller together with its visited words.
+__device__ __forceinline__ void offer_parents(const BfsArgs &a, const int (&c)[kUnroll],
+                                              const int (&par)[kUnroll], const int (&lv)[kUnroll]) {
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s)
+    if (c[s] >= 0 && lv[s] == a.d - 1)
+      atomicMin((unsigned int *)&a.parents[par[s]], (unsigned int)c[s]);
+}
+
 // Claims the targets c[0..kUnroll) (-1: none) from a stream that may hold
 // one target twice.  The visited words of all of them are read first (a
 // plain read is only a filter, the atomic decides) and all atomics are
 // issued before any result is used, so their latencies overlap.
 __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll],
-                                            const int (&par)[kUnroll], bool single, int &fc,
-                                            int &fd, int &fl) {
+                                            const int (&par)[kUnroll], bool single, bool offer,
+                                            int &fc, int &fd, int &fl) {
   uint64_t vw[kUnroll];
+  int lv[kUnroll];
 #pragma unroll
-  for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+  for (int s = 0; s < kUnroll; ++s) {
+    vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+    lv[s] = (offer && c[s] >= 0) ? a.levels[c[s]] : -2;
+  }
+  if (offer) offer_parents(a, c, par, lv);
   uint64_t old[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
@@ -99,11 +119,16 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
 // per word serves them all (issued by the run's last lane, whose previous
 // value of the word every lane of the run then reads).
 __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUnroll],
-                                            const int (&par)[kUnroll], bool single, int &fc,
-                                            int &fd, int &fl) {
+                                            const int (&par)[kUnroll], bool single, bool offer,
+                                            int &fc, int &fd, int &fl) {
   uint64_t vw[kUnroll];
+  int lv[kUnroll];
 #pragma unroll
-  for (int s = 0; s < kUnroll; ++s) vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+  for (int s = 0; s < kUnroll; ++s) {
+    vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
+    lv[s] = (offer && c[s] >= 0) ? a.levels[c[s]] : -2;
+  }
+  if (offer) offer_parents(a, c, par, lv);
   bool want[kUnroll];
   uint64_t old[kUnroll], run[kUnroll];
   int64_t wd[kUnroll];
@@ -136,7 +161,7 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
 // all waves, so a hub is expanded by hundreds of waves at once.
 
 __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_rows, bool single,
-                                         int &fc, int &fd, int &fl) {
+                                         bool offer, int &fc, int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -188,7 +213,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
         }
 #pragma unroll
         for (int s = 0; s < kUnroll; ++s) c[s] = c[s] >= 0 ? ci[c[s]] : -1;
-        claim_batch(a, c, par, single, fc, fd, fl);
+        claim_batch(a, c, par, single, offer, fc, fd, fl);
       }
     }
   }
@@ -218,7 +243,7 @@ __device__ __forceinline__ void bfs_push(const BfsArgs &a, int *mark, bool long_
         c[s] = pos < pe ? ci[pos] : -1;
         par[s] = pu;
       }
-      claim_piece(a, c, par, single, fc, fd, fl);
+      claim_piece(a, c, par, single, offer, fc, fd, fl);
     }
   }
 }
@@ -592,10 +617,13 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   if (count == 0) return;
   const int dir = decide(a, count, s_sumdeg);
   int fc = 0, fd = 0, fl = 0;
-  // parents of this frontier, when a push of several vertices found it
-  if (s_open) frontier_parents(a, s_mark[threadIdx.x >> 6]);
+  // parents of this frontier, when a push of several vertices found it: a
+  // push over the same CSR offers them while it expands the frontier,
+  // otherwise a pass over the frontier's in-edges finds them first
+  const bool offer = s_open && dir == GRB_DIR_PUSH && a.same_csr;
+  if (s_open && !offer) frontier_parents(a, s_mark[threadIdx.x >> 6]);
   if (dir == GRB_DIR_PUSH)
-    bfs_push(a, s_mark[threadIdx.x >> 6], s_long > 0, count == 1, fc, fd, fl);
+    bfs_push(a, s_mark[threadIdx.x >> 6], s_long > 0, count == 1, offer, fc, fd, fl);
   else
     bfs_pull(a, s_mark[threadIdx.x >> 6], fc, fd, fl);
   fc = wave_sum(fc);

@@ -52,7 +52,16 @@ def test_path_graph_byte_model():
     # each too (the path), so every parent is written at claim
     assert bench.parents_bytes(rp, ci, lev, dirs, [1, 1, 1, 1], n) == [4.0, 4.0, 4.0, 0.0]
     # with a frontier of several vertices at level 1, level 2's kernel finds
-    # vertex 2's parent: 12 + 8 x (neighbours [1, 3] -> 1 hits first: 1 edge);
-    # level 2 (one vertex) still writes vertex 3's parent at claim (4)
-    assert bench.parents_bytes(rp, ci, lev, dirs, [1, 2, 1, 1], n) == [4.0, 0.0, 12.0 + 8.0 + 4.0,
+    # vertex 2's parent; pushing over the same CSR it reads the levels of the
+    # two expanded neighbours [1, 3] (8) and writes the parent (4); level 2
+    # (one vertex) still writes vertex 3's parent at claim (4)
+    assert bench.parents_bytes(rp, ci, lev, dirs, [1, 2, 1, 1], n) == [4.0, 0.0, 8.0 + 4.0 + 4.0,
                                                                         0.0]
+    # if level 2 pulls instead, it scans vertex 2's in-neighbours up to the
+    # first one a level up: 12 + 8 x (neighbours [1, 3] -> 1 hits first: 1
+    # edge), and the pull finds vertex 3's parent itself
+    assert bench.parents_bytes(rp, ci, lev, [1, 1, 2, 1], [1, 2, 1, 1], n) == [4.0, 0.0, 20.0,
+                                                                                0.0]
+    # a directed graph always scans in-neighbours
+    assert bench.parents_bytes(rp, ci, lev, dirs, [1, 2, 1, 1], n, symmetric=False) == [
+        4.0, 0.0, 12.0 + 8.0 + 4.0, 0.0]
