@@ -16,7 +16,8 @@ constexpr int kCompactThreads = 1024;  // threads per compaction workgroup (16 w
 constexpr int kCompactWords = 256;     // bitmap words per compaction workgroup
 constexpr int kHeavyDeg = 2048;      // rows longer than this are split for pull
 constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
-constexpr int kExpandGrid = 2048;    // workgroups of the grid-stride expand kernels
+constexpr int kExpandGrid = 1024;    // workgroups of the grid-stride expand kernels (4 per CU: all
+                                     // resident at once, so a small level pays one dispatch round)
 constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
 constexpr int kWaveParts = kExpandGrid * kWavesPerBlock;  // waves of a full-sweep kernel
 constexpr int kUnroll = 4;         // 64-edge steps whose loads are issued together
