@@ -211,6 +211,7 @@ constexpr size_t kMxmWs = 256; // workspace: the triangle counter
 constexpr int kPairBits = 1 << 16;  // structure-only product: LDS bitmap columns per wave
 constexpr int kPairTail = 256;      // ... and LDS entries of a row's part above them
 constexpr int kPairLong = 128;      // rows of B streamed one at a time from this length
+constexpr int kPairUnroll = 8;      // ... 64 x kPairUnroll entries per step
 struct MxmArgs {
   int64_t nrows = 0;  // rows of M (and of A)
   Csr M, A, B;        // B is given by its rows (the columns of B^T)

@@ -255,15 +255,15 @@ __global__ __launch_bounds__(kBlock) void k_mxm_pair(MxmArgs a) {
         lm &= lm - 1;
         const int rb = __shfl(cur, l), re = __shfl(end, l);
         int cnt = 0;
-        for (int p0 = rb; p0 < re; p0 += 64 * kUnroll) {
-          int32_t kk[kUnroll];
+        for (int p0 = rb; p0 < re; p0 += 64 * kPairUnroll) {
+          int32_t kk[kPairUnroll];
 #pragma unroll
-          for (int s = 0; s < kUnroll; ++s) {
+          for (int s = 0; s < kPairUnroll; ++s) {
             const int p = p0 + s * 64 + ln;
             kk[s] = p < re ? bci[p] : -1;
           }
 #pragma unroll
-          for (int s = 0; s < kUnroll; ++s)
+          for (int s = 0; s < kPairUnroll; ++s)
             cnt += __popcll(__ballot(kk[s] >= 0 && pair_hit(bm, tail, dt, tail_lds, gtail, kk[s])));
         }
         if (COUNT) hits += (unsigned long long)cnt;
