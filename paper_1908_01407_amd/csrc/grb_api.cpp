@@ -138,7 +138,7 @@ struct PrWs {
 PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
   Carver c(ws);
   PrWs t{};
-  t.nblk = kExpandGrid;
+  t.nblk = kSweepGrid;
   t.nblk_long = pr_long_grid(pull.nsplit_rows);
   t.ctrl = c.take<Ctrl>(1);
   t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);

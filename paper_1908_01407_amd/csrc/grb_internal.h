@@ -19,7 +19,9 @@ constexpr int kHeavyChunk = 1024;    // edges per split piece of a long row
 constexpr int kExpandGrid = 1024;    // workgroups of the grid-stride expand kernels (4 per CU: all
                                      // resident at once, so a small level pays one dispatch round)
 constexpr int kPushSplit = 256;      // BFS push: rows longer than this are cut in pieces of this size
-constexpr int kWaveParts = kExpandGrid * kWavesPerBlock;  // waves of a full-sweep kernel
+constexpr int kSweepGrid = 4096;     // workgroups of the PageRank sweep (two rounds of 8 waves per SIMD)
+constexpr int kWaveParts = kSweepGrid * kWavesPerBlock;  // balanced word runs of full sweeps
+constexpr int kSweepUnroll = 4;      // PageRank: 64-position steps whose loads are issued together
 constexpr int kUnroll = 4;         // 64-edge steps whose loads are issued together
 constexpr int kMsMaxWordsPerPass = 8;  // batched BFS: query words (of 64) per pass, at most
 constexpr int kPullRows = 4;       // BFS pull: rows per lane whose first loads overlap

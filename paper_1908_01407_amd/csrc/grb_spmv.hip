@@ -7,12 +7,15 @@
 //
 // Load balance: each wave takes a run of bitmap words of rows (64
 // consecutive rows of the CSR of A^T each), runs of about equal work built
-// by grb_matrix_prepare, one word per step, and
-// streams their in-edges as one concatenated list, kUnroll x 64 edges per
-// step, with a segmented sum per row (wave-level load-balanced search);
+// by grb_matrix_prepare, one word at a time, and streams the word's
+// in-edges as one concatenated list, 64 positions per step: the rows'
+// prefix ends sit in LDS, each lane finds the row of its position by
+// bisection (so the steps are independent and kSweepUnroll of them have
+// their loads in flight together), and a segmented sum per step adds each row's
+// segment to the row's LDS accumulator, in step order;
 // rows longer than kPushSplit are cut into fixed pieces that any wave
-// takes, and a second kernel (one thread per long row) adds each long
-// row's pieces in order.  Summation order is fixed, so fp32 and fp64 results are bitwise
+// takes, and a second kernel (one wave per long row) adds each long
+// row's pieces in a fixed order.  Summation order is fixed, so fp32 and fp64 results are bitwise
 // reproducible run to run.  The dangling mass and the L1 change are reduced
 // per workgroup and then in a fixed order in the fix-up kernel, which also
 // decides convergence on the device.
@@ -94,9 +97,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
 
 template <class T, bool AD>
 __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
-  __shared__ int s_mark[kWavesPerBlock][64];
+  __shared__ int s_end[kWavesPerBlock][64];
+  __shared__ int s_base[kWavesPerBlock][64];
+  __shared__ T s_acc[kWavesPerBlock][64];
   if (a.ctrl->converged) return;
-  int *mark = s_mark[threadIdx.x >> 6];
+  const int wid = threadIdx.x >> 6;
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -107,104 +112,105 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   const T dn = (T)(a.ctrl->D / (double)a.n);
   double delta = 0, dang = 0, dfz = 0, after = 0, upd = 0, edges = 0;
   // rows up to kPushSplit long: the wave's run of words (about equal work
-  // per run), one word of rows per step; kUnroll x 64 edges per step (slot
-  // positions first, then all gathers, then the segmented sums in slot order)
-  const int64_t wlo = gw < kWaveParts ? a.pull.wpart[gw] : 0;
-  const int64_t whi = gw < kWaveParts ? a.pull.wpart[gw + 1] : 0;
-  for (int64_t w = wlo; w < whi; ++w) {
-    const int64_t v = w * 64 + ln;
-    const bool inb = v < a.n;
-    uint64_t on_m = ~0ull;
-    if (AD) {
-      on_m = a.act_cur[w];
-      const uint64_t was = a.act_prev[w];
-      // frozen in the previous iteration: x enters the other buffer once
-      if (inb && (((was & ~on_m) >> ln) & 1ull)) xn[v] = x[v];
-      if (!on_m) {  // the word's rows are all frozen
-        if (ln == 0) a.act_nxt[w] = 0ull;
-        continue;
-      }
-    }
-    const bool on = inb && ((on_m >> ln) & 1ull);
-    int cur = 0, end = 0;
-    bool split = false;
-    if (on) {
-      cur = rp[v];
-      end = rp[v + 1];
-      split = end - cur > kPushSplit;
+  // per run), one word of rows at a time
+  for (int64_t part = gw; part < kWaveParts; part += nwaves) {
+    const int64_t wlo = a.pull.wpart[part], whi = a.pull.wpart[part + 1];
+    for (int64_t w = wlo; w < whi; ++w) {
+      const int64_t v = w * 64 + ln;
+      const bool inb = v < a.n;
+      uint64_t on_m = ~0ull;
       if (AD) {
-        upd += 1.0;
-        edges += (double)(end - cur);
-      }
-    }
-    const bool act = on && !split;
-    if (!act) end = cur;
-    T acc = (T)0;
-    for (bool more = true; more;) {
-      int pos[kUnroll], row[kUnroll], se[kUnroll];
-      bool st[kUnroll];
-#pragma unroll
-      for (int s = 0; s < kUnroll; ++s) {
-        pos[s] = -1;
-        row[s] = 0;
-        se[s] = 0;
-        st[s] = false;
-        if (!more) continue;
-        const int len = end - cur;
-        const int incl = wave_incl_scan(len);
-        const int total = lane_last(incl);
-        if (total == 0) {
-          more = false;
+        on_m = a.act_cur[w];
+        const uint64_t was = a.act_prev[w];
+        // frozen in the previous iteration: x enters the other buffer once
+        if (inb && (((was & ~on_m) >> ln) & 1ull)) xn[v] = x[v];
+        if (!on_m) {  // the word's rows are all frozen
+          if (ln == 0) a.act_nxt[w] = 0ull;
           continue;
         }
-        const int excl = incl - len;
-        const bool starts = len > 0 && excl < 64;
-        const int r = slot_rows(mark, starts, excl);
-        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-        if (ln < total) pos[s] = rcur + (ln - rexcl);
-        row[s] = r;
-        st[s] = starts;
-        se[s] = min(incl, 64);
-        if (starts) cur += se[s] - excl;
       }
-      int c[kUnroll];
-#pragma unroll
-      for (int s = 0; s < kUnroll; ++s) c[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
-      T val[kUnroll];
-#pragma unroll
-      for (int s = 0; s < kUnroll; ++s) val[s] = c[s] >= 0 ? x[c[s]] : (T)0;
-#pragma unroll
-      for (int s = 0; s < kUnroll; ++s) {
-        const T y = seg_sum_scan<T>(val[s], row[s]);
-        const T seg = __shfl(y, st[s] ? se[s] - 1 : 0);
-        if (st[s]) acc += seg;
+      const bool on = inb && ((on_m >> ln) & 1ull);
+      int cur = 0, end = 0;
+      bool split = false;
+      if (on) {
+        cur = rp[v];
+        end = rp[v + 1];
+        split = end - cur > kPushSplit;
+        if (AD) {
+          upd += 1.0;
+          edges += (double)(end - cur);
+        }
       }
-    }
-    bool keep = false;
-    if (act) {
-      const T po = p[v];
-      const T pn = rank_update<T>(a, acc, dn);
-      const double ch = fabs((double)pn - (double)po);
-      delta += ch;
-      p[v] = pn;
-      const int od = a.out_rp[v + 1] - a.out_rp[v];
-      if (od == 0) {
-        xn[v] = (T)0;
-        dang += (double)pn;
-      } else {
-        xn[v] = pn / (T)od;
+      const bool act = on && !split;
+      // the word's rows' in-edges as one list of `total` positions; the
+      // prefix ends of the rows go to LDS once, and every 64-position step
+      // finds its rows there by bisection, so no step waits on the one before
+      // and the loads of kSweepUnroll steps are in flight together
+      const int len = act ? end - cur : 0;
+      const int incl = wave_incl_scan(len);
+      const int total = lane_last(incl);
+      s_end[wid][ln] = incl;
+      s_base[wid][ln] = cur - (incl - len);  // position q of this row's edges: base + q
+      s_acc[wid][ln] = (T)0;
+      wave_lds_sync();
+      for (int q0 = 0; q0 < total; q0 += 64 * kSweepUnroll) {
+        int row[kSweepUnroll], c[kSweepUnroll];
+        bool last[kSweepUnroll];
+  #pragma unroll
+        for (int s = 0; s < kSweepUnroll; ++s) {
+          const int q = q0 + s * 64 + ln;
+          row[s] = -1;
+          last[s] = false;
+          c[s] = -1;
+          if (q < total) {
+            int r = 0;
+  #pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+              if (s_end[wid][r + step - 1] <= q) r += step;
+            row[s] = r;
+            last[s] = q + 1 == s_end[wid][r] || ln == 63;
+            c[s] = s_base[wid][r] + q;
+          }
+        }
+  #pragma unroll
+        for (int s = 0; s < kSweepUnroll; ++s) c[s] = c[s] >= 0 ? ci[c[s]] : -1;
+        T val[kSweepUnroll];
+  #pragma unroll
+        for (int s = 0; s < kSweepUnroll; ++s) val[s] = c[s] >= 0 ? x[c[s]] : (T)0;
+  #pragma unroll
+        for (int s = 0; s < kSweepUnroll; ++s) {
+          const T y = seg_sum_scan<T>(val[s], row[s]);
+          if (last[s]) atomicAdd(&s_acc[wid][row[s]], y);  // one segment per row and step
+        }
+      }
+      wave_lds_sync();
+      const T acc = s_acc[wid][ln];
+      bool keep = false;
+      if (act) {
+        const T po = p[v];
+        const T pn = rank_update<T>(a, acc, dn);
+        const double ch = fabs((double)pn - (double)po);
+        delta += ch;
+        p[v] = pn;
+        const int od = a.out_rp[v + 1] - a.out_rp[v];
+        if (od == 0) {
+          xn[v] = (T)0;
+          dang += (double)pn;
+        } else {
+          xn[v] = pn / (T)od;
+        }
+        if (AD) {
+          keep = !(ch <= a.eps * (double)po);
+          if (!keep && od == 0) dfz += (double)pn;
+        }
       }
       if (AD) {
-        keep = !(ch <= a.eps * (double)po);
-        if (!keep && od == 0) dfz += (double)pn;
-      }
-    }
-    if (AD) {
-      // long rows stay set; their kernel clears the bit if they freeze
-      const uint64_t nx = __ballot(keep || (on && split));
-      if (ln == 0) {
-        a.act_nxt[w] = nx;
-        after += (double)__popcll(nx);
+        // long rows stay set; their kernel clears the bit if they freeze
+        const uint64_t nx = __ballot(keep || (on && split));
+        if (ln == 0) {
+          a.act_nxt[w] = nx;
+          after += (double)__popcll(nx);
+        }
       }
     }
   }
@@ -251,8 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_iter(PrArgs a) {
   block_partials(pv, a.blk_part);
 }
 
-// Long rows: one thread per row adds the row's pieces in order and updates
-// its rank; per-workgroup partials follow those of the SpMV kernel.
+// Long rows: one wave per row adds the row's pieces (lane l the pieces
+// l, l + 64, ... in order, then a fixed-order reduction over the lanes) and
+// updates its rank; per-workgroup partials follow those of the SpMV kernel.
 template <class T, bool AD>
 __global__ __launch_bounds__(kBlock) void k_pr_long(PrArgs a) {
   if (a.ctrl->converged) return;
@@ -260,30 +267,34 @@ __global__ __launch_bounds__(kBlock) void k_pr_long(PrArgs a) {
   const T *hp = (const T *)a.heavy_part;
   T *p = (T *)a.p;
   T *xn = (T *)a.xn;
+  const int ln = threadIdx.x & 63;
   double delta = 0, dang = 0, dfz = 0, after = 0;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (i < a.pull.nsplit_rows) {
     const int r = a.pull.split_rows[3 * i], first = a.pull.split_rows[3 * i + 1],
               cnt = a.pull.split_rows[3 * i + 2];
     if (!AD || bit_of(a.act_cur, r)) {
-      T acc = (T)0;
-      for (int k = 0; k < cnt; ++k) acc += hp[first + k];
-      const T po = p[r];
-      const T pn = rank_update<T>(a, acc, dn);
-      const double ch = fabs((double)pn - (double)po);
-      delta = ch;
-      p[r] = pn;
-      const int od = a.out_rp[r + 1] - a.out_rp[r];
-      if (od == 0) {
-        xn[r] = (T)0;
-        dang = (double)pn;
-      } else {
-        xn[r] = pn / (T)od;
-      }
-      if (AD && ch <= a.eps * (double)po) {  // freezes: clear its bit
-        atomicAnd((unsigned long long *)&a.act_nxt[r >> 6], ~(1ull << (r & 63)));
-        after = -1.0;
-        if (od == 0) dfz = (double)pn;
+      T part = (T)0;
+      for (int k = ln; k < cnt; k += 64) part += hp[first + k];
+      const T acc = lane_last(wave_scan(part, (T)0, OpAdd()));
+      if (ln == 0) {
+        const T po = p[r];
+        const T pn = rank_update<T>(a, acc, dn);
+        const double ch = fabs((double)pn - (double)po);
+        delta = ch;
+        p[r] = pn;
+        const int od = a.out_rp[r + 1] - a.out_rp[r];
+        if (od == 0) {
+          xn[r] = (T)0;
+          dang = (double)pn;
+        } else {
+          xn[r] = pn / (T)od;
+        }
+        if (AD && ch <= a.eps * (double)po) {  // freezes: clear its bit
+          atomicAnd((unsigned long long *)&a.act_nxt[r >> 6], ~(1ull << (r & 63)));
+          after = -1.0;
+          if (od == 0) dfz = (double)pn;
+        }
       }
     }
   }
@@ -348,7 +359,7 @@ __global__ __launch_bounds__(1024) void k_pr_fixup(PrArgs a, int init) {
 }  // namespace
 
 int pr_long_grid(int64_t nsplit_rows) {
-  return (int)((nsplit_rows + kBlock - 1) / kBlock);
+  return (int)((nsplit_rows + kWavesPerBlock - 1) / kWavesPerBlock);  // a wave per row
 }
 
 void launch_pr_init(int is_fp64, const PrArgs &a, void *stream) {

@@ -203,90 +203,91 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &f
   const float inf = __int_as_float(0x7f800000);
   // the wave's run of words (runs of about equal work, built by
   // grb_matrix_prepare: rows of similar degree have nearby ids)
-  const int64_t wlo = gw < kWaveParts ? a.pull.wpart[gw] : 0;
-  const int64_t whi = gw < kWaveParts ? a.pull.wpart[gw + 1] : 0;
-  for (int64_t w0 = wlo; w0 < whi; w0 += 64) {
-    const int64_t mw = w0 + ln;
-    clear_behind(a, mw, mw < whi);
-    const uint64_t mc = mw < whi ? ~a.iso[mw] : 0ull;  // candidate rows: rows with in-edges
-    uint64_t nzw = __ballot(mc != 0ull);
-    while (nzw) {
-      const int k = __ffsll((unsigned long long)nzw) - 1;
-      nzw &= nzw - 1;
-      const int64_t w = w0 + k;
-      const uint64_t cand = __shfl(mc, k);
-      const int64_t v = w * 64 + ln;
-      bool act = (cand >> ln) & 1ull;
-      int cur = 0, end = 0;
-      if (act) {
-        cur = rp[v];
-        end = rp[v + 1];
-        if (end - cur > kPushSplit) act = false;  // long rows: pieces below
-      }
-      if (!act) end = cur;
-      const int deg0 = end - cur;
-      float best = inf;
-      // slot positions of kUnroll x 64 edges first, then their loads, then
-      // the segmented minima over frontier neighbours (a distance is read
-      // only for neighbours in the frontier)
-      for (bool more = true; more;) {
-        int pos[kUnroll], row[kUnroll], se[kUnroll];
-        bool st[kUnroll];
-#pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-          pos[s] = -1;
-          row[s] = 0;
-          se[s] = 0;
-          st[s] = false;
-          if (!more) continue;
-          const int len = end - cur;
-          const int incl = wave_incl_scan(len);
-          const int total = lane_last(incl);
-          if (total == 0) {
-            more = false;
-            continue;
+  for (int64_t part = gw; part < kWaveParts; part += nwaves) {
+    const int64_t wlo = a.pull.wpart[part], whi = a.pull.wpart[part + 1];
+    for (int64_t w0 = wlo; w0 < whi; w0 += 64) {
+      const int64_t mw = w0 + ln;
+      clear_behind(a, mw, mw < whi);
+      const uint64_t mc = mw < whi ? ~a.iso[mw] : 0ull;  // candidate rows: rows with in-edges
+      uint64_t nzw = __ballot(mc != 0ull);
+      while (nzw) {
+        const int k = __ffsll((unsigned long long)nzw) - 1;
+        nzw &= nzw - 1;
+        const int64_t w = w0 + k;
+        const uint64_t cand = __shfl(mc, k);
+        const int64_t v = w * 64 + ln;
+        bool act = (cand >> ln) & 1ull;
+        int cur = 0, end = 0;
+        if (act) {
+          cur = rp[v];
+          end = rp[v + 1];
+          if (end - cur > kPushSplit) act = false;  // long rows: pieces below
+        }
+        if (!act) end = cur;
+        const int deg0 = end - cur;
+        float best = inf;
+        // slot positions of kUnroll x 64 edges first, then their loads, then
+        // the segmented minima over frontier neighbours (a distance is read
+        // only for neighbours in the frontier)
+        for (bool more = true; more;) {
+          int pos[kUnroll], row[kUnroll], se[kUnroll];
+          bool st[kUnroll];
+  #pragma unroll
+          for (int s = 0; s < kUnroll; ++s) {
+            pos[s] = -1;
+            row[s] = 0;
+            se[s] = 0;
+            st[s] = false;
+            if (!more) continue;
+            const int len = end - cur;
+            const int incl = wave_incl_scan(len);
+            const int total = lane_last(incl);
+            if (total == 0) {
+              more = false;
+              continue;
+            }
+            const int excl = incl - len;
+            const bool starts = len > 0 && excl < 64;
+            const int r = slot_rows(mark, starts, excl);
+            const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+            if (ln < total) pos[s] = rcur + (ln - rexcl);
+            row[s] = r;
+            st[s] = starts;
+            se[s] = min(incl, 64);
+            if (starts) cur += se[s] - excl;
           }
-          const int excl = incl - len;
-          const bool starts = len > 0 && excl < 64;
-          const int r = slot_rows(mark, starts, excl);
-          const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-          if (ln < total) pos[s] = rcur + (ln - rexcl);
-          row[s] = r;
-          st[s] = starts;
-          se[s] = min(incl, 64);
-          if (starts) cur += se[s] - excl;
+          int cv[kUnroll];
+          float wt[kUnroll];
+  #pragma unroll
+          for (int s = 0; s < kUnroll; ++s) {
+            cv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+            wt[s] = pos[s] >= 0 ? a.wpull[pos[s]] : 0.0f;
+          }
+          // one gather per edge: the frontier distance is +inf off the
+          // frontier
+          float dc[kUnroll];
+  #pragma unroll
+          for (int s = 0; s < kUnroll; ++s) dc[s] = cv[s] >= 0 ? a.fd_cur[cv[s]] : inf;
+  #pragma unroll
+          for (int s = 0; s < kUnroll; ++s) {
+            const float y = seg_min_scan(dc[s] + wt[s], row[s]);
+            const float segmin = __shfl(y, st[s] ? se[s] - 1 : 0);
+            if (st[s]) best = fminf(best, segmin);
+          }
         }
-        int cv[kUnroll];
-        float wt[kUnroll];
-#pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-          cv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
-          wt[s] = pos[s] >= 0 ? a.wpull[pos[s]] : 0.0f;
+        bool improved = false;
+        if (act && best < a.dist[v]) {  // only this wave writes row v in a pull round
+          a.dist[v] = best;
+          a.fd_nxt[v] = best;
+          improved = true;
+          const int pd = a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
+          fc += 1;
+          fd += pd;
+          fl += pd > kPushSplit ? 1 : 0;
         }
-        // one gather per edge: the frontier distance is +inf off the
-        // frontier
-        float dc[kUnroll];
-#pragma unroll
-        for (int s = 0; s < kUnroll; ++s) dc[s] = cv[s] >= 0 ? a.fd_cur[cv[s]] : inf;
-#pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-          const float y = seg_min_scan(dc[s] + wt[s], row[s]);
-          const float segmin = __shfl(y, st[s] ? se[s] - 1 : 0);
-          if (st[s]) best = fminf(best, segmin);
-        }
+        const uint64_t ib = __ballot(improved);
+        if (ib && ln == 0) atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)ib);
       }
-      bool improved = false;
-      if (act && best < a.dist[v]) {  // only this wave writes row v in a pull round
-        a.dist[v] = best;
-        a.fd_nxt[v] = best;
-        improved = true;
-        const int pd = a.same_csr ? deg0 : a.push.rp[v + 1] - a.push.rp[v];
-        fc += 1;
-        fd += pd;
-        fl += pd > kPushSplit ? 1 : 0;
-      }
-      const uint64_t ib = __ballot(improved);
-      if (ib && ln == 0) atomicOr((unsigned long long *)&a.fnxt[w], (unsigned long long)ib);
     }
   }
   // pieces of long rows: each piece's minimum is combined with atomicMin;

@@ -158,3 +158,41 @@ def test_mxm_masked_edge_cases(grb):
         grb.mxm_masked(M, A, B, "plus_times_fp32")  # values are fp64
     with pytest.raises(grb.GrbError):
         grb.mxm_masked(M, A, B, "min_plus_fp64")
+
+
+@pytest.mark.parametrize("semiring", ["plus_pair_int32", "plus_times_fp64"])
+def test_mxm_masked_wide_columns(grb, semiring):
+    """Columns past the structure-only kernel's LDS bitmap (65,536): rows of
+    A with a short tail above it (kept in LDS) and with a long one (more
+    than 256 entries, searched in place)."""
+    rng = np.random.default_rng(77)
+    r, c, k = 64, 48, 300_000
+    rows_a = []
+    for i in range(r):
+        lo = rng.choice(65_536, size=int(rng.integers(0, 200)), replace=False)
+        n_hi = 600 if i % 3 == 0 else int(rng.integers(0, 40))  # long / short tails
+        hi = rng.choice(np.arange(65_536, k), size=n_hi, replace=False)
+        rows_a.append(np.sort(np.concatenate([lo, hi])))
+    rows_b = []
+    for j in range(c):
+        pool = np.concatenate([rows_a[j % r], rng.choice(k, size=300, replace=False)])
+        rows_b.append(np.unique(rng.choice(pool, size=min(len(pool), 500), replace=False)))
+
+    def csr(rows):
+        rp = np.concatenate([[0], np.cumsum([len(x) for x in rows])]).astype(np.int32)
+        ci = np.concatenate(rows).astype(np.int32)
+        return rp, ci, rng.integers(1, 5, ci.shape[0]).astype(np.float64)
+
+    arp, aci, av = csr(rows_a)
+    brp, bci, bv = csr(rows_b)
+    M = np.ones((r, c), dtype=bool)
+    mrp = np.arange(0, r * c + 1, c, dtype=np.int32)
+    mci = np.tile(np.arange(c, dtype=np.int32), r)
+    A = grb.Matrix(r, k, arp, aci, av, symmetric=False)
+    B = grb.Matrix(c, k, brp, bci, bv, symmetric=False)
+    Mm = grb.Matrix(r, c, mrp, mci, None, symmetric=False)
+    got = grb.mxm_masked(Mm, A, B, semiring).cpu().numpy().astype(np.float64)
+    ref = omxm.mxm_masked((r, c, mrp, mci, None), (r, k, arp, aci, av), (c, k, brp, bci, bv),
+                          semiring)
+    assert np.array_equal(got, ref)  # integer-valued products: exact in fp64
+    assert M.sum() == got.shape[0]
