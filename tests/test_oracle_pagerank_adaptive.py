@@ -1,5 +1,5 @@
 """Pins for the adaptive PageRank oracle (PageRankDelta: PageRank whose mask
-holds the converged vertices, Sections 3.2 and 7.3; a vertex freezes once
+holds the converged vertices, Sections 5.1 and 7.3; a vertex freezes once
 its change relative to the previous iterate is at most eps).
 
 The oracle's trajectory is checked against the definition from outside:
