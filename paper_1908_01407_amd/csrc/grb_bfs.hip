@@ -44,32 +44,36 @@ __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
 }
 
 // Finishes the claims won by this lane: level, next-frontier bit, counts.
-// The degree loads of all won targets are issued together.
+// dg[s]: out-degree of target c[s], loaded by the caller together with its
+// visited word (before the claim is decided, so no load follows it).
 // With a one-vertex frontier (`single`) that vertex, par[s], is the only
 // parent a target can have, and it is written at once.
 // `next_set`: the caller has already set the targets' next-frontier bits.
 __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnroll],
                                           const bool (&won)[kUnroll], const int (&par)[kUnroll],
-                                          bool single, bool next_set, int &fc, int &fd, int &fl) {
-  int d0[kUnroll], d1[kUnroll];
+                                          const int (&dg)[kUnroll], bool single, bool next_set,
+                                          int &fc, int &fd, int &fl) {
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
-    d0[s] = 0;
-    d1[s] = 0;
     if (won[s]) {
       a.levels[c[s]] = a.d + 1;
       if (single && a.parents) a.parents[c[s]] = par[s];
       if (!next_set)
         atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], 1ull << (c[s] & 63));
-      d0[s] = a.push.rp[c[s]];
-      d1[s] = a.push.rp[c[s] + 1];
+      fc += 1;
+      fd += dg[s];
+      fl += dg[s] > kPushSplit ? 1 : 0;
     }
   }
+}
+
+// Out-degrees of the targets (0 for none), issued with the visited loads.
+__device__ __forceinline__ void target_degrees(const BfsArgs &a, const int (&c)[kUnroll],
+                                               int (&d0)[kUnroll], int (&d1)[kUnroll]) {
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
-    fc += won[s] ? 1 : 0;
-    fd += d1[s] - d0[s];
-    fl += d1[s] - d0[s] > kPushSplit ? 1 : 0;
+    d0[s] = c[s] >= 0 ? a.push.rp[c[s]] : 0;
+    d1[s] = c[s] >= 0 ? a.push.rp[c[s] + 1] : 0;
   }
 }
 
@@ -94,12 +98,13 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
                                             const int (&par)[kUnroll], bool single, bool offer,
                                             int &fc, int &fd, int &fl) {
   uint64_t vw[kUnroll];
-  int lv[kUnroll];
+  int lv[kUnroll], d0[kUnroll], d1[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
     lv[s] = (offer && c[s] >= 0) ? a.levels[c[s]] : -2;
   }
+  target_degrees(a, c, d0, d1);
   if (offer) offer_parents(a, c, par, lv);
   uint64_t old[kUnroll];
 #pragma unroll
@@ -109,9 +114,13 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
       old[s] = atomicOr((unsigned long long *)&a.visited[c[s] >> 6], 1ull << (c[s] & 63));
   }
   bool won[kUnroll];
+  int dg[kUnroll];
 #pragma unroll
-  for (int s = 0; s < kUnroll; ++s) won[s] = c[s] >= 0 && !((old[s] >> (c[s] & 63)) & 1ull);
-  claim_won(a, c, won, par, single, false, fc, fd, fl);
+  for (int s = 0; s < kUnroll; ++s) {
+    won[s] = c[s] >= 0 && !((old[s] >> (c[s] & 63)) & 1ull);
+    dg[s] = d1[s] - d0[s];
+  }
+  claim_won(a, c, won, par, dg, single, false, fc, fd, fl);
 }
 
 // Claims the targets of one piece of a row: ascending and distinct, so the
@@ -122,12 +131,13 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
                                             const int (&par)[kUnroll], bool single, bool offer,
                                             int &fc, int &fd, int &fl) {
   uint64_t vw[kUnroll];
-  int lv[kUnroll];
+  int lv[kUnroll], d0[kUnroll], d1[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
     lv[s] = (offer && c[s] >= 0) ? a.levels[c[s]] : -2;
   }
+  target_degrees(a, c, d0, d1);
   if (offer) offer_parents(a, c, par, lv);
   bool want[kUnroll];
   uint64_t old[kUnroll], run[kUnroll];
@@ -143,15 +153,17 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
       old[s] = atomicOr((unsigned long long *)&a.visited[wd[s]], (unsigned long long)run[s]);
   }
   bool won[kUnroll];
+  int dg[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     const uint64_t ow = __shfl(old[s], tail[s]);
     won[s] = want[s] && !((ow >> (c[s] & 63)) & 1ull);
+    dg[s] = d1[s] - d0[s];
     // the run's tail also sets the won bits of the next frontier at once
     if (run[s] && wd[s] >= 0 && (run[s] & ~old[s]))
       atomicOr((unsigned long long *)&a.fnxt[wd[s]], (unsigned long long)(run[s] & ~old[s]));
   }
-  claim_won(a, c, won, par, single, true, fc, fd, fl);
+  claim_won(a, c, won, par, dg, single, true, fc, fd, fl);
 }
 
 // Each wave loads 64 bitmap words at once (one per lane) and compacts their
