@@ -192,7 +192,8 @@ grb_info check_ws(void *ws, size_t have, size_t need) {
 
 // ---- matrix metadata ---------------------------------------------------------
 struct MetaLayout {
-  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, wpart_off, iso_off, bytes;
+  size_t heavy_off, heavy_rows_off, split_off, split_rows_off, wpart_off, iso_off, first2_off,
+      bytes;
   int64_t max_pieces, max_rows, max_split, max_split_rows;
 };
 
@@ -208,7 +209,8 @@ MetaLayout meta_layout_one(int64_t nnz, int64_t nrows, size_t base) {
   m.split_rows_off = align_up(m.split_off + (size_t)m.max_split * 2 * sizeof(int32_t));
   m.wpart_off = align_up(m.split_rows_off + (size_t)m.max_split_rows * 3 * sizeof(int32_t));
   m.iso_off = align_up(m.wpart_off + (size_t)(kWaveParts + 1) * sizeof(int32_t));
-  m.bytes = align_up(m.iso_off + (size_t)words_of(nrows) * sizeof(uint64_t));
+  m.first2_off = align_up(m.iso_off + (size_t)words_of(nrows) * sizeof(uint64_t));
+  m.bytes = align_up(m.first2_off + (size_t)nrows * 2 * sizeof(int32_t));
   return m;
 }
 
@@ -309,7 +311,11 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
   if (!rows.empty() &&
       hipMemcpyAsync(hr, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return GRB_PANIC;
+  int2 *f2 = (int2 *)(meta + L.first2_off);
+  launch_first_two(c.rp, c.ci, c.nrows, f2, s);
+  if (hipGetLastError() != hipSuccess) return GRB_PANIC;
   if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+  c.first2 = f2;
   c.heavy = hp;
   c.nheavy = (int64_t)pieces.size() / 2;
   c.heavy_rows = hr;

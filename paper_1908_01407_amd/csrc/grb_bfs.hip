@@ -309,18 +309,23 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
         v[q] = b + q * 64 < total ? queue_slot(mark, mc, cnt, incl, total, b + q * 64, mw) : -1;
         act[q] = v[q] >= 0;
       }
+      // row extents and the first two neighbours (a separate array read
+      // in row order), all issued together
+      int c0[kPullRows], c1[kPullRows];
 #pragma unroll
       for (int q = 0; q < kPullRows; ++q) {
         cur[q] = act[q] ? rp[v[q]] : 0;
         end[q] = act[q] ? rp[v[q] + 1] : 0;
-        if (end[q] - cur[q] > kHeavyDeg || end[q] == cur[q]) act[q] = false;  // pieces / empty
+        const int2 f = act[q] ? a.pull.first2[v[q]] : make_int2(-1, -1);
+        c0[q] = f.x;
+        c1[q] = f.y;
       }
-      int c0[kPullRows], c1[kPullRows];
 #pragma unroll
-      for (int q = 0; q < kPullRows; ++q) {
-        c0[q] = act[q] ? ci[cur[q]] : -1;
-        c1[q] = act[q] && cur[q] + 1 < end[q] ? ci[cur[q] + 1] : -1;
-      }
+      for (int q = 0; q < kPullRows; ++q)
+        if (end[q] - cur[q] > kHeavyDeg || end[q] == cur[q]) {  // pieces / empty
+          act[q] = false;
+          c0[q] = c1[q] = -1;
+        }
       uint64_t b0[kPullRows], b1[kPullRows];
 #pragma unroll
       for (int q = 0; q < kPullRows; ++q) {
@@ -498,8 +503,9 @@ __device__ __forceinline__ void parents_pass(const BfsArgs &a, int *mark) {
       bool found = false;
       int par = -1;
       if (need) {
-        const int c0 = cur < end ? ci[cur] : -1;
-        const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
+        const int2 f = a.pull.first2[v];
+        const int c0 = f.x;
+        const int c1 = f.y;
         const int l0 = c0 >= 0 ? a.levels[c0] : -2;
         const int l1 = c1 >= 0 ? a.levels[c1] : -2;
         if (l0 == tgt) { found = true; par = c0; }
@@ -554,8 +560,9 @@ __device__ __forceinline__ void frontier_parents(const BfsArgs &a, int *mark) {
       bool found = false;
       int par = -1;
       if (need) {
-        const int c0 = cur < end ? ci[cur] : -1;
-        const int c1 = cur + 1 < end ? ci[cur + 1] : -1;
+        const int2 f = a.pull.first2[v];
+        const int c0 = f.x;
+        const int c1 = f.y;
         const int l0 = c0 >= 0 ? a.levels[c0] : -2;
         const int l1 = c1 >= 0 ? a.levels[c1] : -2;
         if (l0 == tgt) { found = true; par = c0; }

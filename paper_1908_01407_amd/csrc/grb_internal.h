@@ -52,6 +52,9 @@ struct Csr {
   const int32_t *wpart = nullptr;
   // rows without entries (and the padding bits past nrows), one bit each
   const uint64_t *iso = nullptr;
+  // first two column ids of every row (-1 where the row is shorter), read
+  // with the row extents so that a pull settled by them never touches col_idx
+  const int2 *first2 = nullptr;
   bool valid() const { return rp != nullptr; }
 };
 
@@ -224,6 +227,8 @@ struct MxmArgs {
 void launch_mxm_dot(const MxmArgs &a, bool count, void *stream);
 
 // generic helpers
+void launch_first_two(const int32_t *rp, const int32_t *ci, int64_t nrows, int2 *out,
+                      void *stream);
 void launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, void *stream);
 void launch_fill_bytes_pattern(void *p, int64_t count, int elem_size, const void *value,
                                void *stream);

@@ -167,6 +167,15 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
 // utilities
 // ---------------------------------------------------------------------------
 
+// first two column ids of every row, -1 where the row is shorter
+__global__ void k_first_two(const int32_t *rp, const int32_t *ci, int64_t nrows, int2 *out) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int b = rp[r], e = rp[r + 1];
+    out[r] = make_int2(e > b ? ci[b] : -1, e > b + 1 ? ci[b + 1] : -1);
+  }
+}
+
 __global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t value) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -243,6 +252,15 @@ void launch_fill_bytes_pattern(void *p, int64_t count, int elem_size, const void
   __builtin_memcpy(&pat, value, (size_t)elem_size);
   hipLaunchKernelGGL(k_fill_pattern, dim3(grid_for(count, kBlock, 4096)), dim3(kBlock), 0,
                      (hipStream_t)stream, (unsigned char *)p, count, elem_size, pat);
+}
+
+void launch_first_two(const int32_t *rp, const int32_t *ci, int64_t nrows, int2 *out,
+                      void *stream) {
+  if (nrows <= 0) return;
+  int64_t g = (nrows + 255) / 256;
+  g = g > 8192 ? 8192 : g;
+  hipLaunchKernelGGL(k_first_two, dim3((unsigned)g), dim3(256), 0, (hipStream_t)stream, rp, ci,
+                     nrows, out);
 }
 
 void launch_popcount(const uint64_t *bm, int64_t nw, int64_t *out, void *stream) {
