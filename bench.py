@@ -223,8 +223,80 @@ def host_info():
     return {"cpu": cpu, "logical_cpus": os.cpu_count()}
 
 
+def mxv_sweep(grb, torch, A, rp, ci):
+    """Forced-push, forced-pull and automatic grb_mxv on the same graph:
+    w<not m, replace> = A' u over LOR_LAND with a structural mask, u a random
+    frontier of density p, m a random visited set of density q.  Algorithmic
+    bytes per product:
+      push: frontier bitmap n/8, list and row extents 16|u|, column ids
+            4 sum deg(u), mask and output bitmaps 2n/8, values 1 per output;
+      pull: mask, frontier and output bitmaps 3n/8, row extents 8 per
+            allowed non-empty row, column ids 4 E_scan (first frontier hit),
+            values 1 per output."""
+    n = A.nrows
+    deg = np.diff(rp).astype(np.int64)
+    rng = np.random.default_rng(5)
+    out = []
+
+    def make(bits, dtype):
+        v = grb.Vector(n, dtype)
+        idx = torch.from_numpy(np.flatnonzero(bits).astype(np.int64)).to(v.values.device)
+        v.values[idx] = 1
+        words = np.packbits(bits.astype(np.uint8), bitorder="little")
+        words = np.concatenate([words, np.zeros((-len(words)) % 8, np.uint8)]).view(np.int64)
+        v.bitmap[: len(words)] = torch.from_numpy(words).to(v.values.device)
+        return v
+
+    ws = grb.workspace(grb.OP_MXV, A)
+    for q in (0.0, 0.5):
+        mask_bits = rng.random(n) < q
+        for p in (1e-4, 1e-3, 1e-2, 0.05, 0.2, 0.5):
+            u_bits = rng.random(n) < p
+            U = make(u_bits, torch.uint8)
+            Mk = make(mask_bits, torch.uint8)
+            W = grb.Vector(n, torch.uint8)
+            allowed = ~mask_bits
+            nxt_rows = allowed & (deg > 0)
+            e_scan = first_hit_scan(rp, ci, nxt_rows, u_bits)
+            hit = np.zeros(n, bool)
+            src = np.repeat(np.arange(n), deg)
+            hit[src[u_bits[ci]]] = True
+            n_out = int((hit & allowed).sum())
+            nu = int(u_bits.sum())
+            push_b = n / 8 + 16 * nu + 4 * int(deg[u_bits].sum()) + 2 * n / 8 + n_out
+            pull_b = 3 * n / 8 + 8 * int(nxt_rows.sum()) + 4 * e_scan + n_out
+            row = {"frontier_density": p, "mask_density": q, "frontier": nu,
+                   "push_edges": int(deg[u_bits].sum()), "pull_edges_scanned": int(e_scan)}
+            for name, dr in (("push", 1), ("pull", 2), ("auto", 0)):
+                d = grb.descriptor(direction=dr, rule=1,
+                                   flags=grb.GRB_MASK_COMP | grb.GRB_MASK_STRUCT | grb.GRB_REPLACE)
+                run = lambda: grb.mxv(W, Mk, None, "lor_land", A, U, desc=d, ws=ws)
+                run()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(5):
+                    run()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / 5
+                row[f"{name}_ms"] = round(ms, 4)
+                if name != "auto":
+                    b = push_b if name == "push" else pull_b
+                    row[f"{name}_gbs"] = round(b / (ms / 1e3) / 1e9, 1)
+                    row[f"{name}_frac_hbm"] = round(b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            out.append(row)
+            log(f"[bench] mxv sweep p={p} q={q}: push {row['push_ms']} ms "
+                f"({row['push_frac_hbm']}), pull {row['pull_ms']} ms ({row['pull_frac_hbm']}), "
+                f"auto {row['auto_ms']} ms")
+            del U, Mk, W, src
+    return out
+
+
 def bench_extras(grb, graphgen, torch, args):
     ex = {}
+    if not args.no_sweep:
+        ex["mxv_sweep_rmat22"] = mxv_sweep(grb, torch, args._A, args._rp, args._ci)
     # SSSP on the same R-MAT graph (min-plus, weights 1..64)
     A = args._A
     ws = grb.workspace(grb.OP_SSSP, A)
@@ -495,6 +567,7 @@ def main():
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-pr", action="store_true")
     ap.add_argument("--no-tc", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-msbfs", action="store_true")
@@ -587,6 +660,7 @@ def main():
     levels = lev.cpu().numpy()
     rp = A.row_ptr.cpu().numpy()
     ci = A.col_idx.cpu().numpy()
+    args._rp, args._ci = rp, ci
     per_level = bfs_bytes_per_level(rp, ci, levels, st["direction"], n)
     par = parents_bytes(rp, ci, levels, st["direction"], st["frontier"], n)
     per_level = [b + p for b, p in zip(per_level, par)]

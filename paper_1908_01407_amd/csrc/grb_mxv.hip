@@ -267,46 +267,91 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
     if constexpr (Sr<SR>::lor) acc = 0;
     else acc = Sr<SR>::identity();
     bool has = false;
-    for (;;) {
+    if constexpr (Sr<SR>::lor) {
+      // OR: the first two neighbours of every allowed row first (one row
+      // per lane, from the prepared first-two array), so that rows settled
+      // by them never stream; the stream below starts after them
+      if (act) {
+        const int2 f = a.pull.first2[i];
+        const bool p0 = f.x >= 0 && bit_of(a.u_bm, f.x);
+        const bool p1 = f.y >= 0 && bit_of(a.u_bm, f.y);
+        if (p0 || p1) has = true;
+        if ((p0 && uv[f.x] != 0 && mat_true(a.pull, cur)) ||
+            (p1 && uv[f.y] != 0 && mat_true(a.pull, cur + 1)))
+          acc = 1;
+        cur = min(cur + 2, end);
+      }
+    }
+    // kU steps of 64 stream positions are laid out first, then all their
+    // loads issue together; products are reduced step by step in order.
+    // OR takes one step at a time: a row stops at its first true product,
+    // and larger batches would scan past it
+    constexpr int kU = Sr<SR>::lor ? 1 : kUnroll;
+    for (bool more = true; more;) {
       bool live = act;
       if constexpr (Sr<SR>::lor) live = live && acc == 0;  // OR saturates at true
-      const int len = live ? end - cur : 0;
-      const int incl = wave_incl_scan(len);
-      const int total = lane_last(incl);
-      if (total == 0) break;
-      const int excl = incl - len;
-      const bool starts = len > 0 && excl < 64;
-      const int r = slot_rows(mark, starts, excl);
-      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-      bool pres = false;
-      T prod;
-      if constexpr (Sr<SR>::lor) prod = 0;
-      else prod = Sr<SR>::identity();
-      if (ln < total) {
-        const int64_t pos = rcur + (ln - rexcl);
-        const int j = ci[pos];
-        if (bit_of(a.u_bm, j)) {
-          pres = true;
-          if constexpr (Sr<SR>::lor) prod = (T)(uv[j] != 0 && mat_true(a.pull, pos));
-          else prod = Sr<SR>::mul(mat_value<T>(a.pull, pos), uv[j], a.pick_vec);
+      int64_t pos[kU];
+      int row[kU], sev[kU], exv[kU];
+      bool st[kU];
+#pragma unroll
+      for (int s = 0; s < kU; ++s) {
+        pos[s] = -1;
+        row[s] = 0;
+        sev[s] = 0;
+        exv[s] = 0;
+        st[s] = false;
+        if (!more) continue;
+        const int len = live ? end - cur : 0;
+        const int incl = wave_incl_scan(len);
+        const int total = lane_last(incl);
+        if (total == 0) {
+          more = false;
+          continue;
+        }
+        const int excl = incl - len;
+        const bool starts = len > 0 && excl < 64;
+        const int r = slot_rows(mark, starts, excl);
+        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+        if (ln < total) pos[s] = rcur + (ln - rexcl);
+        row[s] = r;
+        st[s] = starts;
+        sev[s] = min(incl, 64);
+        exv[s] = excl;
+        if (starts) cur += sev[s] - excl;
+      }
+      int jv[kU];
+#pragma unroll
+      for (int s = 0; s < kU; ++s) jv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+      bool pres[kU];
+#pragma unroll
+      for (int s = 0; s < kU; ++s) pres[s] = jv[s] >= 0 && bit_of(a.u_bm, jv[s]);
+      T prod[kU];
+#pragma unroll
+      for (int s = 0; s < kU; ++s) {
+        if constexpr (Sr<SR>::lor) {
+          prod[s] = pres[s] ? (T)(uv[jv[s]] != 0 && mat_true(a.pull, pos[s])) : (T)0;
+        } else {
+          prod[s] = pres[s] ? Sr<SR>::mul(mat_value<T>(a.pull, pos[s]), uv[jv[s]], a.pick_vec)
+                            : Sr<SR>::identity();
         }
       }
-      const int se = min(incl, 64);
-      const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
-      const uint64_t pm = __ballot(pres);
-      if constexpr (Sr<SR>::lor) {
-        const uint64_t tm = __ballot(prod != 0);
-        if (pm & seg) has = true;
-        if (tm & seg) acc = 1;
-      } else {
-        const T x = wave_seg_scan(prod, r, Sr<SR>::identity(), SrAdd<SR>());
-        const T segv = __shfl(x, starts ? se - 1 : 0);
-        if (pm & seg) {
-          has = true;
-          acc = Sr<SR>::add(acc, segv);
+#pragma unroll
+      for (int s = 0; s < kU; ++s) {
+        const uint64_t seg = st[s] ? (mask_below(sev[s]) & ~mask_below(exv[s])) : 0ull;
+        const uint64_t pm = __ballot(pres[s]);
+        if constexpr (Sr<SR>::lor) {
+          const uint64_t tm = __ballot(prod[s] != 0);
+          if (pm & seg) has = true;
+          if (tm & seg) acc = 1;
+        } else {
+          const T x = wave_seg_scan(prod[s], row[s], Sr<SR>::identity(), SrAdd<SR>());
+          const T segv = __shfl(x, st[s] ? sev[s] - 1 : 0);
+          if (pm & seg) {
+            has = true;
+            acc = Sr<SR>::add(acc, segv);
+          }
         }
       }
-      if (starts) cur += se - excl;
     }
     bool out_has = false;
     if (inb && !heavy) {
@@ -328,31 +373,39 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
     else acc = Sr<SR>::identity();
     if (mask_allowed(a, r)) {
       const int e = min(b + kHeavyChunk, rp[r + 1]);
-      for (int base = b; base < e; base += 64) {
-        const int64_t pos = base + ln;
-        bool pres = false;
-        T prod;
-        if constexpr (Sr<SR>::lor) prod = 0;
-        else prod = Sr<SR>::identity();
-        if (pos < e) {
-          const int j = ci[pos];
-          if (bit_of(a.u_bm, j)) {
-            pres = true;
-            if constexpr (Sr<SR>::lor) prod = (T)(uv[j] != 0 && mat_true(a.pull, pos));
-            else prod = Sr<SR>::mul(mat_value<T>(a.pull, pos), uv[j], a.pick_vec);
-          }
-        }
-        if (__ballot(pres)) pres_any = true;
-        if constexpr (Sr<SR>::lor) {
-          if (__ballot(prod != 0)) {
-            acc = 1;
-            break;
-          }
-        } else {
-          T x = prod;
+      bool done = false;
+      for (int base = b; base < e && !done; base += 64 * kUnroll) {
+        int jv[kUnroll];
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) x = Sr<SR>::add(x, __shfl_xor(x, off));
-          acc = Sr<SR>::add(acc, x);
+        for (int s = 0; s < kUnroll; ++s) {
+          const int64_t pos = base + s * 64 + ln;
+          jv[s] = pos < e ? ci[pos] : -1;
+        }
+        bool pres[kUnroll];
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) pres[s] = jv[s] >= 0 && bit_of(a.u_bm, jv[s]);
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+          const int64_t pos = base + s * 64 + ln;
+          T prod;
+          if constexpr (Sr<SR>::lor) {
+            prod = pres[s] ? (T)(uv[jv[s]] != 0 && mat_true(a.pull, pos)) : (T)0;
+          } else {
+            prod = pres[s] ? Sr<SR>::mul(mat_value<T>(a.pull, pos), uv[jv[s]], a.pick_vec)
+                           : Sr<SR>::identity();
+          }
+          if (__ballot(pres[s])) pres_any = true;
+          if constexpr (Sr<SR>::lor) {
+            if (!done && __ballot(prod != 0)) {
+              acc = 1;
+              done = true;
+            }
+          } else {
+            T x = prod;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x = Sr<SR>::add(x, __shfl_xor(x, off));
+            acc = Sr<SR>::add(acc, x);
+          }
         }
       }
     }
