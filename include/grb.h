@@ -205,11 +205,14 @@ grb_info grb_matrix_ncols(grb_matrix A, int64_t *n);
 grb_info grb_matrix_nvals(grb_matrix A, int64_t *nnz);
 
 /*
- * Derived metadata (split lists of very long rows for the pull kernels) is
- * built into a caller-owned device buffer of at least *bytes bytes.
- * grb_matrix_prepare synchronises `stream` (it reads back how many long
- * rows exist).  Every product and driver requires a prepared matrix
- * (else GRB_UNINITIALIZED_OBJECT).  The buffer is borrowed like the CSR.
+ * Derived metadata is built into a caller-owned device buffer of at least
+ * *bytes bytes, per CSR: pieces of long rows (for the push and pull
+ * kernels), runs of bitmap words of about equal work (for full sweeps), a
+ * bitmap of the empty rows, and the first two column ids of every row.
+ * grb_matrix_prepare synchronises `stream` (it reads the row pointers back
+ * to build the lists).  Every product and driver requires a prepared
+ * matrix (else GRB_UNINITIALIZED_OBJECT), except the masked matrix product
+ * and the triangle count.  The buffer is borrowed like the CSR.
  */
 grb_info grb_matrix_meta_size(grb_matrix A, size_t *bytes);
 grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *stream);
