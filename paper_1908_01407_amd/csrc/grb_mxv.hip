@@ -451,7 +451,10 @@ __global__ void k_mxv_pull_fixup(MxvArgs a) {
 
 template <int SR>
 void run_mxv(const MxvArgs &a, hipStream_t s) {
-  const int gw_out = (int)std::max<int64_t>(1, std::min<int64_t>((a.nw_out + 3) / 4, kExpandGrid));
+  // per-word kernels: one output word per wave (each word is a dependent
+  // chain of loads, so the words run side by side)
+  const int gw_out = (int)std::max<int64_t>(
+      1, std::min<int64_t>((a.nw_out + kWavesPerBlock - 1) / kWavesPerBlock, 1 << 16));
   hipLaunchKernelGGL(k_mxv_init, dim3(64), dim3(256), 0, s, a);
   const bool want_push = a.can_push && a.forced != GRB_DIR_PULL;
   const bool want_pull = a.can_pull && a.forced != GRB_DIR_PUSH;
@@ -473,7 +476,7 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
   }
   if (want_pull) {
-    hipLaunchKernelGGL(k_mxv_pull<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_mxv_pull<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
     if (a.pull.nheavy_rows > 0)
       hipLaunchKernelGGL(k_mxv_pull_fixup<SR>, dim3(64), dim3(256), 0, s, a);
   }
