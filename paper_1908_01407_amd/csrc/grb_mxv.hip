@@ -11,7 +11,8 @@
 //   entries per step, reduced per row with a segmented scan (fixed order,
 //   so floating-point results repeat bit for bit); LOR_LAND stops a row at
 //   its first true product; rows longer than kHeavyDeg are cut into pieces
-//   whose partial results a fix-up kernel adds in piece order.
+//   whose partial results a fix-up kernel (a wave per long row) combines in
+//   a fixed order.
 // The direction is chosen on the device (forced, or the descriptor's rule
 // on the input's size and degree sum), every kernel of the path not taken
 // returns at once.
@@ -144,10 +145,12 @@ __global__ void k_mxv_init(MxvArgs a) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = gt; i < 2 * (int64_t)a.nblk; i += (int64_t)gridDim.x * blockDim.x)
     a.status[i] = 0ull;
-  if (gt == 0) {
-    Ctrl c = {};
-    *a.ctrl = c;
-  }
+  // the control block (a few KB) cleared by the first workgroup's threads
+  // together, 8 bytes each (all its fields are zero when cleared)
+  static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is cleared in 8-byte words");
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < (int)(sizeof(Ctrl) / 8); k += blockDim.x)
+      reinterpret_cast<uint64_t *>(a.ctrl)[k] = 0ull;
 }
 
 template <int SR>
@@ -416,35 +419,47 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
   }
 }
 
+// One wave per long row: lane l combines the pieces l, l + 64, ... in order,
+// then the lanes' results are combined in a fixed order.
 template <int SR>
-__global__ void k_mxv_pull_fixup(MxvArgs a) {
+__global__ __launch_bounds__(kBlock) void k_mxv_pull_fixup(MxvArgs a) {
   using T = typename Sr<SR>::T;
   if (mxv_dir(a) != GRB_DIR_PULL) return;
   const T *hv = (const T *)a.hp_val;
   T *w = (T *)a.w_val;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.pull.nheavy_rows;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  const int ln = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t k = gw; k < a.pull.nheavy_rows; k += nwaves) {
     const int r = a.pull.heavy_rows[3 * k], first = a.pull.heavy_rows[3 * k + 1],
               cnt = a.pull.heavy_rows[3 * k + 2];
-    const bool allowed = mask_allowed(a, r);
     T acc;
     if constexpr (Sr<SR>::lor) acc = 0;
     else acc = Sr<SR>::identity();
     bool has = false;
-    for (int p = 0; p < cnt; ++p) {
+    for (int p = ln; p < cnt; p += 64) {
       if (!a.hp_has[first + p]) continue;
       has = true;
       if constexpr (Sr<SR>::lor) acc = (T)(acc || hv[first + p]);
       else acc = Sr<SR>::add(acc, hv[first + p]);
     }
-    T out = acc;
-    const bool out_has = epilogue<SR>(a, r, allowed, has, acc, &out);
-    const unsigned long long bit = 1ull << (r & 63);
-    if (out_has) {
-      w[r] = out;
-      atomicOr((unsigned long long *)&a.w_bm[r >> 6], bit);
+    has = __ballot(has) != 0ull;
+    if constexpr (Sr<SR>::lor) {
+      acc = (T)(__ballot(acc != 0) != 0ull);
     } else {
-      atomicAnd((unsigned long long *)&a.w_bm[r >> 6], ~bit);
+      acc = lane_last(wave_scan(acc, Sr<SR>::identity(), SrAdd<SR>()));
+    }
+    if (ln == 0) {
+      const bool allowed = mask_allowed(a, r);
+      T out = acc;
+      const bool out_has = epilogue<SR>(a, r, allowed, has, acc, &out);
+      const unsigned long long bit = 1ull << (r & 63);
+      if (out_has) {
+        w[r] = out;
+        atomicOr((unsigned long long *)&a.w_bm[r >> 6], bit);
+      } else {
+        atomicAnd((unsigned long long *)&a.w_bm[r >> 6], ~bit);
+      }
     }
   }
 }
@@ -477,8 +492,11 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
   }
   if (want_pull) {
     hipLaunchKernelGGL(k_mxv_pull<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
-    if (a.pull.nheavy_rows > 0)
-      hipLaunchKernelGGL(k_mxv_pull_fixup<SR>, dim3(64), dim3(256), 0, s, a);
+    if (a.pull.nheavy_rows > 0) {
+      const int gf = (int)std::min<int64_t>(
+          (a.pull.nheavy_rows + kWavesPerBlock - 1) / kWavesPerBlock, kExpandGrid);
+      hipLaunchKernelGGL(k_mxv_pull_fixup<SR>, dim3(gf), dim3(kBlock), 0, s, a);
+    }
   }
 }
 
