@@ -48,21 +48,48 @@ __device__ __forceinline__ void mark_improved(const SsspArgs &a, int v, int &fc,
 
 // Relaxes dist[c[s]] with nd[s] for s < kUnroll (c < 0: none).  The
 // current distances are read first, all at once (a plain read is only a
-// filter, the atomic decides).
+// filter, the atomic decides).  Beside each atomic go the loads a success
+// needs (the next frontier's word, the target's degree), and the marks of
+// all s are issued before any is counted, so a batch waits a fixed number
+// of times whatever its wins.
 __device__ __forceinline__ void relax_batch(const SsspArgs &a, const int (&c)[kUnroll],
                                             const float (&nd)[kUnroll], int &fc, int &fd,
                                             int &fl) {
   float cd[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) cd[s] = c[s] >= 0 ? a.dist[c[s]] : 0.0f;
+  int old[kUnroll], r0[kUnroll], r1[kUnroll];
+  uint64_t w[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
+    old[s] = 0;
+    r0[s] = r1[s] = 0;
+    w[s] = ~0ull;
     if (c[s] >= 0 && nd[s] < cd[s]) {
-      const int old = atomicMin((int *)&a.dist[c[s]], __float_as_int(nd[s]));
-      if (nd[s] < __int_as_float(old)) {
-        atomicMin((int *)&a.fd_nxt[c[s]], __float_as_int(nd[s]));
-        mark_improved(a, c[s], fc, fd, fl);
-      }
+      old[s] = atomicMin((int *)&a.dist[c[s]], __float_as_int(nd[s]));
+      w[s] = a.fnxt[c[s] >> 6];
+      r0[s] = a.push.rp[c[s]];
+      r1[s] = a.push.rp[c[s] + 1];
+    }
+  }
+  uint64_t o[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    o[s] = ~0ull;
+    if (c[s] >= 0 && nd[s] < cd[s] && nd[s] < __int_as_float(old[s])) {
+      atomicMin((int *)&a.fd_nxt[c[s]], __float_as_int(nd[s]));
+      const uint64_t b = 1ull << (c[s] & 63);
+      if (!(w[s] & b))
+        o[s] = atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], (unsigned long long)b);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    if (c[s] >= 0 && !(o[s] & (1ull << (c[s] & 63)))) {
+      const int pd = r1[s] - r0[s];
+      fc += 1;
+      fd += pd;
+      fl += pd > kPushSplit ? 1 : 0;
     }
   }
 }

@@ -33,12 +33,12 @@ struct DCount {
 
 __device__ __forceinline__ int bucket_of(float d, float delta) { return (int)(d / delta); }
 
-// Counts a new member of the next pending set with distance nd.
-__device__ __forceinline__ void count_new(const SsspArgs &a, int v, float nd, float limit,
+// Counts a new member of the next pending set with distance nd and out-
+// degree pd.
+__device__ __forceinline__ void count_new(const SsspArgs &a, int pd, float nd, float limit,
                                           DCount &c) {
   c.pend += 1;
   if (nd < limit) {
-    const int pd = a.push.rp[v + 1] - a.push.rp[v];
     c.near += 1;
     c.sd += pd;
     c.lng += pd > kPushSplit ? 1 : 0;
@@ -47,28 +47,41 @@ __device__ __forceinline__ void count_new(const SsspArgs &a, int v, float nd, fl
   }
 }
 
-// Relaxes dist[c[s]] with nd[s] (c < 0: none); all reads, then all atomics.
+// Relaxes dist[c[s]] with nd[s] (c < 0: none); all reads, then all atomics,
+// each beside the loads its success needs (the pending set's word, the
+// target's degree), then all marks, then the counts.
 __device__ __forceinline__ void relax_near(const SsspArgs &a, const int (&c)[kUnroll],
                                            const float (&nd)[kUnroll], float limit, DCount &cnt) {
   float cd[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) cd[s] = c[s] >= 0 ? a.dist[c[s]] : 0.0f;
-  int old[kUnroll];
+  int old[kUnroll], r0[kUnroll], r1[kUnroll];
+  uint64_t w[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
     old[s] = 0;
-    if (c[s] >= 0 && nd[s] < cd[s]) old[s] = atomicMin((int *)&a.dist[c[s]], __float_as_int(nd[s]));
-  }
-#pragma unroll
-  for (int s = 0; s < kUnroll; ++s) {
-    if (c[s] >= 0 && nd[s] < cd[s] && nd[s] < __int_as_float(old[s])) {
-      const uint64_t b = 1ull << (c[s] & 63);
-      if (!(a.fnxt[c[s] >> 6] & b)) {
-        const uint64_t o = atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], (unsigned long long)b);
-        if (!(o & b)) count_new(a, c[s], nd[s], limit, cnt);
-      }
+    r0[s] = r1[s] = 0;
+    w[s] = ~0ull;
+    if (c[s] >= 0 && nd[s] < cd[s]) {
+      old[s] = atomicMin((int *)&a.dist[c[s]], __float_as_int(nd[s]));
+      w[s] = a.fnxt[c[s] >> 6];
+      r0[s] = a.push.rp[c[s]];
+      r1[s] = a.push.rp[c[s] + 1];
     }
   }
+  uint64_t o[kUnroll];
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s) {
+    o[s] = ~0ull;
+    if (c[s] >= 0 && nd[s] < cd[s] && nd[s] < __int_as_float(old[s])) {
+      const uint64_t b = 1ull << (c[s] & 63);
+      if (!(w[s] & b))
+        o[s] = atomicOr((unsigned long long *)&a.fnxt[c[s] >> 6], (unsigned long long)b);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kUnroll; ++s)
+    if (c[s] >= 0 && !(o[s] & (1ull << (c[s] & 63)))) count_new(a, r1[s] - r0[s], nd[s], limit, cnt);
 }
 
 __device__ void delta_push(const SsspArgs &a, int *mark, float limit, bool pieces, DCount &cnt) {
