@@ -25,6 +25,15 @@
 namespace grb {
 namespace {
 
+// A pull round probes the frontier bitmap before gathering distances when
+// fewer than nnz / kProbeDen edges leave the frontier (the share of the
+// gathers the probe can skip; a frontier of hubs is small in vertices but
+// not in edges), and loads weights for frontier members only below
+// nnz / kSparseDen such edges.
+constexpr int64_t kProbeDen = 4;
+constexpr int64_t kSparseDen = 32;
+enum PullMode { kGatherAll = 0, kProbe = 1, kProbeSparse = 2 };
+
 __device__ __forceinline__ int decide(const SsspArgs &a, int count, int sumdeg) {
   if (a.forced) return a.forced;
   if (!a.can_pull) return GRB_DIR_PUSH;
@@ -222,11 +231,48 @@ __device__ void sssp_push(const SsspArgs &a, int *mark, bool long_rows, int &fc,
   }
 }
 
-__device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &fl) {
+// Pull-round candidate distances fd(c) + w(pos) of the stream positions pos
+// (pos < 0: none) with column ids c (+inf off the frontier).  kGatherAll:
+// the weights load with the ids and every id's distance is gathered (the
+// fewest dependent loads: for frontiers that most edges leave).  kProbe:
+// each id's frontier bit is read first (the bitmap is n/8 bytes and stays
+// in cache) and only frontier members gather their distance.  kProbeSparse:
+// as kProbe, and only members load their weight, beside the distance.
+template <int K>
+__device__ __forceinline__ void pull_terms(const SsspArgs &a, const int (&pos)[K], int mode,
+                                           float (&t)[K]) {
+  const float inf = __int_as_float(0x7f800000);
+  int c[K];
+  float w[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    c[s] = pos[s] >= 0 ? a.pull.ci[pos[s]] : -1;
+    w[s] = (mode != kProbeSparse && pos[s] >= 0) ? a.wpull[pos[s]] : 0.0f;
+  }
+  if (mode == kGatherAll) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) t[s] = (c[s] >= 0 ? a.fd_cur[c[s]] : inf) + w[s];
+    return;
+  }
+  uint64_t fb[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) fb[s] = c[s] >= 0 ? a.fcur[c[s] >> 6] : 0ull;
+  float d[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const bool in = c[s] >= 0 && ((fb[s] >> (c[s] & 63)) & 1ull);
+    d[s] = in ? a.fd_cur[c[s]] : inf;
+    if (mode == kProbeSparse && in) w[s] = a.wpull[pos[s]];
+  }
+#pragma unroll
+  for (int s = 0; s < K; ++s) t[s] = d[s] + w[s];
+}
+
+__device__ void sssp_pull(const SsspArgs &a, int *mark, int mode, int &fc, int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
+  const int32_t *rp = a.pull.rp;
   const float inf = __int_as_float(0x7f800000);
   // the wave's run of words (runs of about equal work, built by
   // grb_matrix_prepare: rows of similar degree have nearby ids)
@@ -283,21 +329,11 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &f
             se[s] = min(incl, 64);
             if (starts) cur += se[s] - excl;
           }
-          int cv[kUnroll];
-          float wt[kUnroll];
+          float tv[kUnroll];
+          pull_terms(a, pos, mode, tv);
   #pragma unroll
           for (int s = 0; s < kUnroll; ++s) {
-            cv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
-            wt[s] = pos[s] >= 0 ? a.wpull[pos[s]] : 0.0f;
-          }
-          // one gather per edge: the frontier distance is +inf off the
-          // frontier
-          float dc[kUnroll];
-  #pragma unroll
-          for (int s = 0; s < kUnroll; ++s) dc[s] = cv[s] >= 0 ? a.fd_cur[cv[s]] : inf;
-  #pragma unroll
-          for (int s = 0; s < kUnroll; ++s) {
-            const float y = seg_min_scan(dc[s] + wt[s], row[s]);
+            const float y = seg_min_scan(tv[s], row[s]);
             const float segmin = __shfl(y, st[s] ? se[s] - 1 : 0);
             if (st[s]) best = fminf(best, segmin);
           }
@@ -342,27 +378,23 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int &fc, int &fd, int &f
           pe[q] = __shfl(e, k);
         }
       }
-      int cv[2][kUnroll];
-      float wt[2][kUnroll];
+      int pos[2][kUnroll];
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int s = 0; s < kUnroll; ++s) {
-          const int pos = pb[q] + s * 64 + ln;
-          cv[q][s] = pos < pe[q] ? ci[pos] : -1;
-          wt[q][s] = pos < pe[q] ? a.wpull[pos] : 0.0f;
+          const int ps = pb[q] + s * 64 + ln;
+          pos[q][s] = ps < pe[q] ? ps : -1;
         }
-      float dc[2][kUnroll];
+      float tv[2][kUnroll];
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int s = 0; s < kUnroll; ++s) dc[q][s] = cv[q][s] >= 0 ? a.fd_cur[cv[q][s]] : inf;
+      for (int q = 0; q < 2; ++q) pull_terms(a, pos[q], mode, tv[q]);
       float best[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         best[q] = inf;
 #pragma unroll
-        for (int s = 0; s < kUnroll; ++s) best[q] = fminf(best[q], dc[q][s] + wt[q][s]);
+        for (int s = 0; s < kUnroll; ++s) best[q] = fminf(best[q], tv[q][s]);
       }
       best[0] = wave_min(best[0]);
       best[1] = wave_min(best[1]);
@@ -411,7 +443,12 @@ __global__ __launch_bounds__(kBlock) void k_sssp_round(SsspArgs a) {
   const int dir = decide(a, s_count, s_sumdeg);
   int fc = 0, fd = 0, fl = 0;
   if (dir == GRB_DIR_PUSH) sssp_push(a, s_mark[threadIdx.x >> 6], s_long > 0, fc, fd, fl);
-  else sssp_pull(a, s_mark[threadIdx.x >> 6], fc, fd, fl);
+  else {
+    const int64_t e = s_sumdeg;  // edges that leave the frontier
+    const int mode = e * kSparseDen < a.nnz ? kProbeSparse
+                     : e * kProbeDen < a.nnz ? kProbe : kGatherAll;
+    sssp_pull(a, s_mark[threadIdx.x >> 6], mode, fc, fd, fl);
+  }
   fc = wave_sum(fc);
   fd = wave_sum(fd);
   fl = wave_sum(fl);
