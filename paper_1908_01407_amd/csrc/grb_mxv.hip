@@ -270,20 +270,31 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
     if constexpr (Sr<SR>::lor) acc = 0;
     else acc = Sr<SR>::identity();
     bool has = false;
+    int cmin = 1 << 30;  // positions a row takes per step when rows are many
     if constexpr (Sr<SR>::lor) {
       // OR: the first two neighbours of every allowed row first (one row
       // per lane, from the prepared first-two array), so that rows settled
       // by them never stream; the stream below starts after them
+      bool q0 = false, q1 = false, p0 = false, p1 = false;
       if (act) {
         const int2 f = a.pull.first2[i];
-        const bool p0 = f.x >= 0 && bit_of(a.u_bm, f.x);
-        const bool p1 = f.y >= 0 && bit_of(a.u_bm, f.y);
+        q0 = f.x >= 0;
+        q1 = f.y >= 0;
+        p0 = q0 && bit_of(a.u_bm, f.x);
+        p1 = q1 && bit_of(a.u_bm, f.y);
         if (p0 || p1) has = true;
         if ((p0 && uv[f.x] != 0 && mat_true(a.pull, cur)) ||
             (p1 && uv[f.y] != 0 && mat_true(a.pull, cur + 1)))
           acc = 1;
         cur = min(cur + 2, end);
       }
+      // the probes' hit rate estimates the frontier's density d; a row
+      // then streams about 2/d positions per step (its first frontier
+      // entry is expected 1/d in), so that a dense frontier does not
+      // gather the entries past the first
+      const int np = __popcll(__ballot(q0)) + __popcll(__ballot(q1));
+      const int nh = __popcll(__ballot(p0)) + __popcll(__ballot(p1));
+      cmin = nh == 0 ? 64 : min(64, max(4, 2 * np / nh));
     }
     // kU steps of 64 stream positions are laid out first, then all their
     // loads issue together; products are reduced step by step in order.
@@ -304,7 +315,12 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
         exv[s] = 0;
         st[s] = false;
         if (!more) continue;
-        const int len = live ? end - cur : 0;
+        int len = live ? end - cur : 0;
+        if (Sr<SR>::lor && cmin < 64) {  // (a step holds 64 positions anyway)
+          // at least a full step between the live rows
+          const int nl = __popcll(__ballot(len > 0));
+          len = min(len, max(cmin, nl ? (64 + nl - 1) / nl : 64));
+        }
         const int incl = wave_incl_scan(len);
         const int total = lane_last(incl);
         if (total == 0) {
