@@ -300,8 +300,8 @@ __device__ void sssp_pull(const SsspArgs &a, int *mark, int mode, int &fc, int &
         const int deg0 = end - cur;
         float best = inf;
         // slot positions of kUnroll x 64 edges first, then their loads, then
-        // the segmented minima over frontier neighbours (a distance is read
-        // only for neighbours in the frontier)
+        // the segmented minima over frontier neighbours (off the frontier a
+        // candidate is +inf)
         for (bool more = true; more;) {
           int pos[kUnroll], row[kUnroll], se[kUnroll];
           bool st[kUnroll];

@@ -153,6 +153,24 @@ def test_sssp_parity(grb, name, mode):
         assert np.array_equal(dist.cpu().numpy(), ref), (name, s)
 
 
+def test_sssp_pull_modes(grb):
+    """A forced-pull SSSP whose rounds span the three pull forms (chosen by
+    the share of edges leaving the frontier: below 1/32 member-only weight
+    loads, below 1/4 a frontier-bit test before the distance gather, else a
+    gather per edge) reaches the oracle's distances."""
+    g, adj = graph("rmat_14")
+    A = matrix(grb, "rmat_14")
+    dist = grb.sssp(A, 0, desc=grb.descriptor(direction=grb.DIR_PULL, flags=grb.GRB_PROFILE))
+    st = grb.last_stats()
+    ref, _, _ = oracle.sssp(adj, 0)
+    assert np.array_equal(dist.cpu().numpy(), ref)
+    assert all(d == grb.DIR_PULL for d in st["direction"])
+    share = [e / A.nnz for e in st["edges"]]
+    assert any(x < 1 / 32 for x in share), share
+    assert any(1 / 32 <= x < 1 / 4 for x in share), share
+    assert any(x >= 1 / 4 for x in share), share
+
+
 @pytest.mark.parametrize("name", SSSP_GRAPHS)
 @pytest.mark.parametrize("delta", [1.0, 7.5, 64.0, 1e6])
 def test_sssp_delta_parity(grb, name, delta):
