@@ -24,6 +24,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python paper_1908_01407_amd/build.py`")
 
+# torch first: the library and torch both link the HIP runtime, and the one
+# loaded first serves the process.  Loaded the other way round, torch's own
+# kernels failed to launch ("invalid device function").
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- enums and flags (mirror include/grb.h) ---------------------------------

@@ -7,6 +7,8 @@ count.  Inputs are seeded synthetic graphs of the paper's kinds (R-MAT with
 a, b, c, d = 0.57, 0.19, 0.19, 0.05 and integer weights 1..64) plus grids and
 hand-built degenerate graphs.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -301,3 +303,22 @@ def test_pagerank_closed_forms(grb):
     p, it2, _ = grb.pagerank(S, dtype=torch.float64, max_iter=50, tol=1e-7)
     assert it2 == it
     assert np.abs(p.cpu().numpy() - ref).sum() <= 1e-10
+
+
+def test_package_imported_before_torch():
+    """Importing the package before torch leaves torch's kernels working
+    (the package loads torch before its library, so both share torch's HIP
+    runtime); a fresh process, BFS levels checked against the oracle."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_1908_01407_amd as grb, graphgen, oracle, numpy as np, torch\n"
+            "g = graphgen.rmat(10)\n"
+            "lev, par = grb.bfs(grb.Matrix.from_raw(g), 0)\n"
+            "ref = oracle.bfs(oracle.Adjacency.from_raw(g), 0)[0]\n"
+            "x = torch.arange(8, device='cuda').sum().item()\n"
+            "assert np.array_equal(lev.cpu().numpy(), ref) and x == 28\n"
+            "print('ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=100)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-3000:]
