@@ -204,9 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_mxv_push(MxvArgs a) {
       if (!mask_allowed(a, i)) continue;
       const uint64_t b = 1ull << (i & 63);
       if constexpr (Sr<SR>::lor) {
-        if (!(a.t_bm[i >> 6] & b)) atomicOr((unsigned long long *)&a.t_bm[i >> 6], b);
-        if (s_val[lo] != 0 && mat_true(a.push, pos) && !(a.t_vb[i >> 6] & b))
-          atomicOr((unsigned long long *)&a.t_vb[i >> 6], b);
+        // one OR per edge: t_vb marks a true product, t_bm a false one (the
+        // merge reads presence as either); two guarded atomics on fixed
+        // arrays, not one through a per-lane choice of array
+        if (s_val[lo] != 0 && mat_true(a.push, pos)) {
+          if (!(a.t_vb[i >> 6] & b)) atomicOr((unsigned long long *)&a.t_vb[i >> 6], b);
+        } else {
+          if (!(a.t_bm[i >> 6] & b)) atomicOr((unsigned long long *)&a.t_bm[i >> 6], b);
+        }
       } else {
         const T prod = Sr<SR>::mul(mat_value<T>(a.push, pos), s_val[lo], a.pick_vec);
         atomic_add_sr<SR>(&((T *)a.t_val)[i], prod);
@@ -229,10 +234,14 @@ __global__ __launch_bounds__(kBlock) void k_mxv_merge(MxvArgs a) {
     const int64_t i = wd * 64 + ln;
     bool has = false;
     if (i < a.n_out) {
-      const bool t_has = bit_of(a.t_bm, i);
+      bool t_has = bit_of(a.t_bm, i);
       T tv;
-      if constexpr (Sr<SR>::lor) tv = (T)bit_of(a.t_vb, i);
-      else tv = ((const T *)a.t_val)[i];
+      if constexpr (Sr<SR>::lor) {
+        tv = (T)bit_of(a.t_vb, i);
+        t_has = t_has || tv;
+      } else {
+        tv = ((const T *)a.t_val)[i];
+      }
       T out = tv;
       has = epilogue<SR>(a, i, mask_allowed(a, i), t_has, tv, &out);
       if (has) w[i] = out;
