@@ -193,26 +193,50 @@ __global__ __launch_bounds__(kBlock) void k_mxv_push(MxvArgs a) {
     const int64_t e0 = (int64_t)t * kPushTile - i0;
     int64_t e1 = (int64_t)(t + 1) * kPushTile - i1;
     if (e1 > sumdeg) e1 = sumdeg;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      int lo = 0, hi = ne - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_deg[mid] <= e) lo = mid; else hi = mid - 1;
-      }
-      const int64_t pos = s_rs[lo] + (e - s_deg[lo]);
-      const int i = a.push.ci[pos];
-      if (!mask_allowed(a, i)) continue;
-      const uint64_t b = 1ull << (i & 63);
-      if constexpr (Sr<SR>::lor) {
-        // one OR per edge: t_vb marks a true product, t_bm a false one (the
-        // merge reads presence as either); two guarded atomics on fixed
-        // arrays, not one through a per-lane choice of array
-        if (s_val[lo] != 0 && mat_true(a.push, pos)) {
-          if (!(a.t_vb[i >> 6] & b)) atomicOr((unsigned long long *)&a.t_vb[i >> 6], b);
-        } else {
-          if (!(a.t_bm[i >> 6] & b)) atomicOr((unsigned long long *)&a.t_bm[i >> 6], b);
+    if constexpr (Sr<SR>::lor) {
+      // One OR per run of lanes whose edges hit the same word of the same
+      // bitmap (t_vb: a true product, t_bm: a false one; the merge reads
+      // presence as either): a long row's sorted targets share words.  The
+      // loop is wave-uniform so that the whole wave combines its runs.
+      const int ln = threadIdx.x & 63;
+      for (int64_t eb = e0 + (threadIdx.x & ~63); eb < e1; eb += kBlock) {
+        const int64_t e = eb + ln;
+        int lo = 0, hi = ne - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_deg[mid] <= e) lo = mid; else hi = mid - 1;
         }
-      } else {
+        int i = -1;
+        int64_t pos = 0;
+        if (e < e1) {
+          pos = s_rs[lo] + (e - s_deg[lo]);
+          i = a.push.ci[pos];
+          if (!mask_allowed(a, i)) i = -1;
+        }
+        const bool tru = i >= 0 && s_val[lo] != 0 && mat_true(a.push, pos);
+        const int64_t key = i >= 0 ? (((int64_t)(i >> 6) << 1) | (tru ? 1 : 0)) : -1;
+        int tail;
+        const uint64_t run = run_tail_or(key, i >= 0 ? 1ull << (i & 63) : 0ull, tail);
+        if (key >= 0 && run) {
+          const int64_t wd = key >> 1;
+          if (key & 1) {
+            if (~a.t_vb[wd] & run) atomicOr((unsigned long long *)&a.t_vb[wd], run);
+          } else {
+            if (~a.t_bm[wd] & run) atomicOr((unsigned long long *)&a.t_bm[wd], run);
+          }
+        }
+      }
+    } else {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+        int lo = 0, hi = ne - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_deg[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const int64_t pos = s_rs[lo] + (e - s_deg[lo]);
+        const int i = a.push.ci[pos];
+        if (!mask_allowed(a, i)) continue;
+        const uint64_t b = 1ull << (i & 63);
         const T prod = Sr<SR>::mul(mat_value<T>(a.push, pos), s_val[lo], a.pick_vec);
         atomic_add_sr<SR>(&((T *)a.t_val)[i], prod);
         if (!(a.t_bm[i >> 6] & b)) atomicOr((unsigned long long *)&a.t_bm[i >> 6], b);
