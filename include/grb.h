@@ -111,7 +111,7 @@ typedef enum grb_direction {
 } grb_direction;
 
 /*
- * Switch rule for GRB_DIR_AUTO (Table 5 and Section 4.4.1 of the paper).
+ * Switch rule for GRB_DIR_AUTO (Table 5 and Section 4.3.1 of the paper).
  *   PAPER: estimate |E_f| = (nnz/n) * nnz(u) and assume |E_u| = nnz, so
  *          pull iff denominator * nnz(u) > n.
  *   EXACT: |E_f| = sum of the input's row degrees (computed on the device
@@ -164,7 +164,7 @@ grb_info grb_csr_copy(grb_csr_builder b, int32_t *row_ptr, int32_t *col_idx, flo
 grb_info grb_csr_free(grb_csr_builder *b);
 
 /*
- * Triangle-counting input (Section 7.4 counts triangles as the sum of
+ * Triangle-counting input (Section 7.5 counts triangles as the sum of
  * L L^T .* L, L the strict lower triangle, rows ordered by degree): from a
  * built symmetric CSR `src`, renumbers the vertices by decreasing degree
  * (ties by increasing id) and keeps, in row i, the neighbours numbered
@@ -188,7 +188,7 @@ grb_info grb_csr_lower_by_degree(grb_csr_builder src, grb_csr_builder *out, int3
  *   row_ptr[nrows+1], col_idx[nnz] with columns ascending inside each row,
  *   values[nnz] of vtype (GRB_FP32/GRB_FP64/GRB_INT32) or NULL;
  *   t_row_ptr/t_col_idx/t_values: the CSR of A^T (= CSC of A), or NULL.
- * Paper, Section 4.4.3: CSR serves row access (pull), CSC column access
+ * Paper, Section 4.3.3: CSR serves row access (pull), CSC column access
  * (push).  With GRB_MATRIX_SYMMETRIC the transpose arguments must be NULL
  * and the CSR is used for both.  A product whose chosen direction needs a
  * missing orientation fails with GRB_NOT_IMPLEMENTED (AUTO falls back to
@@ -228,7 +228,7 @@ grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *s
  *   positions >= n must be zero.
  * The dense layout serves both directions: pull tests presence bits, push
  * compacts the bitmap into a sorted index list inside the workspace
- * (Section 4.4.3: the backend, not the user, switches representations).
+ * (Section 4.3.3: the backend, not the user, switches representations).
  */
 grb_info grb_vector_create(grb_vector *v, int64_t n, grb_type type, void *values,
                            uint64_t *bitmap);
@@ -386,7 +386,7 @@ grb_info grb_pagerank_adaptive(void *p, grb_type type, grb_matrix A, double damp
                                void *stream);
 
 /*
- * Masked sparse matrix-matrix product in the dot-product form (Section 6.2.4,
+ * Masked sparse matrix-matrix product in the dot-product form (Section 6.3.4,
  * masked SpGEMM): for every entry (i, j) of the mask M,
  *   c[e] = sum over k of A(i, k) * B(j, k)    (e = the entry's position
  *                                              in M's CSR arrays),
@@ -405,7 +405,7 @@ grb_info grb_mxm_masked(void *c, grb_matrix M, grb_matrix A, grb_matrix B, grb_s
                         const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Triangle count (Section 7.4): *count (host) receives the sum of
+ * Triangle count (Section 7.5): *count (host) receives the sum of
  * (L L^T) .* L over the structure of L, which is the number of triangles
  * when L is the strict lower triangle of a symmetric adjacency under any
  * numbering (grb_csr_lower_by_degree builds the one that bounds the work).

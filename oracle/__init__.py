@@ -18,8 +18,10 @@ computes, written from the paper (GraphBLAST, Yang, Buluc and Owens):
   Sections 5.1 and 7.3).
 * :func:`msbfs` — k independent BFS runs (multi-nodeset traversal).
 * :func:`triangles` — triangle count and per-vertex counts by definition
-  (Section 7.4), each triangle found once from its lowest edge.
-* :mod:`oracle.mxv` — the plain-loop masked semiring mxv / vxm.
+  (Section 7.5), each triangle found once from its lowest edge.
+* :mod:`oracle.mxv` — the plain-loop masked semiring mxv / vxm over
+  dictionaries (small inputs), and :func:`mxv_dense` — the same definition
+  in C over dense arrays (full-size inputs).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU
@@ -84,6 +86,8 @@ def _load():
         lib.oracle_triangles.restype = i64
         lib.oracle_msbfs.argtypes = [p, i64, p, p, i32]
         lib.oracle_msbfs.restype = i32
+        lib.oracle_mxv.argtypes = [p, i32, i32, p, p, p, p, p, p, i32, i32, p, p]
+        lib.oracle_mxv.restype = i32
         _lib = lib
     return _lib
 
@@ -201,3 +205,35 @@ def msbfs(adj: Adjacency, sources, nthreads: int = 1):
     if rc != 0:
         raise ValueError("oracle_msbfs: bad source")
     return lev
+
+
+# semiring and accumulator codes of oracle_mxv (the library's numbering)
+MXV_SEMIRINGS = {"lor_land": 0, "min_plus_fp32": 1, "min_plus_fp64": 2, "plus_times_fp32": 3,
+                 "plus_times_fp64": 4, "min_first_int32": 5, "min_second_int32": 6}
+MXV_ACCUMS = {None: 0, "min": 1, "plus": 2, "lor": 3}
+MXV_COMP, MXV_STRUCT, MXV_REPLACE = 1, 2, 8
+
+
+def mxv_dense(rows: Adjacency, semiring: str, u_val, u_has, *, vec_first=False, w_val=None,
+              w_has=None, mask_val=None, mask_has=None, flags=0, accum=None):
+    """w<mask> = accum(w, A' u) by its definition over dense arrays (C loop,
+    fp64).  `rows` holds the rows of A' (pass the transpose for a product
+    over A^T); vec_first gives the vxm operand order.  Vectors are value
+    arrays plus boolean presence arrays; mask_has None = no mask.  Returns
+    (values float64[n], present bool[n])."""
+    n = rows.n
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    u8 = lambda a: np.ascontiguousarray(a, dtype=np.uint8)
+    uv, uh = f64(u_val), u8(u_has)
+    wv = f64(np.zeros(n) if w_val is None else w_val)
+    wh = u8(np.zeros(n) if w_has is None else w_has)
+    mv = None if mask_val is None else f64(mask_val)
+    mh = None if mask_has is None else u8(mask_has)
+    out_v = np.empty(n, dtype=np.float64)
+    out_h = np.empty(n, dtype=np.uint8)
+    rc = _load().oracle_mxv(rows._h, MXV_SEMIRINGS[semiring], 1 if vec_first else 0, _ptr(uv),
+                            _ptr(uh), _ptr(wv), _ptr(wh), _ptr(mv), _ptr(mh), int(flags),
+                            MXV_ACCUMS[accum], _ptr(out_v), _ptr(out_h))
+    if rc != 0:
+        raise ValueError("oracle_mxv: bad input")
+    return out_v, out_h.astype(bool)

@@ -1,7 +1,7 @@
 """ORACLE — TEST INFRASTRUCTURE ONLY.
 
 Masked sparse matrix-matrix product in the dot-product form of the paper's
-masked SpGEMM (Section 6.2.4) and the triangle-counting operand of Section
+masked SpGEMM (Section 6.3.4) and the triangle-counting operand of Section
 7.4, written from their definitions with scipy / numpy as plain steps:
 
 * :func:`mxm_masked` — for every entry (i, j) of the mask M, the sum over

@@ -20,6 +20,8 @@
  *                      frozen (PageRankDelta)
  *   oracle_msbfs       k independent oracle_bfs runs (optionally on threads)
  *   oracle_triangles   triangle count (and per-vertex counts) by definition
+ *   oracle_mxv         the masked semiring product over dense arrays, by its
+ *                      definition, one output index at a time
  *
  * parity pins: see tests/test_oracle_*.py (brute force, closed forms,
  * invariants, library special cases).
@@ -453,7 +455,7 @@ static int has_entry(const int32_t *nbr, int64_t lo, int64_t hi, int32_t x) {
 }
 
 /*
- * Triangle count of an undirected graph (Section 7.4: the number of vertex
+ * Triangle count of an undirected graph (Section 7.5: the number of vertex
  * triples that are pairwise adjacent), by its definition: each triangle
  * u < v < w is found exactly once, from its edge (u, v), as a common
  * neighbour w > v of u and v (the shorter of the two sorted tails above v
@@ -487,4 +489,104 @@ int64_t oracle_triangles(const oracle_adj *a, int64_t *per_vertex) {
     }
   }
   return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* masked semiring matrix-vector product                               */
+/* ------------------------------------------------------------------ */
+
+/* semiring codes, numbered as the library's enum (Table 4 of the paper) */
+enum { OR_LOR_LAND = 0, OR_MIN_PLUS_32 = 1, OR_MIN_PLUS_64 = 2, OR_PLUS_TIMES_32 = 3,
+       OR_PLUS_TIMES_64 = 4, OR_MIN_FIRST = 5, OR_MIN_SECOND = 6 };
+/* accumulators */
+enum { OR_NOACCUM = 0, OR_ACC_MIN = 1, OR_ACC_PLUS = 2, OR_ACC_LOR = 3 };
+/* descriptor bits */
+enum { OR_COMP = 1, OR_STRUCT = 2, OR_REPLACE = 8 };
+
+static double sr_add(int sr, double x, double y) {
+  switch (sr) {
+    case OR_LOR_LAND: return (x != 0.0 || y != 0.0) ? 1.0 : 0.0;
+    case OR_PLUS_TIMES_32:
+    case OR_PLUS_TIMES_64: return x + y;
+    default: return x < y ? x : y; /* the min semirings */
+  }
+}
+
+/* the multiply with the operands in the product's order: (a, b) is
+ * (A(i,j), u(j)) for mxv and (u(i), A(i,j)) for vxm */
+static double sr_mul(int sr, double a, double b) {
+  switch (sr) {
+    case OR_LOR_LAND: return (a != 0.0 && b != 0.0) ? 1.0 : 0.0;
+    case OR_MIN_PLUS_32:
+    case OR_MIN_PLUS_64: return a + b;
+    case OR_PLUS_TIMES_32:
+    case OR_PLUS_TIMES_64: return a * b;
+    case OR_MIN_FIRST: return a;
+    default: return b; /* OR_MIN_SECOND */
+  }
+}
+
+/*
+ * w<mask> = accum(w, A' u) over a semiring (Section 3.3 and the caption of
+ * the mxv figure; masking per Section 3.2.1; accum and REPLACE per the
+ * GraphBLAS C API), written out for one output index at a time.  `a` holds
+ * the rows of A' (the caller passes the transposed adjacency when the
+ * product runs over the transpose); a row with no stored weights counts
+ * every entry as 1.  vec_first selects the vxm operand order u(j) (x)
+ * A'(i,j); otherwise A'(i,j) (x) u(j).  Dense vectors: value arrays in
+ * double plus presence bytes.  mask_has NULL means no mask (mask_val NULL
+ * with a mask present means every present entry is non-zero).  Every
+ * quantity is computed in double.  Returns 0, or -1 on bad input.
+ */
+int32_t oracle_mxv(const oracle_adj *a, int32_t sr, int32_t vec_first, const double *u_val,
+                   const uint8_t *u_has, const double *w_val, const uint8_t *w_has,
+                   const double *mask_val, const uint8_t *mask_has, int32_t flags,
+                   int32_t accum, double *out_val, uint8_t *out_has) {
+  if (!a || sr < OR_LOR_LAND || sr > OR_MIN_SECOND || !u_val || !u_has || !w_val || !w_has ||
+      !out_val || !out_has)
+    return -1;
+  for (int64_t i = 0; i < a->n; ++i) {
+    /* t(i): the semiring sum over the stored j of row i with u(j) present */
+    int t_has = 0;
+    double t = 0.0;
+    for (int64_t e = a->off[i]; e < a->off[i + 1]; ++e) {
+      const int32_t j = a->nbr[e];
+      if (!u_has[j]) continue;
+      const double aij = a->w ? a->w[e] : 1.0;
+      const double prod = vec_first ? sr_mul(sr, u_val[j], aij) : sr_mul(sr, aij, u_val[j]);
+      t = t_has ? sr_add(sr, t, prod) : prod;
+      t_has = 1;
+    }
+    /* z(i) */
+    int z_has = t_has;
+    double z = t;
+    if (accum != OR_NOACCUM && w_has[i]) {
+      if (t_has) {
+        if (accum == OR_ACC_MIN) z = w_val[i] < t ? w_val[i] : t;
+        else if (accum == OR_ACC_PLUS) z = w_val[i] + t;
+        else z = (w_val[i] != 0.0 || t != 0.0) ? 1.0 : 0.0;
+      } else {
+        z = w_val[i];
+      }
+      z_has = 1;
+    }
+    /* mask and REPLACE */
+    int allowed = 1;
+    if (mask_has) {
+      int m = mask_has[i] != 0;
+      if (m && !(flags & OR_STRUCT) && mask_val) m = mask_val[i] != 0.0;
+      allowed = (flags & OR_COMP) ? !m : m;
+    }
+    if (allowed) {
+      out_has[i] = (uint8_t)z_has;
+      out_val[i] = z_has ? z : 0.0;
+    } else if (!(flags & OR_REPLACE) && w_has[i]) {
+      out_has[i] = 1;
+      out_val[i] = w_val[i];
+    } else {
+      out_has[i] = 0;
+      out_val[i] = 0.0;
+    }
+  }
+  return 0;
 }

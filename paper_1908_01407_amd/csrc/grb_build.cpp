@@ -162,7 +162,7 @@ extern "C" grb_info grb_csr_free(grb_csr_builder *b) {
   return GRB_SUCCESS;
 }
 
-// Degree-ordered strict lower triangle for triangle counting (Section 7.4:
+// Degree-ordered strict lower triangle for triangle counting (Section 7.5:
 // the count is the reduction of L L^T .* L).  Vertices are renumbered by
 // decreasing degree (ties by increasing id), so row i of L holds the
 // neighbours of i that come earlier in that order, i.e. have at least its

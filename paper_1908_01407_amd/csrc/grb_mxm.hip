@@ -1,6 +1,6 @@
 // Masked sparse matrix-matrix product in the dot-product form,
 // C = (A B^T) .* M, and triangle counting as its reduction to a scalar
-// (Sections 6.2.4 (masked SpGEMM) and 7.4: with L the strict lower triangle
+// (Sections 6.3.4 (masked SpGEMM) and 7.5: with L the strict lower triangle
 // of a symmetric adjacency, the triangle count is the sum of L L^T .* L).
 //
 // Only the entries the mask holds are computed: C(i, j) for j in M(i, :) is

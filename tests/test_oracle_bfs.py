@@ -152,3 +152,39 @@ def test_adjacency_cleaning():
     t = d.transpose()
     off, nbr, _ = t.arrays(weights=False)
     assert off.tolist() == [0, 1, 2, 2, 2] and nbr.tolist() == [1, 0]
+
+
+@pytest.mark.parametrize("nthreads", [1, 8])
+def test_msbfs_equals_stacked_single_source_runs(nthreads):
+    """oracle.msbfs (k runs on a thread pool, query-major output) equals k
+    separate oracle.bfs runs stacked row by row: random, repeated and
+    isolated sources, k not a multiple of the thread count, a directed and
+    an undirected graph.  A wrong row offset, a lost or doubled query, or a
+    race on the shared work counter changes some row."""
+    for g in (graphgen.rmat(11), graphgen.rmat(10, symmetric=False)):
+        adj = oracle.Adjacency.from_raw(g)
+        deg = np.diff(adj.arrays(weights=False)[0])
+        rng = np.random.default_rng(7 + nthreads)
+        k = 77
+        src = rng.integers(0, g.n, k).astype(np.int32)
+        src[5] = src[4]                              # repeated source
+        src[9] = int(np.flatnonzero(deg == 0)[0])    # isolated source
+        src[10] = 0                                  # the hub
+        got = oracle.msbfs(adj, src, nthreads=nthreads)
+        assert got.shape == (k, g.n)
+        for q, s in enumerate(src):
+            ref, _, _ = oracle.bfs(adj, int(s), parents=False)
+            assert np.array_equal(got[q], ref), (q, int(s))
+        # an independent check of a few rows: scipy hop counts
+        off, nbr, _ = adj.arrays(weights=False)
+        S = sp.csr_matrix((np.ones(nbr.size), nbr, off), shape=(g.n, g.n))
+        hops = csg.shortest_path(S, unweighted=True, indices=src[:6])
+        for q in range(6):
+            want = np.where(np.isinf(hops[q]), -1, hops[q]).astype(np.int32)
+            assert np.array_equal(got[q], want), q
+
+
+def test_msbfs_rejects_bad_source():
+    adj = oracle.Adjacency(4, np.array([0, 1]), np.array([1, 2]))
+    with pytest.raises(ValueError):
+        oracle.msbfs(adj, np.array([0, 4], np.int32))

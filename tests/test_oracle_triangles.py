@@ -1,5 +1,5 @@
-"""Pins for the triangle-counting and masked-SpGEMM oracles (Sections 6.2.4
-and 7.4).
+"""Pins for the triangle-counting and masked-SpGEMM oracles (Sections 6.3.4
+and 7.5).
 
 The triangle count is checked against trace(A^3) / 6 and the per-vertex
 counts against diag(A^3) / 2 (dense matrix powers), and against closed
