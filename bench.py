@@ -464,6 +464,12 @@ def bench_msbfs(grb, graphgen, torch, args):
             ms_seq = timed(lambda: [grb.bfs(A, int(s), parents=False, desc=dseq, ws=ws1)
                                     for s in seq_src], 1, torch)
             per_src_seq = ms_seq / len(seq_src)
+            # the timed batch's first 64 queries equal the sequential runs
+            for q, s in enumerate(seq_src):
+                single, _ = grb.bfs(A, int(s), parents=False, desc=dseq, ws=ws1)
+                if not torch.equal(single, lev[:, q]):
+                    raise RuntimeError(f"batched BFS rmat{scale} k={k}: query {q} differs "
+                                       "from its single-source BFS")
             res[f"rmat{scale}_k{k}"] = {
                 "ms": round(ms, 3), "levels": st["iterations"],
                 "sources_per_s": round(k / ms * 1e3, 1),

@@ -222,27 +222,46 @@ grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *s
 /* ------------------------------------------------------------------ */
 
 /*
- * Wraps caller-owned device storage of a length-n vector:
- *   values[n] elements of `type` (the value of index i lives at values[i]),
- *   bitmap[(n+63)/64] presence words, bit (i % 64) of word i / 64; bits at
- *   positions >= n must be zero.
- * The dense layout serves both directions: pull tests presence bits, push
- * compacts the bitmap into a sorted index list inside the workspace
- * (Section 4.3.3: the backend, not the user, switches representations).
+ * Wraps caller-owned device storage of a length-n vector (the Vector
+ * object of Section 3.1.2; the dense and sparse storage formats of Section
+ * 4.3.3, between which the backend, not the user, converts):
+ *   values[n]  elements of `type`, the value of index i at values[i]; or
+ *              NULL: every present entry has the value 1 (true).  Such a
+ *              vector can be an input or a mask, not a product's output;
+ *   bitmap[(n+63)/64]  presence words, bit (i % 64) of word i / 64, bits at
+ *              positions >= n zero; or NULL;
+ *   indices[n] + count  the sparse form: count (one DEVICE int32) present
+ *              indices, sorted ascending without repeats, in indices[0..count);
+ *              both NULL or both given.
+ * At least one of bitmap and indices must be given (n > 0), else
+ * GRB_NULL_POINTER.  A vector with both keeps them equal: the library
+ * writes both whenever it writes the vector, and a caller that writes one
+ * must write the other.  In a product the list form of the input feeds
+ * push directly (no compaction), the bitmap feeds pull (built from the list
+ * in the workspace when the vector has no bitmap); a mask or output given
+ * only as a list is converted through the workspace, and an output's list
+ * is rebuilt from its new bitmap after the product.  A list that is not
+ * sorted or has repeats gives an undefined result (memory accesses stay
+ * inside the arrays).  Errors: GRB_NULL_POINTER, GRB_INVALID_VALUE (n
+ * negative or >= 2^31 - 1, bad type), GRB_OUT_OF_MEMORY.
  */
 grb_info grb_vector_create(grb_vector *v, int64_t n, grb_type type, void *values,
-                           uint64_t *bitmap);
+                           uint64_t *bitmap, int32_t *indices, int32_t *count);
 grb_info grb_vector_free(grb_vector *v);
 grb_info grb_vector_size(grb_vector v, int64_t *n);
-/* Removes every entry (presence bits cleared; values untouched). */
+/* Removes every entry (presence bits cleared, count set to 0; values untouched). */
 grb_info grb_vector_clear(grb_vector v, void *stream);
-/* Every index present with the value *scalar (host pointer to one element). */
+/* Every index present with the value *scalar (host pointer to one element;
+ * may be NULL for a vector without values); the list becomes 0..n-1. */
 grb_info grb_vector_fill(grb_vector v, const void *scalar, void *stream);
 /*
  * Clears v, then sets v(idx[k]) = vals[k] for k < count, from DEVICE arrays
  * idx (int32) and vals (`type`, or NULL: every value 1).  Indices must be
  * in [0, n) (out-of-range entries are skipped); with duplicate indices one
- * of their values is kept.
+ * of their values is kept.  A vector keeping a list gets it rebuilt from the
+ * bitmap (one workgroup; a setup-time call).  Needs the bitmap form (a
+ * list-only vector is written by its owner: GRB_NOT_IMPLEMENTED); vals with
+ * a vector without values: GRB_INVALID_VALUE.
  */
 grb_info grb_vector_build(grb_vector v, const int32_t *idx, const void *vals,
                           int64_t count, void *stream);
@@ -250,6 +269,18 @@ grb_info grb_vector_build(grb_vector v, const int32_t *idx, const void *vals,
  * at least 64 bytes. */
 grb_info grb_vector_nvals(grb_vector v, int64_t *nvals, void *ws, size_t ws_bytes,
                           void *stream);
+/*
+ * Copies the present entries to HOST memory (GraphBLAS extractTuples):
+ * indices[k] (int32, ascending) and values[k] (`type`) for k < *nvals;
+ * either output may be NULL.  Device-side work (compaction of the bitmap
+ * unless the vector keeps a list, gather of the values) uses a workspace of
+ * grb_workspace_size(GRB_OP_EXTRACT, NULL, n) bytes.  Synchronises
+ * `stream`.  *nvals is always set; with *nvals > capacity nothing is
+ * copied and GRB_INSUFFICIENT_SPACE is returned.  Errors also
+ * GRB_NULL_POINTER (nvals), GRB_INVALID_VALUE (capacity < 0), GRB_PANIC.
+ */
+grb_info grb_vector_extract(grb_vector v, int32_t *indices, void *values, int64_t capacity,
+                            int64_t *nvals, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Workspace                                                           */
@@ -262,7 +293,8 @@ typedef enum grb_op {
   GRB_OP_PAGERANK = 3, /* k = 1 for fp32, 2 for fp64 */
   GRB_OP_MSBFS = 4,    /* k = number of sources (batched BFS) */
   GRB_OP_NVALS = 5,
-  GRB_OP_MXM = 6       /* grb_mxm_masked and grb_tricount (A unused) */
+  GRB_OP_MXM = 6,      /* grb_mxm_masked and grb_tricount (A unused) */
+  GRB_OP_EXTRACT = 7   /* grb_vector_extract: k = vector length (A unused) */
 } grb_op;
 
 /* Bytes of device workspace the operation needs on matrix A.  Workspace
@@ -433,8 +465,9 @@ grb_info grb_tricount(int64_t *count, grb_matrix L, const grb_descriptor *d, voi
  *          autotuner of the Python package writes tuned values).
  * Needs the CSR of A^T (or a symmetric matrix) for pull.  Synchronises
  * once per batch of levels.  Errors as grb_bfs, plus GRB_INVALID_VALUE for
- * k < 1 or a bad tile.  Source ids are not range-checked on the host (they
- * are device data): ids outside [0, n) are undefined behaviour.
+ * k < 1 or a bad tile.  Source ids are device data: one outside [0, n) is
+ * skipped on the device (nothing is written for it), the other queries run
+ * to the end, and the call returns GRB_INVALID_INDEX.
  */
 typedef struct grb_msbfs_tile {
   int32_t words_per_pass; /* kt, 0 = all words of the batch; at most 8 words are
@@ -446,6 +479,54 @@ typedef struct grb_msbfs_tile {
 grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_t k,
                    const grb_msbfs_tile *tile, const grb_descriptor *d, void *ws,
                    size_t ws_bytes, void *stream);
+
+/*
+ * Continuous batching of BFS queries (multi-nodeset traversal as one masked
+ * matrix-matrix product, Table 6 and Section 3.3; a serving loop answers
+ * the per-level launch and synchronisation cost the paper discusses in
+ * Section 2.1.4): a session keeps k query lanes over one graph; queries
+ * join free lanes and retire at level boundaries while the other lanes keep
+ * running, so the batch never has to drain before new queries start.
+ *   levels[n * k]  vertex-major level block (as grb_msbfs), caller-owned;
+ *                  in a session, lane q's entry at v is valid only where the
+ *                  lane's query has visited v; read results with
+ *                  grb_msbfs_session_extract;
+ *   ws             GRB_OP_MSBFS workspace for k (held for the session's life).
+ * A lane's levels count from its own start: the source is 0.  Every call of
+ * a session must use one stream.  create: all lanes free (tile, descriptor
+ * and errors as grb_msbfs).
+ */
+typedef struct grb_msbfs_session_s *grb_msbfs_session;
+grb_info grb_msbfs_session_create(grb_msbfs_session *ss, grb_matrix A, int32_t k,
+                                  int32_t *levels, const grb_msbfs_tile *tile,
+                                  const grb_descriptor *d, void *ws, size_t ws_bytes,
+                                  void *stream);
+/*
+ * At the current level boundary, lane lanes[i] starts a BFS from
+ * sources[i], for i < count (HOST arrays).  Errors (nothing is enqueued):
+ * GRB_INVALID_INDEX (a lane outside [0, k) or a source outside [0, n)),
+ * GRB_INVALID_VALUE (a lane still running or named twice, count outside
+ * [0, k]).  Synchronises `stream`.
+ */
+grb_info grb_msbfs_session_join(grb_msbfs_session ss, const int32_t *lanes,
+                                const int32_t *sources, int32_t count, void *stream);
+/*
+ * Runs up to max_levels levels (none when no lane is running), then
+ * synchronises and reports in done[ceil(k / 64)] (HOST words, bit q % 64 of
+ * word q / 64) the lanes whose query ended (its frontier is empty); they are
+ * free again and keep their results until they join again.  *levels_run
+ * (may be NULL) receives the number of levels run.
+ */
+grb_info grb_msbfs_session_step(grb_msbfs_session ss, int32_t max_levels, uint64_t *done,
+                                int32_t *levels_run, void *stream);
+/*
+ * out[i * n + v] (DEVICE, lane-major) = level of the query of lane lanes[i]
+ * (HOST array) at v, -1 where it did not reach v.  Synchronises `stream`.
+ * Errors: GRB_INVALID_INDEX for a lane outside [0, k).
+ */
+grb_info grb_msbfs_session_extract(grb_msbfs_session ss, const int32_t *lanes, int32_t count,
+                                   int32_t *out, void *stream);
+grb_info grb_msbfs_session_free(grb_msbfs_session *ss);
 
 /* ------------------------------------------------------------------ */
 /* Statistics and errors                                               */

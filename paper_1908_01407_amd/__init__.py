@@ -49,7 +49,7 @@ GRB_MASK_COMP, GRB_MASK_STRUCT, GRB_TRAN_A, GRB_REPLACE, GRB_PROFILE = 0x1, 0x2,
 DIR_AUTO, DIR_PUSH, DIR_PULL = 0, 1, 2
 SWITCH_PAPER, SWITCH_EXACT = 0, 1
 GRB_MATRIX_SYMMETRIC = 0x1
-OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS, OP_MXM = 0, 1, 2, 3, 4, 5, 6
+OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS, OP_MXM, OP_EXTRACT = range(8)
 STATS_MAX = 256
 
 
@@ -107,13 +107,14 @@ _SIGS = {
     "grb_matrix_nvals": ([_p, ctypes.POINTER(_i64)], _i32),
     "grb_matrix_meta_size": ([_p, ctypes.POINTER(_sz)], _i32),
     "grb_matrix_prepare": ([_p, _p, _sz, _p], _i32),
-    "grb_vector_create": ([_PP, _i64, _i32, _p, _p], _i32),
+    "grb_vector_create": ([_PP, _i64, _i32, _p, _p, _p, _p], _i32),
     "grb_vector_free": ([_PP], _i32),
     "grb_vector_size": ([_p, ctypes.POINTER(_i64)], _i32),
     "grb_vector_clear": ([_p, _p], _i32),
     "grb_vector_fill": ([_p, _p, _p], _i32),
     "grb_vector_build": ([_p, _p, _p, _i64, _p], _i32),
     "grb_vector_nvals": ([_p, ctypes.POINTER(_i64), _p, _sz, _p], _i32),
+    "grb_vector_extract": ([_p, _p, _p, _i64, ctypes.POINTER(_i64), _p, _sz, _p], _i32),
     "grb_workspace_size": ([_i32, _p, _i64, ctypes.POINTER(_sz)], _i32),
     "grb_mxv": ([_p, _p, _i32, _i32, _p, _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_vxm": ([_p, _p, _i32, _i32, _p, _p, ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
@@ -123,6 +124,12 @@ _SIGS = {
                        _i32),
     "grb_msbfs": ([_p, _p, _p, _i32, ctypes.POINTER(MsbfsTile), ctypes.POINTER(Descriptor), _p,
                    _sz, _p], _i32),
+    "grb_msbfs_session_create": ([_PP, _p, _i32, _p, ctypes.POINTER(MsbfsTile),
+                                  ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
+    "grb_msbfs_session_join": ([_p, _p, _p, _i32, _p], _i32),
+    "grb_msbfs_session_step": ([_p, _i32, _p, ctypes.POINTER(_i32), _p], _i32),
+    "grb_msbfs_session_extract": ([_p, _p, _i32, _p, _p], _i32),
+    "grb_msbfs_session_free": ([_PP], _i32),
     "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
                       ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
@@ -336,20 +343,31 @@ def _type_code(dtype):
 
 
 class Vector:
-    """values[n] + presence bitmap[(n+63)/64] on the device, as a grb_vector."""
+    """A grb_vector over device tensors: `values` [n] (or None: every entry is
+    1), the presence `bitmap` [(n+63)/64] (dense form, or None), and the
+    sparse form's sorted `indices` [n] with their device `count` [1] (or
+    None).  At least one of the two forms."""
 
-    def __init__(self, n: int, dtype=None, device="cuda"):
+    def __init__(self, n: int, dtype=None, device="cuda", *, dense: bool = True,
+                 sparse: bool = False, values: bool = True):
         torch = _torch()
+        if not (dense or sparse):
+            raise ValueError("Vector: needs the dense (bitmap) or the sparse (list) form")
         dtype = dtype if dtype is not None else torch.float32
         if dtype == torch.bool:
             dtype = torch.uint8
         self.n = int(n)
         self.dtype = dtype
-        self.values = torch.zeros(max(self.n, 1), dtype=dtype, device=device)
-        self.bitmap = torch.zeros(max((self.n + 63) // 64, 1), dtype=torch.int64, device=device)
+        self.values = torch.zeros(max(self.n, 1), dtype=dtype, device=device) if values else None
+        self.bitmap = (torch.zeros(max((self.n + 63) // 64, 1), dtype=torch.int64, device=device)
+                       if dense else None)
+        self.indices = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device) if sparse \
+            else None
+        self.count = torch.zeros(1, dtype=torch.int32, device=device) if sparse else None
         h = ctypes.c_void_p()
-        check(_lib.grb_vector_create(ctypes.byref(h), self.n, _type_code(dtype),
-                                     _ptr(self.values), _ptr(self.bitmap)), "grb_vector_create")
+        check(_lib.grb_vector_create(ctypes.byref(h), self.n, _type_code(dtype), _ptr(self.values),
+                                     _ptr(self.bitmap), _ptr(self.indices), _ptr(self.count)),
+              "grb_vector_create")
         self.handle = h
 
     def __del__(self):
@@ -360,26 +378,111 @@ class Vector:
         except (AttributeError, TypeError):
             pass  # module globals already torn down at interpreter exit
 
+    @property
+    def device(self):
+        for t in (self.values, self.bitmap, self.indices):
+            if t is not None:
+                return t.device
+        return None
+
     def set(self, entries: dict, stream=None):
-        """Clears, then sets the given {index: value} entries (via grb_vector_build)."""
+        """Clears, then sets the given {index: value} entries (via
+        grb_vector_build; a vector without values takes the indices only)."""
         torch = _torch()
-        idx = torch.tensor(sorted(entries), dtype=torch.int32, device=self.values.device)
-        vals = torch.tensor([entries[i] for i in sorted(entries)], dtype=self.dtype,
-                            device=self.values.device)
+        keys = sorted(entries)
+        idx = torch.tensor(keys, dtype=torch.int32, device=self.device)
+        vals = None
+        if self.values is not None:
+            vals = torch.tensor([entries[i] for i in keys], dtype=self.dtype, device=self.device)
         check(_lib.grb_vector_build(self.handle, _ptr(idx) if idx.numel() else None,
-                                    _ptr(vals) if vals.numel() else None, idx.numel(),
-                                    _stream(stream)), "grb_vector_build")
+                                    _ptr(vals) if vals is not None and vals.numel() else None,
+                                    idx.numel(), _stream(stream)), "grb_vector_build")
         torch.cuda.current_stream().synchronize()
 
+    def set_list(self, entries: dict):
+        """Writes the sparse form directly, as its owner (sorted indices,
+        count and values; the bitmap too when the vector has one)."""
+        torch = _torch()
+        keys = sorted(entries)
+        if self.indices is None:
+            raise ValueError("set_list: the vector has no list")
+        if keys:
+            self.indices[: len(keys)] = torch.tensor(keys, dtype=torch.int32, device=self.device)
+            if self.values is not None:
+                self.values.zero_()
+                self.values[torch.tensor(keys, dtype=torch.int64, device=self.device)] = \
+                    torch.tensor([entries[i] for i in keys], dtype=self.dtype, device=self.device)
+        self.count.fill_(len(keys))
+        if self.bitmap is not None:
+            bits = np.zeros(self.bitmap.numel() * 64, dtype=np.uint8)
+            bits[keys] = 1
+            words = np.packbits(bits, bitorder="little").view(np.int64)
+            self.bitmap.copy_(torch.from_numpy(words))
+        torch.cuda.current_stream().synchronize()
+
+    def set_any(self, entries: dict):
+        """set() for a vector with a bitmap, set_list() for a list-only one."""
+        if self.bitmap is not None:
+            self.set(entries)
+        else:
+            self.set_list(entries)
+
+    def fill(self, value=None, stream=None):
+        """Every index present with `value` (grb_vector_fill)."""
+        torch = _torch()
+        buf = None
+        if self.values is not None:
+            buf = np.array([value], dtype=torch.empty(0, dtype=self.dtype).numpy().dtype)
+        check(_lib.grb_vector_fill(self.handle, buf.ctypes.data if buf is not None else None,
+                                   _stream(stream)), "grb_vector_fill")
+        torch.cuda.current_stream().synchronize()
+
+    def clear(self, stream=None):
+        check(_lib.grb_vector_clear(self.handle, _stream(stream)), "grb_vector_clear")
+        _torch().cuda.current_stream().synchronize()
+
+    def extract_code(self, capacity=None, ws=None, stream=None):
+        """(grb_info, nvals) of grb_vector_extract into host buffers of
+        `capacity` entries (default n); the tuples are kept in
+        self._extracted when the call succeeds."""
+        torch = _torch()
+        cap = self.n if capacity is None else int(capacity)
+        idx = np.zeros(max(cap, 1), dtype=np.int32)
+        vals = np.zeros(max(cap, 1), dtype=torch.empty(0, dtype=self.dtype).numpy().dtype)
+        ws = ws if ws is not None else workspace(OP_EXTRACT, None, self.n, device=self.device)
+        nv = ctypes.c_int64()
+        code = _lib.grb_vector_extract(self.handle, idx.ctypes.data, vals.ctypes.data, cap,
+                                       ctypes.byref(nv), _ptr(ws), ws.numel(), _stream(stream))
+        if code == GRB_SUCCESS:
+            self._extracted = (idx[: nv.value].copy(), vals[: nv.value].copy())
+        return code, nv.value
+
+    def extract(self, ws=None, stream=None):
+        """(indices int32[k], values[k]) of the present entries, ascending,
+        via grb_vector_extract."""
+        code, _ = self.extract_code(None, ws, stream)
+        check(code, "grb_vector_extract")
+        return self._extracted
+
     def to_dict(self) -> dict:
-        """Present entries as {index: value} (device -> host copy)."""
-        bm = self.bitmap.cpu().numpy().view(np.uint64)
-        vals = self.values.cpu().numpy()
-        bits = np.unpackbits(bm.view(np.uint8), bitorder="little")[: self.n].astype(bool)
+        """Present entries as {index: value}, read straight from the device
+        arrays (the bitmap, else the list)."""
+        torch = _torch()
+        if self.bitmap is not None:
+            bm = self.bitmap.cpu().numpy().view(np.uint64)
+            bits = np.unpackbits(bm.view(np.uint8), bitorder="little")[: self.n].astype(bool)
+            present = np.flatnonzero(bits)
+        else:
+            c = int(self.count.cpu()[0])
+            present = self.indices[:c].cpu().numpy()
+        vals = self.values.cpu().numpy() if self.values is not None else None
         out = {}
-        for i in np.flatnonzero(bits):
+        for i in present:
+            if vals is None:
+                out[int(i)] = True if self.dtype == torch.uint8 else 1
+                continue
             v = vals[i]
-            out[int(i)] = bool(v) if self.dtype == _torch().uint8 else v.item()
+            out[int(i)] = bool(v) if self.dtype == torch.uint8 else v.item()
         return out
 
 
@@ -439,6 +542,67 @@ def msbfs(A: Matrix, sources, *, words_per_pass: int = 0, grid: int = 0,
                          ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
                          _stream(stream)), "grb_msbfs")
     return levels[: A.nrows]
+
+
+class MsbfsSession:
+    """Continuous batching of BFS queries on one graph (grb_msbfs_session_*):
+    k lanes; queries join free lanes and retire at level boundaries while
+    the others keep running.  All calls go to one stream."""
+
+    def __init__(self, A: Matrix, k: int, *, words_per_pass: int = 0, grid: int = 0,
+                 desc: Descriptor | None = None, ws=None, levels=None, stream=None):
+        torch = _torch()
+        self.A, self.k, self.n = A, int(k), A.nrows
+        self.W = (self.k + 63) // 64
+        self.stream = stream
+        self.levels = levels if levels is not None else torch.empty(
+            (max(A.nrows, 1), self.k), dtype=torch.int32, device=A.device)
+        self.ws = ws if ws is not None else workspace(OP_MSBFS, A, self.k)
+        tile = MsbfsTile(words_per_pass, grid)
+        h = ctypes.c_void_p()
+        check(_lib.grb_msbfs_session_create(
+            ctypes.byref(h), A.handle, self.k, _ptr(self.levels), ctypes.byref(tile),
+            ctypes.byref(desc) if desc is not None else None, _ptr(self.ws), self.ws.numel(),
+            _stream(stream)), "grb_msbfs_session_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        try:
+            if h is not None and h.value:
+                _lib.grb_msbfs_session_free(ctypes.byref(h))
+        except (AttributeError, TypeError):
+            pass
+
+    def join(self, lanes, sources):
+        """Starts sources[i] in lane lanes[i] at the current level boundary."""
+        ln = np.ascontiguousarray(lanes, dtype=np.int32)
+        sr = np.ascontiguousarray(sources, dtype=np.int32)
+        if ln.shape != sr.shape:
+            raise ValueError("join: lanes and sources differ in length")
+        check(_lib.grb_msbfs_session_join(self.handle, ln.ctypes.data, sr.ctypes.data, ln.size,
+                                          _stream(self.stream)), "grb_msbfs_session_join")
+
+    def step(self, max_levels: int):
+        """Runs up to max_levels levels; returns (lanes that ended, levels run)."""
+        done = np.zeros(self.W, dtype=np.uint64)
+        ran = ctypes.c_int32()
+        check(_lib.grb_msbfs_session_step(self.handle, int(max_levels), done.ctypes.data,
+                                          ctypes.byref(ran), _stream(self.stream)),
+              "grb_msbfs_session_step")
+        bits = np.unpackbits(done.view(np.uint8), bitorder="little")[: self.k]
+        return [int(q) for q in np.flatnonzero(bits)], ran.value
+
+    def extract(self, lanes, out=None):
+        """int32 [len(lanes), n] levels of the given lanes (-1 unreached)."""
+        torch = _torch()
+        ln = np.ascontiguousarray(lanes, dtype=np.int32)
+        if out is None:
+            out = torch.empty((max(ln.size, 1), max(self.n, 1)), dtype=torch.int32,
+                              device=self.levels.device)
+        check(_lib.grb_msbfs_session_extract(self.handle, ln.ctypes.data, ln.size, _ptr(out),
+                                             _stream(self.stream)), "grb_msbfs_session_extract")
+        return out[: ln.size, : self.n]
 
 
 def pagerank(A: Matrix, *, dtype=None, damping: float = 0.85, max_iter: int = 50,

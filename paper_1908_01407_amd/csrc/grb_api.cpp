@@ -108,6 +108,11 @@ struct MsWs {
   int64_t *stats;
   unsigned long long *cnt;
   uint64_t *V, *F[3], *act[3];
+  // sessions: start level per query, three "has a frontier bit" arrays of W
+  // words, the joining queries' bits per word, lane / source staging
+  int32_t *start, *lanes, *sources;
+  unsigned long long *alive;
+  uint64_t *clr;
   size_t bytes;
 };
 
@@ -121,6 +126,11 @@ MsWs ms_layout(void *ws, int64_t n, int64_t k) {
   t.V = c.take<uint64_t>((size_t)nb);
   for (int i = 0; i < 3; ++i) t.F[i] = c.take<uint64_t>((size_t)nb);
   for (int i = 0; i < 3; ++i) t.act[i] = c.take<uint64_t>((size_t)std::max<int64_t>(nw, 1));
+  t.start = c.take<int32_t>((size_t)std::max<int64_t>(k, 1));
+  t.lanes = c.take<int32_t>((size_t)std::max<int64_t>(k, 1));
+  t.sources = c.take<int32_t>((size_t)std::max<int64_t>(k, 1));
+  t.alive = c.take<unsigned long long>((size_t)3 * std::max<int64_t>(W, 1));
+  t.clr = c.take<uint64_t>((size_t)std::max<int64_t>(W, 1));
   t.bytes = c.off;
   return t;
 }
@@ -153,35 +163,68 @@ PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
 
 struct MxvWs {
   Ctrl *ctrl;
-  uint64_t *status, *t_bm, *t_vb;
+  int64_t *part;
+  uint64_t *status, *status_out, *status_list, *t_bm, *t_vb;
   int32_t *list, *degpre, *rowstart, *tiles;
+  int64_t tiles_cap;
   void *t_val, *hp_val;
   uint8_t *hp_has;
-  int nblk;
+  uint64_t *ubm, *mbm, *wbm;  // bitmaps of operands given only as lists
+  int nblk, nblk_out, nblk_list;
   size_t bytes;
 };
 
-MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz, int64_t nheavy) {
+MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz, int64_t npieces) {
   Carver c(ws);
   MxvWs t{};
   t.nblk = compact_blocks(words_of(n_in));
+  t.nblk_out = compact_blocks(words_of(n_out));
+  t.nblk_list = (int)std::max<int64_t>(1, (n_in + kMxvListChunk - 1) / kMxvListChunk);
   t.ctrl = c.take<Ctrl>(1);
+  t.part = c.take<int64_t>((size_t)2 * kMxvParts);
   t.status = c.take<uint64_t>((size_t)2 * t.nblk);
+  t.status_out = c.take<uint64_t>((size_t)2 * t.nblk_out);
+  t.status_list = c.take<uint64_t>((size_t)t.nblk_list);
   t.list = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
   t.degpre = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
   t.rowstart = c.take<int32_t>((size_t)std::max<int64_t>(n_in, 1));
-  t.tiles = c.take<int32_t>((size_t)((n_in + nnz) / kPushTile + 3));
+  t.tiles_cap = (n_in + nnz) / kPushTile + 3;
+  t.tiles = c.take<int32_t>((size_t)t.tiles_cap);
   t.t_bm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
   t.t_vb = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
   t.t_val = c.take<char>((size_t)std::max<int64_t>(n_out, 1) * 8);
-  t.hp_val = c.take<char>((size_t)std::max<int64_t>(nheavy, 1) * 8);
-  t.hp_has = c.take<uint8_t>((size_t)std::max<int64_t>(nheavy, 1));
+  t.hp_val = c.take<char>((size_t)std::max<int64_t>(npieces, 1) * 8);
+  t.hp_has = c.take<uint8_t>((size_t)std::max<int64_t>(npieces, 1));
+  t.ubm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_in), 1));
+  t.mbm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
+  t.wbm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
   t.bytes = c.off;
   return t;
 }
 
-int64_t heavy_bound(int64_t nnz) { return nnz / kHeavyChunk + nnz / (kHeavyDeg + 1) + 2; }
 int64_t split_bound(int64_t nnz) { return nnz / kPushSplit + nnz / (kPushSplit + 1) + 2; }
+
+struct ExtractWs {
+  Ctrl *ctrl;
+  uint64_t *status;
+  int32_t *list, *cnt;
+  void *vals;
+  int nblk;
+  size_t bytes;
+};
+
+ExtractWs extract_layout(void *ws, int64_t n) {
+  Carver c(ws);
+  ExtractWs t{};
+  t.nblk = compact_blocks(words_of(n));
+  t.ctrl = c.take<Ctrl>(1);
+  t.status = c.take<uint64_t>((size_t)2 * t.nblk);
+  t.cnt = c.take<int32_t>(1);
+  t.list = c.take<int32_t>((size_t)std::max<int64_t>(n, 1));
+  t.vals = c.take<char>((size_t)std::max<int64_t>(n, 1) * 8);
+  t.bytes = c.off;
+  return t;
+}
 
 grb_info check_ws(void *ws, size_t have, size_t need) {
   if (need > have) return GRB_INSUFFICIENT_SPACE;
@@ -251,6 +294,10 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
       rows.push_back(np);
     }
   }
+  int64_t max_deg = 0;
+  for (int64_t r = 0; r < c.nrows; ++r)
+    max_deg = std::max<int64_t>(max_deg, rp[(size_t)r + 1] - rp[(size_t)r]);
+  c.max_deg = max_deg;
   if ((int64_t)pieces.size() / 2 > L.max_pieces || (int64_t)rows.size() / 3 > L.max_rows ||
       (int64_t)split.size() / 2 > L.max_split ||
       (int64_t)split_rows.size() / 3 > L.max_split_rows)
@@ -473,21 +520,42 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
   launch_bfs_start(ba, source, w.F[1], w.F[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
-  // The first batch covers six levels and the empty one that ends most
-  // small-world searches (it also runs the parents pass); later batches
-  // double.  Control block and level records come back in one copy.
-  int chunk = 7;
   const size_t rec_bytes = (size_t)kStatsCap * kStatFields * sizeof(int64_t);
   const size_t head = (size_t)((char *)w.stats - (char *)w.ctrl);
   std::vector<char> host(head + rec_bytes);
   Ctrl hc{};
   bool empty_seen = false;
-  for (;;) {
+  int64_t launches = 0;  // kernel launches timed by the profile events
+  std::vector<int64_t> launch_level;  // first level of each launch
+  // High-diameter, low-degree graphs: levels run in one workgroup while the
+  // frontier is small (no launch per level); a frontier that outgrows it
+  // continues with the level kernel below.
+  const bool small = A->a.max_deg <= kSmallMaxDeg && desc.direction != GRB_DIR_PULL;
+  if (small) {
+    if (profile) (void)hipEventRecord(g_events.get(0), s);
+    uint64_t *F[3] = {w.F[0], w.F[1], w.F[2]};
+    launch_bfs_small(ba, source, cap, F, stream);
+    if (profile) (void)hipEventRecord(g_events.get(1), s);
+    launch_level.push_back(0);
+    launches = 1;
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (!read_back({{host.data(), w.ctrl, head + rec_bytes}}, s)) return GRB_PANIC;
+    std::memcpy(&hc, host.data(), sizeof(Ctrl));
+    d = hc.small_levels;
+    empty_seen = !hc.spilled;  // done, or stopped by the level cap
+  }
+  // The first batch covers six levels and the empty one that ends most
+  // small-world searches; later batches double.  Control block and level
+  // records come back in one copy.
+  int chunk = 7;
+  while (!empty_seen && d < cap) {
     for (int i = 0; i < chunk && d < cap; ++i, ++d) {
       at_level(d);
-      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)launches), s);
       launch_bfs_level(ba, stream);
-      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)launches + 1), s);
+      launch_level.push_back(d);
+      ++launches;
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
     const size_t recs = (size_t)std::min<int64_t>(d, kStatsCap) * kStatFields * sizeof(int64_t);
@@ -497,10 +565,11 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
       empty_seen = true;
       break;
     }
-    if (d >= cap) break;
     chunk = std::min(chunk * 2, 256);
   }
-  if (parents && !empty_seen) {  // stopped by the level cap
+  // parents the level kernel did not resolve: a search stopped by the level
+  // cap, or levels run by the one-workgroup loop
+  if (parents && (small || hc.nlev >= d)) {
     launch_bfs_parents(ba, stream);
     if ((info = check_launch()) != GRB_SUCCESS) return info;
     if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
@@ -512,14 +581,19 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
-    for (int64_t i = 0; i < d; ++i) {
+    // per level: a level launch's time; the one-workgroup loop's time is
+    // spread evenly over the levels it ran
+    kms.assign((size_t)std::max(nrec, 0), 0.0f);
+    for (int64_t i = 0; i < launches; ++i) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
-      if (i < nrec) kms.push_back(ms);
       ms_all += ms;
+      const int64_t l0 = launch_level[(size_t)i];
+      const int64_t l1 = (small && i == 0) ? std::max<int64_t>(hc.small_levels, 1) : l0 + 1;
+      for (int64_t l = l0; l < l1 && l < nrec; ++l) kms[(size_t)l] = ms / (float)(l1 - l0);
     }
   }
-  finish_stats(GRB_OP_BFS, iters, rec, kms, (int)std::min<int64_t>(d, INT32_MAX), ms_all);
+  finish_stats(GRB_OP_BFS, iters, rec, kms, (int)std::min<int64_t>(launches, INT32_MAX), ms_all);
   return GRB_SUCCESS;
 }
 
@@ -937,17 +1011,20 @@ grb_info grb_matrix_prepare(grb_matrix A, void *meta, size_t meta_bytes, void *s
 // ---- vector ------------------------------------------------------------------
 
 grb_info grb_vector_create(grb_vector *v, int64_t n, grb_type type, void *values,
-                           uint64_t *bitmap) {
+                           uint64_t *bitmap, int32_t *indices, int32_t *count) {
   if (!v) return GRB_NULL_POINTER;
   *v = nullptr;
   if (n < 0 || n >= INT32_MAX || !valid_type(type)) return GRB_INVALID_VALUE;
-  if (n > 0 && (!values || !bitmap)) return GRB_NULL_POINTER;
+  if ((indices == nullptr) != (count == nullptr)) return GRB_NULL_POINTER;
+  if (n > 0 && !bitmap && !indices) return GRB_NULL_POINTER;  // no presence storage
   grb_vector_s *x = new (std::nothrow) grb_vector_s;
   if (!x) return GRB_OUT_OF_MEMORY;
   x->n = n;
   x->type = type;
   x->values = values;
   x->bitmap = bitmap;
+  x->indices = indices;
+  x->count = count;
   *v = x;
   return GRB_SUCCESS;
 }
@@ -968,18 +1045,25 @@ grb_info grb_vector_size(grb_vector v, int64_t *n) {
 
 grb_info grb_vector_clear(grb_vector v, void *stream) {
   if (!v) return GRB_UNINITIALIZED_OBJECT;
-  launch_fill_u64(v->bitmap, words_of(v->n), 0ull, stream);
+  if (v->bitmap) launch_fill_u64(v->bitmap, words_of(v->n), 0ull, stream);
+  if (v->count) {
+    const int32_t zero = 0;
+    launch_fill_bytes_pattern(v->count, 1, 4, &zero, stream);
+  }
   return check_launch();
 }
 
 grb_info grb_vector_fill(grb_vector v, const void *scalar, void *stream) {
   if (!v) return GRB_UNINITIALIZED_OBJECT;
-  if (!scalar) return GRB_NULL_POINTER;
-  if (v->n == 0) return GRB_SUCCESS;
-  launch_fill_bytes_pattern(v->values, v->n, elem_size(v->type), scalar, stream);
-  const int64_t nw = words_of(v->n);
-  launch_fill_u64(v->bitmap, nw, ~0ull, stream);
-  if (v->n % 64) launch_fill_u64(v->bitmap + nw - 1, 1, (1ull << (v->n % 64)) - 1, stream);
+  if (!scalar && v->values) return GRB_NULL_POINTER;
+  if (v->n == 0) return grb_vector_clear(v, stream);
+  if (v->values) launch_fill_bytes_pattern(v->values, v->n, elem_size(v->type), scalar, stream);
+  if (v->bitmap) {
+    const int64_t nw = words_of(v->n);
+    launch_fill_u64(v->bitmap, nw, ~0ull, stream);
+    if (v->n % 64) launch_fill_u64(v->bitmap + nw - 1, 1, (1ull << (v->n % 64)) - 1, stream);
+  }
+  if (v->indices) launch_iota(v->indices, v->n, v->count, stream);
   return check_launch();
 }
 
@@ -988,6 +1072,8 @@ grb_info grb_vector_build(grb_vector v, const int32_t *idx, const void *vals, in
   if (!v) return GRB_UNINITIALIZED_OBJECT;
   if (count < 0) return GRB_INVALID_VALUE;
   if (count > 0 && !idx) return GRB_NULL_POINTER;
+  if (vals && !v->values) return GRB_INVALID_VALUE;  // the vector stores no values
+  if (!v->bitmap) return GRB_NOT_IMPLEMENTED;       // a list-only vector is written by its owner
   uint64_t one = 0;
   switch (v->type) {
     case GRB_BOOL: one = 1; break;
@@ -996,6 +1082,8 @@ grb_info grb_vector_build(grb_vector v, const int32_t *idx, const void *vals, in
     case GRB_FP64: { double f = 1.0; std::memcpy(&one, &f, 8); break; }
   }
   launch_vector_build(v->bitmap, v->values, elem_size(v->type), v->n, idx, vals, count, one, stream);
+  // the list (if the vector keeps one) follows the bitmap
+  if (v->indices) launch_bitmap_to_list_small(v->bitmap, v->n, v->indices, v->count, stream);
   return check_launch();
 }
 
@@ -1005,11 +1093,84 @@ grb_info grb_vector_nvals(grb_vector v, int64_t *nvals, void *ws, size_t ws_byte
   grb_info info = check_ws(ws, ws_bytes, 64);
   if (info != GRB_SUCCESS) return info;
   hipStream_t s = (hipStream_t)stream;
+  if (!v->bitmap) {
+    int32_t c = 0;
+    if (!read_back({{&c, v->count, sizeof(c)}}, s)) return GRB_PANIC;
+    *nvals = std::min<int64_t>(std::max<int32_t>(c, 0), v->n);
+    return GRB_SUCCESS;
+  }
   launch_popcount(v->bitmap, words_of(v->n), (int64_t *)ws, stream);
   if ((info = check_launch()) != GRB_SUCCESS) return info;
   int64_t h = 0;
   if (!read_back({{&h, ws, sizeof(h)}}, s)) return GRB_PANIC;
   *nvals = h;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_vector_extract(grb_vector v, int32_t *indices, void *values, int64_t capacity,
+                            int64_t *nvals, void *ws, size_t ws_bytes, void *stream) {
+  if (!v) return GRB_UNINITIALIZED_OBJECT;
+  if (!nvals) return GRB_NULL_POINTER;
+  if (capacity < 0) return GRB_INVALID_VALUE;
+  ExtractWs t = extract_layout(ws, v->n);
+  grb_info info = check_ws(ws, ws_bytes, t.bytes);
+  if (info != GRB_SUCCESS) return info;
+  if (v->n == 0) {
+    *nvals = 0;
+    return GRB_SUCCESS;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t *list = v->indices;
+  const int32_t *cnt = v->count;
+  if (!list) {
+    // bitmap -> sorted list in the workspace (the compaction's look-back
+    // needs its status words and ticket cleared first)
+    launch_fill_u64((uint64_t *)t.ctrl, sizeof(Ctrl) / 8, 0ull, stream);
+    launch_fill_u64(t.status, 2 * (int64_t)t.nblk, 0ull, stream);
+    CompactArgs ca;
+    ca.nb = v->bitmap;
+    ca.nw = words_of(v->n);
+    ca.nbits = v->n;
+    ca.list = t.list;
+    ca.status_cur = t.status;
+    ca.status_next = t.status + t.nblk;
+    ca.ctrl = t.ctrl;
+    ca.count_out = t.cnt;
+    launch_compact(ca, stream);
+    list = t.list;
+    cnt = t.cnt;
+  }
+  const int esz = elem_size(v->type);
+  if (v->values && values)
+    launch_gather_values(v->values, esz, list, cnt, v->n, t.vals, stream);
+  if ((info = check_launch()) != GRB_SUCCESS) return info;
+  int32_t c = 0;
+  if (!read_back({{&c, cnt, sizeof(c)}}, s)) return GRB_PANIC;
+  const int64_t m = std::min<int64_t>(std::max<int32_t>(c, 0), v->n);
+  *nvals = m;
+  if (m > capacity) return GRB_INSUFFICIENT_SPACE;
+  if (m > 0) {
+    if (indices && hipMemcpyAsync(indices, list, (size_t)m * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return GRB_PANIC;
+    if (values) {
+      if (v->values) {
+        if (hipMemcpyAsync(values, t.vals, (size_t)m * esz, hipMemcpyDeviceToHost, s) != hipSuccess)
+          return GRB_PANIC;
+      } else {
+        // a vector without values holds 1 at every entry
+        for (int64_t k = 0; k < m; ++k) {
+          char *dst = (char *)values + k * esz;
+          switch (v->type) {
+            case GRB_BOOL: *(uint8_t *)dst = 1; break;
+            case GRB_INT32: *(int32_t *)dst = 1; break;
+            case GRB_FP32: *(float *)dst = 1.0f; break;
+            default: *(double *)dst = 1.0; break;
+          }
+        }
+      }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+  }
   return GRB_SUCCESS;
 }
 
@@ -1023,6 +1184,11 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
   }
   if (op == GRB_OP_MXM) {
     *bytes = kMxmWs;
+    return GRB_SUCCESS;
+  }
+  if (op == GRB_OP_EXTRACT) {
+    if (k < 0 || k >= INT32_MAX) return GRB_INVALID_VALUE;
+    *bytes = extract_layout(nullptr, k).bytes;
     return GRB_SUCCESS;
   }
   if (!A) return GRB_UNINITIALIZED_OBJECT;
@@ -1043,7 +1209,7 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
       break;
     case GRB_OP_MXV: {
       const int64_t m = std::max(A->nrows, A->ncols);
-      *bytes = mxv_layout(nullptr, m, m, A->nnz, heavy_bound(A->nnz)).bytes;
+      *bytes = mxv_layout(nullptr, m, m, A->nnz, split_bound(A->nnz)).bytes;
       break;
     }
     default: return GRB_INVALID_VALUE;
@@ -1191,6 +1357,196 @@ grb_info grb_msbfs(int32_t *levels, grb_matrix A, const int32_t *sources, int32_
     }
   }
   finish_stats(GRB_OP_MSBFS, iters, rec, kms, (int)std::min<int64_t>(dlev, INT32_MAX), ms_all);
+  // a source outside [0, n) was skipped on the device; the others ran to the end
+  return hc.error ? GRB_INVALID_INDEX : GRB_SUCCESS;
+}
+
+}  // extern "C"
+
+// ---- batched BFS sessions (continuous batching) ---------------------------------
+
+struct grb_msbfs_session_s {
+  grb_matrix A = nullptr;
+  MsWs w{};
+  MsbfsArgs ma;
+  int64_t d = 0;  // levels run so far
+  int grid = 0;
+  std::vector<uint64_t> busy;  // queries joined and not yet retired
+};
+
+namespace {
+
+void session_level(grb_msbfs_session_s &ss, int64_t dd) {
+  const int i = (int)(dd % 3), j = (int)((dd + 1) % 3), q = (int)((dd + 2) % 3);
+  MsbfsArgs &ma = ss.ma;
+  ma.F = ss.w.F[i];
+  ma.Fn = ss.w.F[j];
+  ma.Fc = ss.w.F[q];
+  ma.act = ss.w.act[i];
+  ma.actn = ss.w.act[j];
+  ma.actc = ss.w.act[q];
+  ma.cnt_cur = ss.w.cnt + (size_t)i * 2 * kCntStripes;
+  ma.cnt_nxt = ss.w.cnt + (size_t)j * 2 * kCntStripes;
+  ma.cnt_clr = ss.w.cnt + (size_t)q * 2 * kCntStripes;
+  ma.alive_nxt = ss.w.alive + (size_t)j * ma.W;
+  ma.alive_clr = ss.w.alive + (size_t)q * ma.W;
+  ma.d = (int32_t)std::min<int64_t>(dd, INT32_MAX);
+}
+
+}  // namespace
+
+extern "C" {
+
+grb_info grb_msbfs_session_create(grb_msbfs_session *ss, grb_matrix A, int32_t k, int32_t *levels,
+                                  const grb_msbfs_tile *tile, const grb_descriptor *d, void *ws,
+                                  size_t ws_bytes, void *stream) {
+  if (!ss) return GRB_NULL_POINTER;
+  *ss = nullptr;
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!levels) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (k < 1) return GRB_INVALID_VALUE;
+  const int W = (int)((k + 63) / 64);
+  int kt = W, grid = kExpandGrid;
+  if (tile) {
+    if (tile->reserved[0] || tile->reserved[1] || tile->words_per_pass < 0 ||
+        tile->words_per_pass > W || tile->grid < 0 || tile->grid > 65535)
+      return GRB_INVALID_VALUE;
+    if (tile->words_per_pass) kt = tile->words_per_pass;
+    if (tile->grid) grid = tile->grid;
+  }
+  kt = std::min(kt, kMsMaxWordsPerPass);
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  const bool can_pull = A->at.valid();
+  if (desc.direction == GRB_DIR_PULL && !can_pull) return GRB_NOT_IMPLEMENTED;
+  const int64_t n = A->nrows;
+  MsWs w = ms_layout(ws, n, k);
+  if ((info = check_ws(ws, ws_bytes, w.bytes)) != GRB_SUCCESS) return info;
+  grb_msbfs_session_s *x = new (std::nothrow) grb_msbfs_session_s;
+  if (!x) return GRB_OUT_OF_MEMORY;
+  try {
+    x->busy.assign((size_t)W, 0ull);
+  } catch (const std::bad_alloc &) {
+    delete x;
+    return GRB_OUT_OF_MEMORY;
+  }
+  x->A = A;
+  x->w = w;
+  x->grid = grid;
+  MsbfsArgs &ma = x->ma;
+  ma.n = n;
+  ma.nw = words_of(n);
+  ma.nnz = A->nnz;
+  ma.k = k;
+  ma.W = W;
+  ma.kt = kt;
+  ma.push = A->a;
+  ma.pull = A->at;
+  ma.can_pull = can_pull;
+  ma.levels = levels;
+  ma.V = w.V;
+  ma.cnt_base = w.cnt;
+  ma.ctrl = w.ctrl;
+  ma.stats = nullptr;
+  ma.rule = desc.switch_rule;
+  ma.denom = desc.switch_denominator;
+  ma.forced = desc.direction;
+  ma.start = w.start;
+  session_level(*x, 0);
+  launch_msbfs_session_init(ma, w.F[1], w.F[2], w.act[1], w.act[2], w.alive, stream);
+  if ((info = check_launch()) != GRB_SUCCESS) {
+    delete x;
+    return info;
+  }
+  *ss = x;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_msbfs_session_join(grb_msbfs_session ss, const int32_t *lanes,
+                                const int32_t *sources, int32_t count, void *stream) {
+  if (!ss) return GRB_UNINITIALIZED_OBJECT;
+  if (count < 0 || count > ss->ma.k) return GRB_INVALID_VALUE;
+  if (count == 0) return GRB_SUCCESS;
+  if (!lanes || !sources) return GRB_NULL_POINTER;
+  const int W = ss->ma.W;
+  std::vector<uint64_t> clr((size_t)W, 0ull);
+  for (int32_t i = 0; i < count; ++i) {
+    const int32_t q = lanes[i], v = sources[i];
+    if (q < 0 || q >= ss->ma.k || v < 0 || v >= ss->ma.n) return GRB_INVALID_INDEX;
+    const uint64_t bit = 1ull << (q & 63);
+    // a query still running, or named twice, cannot join
+    if ((ss->busy[(size_t)(q >> 6)] | clr[(size_t)(q >> 6)]) & bit) return GRB_INVALID_VALUE;
+    clr[(size_t)(q >> 6)] |= bit;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ss->w.clr, clr.data(), (size_t)W * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ss->w.lanes, lanes, (size_t)count * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ss->w.sources, sources, (size_t)count * 4, hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return GRB_PANIC;
+  session_level(*ss, ss->d);
+  launch_msbfs_session_join(ss->ma, ss->w.lanes, ss->w.sources, count, ss->w.clr, ss->w.start,
+                            ss->w.alive + (size_t)(ss->d % 3) * W, stream);
+  grb_info info = check_launch();
+  if (info != GRB_SUCCESS) return info;
+  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;  // host arrays are released
+  for (int j = 0; j < W; ++j) ss->busy[(size_t)j] |= clr[(size_t)j];
+  return GRB_SUCCESS;
+}
+
+grb_info grb_msbfs_session_step(grb_msbfs_session ss, int32_t max_levels, uint64_t *done,
+                                int32_t *levels_run, void *stream) {
+  if (!ss) return GRB_UNINITIALIZED_OBJECT;
+  if (max_levels < 0) return GRB_INVALID_VALUE;
+  if (!done) return GRB_NULL_POINTER;
+  const int W = ss->ma.W;
+  bool any = false;
+  for (int j = 0; j < W; ++j) any |= ss->busy[(size_t)j] != 0ull;
+  int32_t ran = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (any) {
+    for (; ran < max_levels; ++ran, ++ss->d) {
+      session_level(*ss, ss->d);
+      launch_msbfs_level(ss->ma, ss->grid, stream);
+    }
+  }
+  grb_info info = check_launch();
+  if (info != GRB_SUCCESS) return info;
+  std::vector<uint64_t> alive((size_t)W, 0ull);
+  if (!read_back({{alive.data(), ss->w.alive + (size_t)(ss->d % 3) * W, (size_t)W * 8}}, s))
+    return GRB_PANIC;
+  for (int j = 0; j < W; ++j) {
+    done[j] = ss->busy[(size_t)j] & ~alive[(size_t)j];
+    ss->busy[(size_t)j] &= alive[(size_t)j];
+  }
+  if (levels_run) *levels_run = ran;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_msbfs_session_extract(grb_msbfs_session ss, const int32_t *lanes, int32_t count,
+                                   int32_t *out, void *stream) {
+  if (!ss) return GRB_UNINITIALIZED_OBJECT;
+  if (count < 0 || count > ss->ma.k) return GRB_INVALID_VALUE;
+  if (count == 0) return GRB_SUCCESS;
+  if (!lanes || !out) return GRB_NULL_POINTER;
+  for (int32_t i = 0; i < count; ++i)
+    if (lanes[i] < 0 || lanes[i] >= ss->ma.k) return GRB_INVALID_INDEX;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(ss->w.lanes, lanes, (size_t)count * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return GRB_PANIC;
+  launch_msbfs_session_extract(ss->ma, ss->w.lanes, count, out, stream);
+  grb_info info = check_launch();
+  if (info != GRB_SUCCESS) return info;
+  if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_msbfs_session_free(grb_msbfs_session *ss) {
+  if (!ss) return GRB_NULL_POINTER;
+  delete *ss;
+  *ss = nullptr;
   return GRB_SUCCESS;
 }
 
@@ -1319,9 +1675,17 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   grb_descriptor desc;
   grb_info info = resolve_desc(d, &desc);
   if (info != GRB_SUCCESS) return info;
-  if (w == u || (mask && w == mask) || (w->values && w->values == u->values) ||
-      (mask && w->bitmap == mask->bitmap))
-    return GRB_INVALID_VALUE;  // output must not alias an input
+  if (w == u || (mask && w == mask)) return GRB_INVALID_VALUE;  // output must not alias an input
+  {
+    const void *wp[] = {w->values, w->bitmap, w->indices, w->count};
+    const void *ip[] = {u->values, u->bitmap, u->indices, u->count,
+                        mask ? mask->values : nullptr, mask ? mask->bitmap : nullptr,
+                        mask ? mask->indices : nullptr, mask ? mask->count : nullptr};
+    for (const void *x : wp)
+      for (const void *y : ip)
+        if (x && x == y) return GRB_INVALID_VALUE;
+  }
+  if (!w->values && w->n > 0) return GRB_INVALID_VALUE;  // the output stores values
   const grb_type dom = domain_of(s);
   if (w->type != dom || u->type != dom) return GRB_DOMAIN_MISMATCH;
   if (!accum_fits(s, accum)) return GRB_DOMAIN_MISMATCH;
@@ -1337,7 +1701,7 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   if ((desc.direction == GRB_DIR_PULL && !can_pull) ||
       (desc.direction == GRB_DIR_PUSH && !can_push) || (!can_pull && !can_push))
     return GRB_NOT_IMPLEMENTED;
-  MxvWs t = mxv_layout(ws, n_in, n_out, A->nnz, can_pull ? pull.nheavy : 0);
+  MxvWs t = mxv_layout(ws, n_in, n_out, A->nnz, can_pull ? pull.nsplit : 0);
   if ((info = check_ws(ws, ws_bytes, t.bytes)) != GRB_SUCCESS) return info;
   MxvArgs a;
   a.n_out = n_out;
@@ -1357,13 +1721,24 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   a.mask_comp = (desc.flags & GRB_MASK_COMP) != 0;
   a.mask_struct = (desc.flags & GRB_MASK_STRUCT) != 0;
   a.replace = (desc.flags & GRB_REPLACE) != 0;
+  // input: a list feeds push directly; pull reads the bitmap, built from the
+  // list in the workspace when the vector has none
   a.u_val = u->values;
-  a.u_bm = u->bitmap;
+  if (u->indices) {
+    a.u_list = u->indices;
+    a.u_cnt = u->count;
+  }
+  a.u_bm = u->bitmap ? u->bitmap : t.ubm;
+  a.u_from_list = u->bitmap == nullptr;
   a.w_val = w->values;
-  a.w_bm = w->bitmap;
+  a.w_bm = w->bitmap ? w->bitmap : t.wbm;
+  if (w->indices) {
+    a.w_list = w->indices;
+    a.w_cnt = w->count;
+  }
   if (mask) {
     a.m_val = mask->values;
-    a.m_bm = mask->bitmap;
+    a.m_bm = mask->bitmap ? mask->bitmap : t.mbm;
     a.m_type = mask->type;
   }
   a.t_val = t.t_val;
@@ -1371,18 +1746,45 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   a.t_vb = t.t_vb;
   a.hp_val = t.hp_val;
   a.hp_has = t.hp_has;
-  a.list = t.list;
+  a.list = u->indices ? u->indices : t.list;
   a.degpre = t.degpre;
   a.rowstart = t.rowstart;
   a.tiles = t.tiles;
+  a.tiles_cap = t.tiles_cap;
   a.status = t.status;
+  a.status_out = t.status_out;
+  a.status_list = t.status_list;
   a.nblk = t.nblk;
+  a.nblk_out = t.nblk_out;
+  a.nblk_list = t.nblk_list;
+  a.part = t.part;
   a.ctrl = t.ctrl;
-  a.rule = desc.switch_rule;
-  a.denom = desc.switch_denominator;
-  a.forced = desc.direction;
+  a.gate.part = t.part;
+  a.gate.forced = desc.direction;
+  a.gate.can_push = can_push;
+  a.gate.can_pull = can_pull;
+  a.gate.rule = desc.switch_rule;
+  a.gate.denom = desc.switch_denominator;
+  a.gate.nnz = A->nnz;
+  a.gate.n_in = n_in;
   if (n_out == 0) return GRB_SUCCESS;
+  // operands given only as lists: their bitmaps in the workspace
+  if (mask && !mask->bitmap) launch_list_to_bitmap(mask->indices, mask->count, n_out, t.mbm, stream);
+  if (!w->bitmap) launch_list_to_bitmap(w->indices, w->count, n_out, t.wbm, stream);
   launch_mxv(a, stream);
+  if (w->indices) {
+    // the output's list follows its new bitmap (bitmap -> sorted list)
+    CompactArgs ca;
+    ca.nb = a.w_bm;
+    ca.nw = a.nw_out;
+    ca.nbits = n_out;
+    ca.list = w->indices;
+    ca.status_cur = t.status_out;
+    ca.status_next = t.status_out + t.nblk_out;
+    ca.ctrl = t.ctrl;
+    ca.count_out = w->count;
+    launch_compact(ca, stream);
+  }
   return check_launch();
 }
 

@@ -726,7 +726,159 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
   }
 }
 
+// ---- one-workgroup level loop for small frontiers -------------------------
+// Each level: a thread takes frontier entries t, t + 1024, ... of the LDS
+// list (vertex, row start, degree), writes their level (delayed from the
+// level that found them, so the stores overlap this level's loads), loads
+// their out-edges four at a time and claims each target with one atomicOr
+// on its visited word, loading the target's row extents at the same time;
+// the winners are appended to the next list (one LDS atomic per wave).
+// Two dependent global round trips and one barrier per level.
+__global__ __launch_bounds__(kSmallThreads) void k_bfs_small(BfsArgs a, int32_t source,
+                                                             int64_t max_levels, uint64_t *F0,
+                                                             uint64_t *F1, uint64_t *F2) {
+  __shared__ int s_v[2][kSmallCap], s_rs[2][kSmallCap], s_dg[2][kSmallCap];
+  __shared__ int s_n[2], s_e[2], s_long[2];
+  const int tid = threadIdx.x, ln = tid & 63;
+  const int32_t *rp = a.push.rp, *ci = a.push.ci;
+  if (tid == 0) {
+    s_v[0][0] = source;
+    s_rs[0][0] = rp[source];
+    s_dg[0][0] = rp[source + 1] - rp[source];
+    s_n[0] = 1;
+    s_e[0] = s_dg[0][0];
+    s_long[0] = s_dg[0][0] > kPushSplit ? 1 : 0;
+  }
+  __syncthreads();
+  int64_t d = 0;
+  int b = 0;
+  bool spill = false;
+  for (;;) {
+    const int nc = s_n[b];
+    if (nc == 0 || d >= max_levels) break;
+    // a frontier too large for the lists, or one the switch rule would
+    // pull, goes to the level kernel
+    if (nc > kSmallCap || s_e[b] > kSmallEdges || decide(a, nc, s_e[b]) == GRB_DIR_PULL) {
+      spill = true;
+      break;
+    }
+    if (tid == 0) {
+      s_n[b ^ 1] = 0;
+      s_e[b ^ 1] = 0;
+      s_long[b ^ 1] = 0;
+      a.ctrl->nlev = (int)d + 1;
+      if (a.stats && d < kStatsCap) {
+        a.stats[d * kStatFields + 0] = nc;
+        a.stats[d * kStatFields + 1] = s_e[b];
+        a.stats[d * kStatFields + 2] = GRB_DIR_PUSH;
+      }
+    }
+    __syncthreads();
+    for (int base = 0; base < nc; base += 4 * kSmallThreads) {
+      int v[4], rs[4], dg[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = base + k * kSmallThreads + tid;
+        v[k] = -1;
+        rs[k] = dg[k] = 0;
+        if (i < nc) {
+          v[k] = s_v[b][i];
+          rs[k] = s_rs[b][i];
+          dg[k] = s_dg[b][i];
+          if (d > 0) a.levels[v[k]] = (int)d;
+        }
+      }
+      const int mx = max(max(dg[0], dg[1]), max(dg[2], dg[3]));
+      for (int q0 = 0; __syncthreads_or(q0 < mx); q0 += 4) {
+        int c[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            c[k * 4 + q] = q0 + q < dg[k] ? ci[rs[k] + q0 + q] : -1;
+        uint64_t old[16];
+        int r0[16], r1[16];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) {
+          old[x] = ~0ull;
+          r0[x] = r1[x] = 0;
+          if (c[x] >= 0) {
+            old[x] = atomicOr((unsigned long long *)&a.visited[c[x] >> 6], 1ull << (c[x] & 63));
+            r0[x] = rp[c[x]];
+            r1[x] = rp[c[x] + 1];
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < 16; ++x) {
+          const bool won = c[x] >= 0 && !((old[x] >> (c[x] & 63)) & 1ull);
+          const uint64_t wm = __ballot(won);
+          if (wm == 0ull) continue;
+          int base_slot = 0;
+          if (ln == 0) {
+            base_slot = atomicAdd(&s_n[b ^ 1], __popcll(wm));
+          }
+          base_slot = __shfl(base_slot, 0);
+          const int dgc = won ? r1[x] - r0[x] : 0;
+          const int esum = wave_sum(dgc), lsum = wave_sum(dgc > kPushSplit ? 1 : 0);
+          if (ln == 0) {
+            atomicAdd(&s_e[b ^ 1], esum);
+            if (lsum) atomicAdd(&s_long[b ^ 1], lsum);
+          }
+          if (won) {
+            const int slot = base_slot + __popcll(wm & mask_below(ln));
+            if (slot < kSmallCap) {
+              s_v[b ^ 1][slot] = c[x];
+              s_rs[b ^ 1][slot] = r0[x];
+              s_dg[b ^ 1][slot] = dgc;
+            } else {
+              // no room in the list: level and frontier bit at once (the
+              // loop hands this frontier to the wide kernel)
+              a.levels[c[x]] = (int)d + 1;
+              uint64_t *fn = ((d + 1) % 3 == 0) ? F0 : (((d + 1) % 3 == 1) ? F1 : F2);
+              atomicOr((unsigned long long *)&fn[c[x] >> 6], 1ull << (c[x] & 63));
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    ++d;
+    b ^= 1;
+  }
+  // levels of the last listed frontier (its loop iteration did not run)
+  const int nl = min(s_n[b], kSmallCap);
+  if (d > 0)
+    for (int i = tid; i < nl; i += kSmallThreads) a.levels[s_v[b][i]] = (int)d;
+  if (spill) {
+    // the frontier of level d goes to the wide kernel as its bitmap and
+    // counters; the start kernel's source bit in F0 is the only other bit set
+    uint64_t *fn = (d % 3 == 0) ? F0 : ((d % 3 == 1) ? F1 : F2);
+    if (tid == 0) F0[source >> 6] = 0ull;
+    for (int i = tid; i < 3 * kCntSlots; i += kSmallThreads) a.ctrl->lists[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < nl; i += kSmallThreads)
+      atomicOr((unsigned long long *)&fn[s_v[b][i] >> 6], 1ull << (s_v[b][i] & 63));
+    if (tid == 0) {
+      int32_t *cnt = a.ctrl->lists + (d % 3) * kCntSlots;
+      cnt[0] = s_n[b];
+      cnt[1] = s_e[b];
+      cnt[2] = s_long[b];
+      a.ctrl->pushed[0] = a.ctrl->pushed[1] = a.ctrl->pushed[2] = 0;  // parents: final pass
+    }
+  }
+  if (tid == 0) {
+    a.ctrl->small_levels = (int)d;
+    a.ctrl->spilled = spill ? 1 : 0;
+  }
+}
+
 }  // namespace
+
+void launch_bfs_small(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
+                      void *stream) {
+  hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kSmallThreads), 0, (hipStream_t)stream, a, source,
+                     max_levels, F[0], F[1], F[2]);
+}
 
 void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                       void *stream) {

@@ -8,6 +8,8 @@
 #include <climits>
 #include <cstdint>
 
+#include "grb_internal.h"
+
 namespace grb {
 
 __device__ __forceinline__ uint64_t mask_below(int k) {
@@ -255,6 +257,28 @@ __device__ __forceinline__ double atomic_min_f64(double *a, double v) {
   }
   return __longlong_as_double((long long)atomicMax(
       (unsigned long long *)a, (unsigned long long)__double_as_longlong(v)));
+}
+
+// Direction of a generic product (Section 4.3.1, Table 5), evaluated by a
+// wave from the first kernel's (count, degree sum) partials; forced
+// directions and single-orientation matrices need no partials.  All 64
+// lanes must be active; every lane gets the same answer.
+__device__ __forceinline__ int gate_dir(const DirGate &g) {
+  if (g.forced) return g.forced;
+  if (!g.can_pull) return GRB_DIR_PUSH;
+  if (!g.can_push) return GRB_DIR_PULL;
+  const int ln = threadIdx.x & 63;
+  int64_t c = 0, d = 0;
+#pragma unroll
+  for (int k = 0; k < kMxvParts / 64; ++k) {
+    c += g.part[2 * (k * 64 + ln)];
+    d += g.part[2 * (k * 64 + ln) + 1];
+  }
+  c = wave_sum64(c);
+  d = wave_sum64(d);
+  const bool pull = g.rule == GRB_SWITCH_EXACT ? (int64_t)g.denom * d > g.nnz
+                                               : (int64_t)g.denom * c > g.n_in;
+  return pull ? GRB_DIR_PULL : GRB_DIR_PUSH;
 }
 
 }  // namespace grb

@@ -55,6 +55,7 @@ struct Csr {
   // first two column ids of every row (-1 where the row is shorter), read
   // with the row extents so that a pull settled by them never touches col_idx
   const int2 *first2 = nullptr;
+  int64_t max_deg = 0;  // longest row (host copy, from prepare)
   bool valid() const { return rp != nullptr; }
 };
 
@@ -71,8 +72,10 @@ struct grb_matrix_s {
 struct grb_vector_s {
   int64_t n = 0;
   grb_type type = GRB_BOOL;
-  void *values = nullptr;
-  uint64_t *bitmap = nullptr;
+  void *values = nullptr;      // n elements by index, or null (every entry is 1)
+  uint64_t *bitmap = nullptr;  // presence words, or null
+  int32_t *indices = nullptr;  // sorted present indices (capacity n), or null
+  int32_t *count = nullptr;    // device int32: entries in `indices`
 };
 
 namespace grb {
@@ -95,7 +98,11 @@ struct Ctrl {
                               // (its vertices' parents are still open)
   double Dfz;                 // adaptive PageRank: dangling mass of the frozen vertices
   int64_t active;             // adaptive PageRank: vertices still active
-  int64_t pad[4];
+  int32_t ticket_list;        // generic product: list preparation workgroup tickets
+  int32_t error;              // batched BFS: a source id was out of range
+  int32_t small_levels;       // BFS / SSSP: levels or rounds run by the one-workgroup loop
+  int32_t spilled;            // ... which then handed a frontier to the wide kernels
+  int64_t pad[2];
 };
 
 // stats record per iteration: {frontier, sumdeg, direction, unused}
@@ -104,6 +111,22 @@ constexpr int kStatFields = 4;
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 inline int64_t words_of(int64_t n) { return (n + 63) / 64; }
+
+// ---- direction of a generic product ----------------------------------------
+// The automatic choice is taken on the device from the input's entry count
+// and degree sum, which the product's first kernel leaves as per-workgroup
+// partials (kMxvParts (count, degree sum) pairs); every later kernel of the
+// product evaluates the rule itself, so no kernel waits on the host.
+constexpr int kMxvParts = 256;     // workgroups of the generic product's first kernel
+constexpr int kMxvPartThreads = 1024;
+constexpr int kMxvListChunk = 4096;  // list entries per workgroup of the list preparation
+struct DirGate {
+  const int64_t *part = nullptr;  // 2 * kMxvParts partials (unused when forced)
+  int forced = 0;                 // grb_direction: 0 = automatic
+  bool can_push = true, can_pull = true;
+  int rule = 0, denom = 10;
+  int64_t nnz = 0, n_in = 0;
+};
 
 // ---- kernel launch interfaces (implemented in grb_kernels.hip) -------------
 struct CompactArgs {
@@ -119,6 +142,10 @@ struct CompactArgs {
   Ctrl *ctrl = nullptr;
   uint64_t *clear = nullptr;     // optional: bitmap zeroed word by word
   bool skip_if_empty = false;    // return at once when ctrl->count == 0
+  bool gated = false;            // return at once unless `gate` picks push
+  DirGate gate;
+  int32_t *count_out = nullptr;  // optional: the list's length is also stored here
+  int64_t nbits = 0;             // bits of the bitmap that count (0 = all nw * 64)
 };
 int compact_blocks(int64_t nw);
 void launch_compact(const CompactArgs &a, void *stream);
@@ -146,6 +173,17 @@ struct BfsArgs {
 void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                       void *stream);
 void launch_bfs_level(const BfsArgs &a, void *stream);
+// BFS levels in one workgroup while the frontier is small (high-diameter,
+// low-degree graphs): frontier lists in LDS, workgroup barriers only; hands
+// the frontier to the wide level kernel (as the bitmap and counters of
+// level ctrl->small_levels) when it outgrows the lists.  Starts at level 0
+// after launch_bfs_start; parents are left to the parents pass.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallCap = 4096;     // frontier vertices per level held in LDS
+constexpr int kSmallEdges = 65536;  // edges of a frontier the loop still expands
+constexpr int kSmallMaxDeg = 64;    // graphs whose rows are at most this long use the loop
+void launch_bfs_small(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
+                      void *stream);
 void launch_bfs_parents(const BfsArgs &a, void *stream);
 
 // SSSP with one kernel per round (grb_sssp.hip); counters as BFS
@@ -253,10 +291,26 @@ struct MsbfsArgs {
   int64_t *stats = nullptr;
   int32_t d = 0;
   int32_t rule = 0, denom = 10, forced = 0;
+  // continuous batching (sessions): per-query start level (discoveries at
+  // level d are written as d + 1 - start[q]) and per-query-word "has a
+  // frontier bit" words of the next level (cleared two levels ahead)
+  const int32_t *start = nullptr;
+  unsigned long long *alive_nxt = nullptr, *alive_clr = nullptr;
 };
 void launch_msbfs_start(const MsbfsArgs &a, const int32_t *sources, uint64_t *F1, uint64_t *F2,
                         uint64_t *act1, uint64_t *act2, void *stream);
 void launch_msbfs_level(const MsbfsArgs &a, int grid_x, void *stream);
+// sessions: every query idle (its bits set in V), blocks and counters cleared
+void launch_msbfs_session_init(const MsbfsArgs &a, uint64_t *F1, uint64_t *F2, uint64_t *act1,
+                               uint64_t *act2, unsigned long long *alive3, void *stream);
+// sessions: queries lanes[i] start from sources[i] at level a.d (device
+// arrays of `count` entries; clr[W] holds the joining queries' bits per word)
+void launch_msbfs_session_join(const MsbfsArgs &a, const int32_t *lanes, const int32_t *sources,
+                               int32_t count, const uint64_t *clr, int32_t *start,
+                               unsigned long long *alive_cur, void *stream);
+// sessions: out[i * n + v] = level of query lanes[i] at v, -1 where unvisited
+void launch_msbfs_session_extract(const MsbfsArgs &a, const int32_t *lanes, int32_t count,
+                                  int32_t *out, void *stream);
 
 // generic masked products (grb_mxv.hip)
 struct MxvArgs {
@@ -276,17 +330,39 @@ struct MxvArgs {
   const void *m_val = nullptr;
   const uint64_t *m_bm = nullptr;
   int m_type = 0;
+  // sparse (list) forms: sorted present indices and their device-side count
+  const int32_t *u_list = nullptr, *u_cnt = nullptr;  // input given as a list
+  bool u_from_list = false;     // u_bm is built from u_list (the vector has no bitmap)
+  const int32_t *m_list = nullptr, *m_cnt = nullptr;  // mask given only as a list
+  int32_t *w_list = nullptr, *w_cnt = nullptr;        // output list to refresh
+  const int32_t *w_list_in = nullptr, *w_cnt_in = nullptr;  // output given only as a list
   // workspace
   void *t_val = nullptr;
   uint64_t *t_bm = nullptr, *t_vb = nullptr;
   void *hp_val = nullptr;       // per pull piece partial value
   uint8_t *hp_has = nullptr;    // per pull piece: any contribution
   int32_t *list = nullptr, *degpre = nullptr, *rowstart = nullptr, *tiles = nullptr;
-  uint64_t *status = nullptr;
-  int nblk = 0;
+  int64_t tiles_cap = 0;        // entries of `tiles`
+  uint64_t *status = nullptr, *status_out = nullptr, *status_list = nullptr;
+  int nblk = 0, nblk_out = 0, nblk_list = 0;
+  int64_t *part = nullptr;      // direction partials of the first kernel
   Ctrl *ctrl = nullptr;
-  int32_t rule = 0, denom = 10, forced = 0;
+  DirGate gate;
 };
 void launch_mxv(const MxvArgs &a, void *stream);
+
+// vectors: sorted list (capacity n) -> presence bitmap (every word written);
+// with a gate, only when the product pulls
+void launch_list_to_bitmap(const int32_t *list, const int32_t *cnt, int64_t n, uint64_t *bm,
+                           void *stream, const DirGate *gate = nullptr);
+// vectors: presence bitmap of n bits -> sorted list and count, one workgroup
+// (no workspace)
+void launch_bitmap_to_list_small(const uint64_t *bm, int64_t n, int32_t *list, int32_t *cnt,
+                                 void *stream);
+// vectors: list entries 0..n-1 and count n
+void launch_iota(int32_t *list, int64_t n, int32_t *cnt, void *stream);
+// vectors: out[k] = values[list[k]] for k < *cnt (elem_size bytes per value)
+void launch_gather_values(const void *values, int elem_size, const int32_t *list,
+                          const int32_t *cnt, int64_t cap, void *out, void *stream);
 
 }  // namespace grb

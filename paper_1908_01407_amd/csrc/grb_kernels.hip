@@ -47,16 +47,22 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
   const int tid = threadIdx.x, wid = tid >> 6, ln = tid & 63;
   // once a frontier is empty every later one is: nothing to compact
   if (a.skip_if_empty && a.ctrl->count == 0) return;
+  // a generic product that pulls needs no list
+  if (a.gated && gate_dir(a.gate) != GRB_DIR_PUSH) return;
   if (tid == 0) s_blk = atomicAdd(&a.ctrl->ticket, 1);
   __syncthreads();
   const int blk = s_blk;
   const int64_t w0 = (int64_t)blk * kCompactWords + wid * WPW;
   if (tid == 0) a.status_next[blk] = 0ull;
 
+  // bits at positions >= nbits (a bitmap's padding) never enter the list
+  const int64_t nbits = a.nbits > 0 ? a.nbits : a.nw * 64;
+  const int64_t wlast = (nbits - 1) >> 6;
+  const uint64_t mlast = mask_below((int)(nbits - wlast * 64));
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     const int64_t w = w0 + k;
-    const uint64_t word = w < a.nw ? a.nb[w] : 0ull;
+    const uint64_t word = w < a.nw ? (a.nb[w] & (w == wlast ? mlast : ~0ull)) : 0ull;
     int deg = 0;
     if ((word >> ln) & 1ull) {
       const int64_t v = w * 64 + ln;
@@ -127,6 +133,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
         const int64_t nt = (cnt + sd + kPushTile - 1) / kPushTile;
         a.ctrl->ntiles = (int)nt;
         if (a.tiles && cnt > 0) a.tiles[nt] = (int)(cnt - 1);
+        if (a.count_out) *a.count_out = (int)cnt;
         a.ctrl->ticket = 0;
       }
     }
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     const int64_t w = w0 + k;
-    const uint64_t word = w < a.nw ? a.nb[w] : 0ull;
+    const uint64_t word = w < a.nw ? (a.nb[w] & (w == wlast ? mlast : ~0ull)) : 0ull;
     if (word == 0ull) continue;
     const bool bit = (word >> ln) & 1ull;
     const int rank = __popcll(word & mask_below(ln));
@@ -213,9 +220,119 @@ __global__ void k_vector_scatter(uint64_t *bitmap, unsigned char *values, int el
     const int64_t i = idx[k];
     if (i < 0 || i >= n) continue;
     atomicOr((unsigned long long *)&bitmap[i >> 6], 1ull << (i & 63));
+    if (!values) continue;
     if (elem == 1) values[i] = vals ? vals[k] : (unsigned char)one;
     else if (elem == 4) ((uint32_t *)values)[i] = vals ? ((const uint32_t *)vals)[k] : (uint32_t)one;
     else ((uint64_t *)values)[i] = vals ? ((const uint64_t *)vals)[k] : one;
+  }
+}
+
+// first position k in [lo, hi) with list[k] >= key (hi if none), found by
+// the wave together: each round probes 64 evenly spaced positions.  Needs
+// all 64 lanes; the list must be sorted for the answer to mean anything,
+// but every probe stays inside [lo, hi) in any case.
+__device__ int64_t wave_lower_bound(const int32_t *list, int64_t lo, int64_t hi, int64_t key) {
+  const int ln = threadIdx.x & 63;
+  while (hi - lo > 64) {
+    // probe f is the first of p_l = lo + l * step at or past the answer (a
+    // probe at or past hi counts as past it); the answer is in (p_{f-1}, p_f]
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t p = lo + ln * step;
+    const bool ge = p >= hi || (int64_t)list[p] >= key;
+    const uint64_t b = __ballot(ge);
+    const int f = b ? __ffsll((unsigned long long)b) - 1 : 64;
+    const int64_t nlo = f == 0 ? lo : lo + (int64_t)(f - 1) * step + 1;
+    const int64_t nhi = f == 64 ? hi : lo + (int64_t)f * step;
+    lo = nlo;
+    hi = nhi < hi ? nhi : hi;
+    if (lo >= hi) return lo;
+  }
+  const int64_t p = lo + ln;
+  const uint64_t b = __ballot(p < hi && (int64_t)list[p] >= key);
+  return b ? lo + (__ffsll((unsigned long long)b) - 1) : hi;
+}
+
+// Sorted list -> presence bitmap: each wave owns 64 consecutive words, finds
+// the list entries that fall in them, ORs their bits in LDS and writes all
+// 64 words (zeros included, so the bitmap needs no clearing first).  With
+// `gated`, returns unless the product pulls.
+__global__ __launch_bounds__(kBlock) void k_list_to_bitmap(const int32_t *list, const int32_t *cnt,
+                                                           int64_t cap, int64_t nw, uint64_t *bm,
+                                                           DirGate gate, bool gated) {
+  __shared__ unsigned long long s_w[kWavesPerBlock][64];
+  if (gated && gate_dir(gate) != GRB_DIR_PULL) return;
+  const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t c = *cnt;
+  c = c < 0 ? 0 : (c > cap ? cap : c);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t w0 = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * 64; w0 < nw; w0 += nwaves * 64) {
+    s_w[wv][ln] = 0ull;
+    wave_lds_sync();
+    const int64_t lo = wave_lower_bound(list, 0, c, w0 * 64);
+    const int64_t hi = wave_lower_bound(list, lo, c, (w0 + 64) * 64);
+    for (int64_t k = lo + ln; k < hi; k += 64) {
+      const int64_t id = list[k];
+      const int64_t off = (id >> 6) - w0;
+      if (off >= 0 && off < 64) atomicOr(&s_w[wv][off], 1ull << (id & 63));
+    }
+    wave_lds_sync();
+    if (w0 + ln < nw) bm[w0 + ln] = s_w[wv][ln];
+    wave_lds_sync();
+  }
+}
+
+// Presence bitmap -> sorted list and count in one workgroup (a setup-time
+// conversion that needs no workspace): 1024 words per round, a block scan of
+// their popcounts places each word's indices.
+__global__ __launch_bounds__(1024) void k_bitmap_to_list_small(const uint64_t *bm, int64_t n,
+                                                               int32_t *list, int32_t *cnt) {
+  const int64_t nw = (n + 63) / 64;
+  __shared__ int s_wave[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int64_t w0 = 0; w0 < nw; w0 += 1024) {
+    const int64_t w = w0 + tid;
+    uint64_t word = w < nw ? bm[w] : 0ull;
+    if (w == nw - 1 && (n & 63)) word &= mask_below((int)(n & 63));  // padding bits
+    const int c = __popcll(word);
+    const int incl = wave_incl_scan(c);
+    if (ln == 63) s_wave[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < 16; ++k) {
+      const int x = s_wave[k];
+      if (k < wv) before += x;
+      total += x;
+    }
+    int pos = s_base + before + incl - c;
+    for (uint64_t x = word; x; x &= x - 1) list[pos++] = (int32_t)(w * 64 + __ffsll((unsigned long long)x) - 1);
+    __syncthreads();
+    if (tid == 0) s_base += total;
+    __syncthreads();
+  }
+  if (tid == 0) *cnt = s_base;
+}
+
+__global__ void k_iota(int32_t *list, int64_t n, int32_t *cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    list[i] = (int32_t)i;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cnt = (int32_t)n;
+}
+
+__global__ void k_gather_values(const unsigned char *values, int elem, const int32_t *list,
+                                const int32_t *cnt, int64_t cap, unsigned char *out) {
+  int64_t c = *cnt;
+  c = c < 0 ? 0 : (c > cap ? cap : c);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < c;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = list[k];
+    if (i < 0 || i >= cap) continue;
+    if (elem == 1) out[k] = values[i];
+    else if (elem == 4) ((uint32_t *)out)[k] = ((const uint32_t *)values)[i];
+    else ((uint64_t *)out)[k] = ((const uint64_t *)values)[i];
   }
 }
 
@@ -275,6 +392,33 @@ void launch_vector_build(uint64_t *bitmap, void *values, int elem_size, int64_t 
   hipLaunchKernelGGL(k_vector_scatter, dim3(grid_for(count, kBlock, 4096)), dim3(kBlock), 0,
                      (hipStream_t)stream, bitmap, (unsigned char *)values, elem_size, n, idx,
                      (const unsigned char *)vals, count, one);
+}
+
+void launch_list_to_bitmap(const int32_t *list, const int32_t *cnt, int64_t n, uint64_t *bm,
+                           void *stream, const DirGate *gate) {
+  const int64_t nw = words_of(n);
+  if (nw <= 0) return;
+  const int g = grid_for(nw, 64 * kWavesPerBlock, 4096);
+  hipLaunchKernelGGL(k_list_to_bitmap, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, list, cnt,
+                     n, nw, bm, gate ? *gate : DirGate(), gate != nullptr);
+}
+
+void launch_bitmap_to_list_small(const uint64_t *bm, int64_t n, int32_t *list, int32_t *cnt,
+                                 void *stream) {
+  hipLaunchKernelGGL(k_bitmap_to_list_small, dim3(1), dim3(1024), 0, (hipStream_t)stream, bm, n,
+                     list, cnt);
+}
+
+void launch_iota(int32_t *list, int64_t n, int32_t *cnt, void *stream) {
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0,
+                     (hipStream_t)stream, list, n, cnt);
+}
+
+void launch_gather_values(const void *values, int elem_size, const int32_t *list,
+                          const int32_t *cnt, int64_t cap, void *out, void *stream) {
+  hipLaunchKernelGGL(k_gather_values, dim3(grid_for(cap, kBlock, 4096)), dim3(kBlock), 0,
+                     (hipStream_t)stream, (const unsigned char *)values, elem_size, list, cnt,
+                     cap, (unsigned char *)out);
 }
 
 }  // namespace grb

@@ -53,10 +53,14 @@ __device__ __forceinline__ int ms_decide(const MsbfsArgs &a, int64_t active, int
 // Writes level d+1 for the new bits of (v, word j) held by each lane:
 // the wave visits every lane with new bits and stores its 64 levels with
 // one coalesced store.
+// In a session the level is relative to the query's start level, and the
+// new bits are ORed into the workgroup's per-word "has a frontier bit"
+// words (s_alive, indexed by word - first word of the pass).
 __device__ __forceinline__ void write_levels(const MsbfsArgs &a, int64_t v, int j,
-                                             uint64_t newbits) {
+                                             uint64_t newbits, unsigned long long *s_alive) {
   const int ln = threadIdx.x & 63;
   uint64_t todo = __ballot(newbits != 0ull);
+  const int j0 = blockIdx.y * a.kt;
   while (todo) {
     const int r = __ffsll((unsigned long long)todo) - 1;
     todo &= todo - 1;
@@ -64,7 +68,9 @@ __device__ __forceinline__ void write_levels(const MsbfsArgs &a, int64_t v, int 
     const int rj = __shfl(j, r);
     const uint64_t nb = __shfl(newbits, r);
     const int64_t q = (int64_t)rj * 64 + ln;
-    if (((nb >> ln) & 1ull) && q < a.k) a.levels[rv * a.k + q] = a.d + 1;
+    if (((nb >> ln) & 1ull) && q < a.k)
+      a.levels[rv * a.k + q] = a.d + 1 - (a.start ? a.start[q] : 0);
+    if (a.alive_nxt && ln == 0) atomicOr(&s_alive[rj - j0], (unsigned long long)nb);
   }
 }
 
@@ -95,7 +101,7 @@ __device__ __forceinline__ uint64_t claim_bits(const MsbfsArgs &a, int64_t v, in
 // claim with atomics like push.
 template <int L>
 __device__ void ms_pull_rows(const MsbfsArgs &a, int *mark, int64_t &act_acc,
-                             int64_t &edges_acc) {
+                             int64_t &edges_acc, unsigned long long *s_alive) {
   constexpr int S = 64 / L;
   const int ln = threadIdx.x & 63;
   const int sl = ln / L, jl = ln % L;
@@ -200,7 +206,7 @@ __device__ void ms_pull_rows(const MsbfsArgs &a, int *mark, int64_t &act_acc,
           anyb = true;
           e_add += a.push.rp[v + 1] - a.push.rp[v];
         }
-        write_levels(a, v, j0 + q, nb);
+        write_levels(a, v, j0 + q, nb, s_alive);
       }
       edges_acc += e_add;
       const uint64_t ab = __ballot(anyb);
@@ -236,18 +242,20 @@ __device__ void ms_pull_rows(const MsbfsArgs &a, int *mark, int64_t &act_acc,
     if (sl == 0 && jv) nb = claim_bits(a, r, j0 + jl, acc & need, ea);
     act_acc += sl == 0 ? __popcll(nb) : 0;
     edges_acc += ea;
-    write_levels(a, sl == 0 ? (int64_t)r : -1, j0 + jl, sl == 0 ? nb : 0ull);
+    write_levels(a, sl == 0 ? (int64_t)r : -1, j0 + jl, sl == 0 ? nb : 0ull, s_alive);
   }
 }
 
-__device__ void ms_pull(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc) {
-  if (a.kt <= 1) ms_pull_rows<1>(a, mark, act_acc, edges_acc);
-  else if (a.kt <= 2) ms_pull_rows<2>(a, mark, act_acc, edges_acc);
-  else if (a.kt <= 4) ms_pull_rows<4>(a, mark, act_acc, edges_acc);
-  else ms_pull_rows<8>(a, mark, act_acc, edges_acc);
+__device__ void ms_pull(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc,
+                        unsigned long long *s_alive) {
+  if (a.kt <= 1) ms_pull_rows<1>(a, mark, act_acc, edges_acc, s_alive);
+  else if (a.kt <= 2) ms_pull_rows<2>(a, mark, act_acc, edges_acc, s_alive);
+  else if (a.kt <= 4) ms_pull_rows<4>(a, mark, act_acc, edges_acc, s_alive);
+  else ms_pull_rows<8>(a, mark, act_acc, edges_acc, s_alive);
 }
 
-__device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc) {
+__device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t &edges_acc,
+                        unsigned long long *s_alive) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -286,7 +294,7 @@ __device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t
           nb = claim_bits(a, tv, j, rf, edges_acc);
           act_acc += __popcll(nb);
         }
-        write_levels(a, tv, j, nb);
+        write_levels(a, tv, j, nb, s_alive);
         if (starts) cur += min(incl, 64) - excl;
       }
     }
@@ -321,7 +329,7 @@ __device__ void ms_push(const MsbfsArgs &a, int *mark, int64_t &act_acc, int64_t
             nb = claim_bits(a, tv, j, fu, edges_acc);
             act_acc += __popcll(nb);
           }
-          write_levels(a, tv, j, nb);
+          write_levels(a, tv, j, nb, s_alive);
         }
       }
     }
@@ -332,7 +340,9 @@ __global__ __launch_bounds__(kBlock) void k_ms_level(MsbfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   __shared__ int64_t s_act, s_edges;
   __shared__ int64_t s_red[kWavesPerBlock][2];
+  __shared__ unsigned long long s_alive[kMsMaxWordsPerPass];
   const bool leader = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+  if (threadIdx.x < kMsMaxWordsPerPass) s_alive[threadIdx.x] = 0ull;
   if (threadIdx.x == 0) {
     int64_t c = 0, e = 0;
     for (int t = 0; t < kCntStripes; ++t) {
@@ -343,6 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_level(MsbfsArgs a) {
     s_edges = e;
     if (leader) {
       for (int i = 0; i < 2 * kCntStripes; ++i) a.cnt_clr[i] = 0;
+      if (a.alive_clr)
+        for (int j = 0; j < a.W; ++j) a.alive_clr[j] = 0ull;
       if (c > 0) {
         a.ctrl->nlev = a.d + 1;
         if (a.stats && a.d < kStatsCap) {
@@ -374,8 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_level(MsbfsArgs a) {
   if (s_act == 0) return;
   const int dir = ms_decide(a, s_act, s_edges);
   int64_t act_acc = 0, edges_acc = 0;
-  if (dir == GRB_DIR_PUSH) ms_push(a, s_mark[threadIdx.x >> 6], act_acc, edges_acc);
-  else ms_pull(a, s_mark[threadIdx.x >> 6], act_acc, edges_acc);
+  if (dir == GRB_DIR_PUSH) ms_push(a, s_mark[threadIdx.x >> 6], act_acc, edges_acc, s_alive);
+  else ms_pull(a, s_mark[threadIdx.x >> 6], act_acc, edges_acc, s_alive);
   act_acc = wave_sum64(act_acc);
   const int64_t ed = wave_sum64(edges_acc);
   if ((threadIdx.x & 63) == 0) {
@@ -383,6 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_level(MsbfsArgs a) {
     s_red[threadIdx.x >> 6][1] = ed;
   }
   __syncthreads();
+  if (a.alive_nxt && threadIdx.x < kMsMaxWordsPerPass) {
+    const int j = blockIdx.y * a.kt + threadIdx.x;
+    const unsigned long long x = s_alive[threadIdx.x];
+    if (x && j < a.W) atomicOr(&a.alive_nxt[j], x);
+  }
   if (threadIdx.x == 0) {
     int64_t c = 0, e = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) {
@@ -419,6 +436,83 @@ __global__ void k_ms_start(MsbfsArgs a, const int32_t *sources, uint64_t *F1, ui
   if (gt == 0) {
     for (int i = 0; i < 6 * kCntStripes; ++i) a.cnt_base[i] = 0;
     a.ctrl->nlev = 0;
+    a.ctrl->error = 0;
+  }
+}
+
+// Session start: every query idle, i.e. all of V set (an idle query has
+// visited everything, so it never claims); frontier blocks, active
+// bitmaps, counters and the three "has a frontier bit" arrays cleared.  The
+// level block is not touched: a query's levels are valid where its V bit is.
+__global__ void k_ms_session_init(MsbfsArgs a, uint64_t *F1, uint64_t *F2, uint64_t *act1,
+                                  uint64_t *act2, unsigned long long *alive3) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nb = a.n * (int64_t)a.W;
+  for (int64_t i = gt; i < nb; i += nt) {
+    a.V[i] = ~0ull;
+    a.F[i] = 0ull;
+    F1[i] = 0ull;
+    F2[i] = 0ull;
+  }
+  for (int64_t i = gt; i < a.nw; i += nt) {
+    a.act[i] = 0ull;
+    act1[i] = 0ull;
+    act2[i] = 0ull;
+  }
+  for (int64_t i = gt; i < 3 * (int64_t)a.W; i += nt) alive3[i] = 0ull;
+  if (gt == 0) {
+    for (int i = 0; i < 6 * kCntStripes; ++i) a.cnt_base[i] = 0;
+    a.ctrl->nlev = 0;
+    a.ctrl->error = 0;
+  }
+}
+
+// Joining queries: their bits cleared in every vertex's V word (clr[j]
+// holds the joining queries of word j)
+__global__ void k_ms_session_clear(MsbfsArgs a, const uint64_t *clr) {
+  const int64_t nb = a.n * (int64_t)a.W;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t m = clr[i % a.W];
+    if (m) a.V[i] &= ~m;
+  }
+}
+
+// ... then each starts at its source at the current level a.d (lanes and
+// sources checked on the host)
+__global__ void k_ms_session_sources(MsbfsArgs a, const int32_t *lanes, const int32_t *sources,
+                                     int32_t count, int32_t *start,
+                                     unsigned long long *alive_cur) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t q = lanes[i], s = sources[i];
+  if (q < 0 || q >= a.k || s < 0 || s >= a.n) return;
+  const int j = (int)(q >> 6);
+  const uint64_t bit = 1ull << (q & 63);
+  atomicOr((unsigned long long *)&a.V[s * a.W + j], (unsigned long long)bit);
+  const uint64_t pf = atomicOr((unsigned long long *)&a.F[s * a.W + j], (unsigned long long)bit);
+  atomicOr((unsigned long long *)&a.act[s >> 6], 1ull << (s & 63));
+  a.levels[s * a.k + q] = 0;
+  start[q] = a.d;
+  atomicOr(&alive_cur[j], (unsigned long long)bit);
+  atomicAdd((unsigned long long *)&a.cnt_cur[0], 1ull);
+  if (pf == 0ull)
+    atomicAdd((unsigned long long *)&a.cnt_cur[1],
+              (unsigned long long)(a.push.rp[s + 1] - a.push.rp[s]));
+}
+
+// out[i * n + v]: level of query lanes[i] at v, -1 where it has not visited v
+__global__ void k_ms_session_extract(MsbfsArgs a, const int32_t *lanes, int32_t count,
+                                     int32_t *out) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    for (int i = 0; i < count; ++i) {
+      const int64_t q = lanes[i];
+      if (q < 0 || q >= a.k) continue;
+      const bool seen = (a.V[v * a.W + (q >> 6)] >> (q & 63)) & 1ull;
+      out[(int64_t)i * a.n + v] = seen ? a.levels[v * a.k + q] : -1;
+    }
   }
 }
 
@@ -427,6 +521,10 @@ __global__ void k_ms_sources(MsbfsArgs a, const int32_t *sources) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= a.k) return;
   const int64_t s = sources[q];
+  if (s < 0 || s >= a.n) {  // reported by the driver; nothing is written for it
+    atomicOr(&a.ctrl->error, 1);
+    return;
+  }
   const int j = (int)(q >> 6);
   const uint64_t bit = 1ull << (q & 63);
   atomicOr((unsigned long long *)&a.V[s * a.W + j], (unsigned long long)bit);
@@ -447,6 +545,31 @@ void launch_msbfs_start(const MsbfsArgs &a, const int32_t *sources, uint64_t *F1
   hipLaunchKernelGGL(k_ms_start, dim3(2048), dim3(256), 0, s, a, sources, F1, F2, act1, act2);
   const int g = (int)((a.k + 255) / 256);
   hipLaunchKernelGGL(k_ms_sources, dim3(g < 1 ? 1 : g), dim3(256), 0, s, a, sources);
+}
+
+void launch_msbfs_session_init(const MsbfsArgs &a, uint64_t *F1, uint64_t *F2, uint64_t *act1,
+                               uint64_t *act2, unsigned long long *alive3, void *stream) {
+  hipLaunchKernelGGL(k_ms_session_init, dim3(2048), dim3(256), 0, (hipStream_t)stream, a, F1, F2,
+                     act1, act2, alive3);
+}
+
+void launch_msbfs_session_join(const MsbfsArgs &a, const int32_t *lanes, const int32_t *sources,
+                               int32_t count, const uint64_t *clr, int32_t *start,
+                               unsigned long long *alive_cur, void *stream) {
+  if (count <= 0) return;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_ms_session_clear, dim3(2048), dim3(256), 0, s, a, clr);
+  hipLaunchKernelGGL(k_ms_session_sources, dim3((count + 255) / 256), dim3(256), 0, s, a, lanes,
+                     sources, count, start, alive_cur);
+}
+
+void launch_msbfs_session_extract(const MsbfsArgs &a, const int32_t *lanes, int32_t count,
+                                  int32_t *out, void *stream) {
+  if (count <= 0 || a.n <= 0) return;
+  int64_t g = (a.n + 255) / 256;
+  g = g > 4096 ? 4096 : g;
+  hipLaunchKernelGGL(k_ms_session_extract, dim3((unsigned)g), dim3(256), 0, (hipStream_t)stream, a,
+                     lanes, count, out);
 }
 
 void launch_msbfs_level(const MsbfsArgs &a, int grid_x, void *stream) {

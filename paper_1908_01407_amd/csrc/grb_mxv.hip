@@ -1,21 +1,28 @@
 // Generic masked semiring products w<mask> = accum(w, A' u) (Section 3.3 of
 // the paper; operand decomposition per its mxv figure), over the closed set
 // of semirings of grb.h, in either direction:
-// * push (SpMSpV): u's presence bitmap is compacted into a sorted list with
-//   degree prefix (the traversal compaction kernel); merge-path tiles over
+// * the first kernel clears the control block and, for the automatic
+//   choice, leaves per-workgroup partials of the input's entry count and
+//   degree sum; every later kernel evaluates the switch rule (Section 4.3.1,
+//   Table 5) from them and returns at once when its direction is not taken,
+//   so the input is compacted only when the product really pushes;
+// * push (SpMSpV): the input as a sorted list with degree prefix (the
+//   compaction kernel for a bitmap input; a list input is used as it is, its
+//   prefix built by a look-back scan over the list); merge-path tiles over
 //   (entries + edges) scatter products into a temporary t with atomic
 //   semiring adds, testing the mask at the scatter; a merge pass applies
 //   accum / mask / REPLACE to w;
-// * pull (masked SpMV, mask first): each wave owns one output bitmap word;
-//   the allowed rows' adjacency is streamed as one concatenated list, 64
-//   entries per step, reduced per row with a segmented scan (fixed order,
-//   so floating-point results repeat bit for bit); LOR_LAND stops a row at
-//   its first true product; rows longer than kHeavyDeg are cut into pieces
-//   whose partial results a fix-up kernel (a wave per long row) combines in
-//   a fixed order.
-// The direction is chosen on the device (forced, or the descriptor's rule
-// on the input's size and degree sum), every kernel of the path not taken
-// returns at once.
+// * pull (masked SpMV, mask first): each wave sweeps a run of output bitmap
+//   words of about equal work (prepared with the matrix); a word without an
+//   allowed non-empty row is finished with word operations; otherwise its
+//   rows up to kPushSplit long are streamed as one concatenated list, 64
+//   positions per step: LOR_LAND pre-checks each row's first two neighbours
+//   and stops a row at its first true product, the other semirings find each
+//   position's row by bisection so that several steps' loads are in flight,
+//   and reduce each row's segments in a fixed order (floating-point results
+//   repeat bit for bit).  Rows longer than kPushSplit are cut into pieces
+//   that any wave takes; a fix-up kernel (a wave per long row) combines a
+//   row's pieces in a fixed order and applies the epilogue.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -31,6 +38,8 @@ template <int SR> struct Sr;
 template <> struct Sr<GRB_LOR_LAND_BOOL> {
   using T = uint8_t;
   static constexpr bool lor = true;
+  __device__ static T identity() { return 0; }
+  __device__ static T add(T a, T b) { return (T)(a || b); }
 };
 template <class V, bool MIN_ADD, bool MUL_PLUS> struct SrArith {
   using T = V;
@@ -87,10 +96,16 @@ __device__ __forceinline__ bool mat_true(const Csr &c, int64_t pos) {
   return ((const double *)c.val)[pos] != 0.0;
 }
 
+// input value of index j (a vector without values holds 1 at every entry)
+template <class T>
+__device__ __forceinline__ T u_at(const MxvArgs &a, int64_t j) {
+  return a.u_val ? ((const T *)a.u_val)[j] : (T)1;
+}
+
 __device__ __forceinline__ bool mask_allowed(const MxvArgs &a, int64_t i) {
   if (!a.has_mask) return true;
   bool m = bit_of(a.m_bm, i);
-  if (m && !a.mask_struct) {
+  if (m && !a.mask_struct && a.m_val) {
     switch (a.m_type) {
       case GRB_BOOL: m = ((const uint8_t *)a.m_val)[i] != 0; break;
       case GRB_INT32: m = ((const int32_t *)a.m_val)[i] != 0; break;
@@ -101,15 +116,15 @@ __device__ __forceinline__ bool mask_allowed(const MxvArgs &a, int64_t i) {
   return m != a.mask_comp;
 }
 
-__device__ __forceinline__ int mxv_dir(const MxvArgs &a) {
-  if (a.forced) return a.forced;
-  if (!a.can_pull) return GRB_DIR_PUSH;
-  if (!a.can_push) return GRB_DIR_PULL;
-  const int count = a.ctrl->count, sumdeg = a.ctrl->sumdeg;
-  const bool pull = a.rule == GRB_SWITCH_EXACT ? (int64_t)a.denom * sumdeg > a.nnz
-                                               : (int64_t)a.denom * count > a.n_in;
-  return pull ? GRB_DIR_PULL : GRB_DIR_PUSH;
+// the mask as one word operation (no mask, structural mask, or a mask
+// without values); `word_mask` says whether that form applies
+__device__ __forceinline__ uint64_t allowed_word(const MxvArgs &a, int64_t wd) {
+  if (!a.has_mask) return ~0ull;
+  const uint64_t m = a.m_bm[wd];
+  return a.mask_comp ? ~m : m;
 }
+
+__device__ __forceinline__ int mxv_dir(const MxvArgs &a) { return gate_dir(a.gate); }
 
 // z / mask / REPLACE for one output index; returns whether w(i) is present
 // afterwards and its value in *out.
@@ -141,16 +156,189 @@ __device__ __forceinline__ bool epilogue(const MxvArgs &a, int64_t i, bool allow
   return true;
 }
 
-__global__ void k_mxv_init(MxvArgs a) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = gt; i < 2 * (int64_t)a.nblk; i += (int64_t)gridDim.x * blockDim.x)
-    a.status[i] = 0ull;
-  // the control block (a few KB) cleared by the first workgroup's threads
-  // together, 8 bytes each (all its fields are zero when cleared)
-  static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is cleared in 8-byte words");
-  if (blockIdx.x == 0)
-    for (int k = threadIdx.x; k < (int)(sizeof(Ctrl) / 8); k += blockDim.x)
+// ---- first kernel: control block, direction partials ------------------------
+template <int SR>
+__global__ __launch_bounds__(kMxvPartThreads) void k_mxv_init(MxvArgs a) {
+  __shared__ int64_t s_c[kMxvPartThreads / 64], s_d[kMxvPartThreads / 64];
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+  if (blockIdx.x == 0) {
+    // the control block (a few KB, every field zero when cleared) and the
+    // look-back status words of the compactions and the list preparation
+    static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is cleared in 8-byte words");
+    for (int k = tid; k < (int)(sizeof(Ctrl) / 8); k += blockDim.x)
       reinterpret_cast<uint64_t *>(a.ctrl)[k] = 0ull;
+  }
+  for (int64_t i = gt; i < 2 * (int64_t)a.nblk; i += nthr) a.status[i] = 0ull;
+  for (int64_t i = gt; i < 2 * (int64_t)a.nblk_out; i += nthr) a.status_out[i] = 0ull;
+  for (int64_t i = gt; i < (int64_t)a.nblk_list; i += nthr) a.status_list[i] = 0ull;
+  // the OR push's temporary bitmaps (other semirings clear theirs only
+  // when they push: their value array is n elements)
+  if (Sr<SR>::lor && a.gate.can_push && a.gate.forced != GRB_DIR_PULL)
+    for (int64_t i = gt; i < a.nw_out; i += nthr) {
+      a.t_bm[i] = 0ull;
+      a.t_vb[i] = 0ull;
+    }
+  if (a.gate.forced || !a.gate.can_push || !a.gate.can_pull) return;
+  // partials of the input's entry count and degree sum (rows of the push CSR)
+  const bool exact = a.gate.rule == GRB_SWITCH_EXACT;
+  const int32_t *rp = a.push.rp;
+  int64_t c = 0, d = 0;
+  if (a.u_list) {
+    int64_t cnt = *a.u_cnt;
+    cnt = cnt < 0 ? 0 : (cnt > a.n_in ? a.n_in : cnt);
+    if (gt == 0) c = cnt;
+    if (exact)
+      for (int64_t k = gt; k < cnt; k += nthr) {
+        const int64_t v = a.u_list[k];
+        if (v >= 0 && v < a.n_in) d += rp[v + 1] - rp[v];
+      }
+  } else if (!exact) {
+    for (int64_t w = gt; w < a.nw_in; w += nthr) c += __popcll(a.u_bm[w]);
+  } else {
+    // a wave per word (lane = row), four words in flight
+    const int64_t gwv = gt >> 6, nwv = nthr >> 6;
+    for (int64_t w0 = gwv; w0 < a.nw_in; w0 += 4 * nwv) {
+      uint64_t word[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t w = w0 + q * nwv;
+        word[q] = w < a.nw_in ? a.u_bm[w] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t v = (w0 + q * nwv) * 64 + ln;
+        if (((word[q] >> ln) & 1ull) && v < a.n_in) {
+          c += 1;
+          d += rp[v + 1] - rp[v];
+        }
+      }
+    }
+  }
+  c = wave_sum64(c);
+  d = wave_sum64(d);
+  if (ln == 0) {
+    s_c[wv] = c;
+    s_d[wv] = d;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int64_t tc = 0, td = 0;
+    for (int k = 0; k < kMxvPartThreads / 64; ++k) {
+      tc += s_c[k];
+      td += s_d[k];
+    }
+    a.part[2 * blockIdx.x] = tc;
+    a.part[2 * blockIdx.x + 1] = td;
+  }
+}
+
+// ---- push -------------------------------------------------------------------
+
+// A list input's degree prefix, row starts and merge-path tile starts (what
+// the compaction produces for a bitmap input), by a decoupled look-back over
+// chunks of kListChunk entries; workgroups are ordered by ticket.
+constexpr int kListPer = kMxvListChunk / kCompactThreads;
+constexpr int kListChunk = kMxvListChunk;
+constexpr uint64_t kStAgg = 1, kStPre = 2;
+
+__global__ __launch_bounds__(kCompactThreads) void k_mxv_list_prep(MxvArgs a) {
+  constexpr int NWV = kCompactThreads / 64;
+  __shared__ int s_blk;
+  __shared__ int64_t s_wsum[NWV];
+  __shared__ int64_t s_base;
+  if (mxv_dir(a) != GRB_DIR_PUSH) return;
+  const int tid = threadIdx.x, wid = tid >> 6, ln = tid & 63;
+  int64_t cnt = *a.u_cnt;
+  cnt = cnt < 0 ? 0 : (cnt > a.n_in ? a.n_in : cnt);
+  // exactly the first ceil(cnt / kListChunk) workgroups take tickets, so the
+  // chunks are covered and every workgroup a look-back waits on is running
+  if ((int64_t)blockIdx.x * kListChunk >= cnt) return;
+  if (tid == 0) s_blk = atomicAdd(&a.ctrl->ticket_list, 1);
+  __syncthreads();
+  const int blk = s_blk;
+  const int64_t k0 = (int64_t)blk * kListChunk;
+  const int32_t *rp = a.push.rp;
+  int deg[kListPer], rs[kListPer];
+  int64_t tsum = 0;
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    const int64_t k = k0 + (int64_t)tid * kListPer + j;
+    deg[j] = 0;
+    rs[j] = 0;
+    if (k < cnt) {
+      const int64_t v = a.u_list[k];
+      if (v >= 0 && v < a.n_in) {
+        rs[j] = rp[v];
+        deg[j] = rp[v + 1] - rs[j];
+      }
+    }
+    tsum += deg[j];
+  }
+  // block scan of the threads' degree sums
+  int64_t incl = tsum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(incl, off);
+    if (ln >= off) incl += y;
+  }
+  if (ln == 63) s_wsum[wid] = incl;
+  __syncthreads();
+  int64_t before = 0, btot = 0;
+  for (int k = 0; k < NWV; ++k) {
+    if (k < wid) before += s_wsum[k];
+    btot += s_wsum[k];
+  }
+  if (wid == 0) {
+    // status word: flag (2 bits) | degree sum (62 bits)
+    int64_t ed = 0;
+    if (blk > 0) {
+      if (ln == 0)
+        store_relaxed_u64(&a.status_list[blk], (kStAgg << 62) | (uint64_t)btot);
+      for (int jhi = blk - 1;; jhi -= 64) {
+        const int j = jhi - ln;
+        uint64_t st = kStPre << 62;
+        if (j >= 0) {
+          do { st = load_relaxed_u64(&a.status_list[j]); } while ((st >> 62) == 0);
+        }
+        const uint64_t pre = __ballot((st >> 62) == kStPre);
+        const int f = pre ? (__ffsll((unsigned long long)pre) - 1) : 64;
+        ed += wave_sum64(ln <= f ? (int64_t)(st & ((1ull << 62) - 1)) : 0);
+        if (pre) break;
+      }
+    }
+    if (ln == 0) {
+      store_relaxed_u64(&a.status_list[blk], (kStPre << 62) | (uint64_t)(ed + btot));
+      s_base = ed;
+      if (k0 + kListChunk >= cnt) {  // the workgroup holding the list's end
+        const int64_t sd = ed + btot;
+        const int64_t nt = (cnt + sd + kPushTile - 1) / kPushTile;
+        // a list with repeated indices can exceed the tile capacity: then it
+        // contributes nothing (its result is undefined, memory stays safe)
+        const bool fits = nt < a.tiles_cap && sd <= a.nnz;
+        a.ctrl->count = fits ? (int)cnt : 0;
+        a.ctrl->sumdeg = fits ? (int)sd : 0;
+        a.ctrl->ntiles = fits ? (int)nt : 0;
+        if (fits) a.tiles[nt] = (int)(cnt - 1);
+      }
+    }
+  }
+  __syncthreads();
+  int64_t dex = s_base + before + incl - tsum;
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    const int64_t k = k0 + (int64_t)tid * kListPer + j;
+    if (k < cnt) {
+      a.degpre[k] = (int)dex;
+      a.rowstart[k] = rs[j];
+      const int64_t s0 = dex + k, s1 = s0 + deg[j];
+      for (int64_t t = (s0 + kPushTile - 1) / kPushTile; t * kPushTile <= s1 && t < a.tiles_cap;
+           ++t)
+        a.tiles[t] = (int)k;
+    }
+    dex += deg[j];
+  }
 }
 
 template <int SR>
@@ -165,10 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_mxv_prep(MxvArgs a) {
       a.t_bm[w] = 0ull;
       a.t_vb[w] = 0ull;
     }
-    if constexpr (!Sr<SR>::lor) {
-      const int64_t i = w * 64 + ln;
-      if (i < a.n_out) ((T *)a.t_val)[i] = Sr<SR>::identity();
-    }
+    const int64_t i = w * 64 + ln;
+    if (i < a.n_out) ((T *)a.t_val)[i] = Sr<SR>::identity();
   }
 }
 
@@ -179,7 +365,6 @@ __global__ __launch_bounds__(kBlock) void k_mxv_push(MxvArgs a) {
   __shared__ T s_val[kPushTile + 1];
   if (mxv_dir(a) != GRB_DIR_PUSH) return;
   const int ntiles = a.ctrl->ntiles, sumdeg = a.ctrl->sumdeg;
-  const T *uv = (const T *)a.u_val;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int i0 = a.tiles[t], i1 = a.tiles[t + 1];
     const int ne = i1 - i0 + 1;
@@ -187,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_mxv_push(MxvArgs a) {
       const int j = a.list[i0 + k];
       s_deg[k] = a.degpre[i0 + k];
       s_rs[k] = a.rowstart[i0 + k];
-      s_val[k] = uv[j];
+      s_val[k] = (j >= 0 && j < a.n_in) ? u_at<T>(a, j) : (T)0;
     }
     __syncthreads();
     const int64_t e0 = (int64_t)t * kPushTile - i0;
@@ -275,203 +460,277 @@ __global__ __launch_bounds__(kBlock) void k_mxv_merge(MxvArgs a) {
   }
 }
 
+// ---- pull -------------------------------------------------------------------
+
+// The 64 rows of output word wd: rows up to kPushSplit long are computed
+// here; allowed longer rows are left to the fix-up kernel (their bits of
+// the output word are kept).
 template <int SR>
-__global__ __launch_bounds__(kBlock) void k_mxv_pull(MxvArgs a) {
+__device__ void pull_word(const MxvArgs &a, int64_t wd, int *mark, int *s_end, int *s_base) {
   using T = typename Sr<SR>::T;
-  __shared__ int s_mark[kWavesPerBlock][64];
-  if (mxv_dir(a) != GRB_DIR_PULL) return;
-  int *mark = s_mark[threadIdx.x >> 6];
   const int ln = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t *rp = a.pull.rp, *ci = a.pull.ci;
-  const T *uv = (const T *)a.u_val;
   T *w = (T *)a.w_val;
-  for (int64_t wd = gw; wd < a.nw_out; wd += nwaves) {
-    const int64_t i = wd * 64 + ln;
-    const bool inb = i < a.n_out;
-    const bool allowed = inb && mask_allowed(a, i);
-    int cur = 0, end = 0;
-    bool heavy = false;
-    if (allowed) {
-      cur = rp[i];
-      end = rp[i + 1];
-      heavy = end - cur > kHeavyDeg;
-    }
-    const bool act = allowed && !heavy;
-    T acc;
-    if constexpr (Sr<SR>::lor) acc = 0;
-    else acc = Sr<SR>::identity();
-    bool has = false;
-    int cmin = 1 << 30;  // positions a row takes per step when rows are many
-    if constexpr (Sr<SR>::lor) {
-      // OR: the first two neighbours of every allowed row first (one row
-      // per lane, from the prepared first-two array), so that rows settled
-      // by them never stream; the stream below starts after them
-      bool q0 = false, q1 = false, p0 = false, p1 = false;
-      if (act) {
-        const int2 f = a.pull.first2[i];
-        q0 = f.x >= 0;
-        q1 = f.y >= 0;
-        p0 = q0 && bit_of(a.u_bm, f.x);
-        p1 = q1 && bit_of(a.u_bm, f.y);
-        if (p0 || p1) has = true;
-        if ((p0 && uv[f.x] != 0 && mat_true(a.pull, cur)) ||
-            (p1 && uv[f.y] != 0 && mat_true(a.pull, cur + 1)))
-          acc = 1;
-        cur = min(cur + 2, end);
-      }
-      // the probes' hit rate estimates the frontier's density d; a row
-      // then streams about 2/d positions per step (its first frontier
-      // entry is expected 1/d in), so that a dense frontier does not
-      // gather the entries past the first
-      const int np = __popcll(__ballot(q0)) + __popcll(__ballot(q1));
-      const int nh = __popcll(__ballot(p0)) + __popcll(__ballot(p1));
-      cmin = nh == 0 ? 64 : min(64, max(4, 2 * np / nh));
-    }
-    // kU steps of 64 stream positions are laid out first, then all their
-    // loads issue together; products are reduced step by step in order.
-    // OR takes one step at a time: a row stops at its first true product,
-    // and larger batches would scan past it
-    constexpr int kU = Sr<SR>::lor ? 1 : kUnroll;
-    for (bool more = true; more;) {
-      bool live = act;
-      if constexpr (Sr<SR>::lor) live = live && acc == 0;  // OR saturates at true
-      int64_t pos[kU];
-      int row[kU], sev[kU], exv[kU];
-      bool st[kU];
-#pragma unroll
-      for (int s = 0; s < kU; ++s) {
-        pos[s] = -1;
-        row[s] = 0;
-        sev[s] = 0;
-        exv[s] = 0;
-        st[s] = false;
-        if (!more) continue;
-        int len = live ? end - cur : 0;
-        if (Sr<SR>::lor && cmin < 64) {  // (a step holds 64 positions anyway)
-          // at least a full step between the live rows
-          const int nl = __popcll(__ballot(len > 0));
-          len = min(len, max(cmin, nl ? (64 + nl - 1) / nl : 64));
-        }
-        const int incl = wave_incl_scan(len);
-        const int total = lane_last(incl);
-        if (total == 0) {
-          more = false;
-          continue;
-        }
-        const int excl = incl - len;
-        const bool starts = len > 0 && excl < 64;
-        const int r = slot_rows(mark, starts, excl);
-        const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
-        if (ln < total) pos[s] = rcur + (ln - rexcl);
-        row[s] = r;
-        st[s] = starts;
-        sev[s] = min(incl, 64);
-        exv[s] = excl;
-        if (starts) cur += sev[s] - excl;
-      }
-      int jv[kU];
-#pragma unroll
-      for (int s = 0; s < kU; ++s) jv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
-      bool pres[kU];
-#pragma unroll
-      for (int s = 0; s < kU; ++s) pres[s] = jv[s] >= 0 && bit_of(a.u_bm, jv[s]);
-      T prod[kU];
-#pragma unroll
-      for (int s = 0; s < kU; ++s) {
-        if constexpr (Sr<SR>::lor) {
-          prod[s] = pres[s] ? (T)(uv[jv[s]] != 0 && mat_true(a.pull, pos[s])) : (T)0;
-        } else {
-          prod[s] = pres[s] ? Sr<SR>::mul(mat_value<T>(a.pull, pos[s]), uv[jv[s]], a.pick_vec)
-                            : Sr<SR>::identity();
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < kU; ++s) {
-        const uint64_t seg = st[s] ? (mask_below(sev[s]) & ~mask_below(exv[s])) : 0ull;
-        const uint64_t pm = __ballot(pres[s]);
-        if constexpr (Sr<SR>::lor) {
-          const uint64_t tm = __ballot(prod[s] != 0);
-          if (pm & seg) has = true;
-          if (tm & seg) acc = 1;
-        } else {
-          const T x = wave_seg_scan(prod[s], row[s], Sr<SR>::identity(), SrAdd<SR>());
-          const T segv = __shfl(x, st[s] ? sev[s] - 1 : 0);
-          if (pm & seg) {
-            has = true;
-            acc = Sr<SR>::add(acc, segv);
-          }
-        }
-      }
-    }
-    bool out_has = false;
-    if (inb && !heavy) {
-      T out = acc;
-      out_has = epilogue<SR>(a, i, allowed, has, acc, &out);
-      if (out_has) w[i] = out;
-    }
-    const uint64_t hmask = __ballot(heavy);
-    const uint64_t bits = __ballot(out_has);
-    if (ln == 0) a.w_bm[wd] = (bits & ~hmask) | (a.w_bm[wd] & hmask);
+  const int64_t i = wd * 64 + ln;
+  const bool inb = i < a.n_out;
+  const bool allowed = inb && mask_allowed(a, i);
+  int cur = 0, end = 0;
+  bool lng = false;
+  if (allowed) {
+    cur = rp[i];
+    end = rp[i + 1];
+    lng = end - cur > kPushSplit;
   }
-  // pieces of long rows: partial results, combined in piece order later
-  T *hv = (T *)a.hp_val;
-  for (int64_t h = gw; h < a.pull.nheavy; h += nwaves) {
-    const int r = a.pull.heavy[2 * h], b = a.pull.heavy[2 * h + 1];
-    bool pres_any = false;
-    T acc;
-    if constexpr (Sr<SR>::lor) acc = 0;
-    else acc = Sr<SR>::identity();
-    if (mask_allowed(a, r)) {
-      const int e = min(b + kHeavyChunk, rp[r + 1]);
-      bool done = false;
-      for (int base = b; base < e && !done; base += 64 * kUnroll) {
-        int jv[kUnroll];
+  const bool act = allowed && !lng && end > cur;
+  T acc = Sr<SR>::identity();
+  bool has = false;
+  if constexpr (Sr<SR>::lor) {
+    // first two neighbours of every allowed row first (prepared first-two
+    // array), so that rows settled by them never stream
+    bool q0 = false, q1 = false, p0 = false, p1 = false;
+    if (act) {
+      const int2 f = a.pull.first2[i];
+      q0 = f.x >= 0;
+      q1 = f.y >= 0;
+      p0 = q0 && bit_of(a.u_bm, f.x);
+      p1 = q1 && bit_of(a.u_bm, f.y);
+      if (p0 || p1) has = true;
+      if ((p0 && u_at<T>(a, f.x) != 0 && mat_true(a.pull, cur)) ||
+          (p1 && u_at<T>(a, f.y) != 0 && mat_true(a.pull, cur + 1)))
+        acc = 1;
+      cur = min(cur + 2, end);
+    }
+    // the probes' hit rate estimates the frontier's density d; a row then
+    // streams about 2/d positions per step (its first frontier entry is
+    // expected 1/d in), so a dense frontier does not gather past the first
+    const int np = __popcll(__ballot(q0)) + __popcll(__ballot(q1));
+    const int nh = __popcll(__ballot(p0)) + __popcll(__ballot(p1));
+    const int cmin = nh == 0 ? 64 : min(64, max(4, 2 * np / nh));
+    for (;;) {
+      int len = (act && acc == 0) ? end - cur : 0;  // OR saturates at true
+      if (cmin < 64) {
+        const int nl = __popcll(__ballot(len > 0));
+        len = min(len, max(cmin, nl ? (64 + nl - 1) / nl : 64));
+      }
+      const int incl = wave_incl_scan(len);
+      const int total = lane_last(incl);
+      if (total == 0) break;
+      const int excl = incl - len;
+      const bool starts = len > 0 && excl < 64;
+      const int r = slot_rows(mark, starts, excl);
+      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+      const int64_t pos = ln < total ? rcur + (ln - rexcl) : -1;
+      const int sev = min(incl, 64);
+      if (starts) cur += sev - excl;
+      const int j = pos >= 0 ? ci[pos] : -1;
+      const bool pres = j >= 0 && bit_of(a.u_bm, j);
+      const bool prod = pres && u_at<T>(a, j) != 0 && mat_true(a.pull, pos);
+      const uint64_t seg = starts ? (mask_below(sev) & ~mask_below(excl)) : 0ull;
+      if (__ballot(pres) & seg) has = true;
+      if (__ballot(prod) & seg) acc = 1;
+    }
+  } else {
+    // the word's rows as one list of `total` positions; each position finds
+    // its row by bisection of the rows' prefix ends (LDS), so the loads of
+    // kUnroll steps are in flight together; each row adds its segment of a
+    // step in step order (fixed order)
+    const int len = act ? end - cur : 0;
+    const int incl = wave_incl_scan(len);
+    const int total = lane_last(incl);
+    const int excl = incl - len;
+    s_end[ln] = incl;
+    s_base[ln] = cur - excl;
+    wave_lds_sync();
+    for (int q0 = 0; q0 < total; q0 += 64 * kUnroll) {
+      int row[kUnroll];
+      int64_t pos[kUnroll];
 #pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-          const int64_t pos = base + s * 64 + ln;
-          jv[s] = pos < e ? ci[pos] : -1;
+      for (int s = 0; s < kUnroll; ++s) {
+        const int q = q0 + s * 64 + ln;
+        row[s] = -1;
+        pos[s] = -1;
+        if (q < total) {
+          int r = 0;
+#pragma unroll
+          for (int step = 32; step >= 1; step >>= 1)
+            if (s_end[r + step - 1] <= q) r += step;
+          row[s] = r;
+          pos[s] = (int64_t)s_base[r] + q;
         }
-        bool pres[kUnroll];
+      }
+      int jv[kUnroll];
 #pragma unroll
-        for (int s = 0; s < kUnroll; ++s) pres[s] = jv[s] >= 0 && bit_of(a.u_bm, jv[s]);
+      for (int s = 0; s < kUnroll; ++s) jv[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+      bool pres[kUnroll];
 #pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-          const int64_t pos = base + s * 64 + ln;
-          T prod;
-          if constexpr (Sr<SR>::lor) {
-            prod = pres[s] ? (T)(uv[jv[s]] != 0 && mat_true(a.pull, pos)) : (T)0;
-          } else {
-            prod = pres[s] ? Sr<SR>::mul(mat_value<T>(a.pull, pos), uv[jv[s]], a.pick_vec)
-                           : Sr<SR>::identity();
-          }
-          if (__ballot(pres[s])) pres_any = true;
-          if constexpr (Sr<SR>::lor) {
-            if (!done && __ballot(prod != 0)) {
-              acc = 1;
-              done = true;
-            }
-          } else {
-            T x = prod;
+      for (int s = 0; s < kUnroll; ++s) pres[s] = jv[s] >= 0 && bit_of(a.u_bm, jv[s]);
+      T prod[kUnroll];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) x = Sr<SR>::add(x, __shfl_xor(x, off));
-            acc = Sr<SR>::add(acc, x);
-          }
+      for (int s = 0; s < kUnroll; ++s)
+        prod[s] = pres[s] ? Sr<SR>::mul(mat_value<T>(a.pull, pos[s]), u_at<T>(a, jv[s]), a.pick_vec)
+                          : Sr<SR>::identity();
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const int sb = q0 + s * 64;
+        const T y = wave_seg_scan(prod[s], row[s], Sr<SR>::identity(), SrAdd<SR>());
+        const uint64_t pm = __ballot(pres[s]);
+        // this lane's row: its part of step s and the lane holding its end
+        const int lo = max(excl, sb) - sb, hi = min(incl, sb + 64) - sb;
+        const bool mine = len > 0 && lo < hi;
+        const T segv = __shfl(y, mine ? hi - 1 : 0);
+        if (mine && (pm & mask_below(hi) & ~mask_below(lo))) {
+          has = true;
+          acc = Sr<SR>::add(acc, segv);
         }
       }
     }
-    if (ln == 0) {
-      hv[h] = acc;
-      a.hp_has[h] = pres_any ? 1 : 0;
+    wave_lds_sync();
+  }
+  bool out_has = false;
+  if (inb && !(allowed && lng)) {
+    T out = acc;
+    out_has = epilogue<SR>(a, i, allowed, has, acc, &out);
+    if (out_has) w[i] = out;
+  }
+  const uint64_t lmask = __ballot(allowed && lng);
+  const uint64_t bits = __ballot(out_has);
+  if (ln == 0) a.w_bm[wd] = (bits & ~lmask) | (a.w_bm[wd] & lmask);
+}
+
+// One piece (positions [b, e), at most kPushSplit = 64 * kUnroll) of a long
+// row, reduced by the wave in a fixed order; every lane gets the result.
+template <int SR>
+__device__ __forceinline__ void pull_piece(const MxvArgs &a, int64_t b, int64_t e,
+                                           typename Sr<SR>::T &acc, bool &has) {
+  using T = typename Sr<SR>::T;
+  const int ln = threadIdx.x & 63;
+  const int32_t *ci = a.pull.ci;
+  acc = Sr<SR>::identity();
+  has = false;
+  if constexpr (Sr<SR>::lor) {
+    // the first step alone (a dense frontier ends the piece there), then
+    // the rest at once
+    {
+      const int64_t pos = b + ln;
+      const int j = pos < e ? ci[pos] : -1;
+      const bool pres = j >= 0 && bit_of(a.u_bm, j);
+      has = __ballot(pres) != 0ull;
+      if (__ballot(pres && u_at<T>(a, j) != 0 && mat_true(a.pull, pos))) {
+        acc = 1;
+        return;
+      }
+    }
+    int jv[kUnroll - 1];
+#pragma unroll
+    for (int s = 1; s < kUnroll; ++s) {
+      const int64_t pos = b + s * 64 + ln;
+      jv[s - 1] = pos < e ? ci[pos] : -1;
+    }
+    bool pres[kUnroll - 1], tru[kUnroll - 1];
+#pragma unroll
+    for (int s = 1; s < kUnroll; ++s) {
+      const int64_t pos = b + s * 64 + ln;
+      pres[s - 1] = jv[s - 1] >= 0 && bit_of(a.u_bm, jv[s - 1]);
+      tru[s - 1] = pres[s - 1] && u_at<T>(a, jv[s - 1]) != 0 && mat_true(a.pull, pos);
+    }
+#pragma unroll
+    for (int s = 0; s < kUnroll - 1; ++s) {
+      if (__ballot(pres[s])) has = true;
+      if (__ballot(tru[s])) acc = 1;
+    }
+  } else {
+    int jv[kUnroll];
+#pragma unroll
+    for (int s = 0; s < kUnroll; ++s) {
+      const int64_t pos = b + s * 64 + ln;
+      jv[s] = pos < e ? ci[pos] : -1;
+    }
+    bool pres[kUnroll];
+#pragma unroll
+    for (int s = 0; s < kUnroll; ++s) pres[s] = jv[s] >= 0 && bit_of(a.u_bm, jv[s]);
+#pragma unroll
+    for (int s = 0; s < kUnroll; ++s) {
+      const int64_t pos = b + s * 64 + ln;
+      const T prod = pres[s] ? Sr<SR>::mul(mat_value<T>(a.pull, pos), u_at<T>(a, jv[s]),
+                                           a.pick_vec)
+                             : Sr<SR>::identity();
+      if (__ballot(pres[s])) has = true;
+      acc = Sr<SR>::add(acc, lane_last(wave_scan(prod, Sr<SR>::identity(), SrAdd<SR>())));
     }
   }
 }
 
-// One wave per long row: lane l combines the pieces l, l + 64, ... in order,
-// then the lanes' results are combined in a fixed order.
 template <int SR>
-__global__ __launch_bounds__(kBlock) void k_mxv_pull_fixup(MxvArgs a) {
+__global__ __launch_bounds__(kBlock) void k_mxv_sweep(MxvArgs a) {
+  using T = typename Sr<SR>::T;
+  __shared__ int s_mark[kWavesPerBlock][64];
+  __shared__ int s_end[kWavesPerBlock][64];
+  __shared__ int s_base[kWavesPerBlock][64];
+  if (mxv_dir(a) != GRB_DIR_PULL) return;
+  const int wid = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wid;
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  // the mask as a word operation: none, structural, or without values
+  const bool word_mask = !a.has_mask || a.mask_struct || !a.m_val;
+  for (int64_t part = gw; part < kWaveParts; part += nwaves) {
+    const int64_t wlo = a.pull.wpart[part], whi = a.pull.wpart[part + 1];
+    for (int64_t w0 = wlo; w0 < whi; w0 += 64) {
+      // 64 words at once: a word without an allowed row that has entries
+      // gets no product, so its output word is a word operation
+      const int64_t mw = w0 + ln;
+      bool rows = false;
+      if (mw < whi) {
+        if (word_mask) {
+          const uint64_t allow = allowed_word(a, mw);
+          if ((allow & ~a.pull.iso[mw]) == 0ull) {
+            const uint64_t old = a.w_bm[mw];
+            const uint64_t nb = (allow & (a.accum != GRB_NOACCUM ? old : 0ull)) |
+                                (~allow & (a.replace ? 0ull : old));
+            if (nb != old) a.w_bm[mw] = nb;
+          } else {
+            rows = true;
+          }
+        } else {
+          rows = true;
+        }
+      }
+      for (uint64_t todo = __ballot(rows); todo; todo &= todo - 1) {
+        const int k = __ffsll((unsigned long long)todo) - 1;
+        pull_word<SR>(a, w0 + k, s_mark[wid], s_end[wid], s_base[wid]);
+      }
+    }
+  }
+  // pieces of the allowed long rows: partial results, combined in piece
+  // order by the fix-up kernel; lane l of a wave holds piece hb + l * nwaves
+  T *hv = (T *)a.hp_val;
+  for (int64_t hb = gw; hb < a.pull.nsplit; hb += 64 * nwaves) {
+    const int64_t h = hb + (int64_t)ln * nwaves;
+    int64_t r = -1, b = 0;
+    if (h < a.pull.nsplit) {
+      r = a.pull.split[2 * h];
+      b = a.pull.split[2 * h + 1];
+      if (!mask_allowed(a, r)) r = -1;
+    }
+    for (uint64_t todo = __ballot(r >= 0); todo; todo &= todo - 1) {
+      const int k = __ffsll((unsigned long long)todo) - 1;
+      const int64_t rk = __shfl(r, k), bk = __shfl(b, k);
+      const int64_t ek = min(bk + (int64_t)kPushSplit, (int64_t)a.pull.rp[rk + 1]);
+      T acc;
+      bool has;
+      pull_piece<SR>(a, bk, ek, acc, has);
+      if (ln == 0) {
+        const int64_t hk = hb + (int64_t)k * nwaves;
+        hv[hk] = acc;
+        a.hp_has[hk] = has ? 1 : 0;
+      }
+    }
+  }
+}
+
+// One wave per allowed long row: lane l combines the pieces l, l + 64, ...
+// in order, then the lanes' results are combined in a fixed order.
+template <int SR>
+__global__ __launch_bounds__(kBlock) void k_mxv_fixup(MxvArgs a) {
   using T = typename Sr<SR>::T;
   if (mxv_dir(a) != GRB_DIR_PULL) return;
   const T *hv = (const T *)a.hp_val;
@@ -479,29 +738,22 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull_fixup(MxvArgs a) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t k = gw; k < a.pull.nheavy_rows; k += nwaves) {
-    const int r = a.pull.heavy_rows[3 * k], first = a.pull.heavy_rows[3 * k + 1],
-              cnt = a.pull.heavy_rows[3 * k + 2];
-    T acc;
-    if constexpr (Sr<SR>::lor) acc = 0;
-    else acc = Sr<SR>::identity();
+  for (int64_t k = gw; k < a.pull.nsplit_rows; k += nwaves) {
+    const int r = a.pull.split_rows[3 * k], first = a.pull.split_rows[3 * k + 1],
+              cnt = a.pull.split_rows[3 * k + 2];
+    if (!mask_allowed(a, r)) continue;  // the sweep wrote this row
+    T acc = Sr<SR>::identity();
     bool has = false;
     for (int p = ln; p < cnt; p += 64) {
       if (!a.hp_has[first + p]) continue;
       has = true;
-      if constexpr (Sr<SR>::lor) acc = (T)(acc || hv[first + p]);
-      else acc = Sr<SR>::add(acc, hv[first + p]);
+      acc = Sr<SR>::add(acc, hv[first + p]);
     }
     has = __ballot(has) != 0ull;
-    if constexpr (Sr<SR>::lor) {
-      acc = (T)(__ballot(acc != 0) != 0ull);
-    } else {
-      acc = lane_last(wave_scan(acc, Sr<SR>::identity(), SrAdd<SR>()));
-    }
+    acc = lane_last(wave_scan(acc, Sr<SR>::identity(), SrAdd<SR>()));
     if (ln == 0) {
-      const bool allowed = mask_allowed(a, r);
       T out = acc;
-      const bool out_has = epilogue<SR>(a, r, allowed, has, acc, &out);
+      const bool out_has = epilogue<SR>(a, r, true, has, acc, &out);
       const unsigned long long bit = 1ull << (r & 63);
       if (out_has) {
         w[r] = out;
@@ -515,36 +767,44 @@ __global__ __launch_bounds__(kBlock) void k_mxv_pull_fixup(MxvArgs a) {
 
 template <int SR>
 void run_mxv(const MxvArgs &a, hipStream_t s) {
-  // per-word kernels: one output word per wave (each word is a dependent
-  // chain of loads, so the words run side by side)
   const int gw_out = (int)std::max<int64_t>(
       1, std::min<int64_t>((a.nw_out + kWavesPerBlock - 1) / kWavesPerBlock, 1 << 16));
-  hipLaunchKernelGGL(k_mxv_init, dim3(64), dim3(256), 0, s, a);
-  const bool want_push = a.can_push && a.forced != GRB_DIR_PULL;
-  const bool want_pull = a.can_pull && a.forced != GRB_DIR_PUSH;
+  hipLaunchKernelGGL(k_mxv_init<SR>, dim3(kMxvParts), dim3(kMxvPartThreads), 0, s, a);
+  const bool want_push = a.gate.can_push && a.gate.forced != GRB_DIR_PULL;
+  const bool want_pull = a.gate.can_pull && a.gate.forced != GRB_DIR_PUSH;
   if (want_push) {
-    CompactArgs ca;
-    ca.nb = a.u_bm;
-    ca.nw = a.nw_in;
-    ca.rp = a.push.rp;
-    ca.list = a.list;
-    ca.degpre = a.degpre;
-    ca.rowstart = a.rowstart;
-    ca.tiles = a.tiles;
-    ca.status_cur = a.status;
-    ca.status_next = a.status + a.nblk;
-    ca.ctrl = a.ctrl;
-    launch_compact(ca, s);
-    hipLaunchKernelGGL(k_mxv_prep<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
+    if (a.u_list) {
+      const int g = (int)std::max<int64_t>(1, (a.n_in + kListChunk - 1) / kListChunk);
+      hipLaunchKernelGGL(k_mxv_list_prep, dim3(g), dim3(kCompactThreads), 0, s, a);
+    } else {
+      CompactArgs ca;
+      ca.nb = a.u_bm;
+      ca.nw = a.nw_in;
+      ca.nbits = a.n_in;
+      ca.rp = a.push.rp;
+      ca.list = a.list;
+      ca.degpre = a.degpre;
+      ca.rowstart = a.rowstart;
+      ca.tiles = a.tiles;
+      ca.status_cur = a.status;
+      ca.status_next = a.status + a.nblk;
+      ca.ctrl = a.ctrl;
+      ca.gated = true;
+      ca.gate = a.gate;
+      launch_compact(ca, s);
+    }
+    if (!Sr<SR>::lor) hipLaunchKernelGGL(k_mxv_prep<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_mxv_push<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
   }
   if (want_pull) {
-    hipLaunchKernelGGL(k_mxv_pull<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
-    if (a.pull.nheavy_rows > 0) {
+    if (a.u_from_list)
+      launch_list_to_bitmap(a.u_list, a.u_cnt, a.n_in, const_cast<uint64_t *>(a.u_bm), s, &a.gate);
+    hipLaunchKernelGGL(k_mxv_sweep<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
+    if (a.pull.nsplit_rows > 0) {
       const int gf = (int)std::min<int64_t>(
-          (a.pull.nheavy_rows + kWavesPerBlock - 1) / kWavesPerBlock, kExpandGrid);
-      hipLaunchKernelGGL(k_mxv_pull_fixup<SR>, dim3(gf), dim3(kBlock), 0, s, a);
+          (a.pull.nsplit_rows + kWavesPerBlock - 1) / kWavesPerBlock, kExpandGrid);
+      hipLaunchKernelGGL(k_mxv_fixup<SR>, dim3(gf), dim3(kBlock), 0, s, a);
     }
   }
 }

@@ -8,7 +8,10 @@ rows per edge; narrower passes keep the gathered frontier block (n x
 words_per_pass x 8 bytes) small enough to stay in the caches.  The best
 shape and rule depend on the graph, k and the device, so they are measured:
 every candidate runs the real batch on the real graph and the fastest is
-cached in a JSON file keyed by device, graph size and k.
+cached in a JSON file keyed by device, graph size and k.  A candidate is
+eligible only if its levels equal a reference run's bit for bit (the
+default tile, itself checked against single-source BFS on its first
+queries).
 """
 from __future__ import annotations
 
@@ -56,11 +59,28 @@ def tune_msbfs(A, sources, *, repeats: int = 2, cache_path: str | None = DEFAULT
         return cache[key]
     ws = grb.workspace(grb.OP_MSBFS, A, k)
     levels = torch.empty((A.nrows, k), dtype=torch.int32, device=A.device)
+    # reference levels: the default tile, its first queries checked against
+    # single-source BFS runs (a different kernel); every candidate must then
+    # reproduce the reference block exactly, or it is not eligible
+    ref = grb.msbfs(A, sources, ws=ws).clone()
+    src_host = [int(s) for s in (sources.tolist() if hasattr(sources, "tolist") else sources)]
+    ws1 = grb.workspace(grb.OP_BFS, A)
+    for q in range(min(k, 4)):
+        single, _ = grb.bfs(A, src_host[q], parents=False, ws=ws1)
+        if not torch.equal(single, ref[:, q]):
+            raise RuntimeError(f"batched BFS query {q} differs from single-source BFS")
+    del ws1
     table = []
     for kt, g, rule in candidates(k):
         desc = grb.descriptor(rule=RULES[rule])
         grb.msbfs(A, sources, words_per_pass=kt, grid=g, desc=desc, ws=ws, levels=levels)
         torch.cuda.synchronize()
+        if not torch.equal(levels, ref):
+            if log:
+                log(f"[tune] kt={kt} grid={g} rule={rule}: levels differ, rejected")
+            table.append({"words_per_pass": kt, "grid": g, "rule": rule, "ms": None,
+                          "rejected": True})
+            continue
         t0 = time.perf_counter()
         for _ in range(repeats):
             grb.msbfs(A, sources, words_per_pass=kt, grid=g, desc=desc, ws=ws, levels=levels)
@@ -69,7 +89,10 @@ def tune_msbfs(A, sources, *, repeats: int = 2, cache_path: str | None = DEFAULT
         table.append({"words_per_pass": kt, "grid": g, "rule": rule, "ms": round(ms, 4)})
         if log:
             log(f"[tune] kt={kt} grid={g} rule={rule}: {ms:.3f} ms")
-    best = min(table, key=lambda r: r["ms"])
+    ok = [r for r in table if r["ms"] is not None]
+    if not ok:
+        raise RuntimeError("no batched-BFS tile reproduced the reference levels")
+    best = min(ok, key=lambda r: r["ms"])
     res = {"words_per_pass": best["words_per_pass"], "grid": best["grid"], "rule": best["rule"],
            "ms": best["ms"], "table": table}
     cache[key] = res

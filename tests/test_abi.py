@@ -92,17 +92,34 @@ def test_matrix_create_validation(grb):
 
 def test_vector_and_workspace_validation(grb):
     h = ctypes.c_void_p()
-    assert grb.grb_vector_create(ctypes.byref(h), -1, 2, FAKE, FAKE) == 4
-    assert grb.grb_vector_create(ctypes.byref(h), 10, 7, FAKE, FAKE) == 4
-    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, None, FAKE) == 3
-    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, FAKE) == 0
+    assert grb.grb_vector_create(ctypes.byref(h), -1, 2, FAKE, FAKE, None, None) == 4
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 7, FAKE, FAKE, None, None) == 4
+    # no presence storage (neither bitmap nor list), or half a list
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, None, None, None) == 3
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, None, FAKE, None) == 3
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, None, None, FAKE) == 3
+    # values may be absent (every entry 1); list-only and both forms
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, None, FAKE, None, None) == 0
+    assert grb.grb_vector_free(ctypes.byref(h)) == 0
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, None, FAKE, FAKE) == 0
+    assert grb.grb_vector_free(ctypes.byref(h)) == 0
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, FAKE, FAKE, FAKE) == 0
+    assert grb.grb_vector_free(ctypes.byref(h)) == 0
+    assert grb.grb_vector_create(ctypes.byref(h), 10, 2, FAKE, FAKE, None, None) == 0
     n = ctypes.c_int64()
     assert grb.grb_vector_size(h, ctypes.byref(n)) == 0 and n.value == 10
     assert grb.grb_vector_nvals(h, ctypes.byref(n), None, 0, None) == 9  # workspace too small
+    # extract: argument errors are caught before any device work
+    assert grb.grb_vector_extract(h, None, None, 5, None, None, 0, None) == 3
+    assert grb.grb_vector_extract(h, None, None, -1, ctypes.byref(n), None, 0, None) == 4
+    assert grb.grb_vector_extract(h, None, None, 5, ctypes.byref(n), None, 0, None) == 9
+    assert grb.grb_vector_extract(None, None, None, 5, ctypes.byref(n), None, 0, None) == 2
     assert grb.grb_vector_free(ctypes.byref(h)) == 0
     sz = ctypes.c_size_t()
     assert grb.grb_workspace_size(1, None, 0, ctypes.byref(sz)) == 2
     assert grb.grb_workspace_size(5, None, 0, ctypes.byref(sz)) == 0 and sz.value >= 64
+    assert grb.grb_workspace_size(7, None, 1000, ctypes.byref(sz)) == 0 and sz.value > 12000
+    assert grb.grb_workspace_size(7, None, -1, ctypes.byref(sz)) == 4
     rc, m = _create(grb, n=1000, nnz=5000, flags=1)
     for op in (0, 1, 2):
         assert grb.grb_workspace_size(op, m, 0, ctypes.byref(sz)) == 0 and sz.value > 0

@@ -68,6 +68,70 @@ def test_sssp_rmat22(grb, rmat22, rule):
     assert np.array_equal(dist.cpu().numpy(), ref)
 
 
+def test_sssp_rmat22_forced_pull(grb, rmat22):
+    """Every round pulled (the benchmark's forced-pull run): the pull forms
+    that gather a distance per edge, test the frontier bit first, or load
+    only members' weights all run at full size."""
+    A, adj = rmat22
+    ref, _, _ = oracle.sssp(adj, 0)
+    dist = grb.sssp(A, 0, desc=grb.descriptor(direction=2, flags=grb.GRB_PROFILE))
+    st = grb.last_stats()
+    assert st["pulls"] == st["iterations"] and st["pushes"] == 0
+    assert np.array_equal(dist.cpu().numpy(), ref)
+
+
+def _to_words(bits):
+    b = np.packbits(bits.astype(np.uint8), bitorder="little")
+    b = np.concatenate([b, np.zeros((-len(b)) % 8, np.uint8)])
+    return b.view(np.int64)
+
+
+def _vector(grb, vals, has, dtype):
+    n = has.shape[0]
+    v = grb.Vector(n, dtype)
+    v.values[:n] = torch.from_numpy(vals.astype(np.uint8)).to(v.values.device)
+    words = _to_words(has)
+    v.bitmap[: len(words)] = torch.from_numpy(words).to(v.values.device)
+    return v
+
+
+SWEEP = [(1e-4, 0.0), (1e-2, 0.5), (0.05, 0.0), (0.2, 0.5)]
+
+
+@pytest.mark.parametrize("pq", SWEEP, ids=[f"p{p}_q{q}" for p, q in SWEEP])
+def test_mxv_sweep_rmat22(grb, rmat22, pq):
+    """Points of the benchmark's mxv sweep, element by element against the
+    oracle's dense-array product: w<not m, struct, replace> = A u over
+    LOR_LAND, u random of density p (a tenth of its entries false), m a
+    random set of density q, w holding stale entries that REPLACE must clear
+    outside the mask; forced push, forced pull and automatic."""
+    A, adj = rmat22
+    p, q = pq
+    n = A.nrows
+    rng = np.random.default_rng(int(p * 1e6) * 7 + int(q * 10))
+    u_has = rng.random(n) < p
+    u_val = u_has & (rng.random(n) >= 0.1)
+    m_has = rng.random(n) < q
+    w_has = rng.random(n) < 0.3
+    w_val = w_has & (rng.random(n) < 0.5)
+    flags = grb.GRB_MASK_COMP | grb.GRB_MASK_STRUCT | grb.GRB_REPLACE
+    ref_v, ref_h = oracle.mxv_dense(adj, "lor_land", u_val, u_has, w_val=w_val, w_has=w_has,
+                                    mask_val=m_has, mask_has=m_has, flags=flags)
+    U = _vector(grb, u_val, u_has, torch.uint8)
+    Mk = _vector(grb, m_has, m_has, torch.uint8)
+    ws = grb.workspace(grb.OP_MXV, A)
+    for direction in (1, 2, 0):
+        W = _vector(grb, w_val, w_has, torch.uint8)
+        grb.mxv(W, Mk, None, "lor_land", A, U,
+                desc=grb.descriptor(direction=direction, rule=1, flags=flags), ws=ws)
+        torch.cuda.synchronize()
+        words = W.bitmap.cpu().numpy().view(np.uint8)
+        got_h = np.unpackbits(words, bitorder="little")[:n].astype(bool)
+        assert np.array_equal(got_h, ref_h), (direction, int((got_h != ref_h).sum()))
+        got_v = W.values[:n].cpu().numpy()
+        assert np.array_equal(got_v[ref_h] != 0, ref_v[ref_h] != 0), direction
+
+
 def test_grid3000_bfs_sssp(grb, grid3000):
     A, adj = grid3000
     ref_lev, ref_par, nl = oracle.bfs(adj, 0)

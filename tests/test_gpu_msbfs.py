@@ -38,11 +38,15 @@ def test_msbfs_rmat14(grb, rmat14, k, mode):
         deg = np.diff(adj.arrays(weights=False)[0])
         src[2] = int(np.flatnonzero(deg == 0)[0])  # isolated source
     ref = oracle.msbfs(adj, src, nthreads=8)
-    for kt in sorted({0, 1, 2}):
-        lev = grb.msbfs(A, src, words_per_pass=min(kt, (k + 63) // 64),
-                        desc=grb.descriptor(direction=mode[0], rule=mode[1]))
-        got = lev.cpu().numpy().T
-        assert np.array_equal(got, ref), (k, mode, kt)
+    W = (k + 63) // 64
+    # every tile the autotuner may pick: query words per pass (clamped to
+    # the batch) by launch width (0 = the default width)
+    for kt in sorted({min(x, W) for x in (0, 1, 2, 4, 8)}):
+        for grid in (0, 1024, 4096):
+            lev = grb.msbfs(A, src, words_per_pass=kt, grid=grid,
+                            desc=grb.descriptor(direction=mode[0], rule=mode[1]))
+            got = lev.cpu().numpy().T
+            assert np.array_equal(got, ref), (k, mode, kt, grid)
 
 
 def test_msbfs_grid_and_directed(grb):
