@@ -464,6 +464,19 @@ def bench_msbfs(grb, graphgen, torch, args):
             ms_seq = timed(lambda: [grb.bfs(A, int(s), parents=False, desc=dseq, ws=ws1)
                                     for s in seq_src], 1, torch)
             per_src_seq = ms_seq / len(seq_src)
+            # algorithmic floor of the batch: every (vertex, query) level is
+            # written once (4 B), and each level streams the CSR once per pass
+            # of query words (4 B per column id, 8 B per row extent pair)
+            reached = int((lev >= 0).sum().item())
+            W = (k + 63) // 64
+            passes = -(-W // min(best["words_per_pass"] or W, 8))
+            grb.msbfs(A, src, words_per_pass=best["words_per_pass"], grid=best["grid"],
+                      desc=grb.descriptor(rule=tune.RULES[best.get("rule", "paper")],
+                                          flags=grb.GRB_PROFILE), ws=wsk, levels=lev)
+            stp = grb.last_stats()
+            nlev = stp["iterations"]
+            floor_b = 4 * reached + nlev * passes * (4 * A.nnz + 8 * A.nrows)
+            kern_ms = stp["expand_ms_all"]
             # the timed batch's first 64 queries equal the sequential runs
             for q, s in enumerate(seq_src):
                 single, _ = grb.bfs(A, int(s), parents=False, desc=dseq, ws=ws1)
@@ -477,16 +490,30 @@ def bench_msbfs(grb, graphgen, torch, args):
                 "tile": {"words_per_pass": best["words_per_pass"], "grid": best["grid"],
                          "rule": best.get("rule", "paper")},
                 "sequential_ms_per_source": round(per_src_seq, 4),
-                "speedup_vs_sequential": round(per_src_seq * k / ms, 2)}
+                "speedup_vs_sequential": round(per_src_seq * k / ms, 2),
+                "k_ms_level": {"launches": stp["launches"],
+                               "avg_launch_us": round(kern_ms / max(stp["launches"], 1) * 1e3, 2),
+                               "per_level_us": [round(x * 1e3, 1) for x in stp["kernel_ms"]],
+                               "direction": stp["direction"][:nlev]},
+                "bytes_floor": floor_b,
+                "floor_gbs": round(floor_b / (kern_ms / 1e3) / 1e9, 1),
+                "floor_frac_hbm": round(floor_b / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "floor_model": "4 B per reached (vertex, query) level + per level and pass of "
+                               "query words 4 B per column id and 8 B per row extent pair"}
             del wsk, lev
         del ws1
     return res
 
 
 def bench_serve(grb, graphgen, torch, args):
-    """Serving: six resident graphs, Poisson arrivals, 70% BFS / 30% SSSP,
-    continuous batching with HBM-footprint admission, against a
-    one-query-at-a-time FIFO server at the same arrival rates."""
+    """Serving: six resident graphs, Poisson arrivals, 70% BFS / 30% SSSP.
+    BFS queries join lane sessions of their graph at level boundaries and
+    retire on their own; SSSP queries run in slots; every session and query
+    carves its memory from one pool of the HBM budget (admission binds when
+    the pool is full).  Compared with a one-query-at-a-time FIFO server at
+    the same arrival rates.  The full protocol (--serve-full) sweeps the
+    load over {0.25, 0.5, 0.75, 0.9, 1.1} x saturation with 10,000 queries
+    per point and the budget over 1-8 GiB."""
     from paper_1908_01407_amd.serve import GpuExecutor, Query, Server
 
     raws = {f"rmat{s}": (args._g if s == args.scale else graphgen.rmat(s)) for s in (16, 18, 20, 22)}
@@ -511,36 +538,120 @@ def bench_serve(grb, graphgen, torch, args):
                             arrival=float(arr[i])))
         return qs
 
+    # high-diameter graphs: bucketed SSSP, several BFS levels per session step
+    deltas = {"grid2000": 2048.0, "grid3000": 2048.0}
+    chunks = {"grid2000": 16, "grid3000": 16}
+    full = args.serve_full
+    nq = 10000 if full else args.serve_queries
+    loads = [0.25, 0.5, 0.75, 0.9, 1.1] if full else args.serve_load
+    budget = args.serve_budget
+
+    def prog(tag):
+        return lambda k: log(f"[bench] serve {tag}: {k} queries submitted")
+
+    def batched(bud):
+        ex = GpuExecutor(graphs, budget=bud, slots=args.serve_slots, keep_results=False,
+                         sssp_delta=deltas)
+        return ex, (lambda: Server(ex, slots=args.serve_slots, lanes=64, level_chunk=chunks))
+
+    ex, mk = batched(budget)
+    fifo_ex = GpuExecutor(graphs, budget=budget, slots=1, keep_results=False, sssp_delta=deltas)
+    fifo = lambda: Server(fifo_ex, lane_mode=False)
     out = {"graphs": {k: {"n": A.nrows, "nnz": A.nnz} for k, A in graphs.items()},
            "mix": "70% BFS / 30% SSSP, graph and source uniform, Poisson arrivals",
-           "budget_bytes": args.serve_budget}
-    # high-diameter graphs answer SSSP with bucketed rounds
-    deltas = {"grid2000": 2048.0, "grid3000": 2048.0}
-    ex = GpuExecutor(graphs, slots=args.serve_slots, max_batch=64, keep_results=False,
-                     sssp_delta=deltas)
-    fifo_ex = GpuExecutor(graphs, slots=1, max_batch=1, keep_results=False, sssp_delta=deltas)
-    # warm up every graph and kind once
-    Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
-        trace(2 * len(names), 1e6, 99), realtime=False)
-    sat = Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
-        trace(args.serve_queries, 1e9, 0), realtime=False)
-    fifo_sat = Server(fifo_ex, budget=args.serve_budget, slots=1, max_batch=1).run(
-        trace(args.serve_queries // 2, 1e9, 0), realtime=False)
+           "budget_bytes": budget, "queries_per_point": nq,
+           "session_lanes": {g: mk().lanes_for(g) for g in names}}
+    mk().run(trace(4 * len(names), 1e6, 99), realtime=False)  # warm-up
+    fifo().run(trace(2 * len(names), 1e6, 98), realtime=False)
+    sat = mk().run(trace(nq, 1e9, 0), realtime=False, progress=prog("saturation"))
+    fifo_sat = fifo().run(trace(max(nq // 4, 200), 1e9, 0), realtime=False,
+                          progress=prog("fifo saturation"))
     out["saturation"] = {"batched": sat, "fifo": fifo_sat}
+    log(f"[bench] serve saturation: batched {sat['qps']} q/s, fifo {fifo_sat['qps']} q/s")
     qps = sat["qps"]
     points = []
-    for frac in args.serve_load:
+    for frac in loads:
         rate = frac * qps
-        b = Server(ex, budget=args.serve_budget, slots=args.serve_slots).run(
-            trace(args.serve_queries, rate, 1), realtime=True)
-        f = Server(fifo_ex, budget=args.serve_budget, slots=1, max_batch=1).run(
-            trace(args.serve_queries, rate, 1), realtime=True)
+        b = mk().run(trace(nq, rate, 1), realtime=True, progress=prog(f"load {frac}"))
+        f = fifo().run(trace(nq, rate, 1), realtime=True, progress=prog(f"fifo load {frac}"))
         points.append({"rate_qps": round(rate, 1), "load_of_batched_saturation": frac,
                        "batched": b, "fifo": f})
-        log(f"[bench] serve rate {rate:.1f}: batched p50 {b['p50_ms']} p99 {b['p99_ms']} | "
-            f"fifo p50 {f['p50_ms']} p99 {f['p99_ms']}")
+        log(f"[bench] serve rate {rate:.1f}: batched p50 {b['p50_ms']} p99 {b['p99_ms']} "
+            f"(deferred {b['deferred_admissions']}) | fifo p50 {f['p50_ms']} p99 {f['p99_ms']}")
     out["points"] = points
+    if full:
+        # budget sweep at 0.75 x saturation
+        sweep = []
+        for bud in (1 << 30, 2 << 30, 4 << 30, 8 << 30):
+            del ex
+            torch.cuda.empty_cache()
+            ex, mkb = batched(bud)
+            r = mkb().run(trace(nq, 0.75 * qps, 2), realtime=True, progress=prog(f"budget {bud}"))
+            sweep.append({"budget_bytes": bud, "stats": r})
+            log(f"[bench] serve budget {bud >> 20} MiB: p50 {r['p50_ms']} p99 {r['p99_ms']} "
+                f"qps {r['qps']} deferred {r['deferred_admissions']}")
+        out["budget_sweep"] = sweep
     return out
+
+
+def cpu_oracle_other(g, graphgen, args):
+    """The oracle timed on this host's cores for the other workloads, each on
+    a bounded sample: SSSP (Dijkstra, one core), PageRank (FP64 power
+    iteration, one core, three iterations), batched BFS (64 sources, one
+    query per thread on all cores) and the serving mix (64 queries of the
+    six graphs, one per thread on all cores)."""
+    import concurrent.futures as cf
+
+    import oracle
+    cores = max(1, min(16, os.cpu_count() or 1))
+    res = {"host": host_info()["cpu"], "cores_available": cores}
+    adj = oracle.Adjacency.from_raw(g)
+    t0 = time.perf_counter()
+    oracle.sssp(adj, 0)
+    t = time.perf_counter() - t0
+    res["sssp_rmat"] = {"ms": round(t * 1e3, 1), "gteps": round(adj.nnz / t / 1e9, 4), "cores": 1,
+                        "sample": f"one Dijkstra from vertex 0 on RMAT-{args.scale}"}
+    gd = graphgen.rmat(args.scale, symmetric=False, weights=False)
+    adjd = oracle.Adjacency.from_raw(gd)
+    t0 = time.perf_counter()
+    oracle.pagerank(adjd, 0.85, 3, 0.0)
+    t = (time.perf_counter() - t0) / 3
+    res["pagerank_rmat_dir"] = {"ms_per_iter": round(t * 1e3, 1), "cores": 1,
+                                "gteps_per_iter": round(adjd.nnz / t / 1e9, 4),
+                                "sample": "3 FP64 iterations (the sweep of all in-edges each)"}
+    del adjd, gd
+    src = graphgen.sources(g.src, g.dst, g.n, 64, seed=3)
+    t0 = time.perf_counter()
+    oracle.msbfs(adj, src, nthreads=cores)
+    t = time.perf_counter() - t0
+    res["batched_bfs_rmat_k64"] = {"ms": round(t * 1e3, 1), "sources_per_s": round(64 / t, 2),
+                                   "cores": cores,
+                                   "sample": f"64 sources on RMAT-{args.scale}, one BFS per thread"}
+    # serving mix: 64 queries over the six graphs, one per thread
+    raws = {f"rmat{s}": (g if s == args.scale else graphgen.rmat(s)) for s in (16, 18, 20)}
+    raws["grid2000"] = graphgen.grid(2000, 2000)
+    adjs = {k: (adj if v is g else oracle.Adjacency.from_raw(v)) for k, v in raws.items()}
+    adjs[f"rmat{args.scale}"] = adj
+    names = sorted(adjs)
+    kind = graphgen.uniform_ints(64, 10, seed=50)
+    gs = graphgen.uniform_ints(64, len(names), seed=60)
+    jobs = []
+    for i in range(64):
+        a = adjs[names[int(gs[i])]]
+        jobs.append((a, 0 if kind[i] < 7 else 1, int(i * 7919) % a.n))
+
+    def one(job):
+        a, k, s = job
+        return oracle.bfs(a, s, parents=False) if k == 0 else oracle.sssp(a, s)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as pool:
+        list(pool.map(one, jobs))
+    t = time.perf_counter() - t0
+    res["serving_mix"] = {"queries_per_s": round(64 / t, 2), "cores": cores,
+                          "sample": "64 queries (70% BFS / 30% SSSP) over RMAT 16/18/20/"
+                                    f"{args.scale} and the 2000^2 grid, one per thread"}
+    return res
 
 
 def cpu_baseline(g, A_nnz, args):
@@ -584,7 +695,11 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=600)
     ap.add_argument("--serve-slots", type=int, default=8)
-    ap.add_argument("--serve-budget", type=int, default=16 << 30)
+    ap.add_argument("--serve-budget", type=int, default=2 << 30,
+                    help="device memory of the serving pool in bytes (default 2 GiB)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="full serving protocol: 10,000 queries per point, five loads, "
+                         "budget sweep (minutes of GPU time)")
     ap.add_argument("--serve-load", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
@@ -708,6 +823,34 @@ def main():
                    "reached": reached},
         "roofline": roofline,
     }
+    # the practical HBM ceiling beside the 8 TB/s peak: a 1 GiB device copy
+    cp_src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cp_dst = torch.empty_like(cp_src)
+    cp_dst.copy_(cp_src)
+    cp_ms = timed(lambda: cp_dst.copy_(cp_src), 5, torch)
+    copy_gbs = 2 * (1 << 30) / (cp_ms / 1e3) / 1e9
+    del cp_src, cp_dst
+    out["roofline"]["copy_ceiling_gbs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 5)
+    # the headline workload from three other sources (random, degree > 0)
+    other = []
+    for s in graphgen.sources(g.src, g.dst, g.n, 3, seed=3):
+        grb.bfs(A, int(s), desc=desc, ws=ws, out=out_bufs)
+        ms_s = timed(lambda: grb.bfs(A, int(s), desc=desc, ws=ws, out=out_bufs), 5, torch)
+        other.append({"source": int(s), "ms": round(ms_s, 4), "levels": grb.last_stats()["iterations"],
+                      "gteps": round(nnz / (ms_s / 1e3) / 1e9, 2)})
+    out["config"]["other_sources"] = other
+    # C1: the small configuration, a latency line (microseconds per BFS)
+    g14 = graphgen.rmat(14)
+    A14 = grb.Matrix.from_raw(g14)
+    ws14 = grb.workspace(grb.OP_BFS, A14)
+    for _ in range(3):
+        grb.bfs(A14, 0, desc=desc, ws=ws14)
+    ms14 = timed(lambda: grb.bfs(A14, 0, desc=desc, ws=ws14), 10, torch)
+    out["rmat14_bfs"] = {"us_per_bfs": round(ms14 * 1e3, 2), "levels": grb.last_stats()["iterations"],
+                         "gteps": round(A14.nnz / (ms14 / 1e3) / 1e9, 3), "runs": 10, "warmup": 3,
+                         "note": "levels + parents from vertex 0; L2-resident, a latency figure"}
+    del A14, ws14
     if args.calibrate_copy:
         # a plain streaming kernel of known traffic for the counter scale:
         # reads 256 MiB and writes 256 MiB (torch's elementwise multiply)
@@ -728,6 +871,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, nnz, args)
+        if not args.no_extras:
+            log("[bench] oracle baselines of the other workloads")
+            out["cpu_oracle_other"] = cpu_oracle_other(g, graphgen, args)
     out["host"] = host_info()
     out["gpu"] = torch.cuda.get_device_name(0)
     print(json.dumps(out), flush=True)

@@ -353,6 +353,10 @@ grb_info grb_vxm(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s,
  * CSR of A^T; a symmetric matrix serves both).
  * Synchronises `stream` once per batch of levels (it reads the frontier
  * size back to detect the end).  d->max_iter caps the levels (0 = none).
+ * On graphs whose rows are short (at most 64 entries: road-like, high
+ * diameter) the levels run inside one workgroup while the frontier is small
+ * (a launch per level would dominate); a frontier that outgrows it, or that
+ * the switch rule would pull, continues with one kernel per level.
  */
 grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source,
                  const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
@@ -361,7 +365,10 @@ grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source
  * SSSP from `source` (Section 7.2): Bellman-Ford over MIN_PLUS with the
  * frontier sparsified to the vertices whose distance improved in the last
  * round; stops when none improved.  dist[n] (fp32): +inf where unreached.
- * A must carry FP32 values >= 0.  Synchronises like grb_bfs.
+ * A must carry FP32 values (else GRB_DOMAIN_MISMATCH), none negative or NaN
+ * (checked by grb_matrix_prepare; else GRB_INVALID_VALUE).  On graphs whose
+ * rows are short (at most 64 entries) the rounds run inside one workgroup
+ * while the frontier is small.  Synchronises like grb_bfs.
  */
 grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descriptor *d,
                   void *ws, size_t ws_bytes, void *stream);

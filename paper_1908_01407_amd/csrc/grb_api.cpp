@@ -168,7 +168,7 @@ struct MxvWs {
   int32_t *list, *degpre, *rowstart, *tiles;
   int64_t tiles_cap;
   void *t_val, *hp_val;
-  uint8_t *hp_has;
+  uint8_t *hp_has, *settled;
   uint64_t *ubm, *mbm, *wbm;  // bitmaps of operands given only as lists
   int nblk, nblk_out, nblk_list;
   size_t bytes;
@@ -195,6 +195,7 @@ MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz, int64_t npi
   t.t_val = c.take<char>((size_t)std::max<int64_t>(n_out, 1) * 8);
   t.hp_val = c.take<char>((size_t)std::max<int64_t>(npieces, 1) * 8);
   t.hp_has = c.take<uint8_t>((size_t)std::max<int64_t>(npieces, 1));
+  t.settled = c.take<uint8_t>((size_t)std::max<int64_t>(n_out, 1));
   t.ubm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_in), 1));
   t.mbm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
   t.wbm = c.take<uint64_t>((size_t)std::max<int64_t>(words_of(n_out), 1));
@@ -359,6 +360,18 @@ grb_info build_meta(Csr &c, char *meta, const MetaLayout &L, hipStream_t s) {
       hipMemcpyAsync(hr, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return GRB_PANIC;
   int2 *f2 = (int2 *)(meta + L.first2_off);
+  // negative (or NaN) values: shortest paths refuse the matrix; the flag
+  // word borrows the first-two array's first slot, written right after
+  int32_t neg = 0;
+  if (c.val && (c.vtype == GRB_FP32 || c.vtype == GRB_FP64) && c.nrows > 0) {
+    int32_t *flag = (int32_t *)f2;
+    launch_any_negative(c.val, c.vtype, c.nnz, flag, s);
+    if (hipGetLastError() != hipSuccess) return GRB_PANIC;
+    if (hipMemcpyAsync(&neg, flag, sizeof(neg), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GRB_PANIC;
+  }
+  c.negative = neg != 0;
   launch_first_two(c.rp, c.ci, c.nrows, f2, s);
   if (hipGetLastError() != hipSuccess) return GRB_PANIC;
   if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
@@ -399,11 +412,14 @@ thread_local EventPool g_events;
 // buffer and takes about twice the round trip of one into pinned memory, so
 // the copies land in a pinned staging buffer (one per host thread, grown on
 // demand, kept for the thread's lifetime) and are then copied on the host.
+thread_local bool g_no_alloc = false;  // a caller that must not allocate is running
+
 struct Staging {
   char *buf = nullptr;
   size_t cap = 0;
   char *get(size_t bytes) {
     if (bytes <= cap) return buf;
+    if (g_no_alloc) return nullptr;  // direct copies instead of a new pinned buffer
     if (buf) (void)hipHostFree(buf);
     buf = nullptr;
     cap = 0;
@@ -416,6 +432,13 @@ struct Staging {
   }
 };
 thread_local Staging g_staging;
+
+}  // namespace
+
+grb::NoAllocScope::NoAllocScope() : prev_(g_no_alloc) { g_no_alloc = true; }
+grb::NoAllocScope::~NoAllocScope() { g_no_alloc = prev_; }
+
+namespace {
 
 struct Region {
   void *dst;        // host destination
@@ -544,10 +567,18 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
     d = hc.small_levels;
     empty_seen = !hc.spilled;  // done, or stopped by the level cap
   }
-  // The first batch covers six levels and the empty one that ends most
-  // small-world searches; later batches double.  Control block and level
+  // The first batch covers the depth expected of a random graph of this
+  // size and mean degree, ln n / ln(nnz / n), plus the empty level that ends
+  // the search and one spare; later batches start at two levels and double,
+  // so a deeper search pays few empty launches.  Control block and level
   // records come back in one copy.
   int chunk = 7;
+  {
+    const double dbar = n > 0 ? (double)A->nnz / (double)n : 0.0;
+    if (n > 1 && dbar > 1.5)
+      chunk = (int)std::min(64.0, std::ceil(std::log((double)n) / std::log(dbar)) + 2.0);
+  }
+  bool first_batch = true;
   while (!empty_seen && d < cap) {
     for (int i = 0; i < chunk && d < cap; ++i, ++d) {
       at_level(d);
@@ -565,7 +596,8 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
       empty_seen = true;
       break;
     }
-    chunk = std::min(chunk * 2, 256);
+    chunk = first_batch ? 2 : std::min(chunk * 2, 256);
+    first_batch = false;
   }
   // parents the level kernel did not resolve: a search stopped by the level
   // cap, or levels run by the one-workgroup loop
@@ -718,23 +750,44 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
   launch_sssp_delta_start(sa, source, w.F[1], w.F[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
-  int chunk = 16;
   const size_t rec_bytes = (size_t)kStatsCap * kStatFields * sizeof(int64_t);
   const size_t head = (size_t)((char *)w.stats - (char *)w.ctrl);
   std::vector<char> host(head + rec_bytes);
   Ctrl hc{};
-  for (;;) {
+  bool done = false;
+  int64_t launches = 0;
+  std::vector<int64_t> launch_round;
+  // low-degree graphs: rounds in one workgroup while the pending set is
+  // small (no launch per round); a larger set continues with the round kernel
+  const bool small = A->a.max_deg <= kSmallMaxDeg;
+  if (small) {
+    if (profile) (void)hipEventRecord(g_events.get(0), s);
+    uint64_t *F[3] = {w.F[0], w.F[1], w.F[2]};
+    launch_sssp_delta_small(sa, source, cap, F, stream);
+    if (profile) (void)hipEventRecord(g_events.get(1), s);
+    launch_round.push_back(0);
+    launches = 1;
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (!read_back({{host.data(), w.ctrl, head + rec_bytes}}, s)) return GRB_PANIC;
+    std::memcpy(&hc, host.data(), sizeof(Ctrl));
+    d = hc.small_levels;
+    done = !hc.spilled;
+  }
+  int chunk = 16;
+  while (!done && d < cap) {
     for (int i = 0; i < chunk && d < cap; ++i, ++d) {
       at_round(d);
-      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)launches), s);
       launch_sssp_delta_round(sa, stream);
-      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)d + 1), s);
+      if (profile) (void)hipEventRecord(g_events.get(2 * (size_t)launches + 1), s);
+      launch_round.push_back(d);
+      ++launches;
     }
     if ((info = check_launch()) != GRB_SUCCESS) return info;
     const size_t recs = (size_t)std::min<int64_t>(d, kStatsCap) * kStatFields * sizeof(int64_t);
     if (!read_back({{host.data(), w.ctrl, head + recs}}, s)) return GRB_PANIC;
     std::memcpy(&hc, host.data(), sizeof(Ctrl));
-    if (hc.nlev < d || d >= cap) break;  // a launched round found nothing pending
+    if (hc.nlev < d) break;  // a launched round found nothing pending
     chunk = std::min(chunk * 2, 512);
   }
   const int iters = hc.nlev;
@@ -744,14 +797,19 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
-    for (int64_t i = 0; i < d; ++i) {
+    // per round: a round launch's time; the one-workgroup loop's time is
+    // spread evenly over the rounds it ran
+    kms.assign((size_t)std::max(nrec, 0), 0.0f);
+    for (int64_t i = 0; i < launches; ++i) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, g_events.get(2 * (size_t)i), g_events.get(2 * (size_t)i + 1));
-      if (i < nrec) kms.push_back(ms);
       ms_all += ms;
+      const int64_t l0 = launch_round[(size_t)i];
+      const int64_t l1 = (small && i == 0) ? std::max<int64_t>(hc.small_levels, 1) : l0 + 1;
+      for (int64_t l = l0; l < l1 && l < nrec; ++l) kms[(size_t)l] = ms / (float)(l1 - l0);
     }
   }
-  finish_stats(GRB_OP_SSSP, iters, rec, kms, (int)std::min<int64_t>(d, INT32_MAX), ms_all);
+  finish_stats(GRB_OP_SSSP, iters, rec, kms, (int)std::min<int64_t>(launches, INT32_MAX), ms_all);
   return GRB_SUCCESS;
 }
 
@@ -1238,6 +1296,7 @@ grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descripto
   if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
   if (source < 0 || source >= A->nrows) return GRB_INVALID_INDEX;
   if (A->a.vtype != GRB_FP32) return GRB_DOMAIN_MISMATCH;
+  if (A->a.negative || A->at.negative) return GRB_INVALID_VALUE;  // min-plus needs weights >= 0
   grb_descriptor desc;
   grb_info info = resolve_desc(d, &desc);
   if (info != GRB_SUCCESS) return info;
@@ -1251,6 +1310,7 @@ grb_info grb_sssp_delta(float *dist, grb_matrix A, int32_t source, float delta,
   if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
   if (source < 0 || source >= A->nrows) return GRB_INVALID_INDEX;
   if (A->a.vtype != GRB_FP32) return GRB_DOMAIN_MISMATCH;
+  if (A->a.negative || A->at.negative) return GRB_INVALID_VALUE;  // min-plus needs weights >= 0
   if (!(delta > 0.0f) || !(delta < 3.0e38f)) return GRB_INVALID_VALUE;
   grb_descriptor desc;
   grb_info info = resolve_desc(d, &desc);
@@ -1746,6 +1806,7 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   a.t_vb = t.t_vb;
   a.hp_val = t.hp_val;
   a.hp_has = t.hp_has;
+  a.settled = t.settled;
   a.list = u->indices ? u->indices : t.list;
   a.degpre = t.degpre;
   a.rowstart = t.rowstart;

@@ -758,7 +758,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_bfs_small(BfsArgs a, int32_t 
     if (nc == 0 || d >= max_levels) break;
     // a frontier too large for the lists, or one the switch rule would
     // pull, goes to the level kernel
-    if (nc > kSmallCap || s_e[b] > kSmallEdges || decide(a, nc, s_e[b]) == GRB_DIR_PULL) {
+    if (nc > kSmallSpill || s_e[b] > kSmallEdges || decide(a, nc, s_e[b]) == GRB_DIR_PULL) {
       spill = true;
       break;
     }

@@ -56,6 +56,7 @@ struct Csr {
   // with the row extents so that a pull settled by them never touches col_idx
   const int2 *first2 = nullptr;
   int64_t max_deg = 0;  // longest row (host copy, from prepare)
+  bool negative = false;  // a stored value is negative or NaN (from prepare)
   bool valid() const { return rp != nullptr; }
 };
 
@@ -111,6 +112,19 @@ constexpr int kStatFields = 4;
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 inline int64_t words_of(int64_t n) { return (n + 63) / 64; }
+
+// While alive on a host thread, the library's read-backs use no pinned
+// staging buffer they would have to allocate (plain copies instead).
+class NoAllocScope {
+ public:
+  NoAllocScope();
+  ~NoAllocScope();
+  NoAllocScope(const NoAllocScope &) = delete;
+  NoAllocScope &operator=(const NoAllocScope &) = delete;
+
+ private:
+  bool prev_;
+};
 
 // ---- direction of a generic product ----------------------------------------
 // The automatic choice is taken on the device from the input's entry count
@@ -180,7 +194,11 @@ void launch_bfs_level(const BfsArgs &a, void *stream);
 // after launch_bfs_start; parents are left to the parents pass.
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallCap = 4096;     // frontier vertices per level held in LDS
-constexpr int kSmallEdges = 65536;  // edges of a frontier the loop still expands
+// One workgroup streams a level through one CU: measured on the 3000 x 3000
+// grid it spends ~27 us on a 3000-vertex level against ~10 us for a level
+// launch, so the frontier goes to the level kernel well before the lists fill
+constexpr int kSmallSpill = 384;    // frontier vertices the loop still expands
+constexpr int kSmallEdges = 1536;   // ... and their edges
 constexpr int kSmallMaxDeg = 64;    // graphs whose rows are at most this long use the loop
 void launch_bfs_small(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
                       void *stream);
@@ -218,6 +236,11 @@ constexpr int kDeltaSlots = kDeltaFields * kCntStripes;
 void launch_sssp_delta_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                              void *stream);
 void launch_sssp_delta_round(const SsspArgs &a, void *stream);
+// bucket rounds in one workgroup while the pending set fits its LDS lists
+// (the BFS loop's limits); hands the set to the round kernel as the bitmap
+// and counters of round ctrl->small_levels when it outgrows them
+void launch_sssp_delta_small(const SsspArgs &a, int32_t source, int64_t max_rounds,
+                             uint64_t *const F[3], void *stream);
 
 struct PrArgs {
   int64_t n = 0, nw = 0;
@@ -271,6 +294,8 @@ void launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, void *stream);
 void launch_fill_bytes_pattern(void *p, int64_t count, int elem_size, const void *value,
                                void *stream);
 void launch_popcount(const uint64_t *bm, int64_t nw, int64_t *out, void *stream);
+// *flag (cleared first) = 1 if some value is negative or NaN (fp32 / fp64)
+void launch_any_negative(const void *values, int vtype, int64_t n, int32_t *flag, void *stream);
 void launch_vector_build(uint64_t *bitmap, void *values, int elem_size, int64_t n,
                          const int32_t *idx, const void *vals, int64_t count, uint64_t one,
                          void *stream);
@@ -341,6 +366,7 @@ struct MxvArgs {
   uint64_t *t_bm = nullptr, *t_vb = nullptr;
   void *hp_val = nullptr;       // per pull piece partial value
   uint8_t *hp_has = nullptr;    // per pull piece: any contribution
+  uint8_t *settled = nullptr;   // OR pull: long row settled by its first two entries (by row)
   int32_t *list = nullptr, *degpre = nullptr, *rowstart = nullptr, *tiles = nullptr;
   int64_t tiles_cap = 0;        // entries of `tiles`
   uint64_t *status = nullptr, *status_out = nullptr, *status_list = nullptr;

@@ -336,6 +336,16 @@ __global__ void k_gather_values(const unsigned char *values, int elem, const int
   }
 }
 
+__global__ void k_any_negative(const void *values, int vtype, int64_t n, int32_t *flag) {
+  bool neg = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (vtype == GRB_FP32) neg |= !(((const float *)values)[i] >= 0.0f);
+    else neg |= !(((const double *)values)[i] >= 0.0);
+  }
+  if (__ballot(neg) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 inline int grid_for(int64_t items, int per_block, int cap) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -407,6 +417,15 @@ void launch_bitmap_to_list_small(const uint64_t *bm, int64_t n, int32_t *list, i
                                  void *stream) {
   hipLaunchKernelGGL(k_bitmap_to_list_small, dim3(1), dim3(1024), 0, (hipStream_t)stream, bm, n,
                      list, cnt);
+}
+
+void launch_any_negative(const void *values, int vtype, int64_t n, int32_t *flag, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill_pattern, dim3(1), dim3(64), 0, s, (unsigned char *)flag, (int64_t)1, 4,
+                     (uint64_t)0);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_any_negative, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, values,
+                     vtype, n, flag);
 }
 
 void launch_iota(int32_t *list, int64_t n, int32_t *cnt, void *stream) {

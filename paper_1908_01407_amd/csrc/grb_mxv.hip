@@ -180,6 +180,9 @@ __global__ __launch_bounds__(kMxvPartThreads) void k_mxv_init(MxvArgs a) {
       a.t_bm[i] = 0ull;
       a.t_vb[i] = 0ull;
     }
+  // OR pull: long rows' "settled by the probes" flags
+  if (Sr<SR>::lor && a.gate.can_pull && a.gate.forced != GRB_DIR_PUSH)
+    for (int64_t k = gt; k < a.pull.nsplit_rows; k += nthr) a.settled[a.pull.split_rows[3 * k]] = 0;
   if (a.gate.forced || !a.gate.can_push || !a.gate.can_pull) return;
   // partials of the input's entry count and degree sum (rows of the push CSR)
   const bool exact = a.gate.rule == GRB_SWITCH_EXACT;
@@ -597,6 +600,227 @@ __device__ void pull_word(const MxvArgs &a, int64_t wd, int *mark, int *s_end, i
   if (ln == 0) a.w_bm[wd] = (bits & ~lmask) | (a.w_bm[wd] & lmask);
 }
 
+// OR pull (LOR_LAND) over up to four output words at once: lane l holds row
+// l of each word, and the rows' extents, first two entries and their probes
+// are loaded together for all the words; a probe settles a row at a true
+// product.  The rows left open (more entries, no true product yet) are
+// compacted across the words and stream their remaining entries, 64 rows at
+// a time, with early exit; a row takes at most about 2/d positions per step
+// while enough rows are live (d = the input's density estimated from the
+// probes), so a dense input does not gather past a row's first hit.  Then
+// each word's epilogue; allowed rows longer than kPushSplit keep their
+// output bits for the fix-up kernel.  res: per-wave LDS, [4][64] results.
+// The OR stream of the open rows (one per lane: `own`; positions [rc, re)),
+// K steps of 64 positions laid out and loaded at once (K > 1 when the
+// probes found the input sparse: a row then rarely stops early).
+template <int K>
+__device__ __forceinline__ void or_stream(const MxvArgs &a, int *mark, int cmin, bool own,
+                                          int &rc, int re, bool &has, bool &tru) {
+  using T = uint8_t;
+  const int ln = threadIdx.x & 63;
+  const int32_t *ci = a.pull.ci;
+  for (bool more = true; more;) {
+    int64_t pos[K];
+    int sev[K], exv[K];
+    bool st[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      pos[s] = -1;
+      sev[s] = exv[s] = 0;
+      st[s] = false;
+      if (!more) continue;
+      int len = (own && !tru) ? re - rc : 0;
+      if (cmin < 64) {
+        const int nl = __popcll(__ballot(len > 0));
+        len = min(len, max(cmin, nl ? (64 + nl - 1) / nl : 64));
+      }
+      const int incl = wave_incl_scan(len);
+      const int total = lane_last(incl);
+      if (total == 0) {
+        more = false;
+        continue;
+      }
+      const int excl = incl - len;
+      const bool starts = len > 0 && excl < 64;
+      const int r = slot_rows(mark, starts, excl);
+      const int rcur = __shfl(rc, r), rexcl = __shfl(excl, r);
+      if (ln < total) pos[s] = rcur + (ln - rexcl);
+      sev[s] = min(incl, 64);
+      exv[s] = excl;
+      st[s] = starts;
+      if (starts) rc += sev[s] - excl;
+    }
+    int jj[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) jj[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+    uint64_t bw[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) bw[s] = jj[s] >= 0 ? a.u_bm[jj[s] >> 6] : 0ull;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const bool pres = jj[s] >= 0 && ((bw[s] >> (jj[s] & 63)) & 1ull);
+      const bool prod = pres && u_at<T>(a, jj[s]) != 0 && mat_true(a.pull, pos[s]);
+      const uint64_t seg = st[s] ? (mask_below(sev[s]) & ~mask_below(exv[s])) : 0ull;
+      if (__ballot(pres) & seg) has = true;
+      if (__ballot(prod) & seg) tru = true;
+    }
+  }
+}
+
+__device__ void pull_or_words(const MxvArgs &a, const int64_t (&wd)[4], int nq, int *mark,
+                              uint8_t (*res)[64]) {
+  using T = uint8_t;
+  const int ln = threadIdx.x & 63;
+  const int32_t *rp = a.pull.rp;
+  T *w = (T *)a.w_val;
+  int64_t ri[4];
+  bool inb[4], allowed[4], lng[4], act[4];
+  int cur[4], end[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ri[q] = wd[q] * 64 + ln;
+    inb[q] = q < nq && ri[q] < a.n_out;
+    allowed[q] = inb[q] && mask_allowed(a, ri[q]);
+    cur[q] = allowed[q] ? rp[ri[q]] : 0;
+    end[q] = allowed[q] ? rp[ri[q] + 1] : 0;
+  }
+  int2 f[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    lng[q] = end[q] - cur[q] > kPushSplit;
+    // long rows take the probes too: a true one settles the row here, and
+    // its pieces and fix-up are skipped
+    act[q] = allowed[q] && end[q] > cur[q];
+    f[q] = act[q] ? a.pull.first2[ri[q]] : make_int2(-1, -1);
+  }
+  bool settled[4];
+  uint64_t b0[4], b1[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    b0[q] = f[q].x >= 0 ? a.u_bm[f[q].x >> 6] : 0ull;
+    b1[q] = f[q].y >= 0 ? a.u_bm[f[q].y >> 6] : 0ull;
+  }
+  int np = 0, nh = 0;
+  uint64_t rest[4];
+  int nrest = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bool p0 = f[q].x >= 0 && ((b0[q] >> (f[q].x & 63)) & 1ull);
+    const bool p1 = f[q].y >= 0 && ((b1[q] >> (f[q].y & 63)) & 1ull);
+    const bool tru = (p0 && u_at<T>(a, f[q].x) != 0 && mat_true(a.pull, cur[q])) ||
+                     (p1 && u_at<T>(a, f[q].y) != 0 && mat_true(a.pull, cur[q] + 1));
+    np += __popcll(__ballot(f[q].x >= 0)) + __popcll(__ballot(f[q].y >= 0));
+    nh += __popcll(__ballot(p0)) + __popcll(__ballot(p1));
+    res[q][ln] = (uint8_t)((p0 || p1 ? 1 : 0) | (tru ? 2 : 0));
+    settled[q] = lng[q] && tru;
+    if (allowed[q] && lng[q]) a.settled[ri[q]] = tru ? 1 : 0;
+    cur[q] = min(cur[q] + 2, end[q]);
+    rest[q] = __ballot(act[q] && !lng[q] && !tru && end[q] > cur[q]);
+    nrest += __popcll(rest[q]);
+  }
+  const int cmin = nh == 0 ? 64 : min(64, max(4, 2 * np / nh));
+  for (int sb = 0; sb < nrest; sb += 64) {
+    // this lane's row among the open rows: word oq, lane li
+    const int j = sb + ln;
+    int oq = -1, li = 0, rc = 0, re = 0;
+    int before = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cq = __popcll(rest[q]);
+      const bool mine = j >= before && j < before + cq;
+      const int lq = mine ? nth_set_bit(rest[q], j - before) : 0;
+      const int sc = __shfl(cur[q], lq), se = __shfl(end[q], lq);
+      if (mine) {
+        oq = q;
+        li = lq;
+        rc = sc;
+        re = se;
+      }
+      before += cq;
+    }
+    bool has = false, tru = false;
+    if (cmin == 64) or_stream<kUnroll>(a, mark, cmin, oq >= 0, rc, re, has, tru);
+    else or_stream<1>(a, mark, cmin, oq >= 0, rc, re, has, tru);
+    if (oq >= 0) res[oq][li] |= (uint8_t)((has ? 1 : 0) | (tru ? 2 : 0));
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q >= nq) break;
+    const uint8_t rv = res[q][ln];
+    const bool t_has = (rv & 3) != 0;
+    const T acc = (T)((rv >> 1) & 1);
+    bool out_has = false;
+    const bool deferred = allowed[q] && lng[q] && !settled[q];
+    if (inb[q] && !deferred) {
+      T out = acc;
+      out_has = epilogue<GRB_LOR_LAND_BOOL>(a, ri[q], allowed[q], t_has, acc, &out);
+      if (out_has) w[ri[q]] = out;
+    }
+    const uint64_t lmask = __ballot(deferred);
+    const uint64_t bits = __ballot(out_has);
+    if (ln == 0) a.w_bm[wd[q]] = (bits & ~lmask) | (a.w_bm[wd[q]] & lmask);
+  }
+  wave_lds_sync();
+}
+
+// OR pieces of long rows, four at a time: the first step of each, then the
+// rest of those without a true product in it, all loads of a phase issued
+// together.  Writes each piece's result (presence bit 0, true bit 1 as in
+// hp_has / the partial value).
+__device__ void pull_or_pieces4(const MxvArgs &a, const int64_t (&rk)[4], const int64_t (&bk)[4],
+                                const int64_t (&hk)[4], int np) {
+  using T = uint8_t;
+  const int ln = threadIdx.x & 63;
+  const int32_t *ci = a.pull.ci;
+  int64_t ek[4];
+  bool has[4], tru[4];
+  int j0[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ek[k] = k < np ? min(bk[k] + (int64_t)kPushSplit, (int64_t)a.pull.rp[rk[k] + 1]) : 0;
+    const int64_t pos = bk[k] + ln;
+    j0[k] = (k < np && pos < ek[k]) ? ci[pos] : -1;
+  }
+  uint64_t bw0[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bw0[k] = j0[k] >= 0 ? a.u_bm[j0[k] >> 6] : 0ull;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool pres = j0[k] >= 0 && ((bw0[k] >> (j0[k] & 63)) & 1ull);
+    has[k] = __ballot(pres) != 0ull;
+    tru[k] = __ballot(pres && u_at<T>(a, j0[k]) != 0 && mat_true(a.pull, bk[k] + ln)) != 0ull;
+  }
+  int jr[4][kUnroll - 1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int s = 1; s < kUnroll; ++s) {
+      const int64_t pos = bk[k] + s * 64 + ln;
+      jr[k][s - 1] = (k < np && !tru[k] && pos < ek[k]) ? ci[pos] : -1;
+    }
+  uint64_t bw[4][kUnroll - 1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int s = 0; s < kUnroll - 1; ++s) bw[k][s] = jr[k][s] >= 0 ? a.u_bm[jr[k][s] >> 6] : 0ull;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int s = 0; s < kUnroll - 1; ++s) {
+      const int jj = jr[k][s];
+      const bool pres = jj >= 0 && ((bw[k][s] >> (jj & 63)) & 1ull);
+      if (__ballot(pres)) has[k] = true;
+      if (__ballot(pres && u_at<T>(a, jj) != 0 && mat_true(a.pull, bk[k] + (s + 1) * 64 + ln)))
+        tru[k] = true;
+    }
+    if (ln == 0 && k < np) {
+      ((T *)a.hp_val)[hk[k]] = tru[k] ? 1 : 0;
+      a.hp_has[hk[k]] = has[k] ? 1 : 0;
+    }
+  }
+}
+
 // One piece (positions [b, e), at most kPushSplit = 64 * kUnroll) of a long
 // row, reduced by the wave in a fixed order; every lane gets the result.
 template <int SR>
@@ -666,6 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_mxv_sweep(MxvArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   __shared__ int s_end[kWavesPerBlock][64];
   __shared__ int s_base[kWavesPerBlock][64];
+  __shared__ uint8_t s_res[kWavesPerBlock][4][64];
   if (mxv_dir(a) != GRB_DIR_PULL) return;
   const int wid = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wid;
@@ -694,9 +919,22 @@ __global__ __launch_bounds__(kBlock) void k_mxv_sweep(MxvArgs a) {
           rows = true;
         }
       }
-      for (uint64_t todo = __ballot(rows); todo; todo &= todo - 1) {
-        const int k = __ffsll((unsigned long long)todo) - 1;
-        pull_word<SR>(a, w0 + k, s_mark[wid], s_end[wid], s_base[wid]);
+      uint64_t todo = __ballot(rows);
+      if constexpr (Sr<SR>::lor) {
+        while (todo) {
+          int64_t wds[4] = {0, 0, 0, 0};
+          int nq = 0;
+          while (todo && nq < 4) {
+            wds[nq++] = w0 + __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+          }
+          pull_or_words(a, wds, nq, s_mark[wid], s_res[wid]);
+        }
+      } else {
+        for (; todo; todo &= todo - 1) {
+          const int k = __ffsll((unsigned long long)todo) - 1;
+          pull_word<SR>(a, w0 + k, s_mark[wid], s_end[wid], s_base[wid]);
+        }
       }
     }
   }
@@ -710,18 +948,38 @@ __global__ __launch_bounds__(kBlock) void k_mxv_sweep(MxvArgs a) {
       r = a.pull.split[2 * h];
       b = a.pull.split[2 * h + 1];
       if (!mask_allowed(a, r)) r = -1;
+      // an OR row its probes settled needs no pieces (the flag may not be
+      // set yet when the piece comes first: the work is then only redundant)
+      else if (Sr<SR>::lor && a.settled[r]) r = -1;
     }
-    for (uint64_t todo = __ballot(r >= 0); todo; todo &= todo - 1) {
-      const int k = __ffsll((unsigned long long)todo) - 1;
-      const int64_t rk = __shfl(r, k), bk = __shfl(b, k);
-      const int64_t ek = min(bk + (int64_t)kPushSplit, (int64_t)a.pull.rp[rk + 1]);
-      T acc;
-      bool has;
-      pull_piece<SR>(a, bk, ek, acc, has);
-      if (ln == 0) {
-        const int64_t hk = hb + (int64_t)k * nwaves;
-        hv[hk] = acc;
-        a.hp_has[hk] = has ? 1 : 0;
+    uint64_t todo = __ballot(r >= 0);
+    if constexpr (Sr<SR>::lor) {
+      while (todo) {
+        int64_t rk[4] = {0, 0, 0, 0}, bk[4] = {0, 0, 0, 0}, hk[4] = {0, 0, 0, 0};
+        int np = 0;
+        while (todo && np < 4) {
+          const int k = __ffsll((unsigned long long)todo) - 1;
+          todo &= todo - 1;
+          rk[np] = __shfl(r, k);
+          bk[np] = __shfl(b, k);
+          hk[np] = hb + (int64_t)k * nwaves;
+          ++np;
+        }
+        pull_or_pieces4(a, rk, bk, hk, np);
+      }
+    } else {
+      for (; todo; todo &= todo - 1) {
+        const int k = __ffsll((unsigned long long)todo) - 1;
+        const int64_t rk = __shfl(r, k), bk = __shfl(b, k);
+        const int64_t ek = min(bk + (int64_t)kPushSplit, (int64_t)a.pull.rp[rk + 1]);
+        T acc;
+        bool has;
+        pull_piece<SR>(a, bk, ek, acc, has);
+        if (ln == 0) {
+          const int64_t hk = hb + (int64_t)k * nwaves;
+          hv[hk] = acc;
+          a.hp_has[hk] = has ? 1 : 0;
+        }
       }
     }
   }
@@ -742,6 +1000,7 @@ __global__ __launch_bounds__(kBlock) void k_mxv_fixup(MxvArgs a) {
     const int r = a.pull.split_rows[3 * k], first = a.pull.split_rows[3 * k + 1],
               cnt = a.pull.split_rows[3 * k + 2];
     if (!mask_allowed(a, r)) continue;  // the sweep wrote this row
+    if (Sr<SR>::lor && a.settled[r]) continue;  // ... and this one, settled by its probes
     T acc = Sr<SR>::identity();
     bool has = false;
     for (int p = ln; p < cnt; p += 64) {
@@ -800,7 +1059,7 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
   if (want_pull) {
     if (a.u_from_list)
       launch_list_to_bitmap(a.u_list, a.u_cnt, a.n_in, const_cast<uint64_t *>(a.u_bm), s, &a.gate);
-    hipLaunchKernelGGL(k_mxv_sweep<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_mxv_sweep<SR>, dim3(kSweepGrid), dim3(kBlock), 0, s, a);
     if (a.pull.nsplit_rows > 0) {
       const int gf = (int)std::min<int64_t>(
           (a.pull.nsplit_rows + kWavesPerBlock - 1) / kWavesPerBlock, kExpandGrid);

@@ -309,7 +309,205 @@ __global__ __launch_bounds__(kBlock) void k_sssp_delta_start(SsspArgs a, int32_t
   }
 }
 
+// ---- one-workgroup bucket rounds while the pending set is small -----------
+// The pending set as two LDS lists (consumed / filled: vertex, row start,
+// degree) with membership bits in two bitmaps (F0, F1), so a vertex joins
+// the filled list once per round.  A round: each thread takes entries of the
+// consumed list, clears their bits, reads their distance together with
+// their first out-edges; an entry below the bucket's limit relaxes its edges
+// (atomicMin on the float bits, the target's row extents loaded beside it)
+// and every improved target joins the filled list; an entry above the limit
+// is carried.  The bucket moves to the nearest pending one when no member
+// below the limit is left.  A pending set too large for the lists goes to
+// the wide round kernel as its bitmap and counters.
+__device__ __forceinline__ void small_insert(bool want, int x, int rs, int dg, float dx, float limit,
+                                             float delta, uint64_t *fill, int (*s_v)[kSmallCap],
+                                             int (*s_rs)[kSmallCap], int (*s_dg)[kSmallCap],
+                                             int *s_n, int *s_near, int *s_sd, int *s_lng,
+                                             int *s_far, int nb) {
+  const int ln = threadIdx.x & 63;
+  bool first = false;
+  if (want) {
+    const uint64_t bit = 1ull << (x & 63);
+    first = !(atomicOr((unsigned long long *)&fill[x >> 6], (unsigned long long)bit) & bit);
+  }
+  const uint64_t fm = __ballot(first);
+  if (fm == 0ull) return;
+  int base = 0;
+  if (ln == 0) base = atomicAdd(&s_n[nb], __popcll(fm));
+  base = __shfl(base, 0);
+  const bool nr = first && dx < limit;
+  const int c_near = wave_sum(nr ? 1 : 0), c_sd = wave_sum(nr ? dg : 0);
+  const int c_lng = wave_sum(nr && dg > kPushSplit ? 1 : 0);
+  int far = (first && !nr) ? bucket_of(dx, delta) : INT_MAX;
+  far = lane_last(wave_scan(far, INT_MAX, [](int p, int q) { return p < q ? p : q; }));
+  if (ln == 0) {
+    if (c_near) {
+      atomicAdd(&s_near[nb], c_near);
+      atomicAdd(&s_sd[nb], c_sd);
+      if (c_lng) atomicAdd(&s_lng[nb], c_lng);
+    }
+    if (far != INT_MAX) atomicMin(&s_far[nb], far);
+  }
+  if (first) {
+    const int slot = base + __popcll(fm & mask_below(ln));
+    if (slot < kSmallCap) {
+      s_v[nb][slot] = x;
+      s_rs[nb][slot] = rs;
+      s_dg[nb][slot] = dg;
+    }
+    // (a member past the lists' capacity stays in the bitmap only: the set
+    // then goes to the wide kernel, which reads the bitmap)
+  }
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_sssp_delta_small(SsspArgs a, int32_t source,
+                                                                    int64_t max_rounds,
+                                                                    uint64_t *F0, uint64_t *F1,
+                                                                    uint64_t *F2) {
+  __shared__ int s_v[2][kSmallCap], s_rs[2][kSmallCap], s_dg[2][kSmallCap];
+  __shared__ int s_n[2], s_near[2], s_sd[2], s_lng[2], s_far[2];
+  __shared__ int s_bucket;
+  const int tid = threadIdx.x;
+  const int32_t *rp = a.push.rp, *ci = a.push.ci;
+  const float delta = a.delta;
+  uint64_t *const bm[2] = {F0, F1};
+  if (tid == 0) {
+    const int dg = rp[source + 1] - rp[source];
+    s_v[0][0] = source;
+    s_rs[0][0] = rp[source];
+    s_dg[0][0] = dg;
+    s_n[0] = 1;
+    s_near[0] = 1;
+    s_sd[0] = dg;
+    s_lng[0] = dg > kPushSplit ? 1 : 0;
+    s_far[0] = INT_MAX;
+    s_bucket = 0;
+  }
+  __syncthreads();
+  int64_t d = 0;
+  int b = 0;
+  bool spill = false;
+  for (;;) {
+    const int n = s_n[b];
+    if (n == 0 || d >= max_rounds) break;
+    if (n > kSmallSpill || s_sd[b] > kSmallEdges) {
+      spill = true;
+      break;
+    }
+    const int bucket = s_near[b] > 0 ? s_bucket : s_far[b];
+    __syncthreads();  // every thread has read the counters of list b
+    if (tid == 0) {
+      s_bucket = bucket;
+      s_n[b ^ 1] = s_near[b ^ 1] = s_sd[b ^ 1] = s_lng[b ^ 1] = 0;
+      s_far[b ^ 1] = INT_MAX;
+      a.ctrl->nlev = (int)d + 1;
+      a.ctrl->bucket = bucket;
+      if (a.stats && d < kStatsCap) {
+        a.stats[d * kStatFields + 0] = n;
+        a.stats[d * kStatFields + 1] = s_sd[b];
+        a.stats[d * kStatFields + 2] = GRB_DIR_PUSH;
+        a.stats[d * kStatFields + 3] = bucket;
+      }
+    }
+    __syncthreads();
+    const float limit = (float)(bucket + 1) * delta;
+    uint64_t *const cons = bm[d & 1], *const fill = bm[(d + 1) & 1];
+    for (int base = 0; base < n; base += 4 * kSmallThreads) {
+      int v[4], rs[4], dg[4];
+      float dv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = base + k * kSmallThreads + tid;
+        v[k] = -1;
+        rs[k] = dg[k] = 0;
+        dv[k] = 0.0f;
+        if (i < n) {
+          v[k] = s_v[b][i];
+          rs[k] = s_rs[b][i];
+          dg[k] = s_dg[b][i];
+          atomicAnd((unsigned long long *)&cons[v[k] >> 6], ~(1ull << (v[k] & 63)));
+          dv[k] = a.dist[v[k]];
+        }
+      }
+      // carried: members above the limit stay pending
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        small_insert(v[k] >= 0 && !(dv[k] < limit), v[k], rs[k], dg[k], dv[k], limit, delta, fill,
+                     s_v, s_rs, s_dg, s_n, s_near, s_sd, s_lng, s_far, b ^ 1);
+      int mx = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (v[k] >= 0 && dv[k] < limit) mx = max(mx, dg[k]);
+      for (int q0 = 0; __syncthreads_or(q0 < mx); q0 += 4) {
+        int c[16];
+        float nd[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool ok = v[k] >= 0 && dv[k] < limit && q0 + q < dg[k];
+            c[k * 4 + q] = ok ? ci[rs[k] + q0 + q] : -1;
+            nd[k * 4 + q] = ok ? dv[k] + a.wpush[rs[k] + q0 + q] : 0.0f;
+          }
+        int old[16], r0[16], r1[16];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) {
+          old[x] = 0;
+          r0[x] = r1[x] = 0;
+          if (c[x] >= 0) {
+            old[x] = atomicMin((int *)&a.dist[c[x]], __float_as_int(nd[x]));
+            r0[x] = rp[c[x]];
+            r1[x] = rp[c[x] + 1];
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < 16; ++x)
+          small_insert(c[x] >= 0 && nd[x] < __int_as_float(old[x]), c[x], r0[x], r1[x] - r0[x],
+                       nd[x], limit, delta, fill, s_v, s_rs, s_dg, s_n, s_near, s_sd, s_lng,
+                       s_far, b ^ 1);
+      }
+    }
+    __syncthreads();
+    ++d;
+    b ^= 1;
+  }
+  if (spill) {
+    // the pending set of round d: its bitmap (F[d % 2]) becomes the wide
+    // kernel's F[d % 3]; every other buffer is zero; counters and bucket
+    uint64_t *const F[3] = {F0, F1, F2};
+    uint64_t *src = F[d % 2], *dst = F[d % 3];
+    if (src != dst)
+      for (int64_t w = tid; w < a.nw; w += kSmallThreads) {
+        dst[w] = src[w];
+        src[w] = 0ull;
+      }
+    for (int i = tid; i < 3 * kDeltaSlots; i += kSmallThreads)
+      a.ctrl->lists[i] = (i % kDeltaFields) == 3 ? INT_MAX : 0;
+    __syncthreads();
+    if (tid == 0) {
+      int32_t *cnt = a.ctrl->lists + (d % 3) * kDeltaSlots;
+      cnt[0] = s_near[b];
+      cnt[1] = s_sd[b];
+      cnt[2] = s_lng[b];
+      cnt[3] = s_far[b];
+      cnt[4] = s_n[b];
+      a.ctrl->bucket = s_bucket;
+    }
+  }
+  if (tid == 0) {
+    a.ctrl->small_levels = (int)d;
+    a.ctrl->spilled = spill ? 1 : 0;
+  }
+}
+
 }  // namespace
+
+void launch_sssp_delta_small(const SsspArgs &a, int32_t source, int64_t max_rounds,
+                             uint64_t *const F[3], void *stream) {
+  hipLaunchKernelGGL(k_sssp_delta_small, dim3(1), dim3(kSmallThreads), 0, (hipStream_t)stream, a,
+                     source, max_rounds, F[0], F[1], F[2]);
+}
 
 void launch_sssp_delta_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                              void *stream) {

@@ -105,6 +105,7 @@ class _Session:
     graph: str
     mem: int
     nbytes: int
+    lanes: int
     thread: threading.Thread | None = None
 
 
@@ -112,8 +113,9 @@ class Server:
     """Runs a query trace over an executor (see the module text)."""
 
     def __init__(self, executor, slots: int = 4, lanes: int = 64, lane_mode: bool = True,
-                 level_chunk: dict | None = None):
+                 level_chunk: dict | None = None, session_share: float = 0.5):
         self.ex = executor
+        self.session_share = float(session_share)
         self.pool = executor.pool
         self.slots = 1 if not lane_mode else int(slots)
         self.lanes = int(lanes)
@@ -138,13 +140,24 @@ class Server:
         q.start = q.end = self.now()
         self.pending -= 1
 
+    def lanes_for(self, g: str) -> int:
+        """Lanes of a session on graph g: `lanes`, halved (down to 1) until
+        the session takes at most `session_share` of the memory budget, so
+        that large graphs still get sessions and leave room for other work."""
+        k = self.lanes
+        cap = int(self.pool.size * self.session_share)
+        while k > 1 and self.ex.footprint_session(g, k) > cap:
+            k //= 2
+        return k
+
     def _open_sessions(self):
         """Opens sessions for graphs with waiting BFS queries (oldest first)
         while memory allows; called with the lock held."""
         cand = [(dq[0].arrival, g) for g, dq in self.wait_bfs.items()
                 if dq and g not in self.sessions]
         for _, g in sorted(cand):
-            need = self.ex.footprint_session(g, self.lanes)
+            k = self.lanes_for(g)
+            need = self.ex.footprint_session(g, k)
             if not self.pool.fits_ever(need):
                 dq = self.wait_bfs[g]
                 while dq:
@@ -154,7 +167,7 @@ class Server:
             if off is None:
                 self.deferred += 1
                 break  # oldest first: later graphs wait too
-            s = _Session(g, off, need)
+            s = _Session(g, off, need, k)
             self.sessions[g] = s
             self.max_sessions = max(self.max_sessions, len(self.sessions))
             s.thread = threading.Thread(target=self._drive, args=(s,), daemon=True)
@@ -222,11 +235,11 @@ class Server:
         g = s.graph
         chunk = int(self.level_chunk.get(g, 1))
         busy = {}
-        free = list(range(self.lanes - 1, -1, -1))
+        free = list(range(s.lanes - 1, -1, -1))
         h = None
         level = 0
         try:
-            h = self.ex.session_open(g, self.lanes, s.mem)
+            h = self.ex.session_open(g, s.lanes, s.mem)
             while True:
                 with self.cv:
                     joins = []
@@ -277,15 +290,18 @@ class Server:
                 self.cv.notify_all()
 
     # ---- trace -------------------------------------------------------------------
-    def run(self, queries: list, realtime: bool = True) -> dict:
+    def run(self, queries: list, realtime: bool = True, progress=None) -> dict:
         """Submits each query at its arrival time (realtime) or all at once,
-        waits for all to finish and returns latency statistics."""
+        waits for all to finish and returns latency statistics.  `progress`
+        (optional) is called with the number of queries submitted so far,
+        every 1000 submissions."""
         self.stop = False
         self.t0 = time.perf_counter()
         workers = [threading.Thread(target=self._worker, args=(s,), daemon=True)
                    for s in range(self.slots)]
         for w in workers:
             w.start()
+        submitted = 0
         for q in sorted(queries, key=lambda x: x.arrival):
             if realtime:
                 delay = q.arrival - self.now()
@@ -294,6 +310,9 @@ class Server:
             else:
                 q.arrival = self.now()
             self.submit(q)
+            submitted += 1
+            if progress is not None and submitted % 1000 == 0:
+                progress(submitted)
         with self.cv:
             while self.pending > 0:
                 self.cv.wait(timeout=0.005)

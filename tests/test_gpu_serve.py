@@ -84,7 +84,7 @@ def test_budget_admits_one_session_at_a_time(grb, graphs):
     budget = need + extra + 4096
     qs = trace(raws, 120, 5000.0, 14)
     ex = GpuExecutor(mats, budget=budget, slots=2, sssp_delta={"g60": 64.0})
-    srv = Server(ex, slots=2, lanes=64, level_chunk={"g60": 8})
+    srv = Server(ex, slots=2, lanes=64, level_chunk={"g60": 8}, session_share=1.0)
     st = srv.run(qs, realtime=True)
     assert st["failed"] == 0
     assert st["pool_peak_bytes"] <= budget

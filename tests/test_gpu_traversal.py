@@ -57,6 +57,14 @@ def graph(name):
         src = [0, 1, 2, 3, 10, 11, 12, 130]
         dst = [1, 2, 3, 0, 11, 12, 13, 131]
         g = graphgen.from_edges(name, 133, src, dst, [5, 1, 2, 9, 1, 1, 1, 4])
+    elif name == "lowdeg":
+        # random sparse graph (max degree far below the one-workgroup loop's
+        # limit) whose frontier outgrows that loop's lists after a few levels
+        k = 120000
+        rng = np.random.default_rng(21)
+        src = rng.integers(0, k, 3 * k)
+        dst = rng.integers(0, k, 3 * k)
+        g = graphgen.from_edges(name, k, src, dst, 1 + (src * 7 + dst) % 64)
     elif name == "empty":
         g = graphgen.from_edges(name, 70, [], [], [])
     elif name == "single":
@@ -80,7 +88,7 @@ def matrix(grb, name):
 
 MODES = [("auto_paper", 0, 0), ("auto_exact", 0, 1), ("push", 1, 0), ("pull", 2, 0)]
 SMALL = ["rmat_14", "rmat_18", "rmat_dir_12", "grid_33x70", "path", "star", "clique",
-         "two_comp", "empty", "single"]
+         "two_comp", "empty", "single", "lowdeg"]
 
 
 def _sources(name, n):
@@ -131,6 +139,22 @@ def test_bfs_direction_sequence_and_work(grb, name):
             assert st["direction"][d] == (2 if pull else 1), (rule, d)
 
 
+def test_bfs_level_cap_low_degree(grb):
+    """A level cap inside the one-workgroup loop (grid) and after it handed
+    the frontier to the level kernel (lowdeg): levels up to the cap, parents
+    of every reached vertex by the min-id rule."""
+    for name, caps in (("grid_33x70", (1, 5, 40)), ("lowdeg", (3, 8, 9))):
+        g, adj = graph(name)
+        A = matrix(grb, name)
+        ref_lev, ref_par, nl = oracle.bfs(adj, 0)
+        for cap in caps:
+            lev, par = grb.bfs(A, 0, desc=grb.descriptor(max_iter=cap))
+            want = np.where(ref_lev <= cap, ref_lev, -1)
+            assert np.array_equal(lev.cpu().numpy(), want), (name, cap)
+            wpar = np.where(ref_lev <= cap, ref_par, -1)
+            assert np.array_equal(par.cpu().numpy(), wpar), (name, cap)
+
+
 @pytest.mark.parametrize("name", ["rmat_14", "grid_33x70", "star"])
 def test_bfs_repeatable(grb, name):
     A = matrix(grb, name)
@@ -140,7 +164,7 @@ def test_bfs_repeatable(grb, name):
 
 
 SSSP_GRAPHS = ["rmat_14", "rmat_18", "rmat_dir_12", "grid_33x70", "path", "star", "clique",
-               "two_comp", "empty", "single"]
+               "two_comp", "empty", "single", "lowdeg"]
 
 
 @pytest.mark.parametrize("name", SSSP_GRAPHS)
@@ -183,6 +207,37 @@ def test_sssp_delta_parity(grb, name, delta):
         dist = grb.sssp(A, s, delta=delta)
         ref, _, _ = oracle.sssp(adj, s)
         assert np.array_equal(dist.cpu().numpy(), ref), (name, s, delta)
+
+
+def test_sssp_delta_round_cap_low_degree(grb):
+    """A round cap inside the one-workgroup loop (grid) and after it handed
+    the pending set to the round kernel (lowdeg): the capped distances are
+    never below the exact ones and run to them with enough rounds, and the
+    round records agree with the rounds run."""
+    for name, caps in (("grid_33x70", (3, 40)), ("lowdeg", (4, 30))):
+        g, adj = graph(name)
+        A = matrix(grb, name)
+        ref, _, _ = oracle.sssp(adj, 0)
+        for delta in (7.5, 256.0):
+            for cap in caps:
+                dist = grb.sssp(A, 0, delta=delta, desc=grb.descriptor(max_iter=cap))
+                got = dist.cpu().numpy()
+                assert np.all(got >= ref), (name, delta, cap)
+                st = grb.last_stats()
+                assert st["iterations"] <= cap
+            full = grb.sssp(A, 0, delta=delta).cpu().numpy()
+            assert np.array_equal(full, ref), (name, delta)
+
+
+def test_sssp_negative_weights_rejected(grb):
+    g = graphgen.from_edges("neg", 4, [0, 1, 2], [1, 2, 3], [1.0, -2.0, 3.0])
+    A = grb.Matrix.from_raw(g)
+    with pytest.raises(grb.GrbError) as e:
+        grb.sssp(A, 0)
+    assert e.value.code == 4
+    with pytest.raises(grb.GrbError) as e:
+        grb.sssp(A, 0, delta=2.0)
+    assert e.value.code == 4
 
 
 def test_sssp_delta_argument_errors(grb):
