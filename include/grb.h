@@ -362,6 +362,22 @@ grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source
                  const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * grb_bfs for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same BFS,
+ * levels and parents as grb_bfs, with its workspace in a device array of
+ * the library (8 MiB + 64 KiB, held on each GPU the library runs on until
+ * the process ends) instead of a caller buffer; read-backs use no pinned
+ * staging buffer; GRB_PROFILE is ignored (it would create timing events).
+ * Graphs of more than 2^24 vertices: GRB_INSUFFICIENT_SPACE.  Runs on the
+ * current device, whose array is found on the first call there.  All calls
+ * on one GPU share its array: calls that overlap on one GPU race (issue them
+ * from one stream, one at a time).  Other errors and synchronisation as
+ * grb_bfs.
+ */
+grb_info grb_bfs_noalloc(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source,
+                         const grb_descriptor *d, void *stream);
+
+/*
  * SSSP from `source` (Section 7.2): Bellman-Ford over MIN_PLUS with the
  * frontier sparsified to the vertices whose distance improved in the last
  * round; stops when none improved.  dist[n] (fp32): +inf where unreached.

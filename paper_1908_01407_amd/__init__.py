@@ -130,6 +130,7 @@ _SIGS = {
     "grb_msbfs_session_step": ([_p, _i32, _p, ctypes.POINTER(_i32), _p], _i32),
     "grb_msbfs_session_extract": ([_p, _p, _i32, _p, _p], _i32),
     "grb_msbfs_session_free": ([_PP], _i32),
+    "grb_bfs_noalloc": ([_p, _p, _p, _i32, ctypes.POINTER(Descriptor), _p], _i32),
     "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
                       ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
