@@ -88,6 +88,8 @@ def _load():
         lib.oracle_msbfs.restype = i32
         lib.oracle_mxv.argtypes = [p, i32, i32, p, p, p, p, p, p, i32, i32, p, p]
         lib.oracle_mxv.restype = i32
+        lib.oracle_cc.argtypes = [p, p]
+        lib.oracle_cc.restype = i64
         _lib = lib
     return _lib
 
@@ -195,6 +197,16 @@ def triangles(adj: Adjacency):
     if t < 0:
         raise ValueError("oracle_triangles: bad input")
     return int(t), pv
+
+
+def cc(adj: Adjacency):
+    """(labels int32[n], number of components): the smallest vertex id of
+    each vertex's component (symmetric adjacency)."""
+    lab = np.empty(adj.n, dtype=np.int32)
+    c = _load().oracle_cc(adj._h, _ptr(lab))
+    if c < 0:
+        raise ValueError("oracle_cc: bad input")
+    return lab, int(c)
 
 
 def msbfs(adj: Adjacency, sources, nthreads: int = 1):

@@ -22,6 +22,10 @@
  *   oracle_triangles   triangle count (and per-vertex counts) by definition
  *   oracle_mxv         the masked semiring product over dense arrays, by its
  *                      definition, one output index at a time
+ *   oracle_cc          connected components of a symmetric graph: each
+ *                      vertex labelled with the smallest vertex id of its
+ *                      component (the fixed point the linear-algebraic
+ *                      connected-components iteration of Section 7.4 reaches)
  *
  * parity pins: see tests/test_oracle_*.py (brute force, closed forms,
  * invariants, library special cases).
@@ -589,4 +593,40 @@ int32_t oracle_mxv(const oracle_adj *a, int32_t sr, int32_t vec_first, const dou
     }
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* connected components                                                */
+/* ------------------------------------------------------------------ */
+
+/* label[v] = the smallest id in v's component: vertices are visited in
+ * increasing id order, and an unlabelled one starts a queue search that
+ * labels its whole component with its own id (no smaller id can be in it,
+ * since that vertex would already have labelled the component).  Returns
+ * the number of components, or -1 on bad input. */
+int64_t oracle_cc(const oracle_adj *a, int32_t *label) {
+  if (!a || !label) return -1;
+  int32_t *queue = (int32_t *)malloc((size_t)(a->n > 0 ? a->n : 1) * sizeof(int32_t));
+  if (!queue) return -1;
+  for (int64_t v = 0; v < a->n; ++v) label[v] = -1;
+  int64_t comps = 0;
+  for (int64_t s = 0; s < a->n; ++s) {
+    if (label[s] >= 0) continue;
+    ++comps;
+    int64_t head = 0, tail = 0;
+    label[s] = (int32_t)s;
+    queue[tail++] = (int32_t)s;
+    while (head < tail) {
+      const int32_t u = queue[head++];
+      for (int64_t e = a->off[u]; e < a->off[u + 1]; ++e) {
+        const int32_t v = a->nbr[e];
+        if (label[v] < 0) {
+          label[v] = (int32_t)s;
+          queue[tail++] = v;
+        }
+      }
+    }
+  }
+  free(queue);
+  return comps;
 }
