@@ -294,7 +294,8 @@ typedef enum grb_op {
   GRB_OP_MSBFS = 4,    /* k = number of sources (batched BFS) */
   GRB_OP_NVALS = 5,
   GRB_OP_MXM = 6,      /* grb_mxm_masked and grb_tricount (A unused) */
-  GRB_OP_EXTRACT = 7   /* grb_vector_extract: k = vector length (A unused) */
+  GRB_OP_EXTRACT = 7,  /* grb_vector_extract: k = vector length (A unused) */
+  GRB_OP_CC = 8        /* grb_cc */
 } grb_op;
 
 /* Bytes of device workspace the operation needs on matrix A.  Workspace
@@ -439,6 +440,23 @@ grb_info grb_pagerank_adaptive(void *p, grb_type type, grb_matrix A, double damp
                                double *delta_out, int64_t *active_out,
                                const grb_descriptor *d, void *ws, size_t ws_bytes,
                                void *stream);
+
+/*
+ * Connected components (Section 7.4: FastSV, the linear-algebraic form of
+ * Shiloach-Vishkin hooking and shortcutting).  labels[n] (int32) receives,
+ * for every vertex, the smallest vertex id of its component (weak
+ * components of a directed matrix: A must then carry the CSR of A^T, else
+ * GRB_NOT_IMPLEMENTED).  Each iteration takes the smallest grandparent among
+ * the neighbours with grb_mxv over MIN_SECOND (accumulated with min), then
+ * hooks the old parent and the vertex to it, shortcuts to the grandparent
+ * and recomputes the grandparents; it stops once no grandparent changes or
+ * after d->max_iter iterations (0 = no cap).  *iters (may be
+ * NULL) receives the iterations run.  The descriptor may carry no flags but
+ * GRB_PROFILE; its direction and switch rule apply to the products.
+ * Workspace: GRB_OP_CC.  Synchronises once per batch of iterations.
+ */
+grb_info grb_cc(int32_t *labels, grb_matrix A, int32_t *iters, const grb_descriptor *d,
+                void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Masked sparse matrix-matrix product in the dot-product form (Section 6.3.4,

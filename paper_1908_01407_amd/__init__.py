@@ -49,7 +49,7 @@ GRB_MASK_COMP, GRB_MASK_STRUCT, GRB_TRAN_A, GRB_REPLACE, GRB_PROFILE = 0x1, 0x2,
 DIR_AUTO, DIR_PUSH, DIR_PULL = 0, 1, 2
 SWITCH_PAPER, SWITCH_EXACT = 0, 1
 GRB_MATRIX_SYMMETRIC = 0x1
-OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS, OP_MXM, OP_EXTRACT = range(8)
+OP_MXV, OP_BFS, OP_SSSP, OP_PAGERANK, OP_MSBFS, OP_NVALS, OP_MXM, OP_EXTRACT, OP_CC = range(9)
 STATS_MAX = 256
 
 
@@ -131,6 +131,7 @@ _SIGS = {
     "grb_msbfs_session_extract": ([_p, _p, _i32, _p, _p], _i32),
     "grb_msbfs_session_free": ([_PP], _i32),
     "grb_bfs_noalloc": ([_p, _p, _p, _i32, ctypes.POINTER(Descriptor), _p], _i32),
+    "grb_cc": ([_p, _p, ctypes.POINTER(_i32), ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
     "grb_pagerank": ([_p, _i32, _p, ctypes.c_double, _i32, ctypes.c_double,
                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
                       ctypes.POINTER(Descriptor), _p, _sz, _p], _i32),
@@ -604,6 +605,19 @@ class MsbfsSession:
         check(_lib.grb_msbfs_session_extract(self.handle, ln.ctypes.data, ln.size, _ptr(out),
                                              _stream(self.stream)), "grb_msbfs_session_extract")
         return out[: ln.size, : self.n]
+
+
+def cc(A: Matrix, *, desc: Descriptor | None = None, ws=None, stream=None):
+    """(labels int32[n], iterations) via grb_cc: each vertex labelled with the
+    smallest vertex id of its component."""
+    torch = _torch()
+    labels = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=A.device)
+    ws = ws if ws is not None else workspace(OP_CC, A)
+    it = ctypes.c_int32()
+    check(_lib.grb_cc(_ptr(labels), A.handle, ctypes.byref(it),
+                      ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
+                      _stream(stream)), "grb_cc")
+    return labels[: A.nrows], it.value
 
 
 def pagerank(A: Matrix, *, dtype=None, damping: float = 0.85, max_iter: int = 50,

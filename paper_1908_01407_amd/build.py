@@ -25,7 +25,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["grb_kernels.hip", "grb_bfs.hip", "grb_sssp.hip", "grb_sssp_delta.hip", "grb_msbfs.hip", "grb_spmv.hip", "grb_mxv.hip", "grb_mxm.hip", "grb_noalloc.hip", "grb_api.cpp", "grb_build.cpp"]
+SOURCES = ["grb_kernels.hip", "grb_bfs.hip", "grb_sssp.hip", "grb_sssp_delta.hip", "grb_msbfs.hip", "grb_spmv.hip", "grb_mxv.hip", "grb_mxm.hip", "grb_cc.hip", "grb_noalloc.hip", "grb_api.cpp", "grb_build.cpp"]
 
 
 def _compile(src: str) -> str:

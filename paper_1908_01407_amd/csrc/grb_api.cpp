@@ -227,6 +227,32 @@ ExtractWs extract_layout(void *ws, int64_t n) {
   return t;
 }
 
+struct CcWs {
+  int64_t *changed;
+  int32_t *f, *f_old, *gf, *mngf;
+  uint64_t *gf_bm, *mngf_bm;
+  void *mxv;
+  size_t mxv_bytes;
+  size_t bytes;
+};
+
+CcWs cc_layout(void *ws, int64_t n, size_t mxv_bytes) {
+  Carver c(ws);
+  CcWs t{};
+  const size_t m = (size_t)std::max<int64_t>(n, 1), mw = (size_t)std::max<int64_t>(words_of(n), 1);
+  t.changed = c.take<int64_t>((size_t)kStatsCap);
+  t.f = c.take<int32_t>(m);
+  t.f_old = c.take<int32_t>(m);
+  t.gf = c.take<int32_t>(m);
+  t.mngf = c.take<int32_t>(m);
+  t.gf_bm = c.take<uint64_t>(mw);
+  t.mngf_bm = c.take<uint64_t>(mw);
+  t.mxv = c.take<char>(mxv_bytes);
+  t.mxv_bytes = mxv_bytes;
+  t.bytes = c.off;
+  return t;
+}
+
 grb_info check_ws(void *ws, size_t have, size_t need) {
   if (need > have) return GRB_INSUFFICIENT_SPACE;
   if (!ws) return GRB_NULL_POINTER;
@@ -1244,6 +1270,14 @@ grb_info grb_workspace_size(grb_op op, grb_matrix A, int64_t k, size_t *bytes) {
     *bytes = kMxmWs;
     return GRB_SUCCESS;
   }
+  if (op == GRB_OP_CC) {
+    if (!A) return GRB_UNINITIALIZED_OBJECT;
+    size_t mb = 0;
+    grb_info info = grb_workspace_size(GRB_OP_MXV, A, 0, &mb);
+    if (info != GRB_SUCCESS) return info;
+    *bytes = cc_layout(nullptr, A->nrows, mb).bytes;
+    return GRB_SUCCESS;
+  }
   if (op == GRB_OP_EXTRACT) {
     if (k < 0 || k >= INT32_MAX) return GRB_INVALID_VALUE;
     *bytes = extract_layout(nullptr, k).bytes;
@@ -1607,6 +1641,98 @@ grb_info grb_msbfs_session_free(grb_msbfs_session *ss) {
   if (!ss) return GRB_NULL_POINTER;
   delete *ss;
   *ss = nullptr;
+  return GRB_SUCCESS;
+}
+
+grb_info grb_cc(int32_t *labels, grb_matrix A, int32_t *iters, const grb_descriptor *d,
+                void *ws, size_t ws_bytes, void *stream) {
+  if (!A || !A->prepared) return GRB_UNINITIALIZED_OBJECT;
+  if (!labels) return GRB_NULL_POINTER;
+  if (A->nrows != A->ncols) return GRB_DIMENSION_MISMATCH;
+  if (!A->symmetric && !A->at.valid()) return GRB_NOT_IMPLEMENTED;  // needs both directions
+  grb_descriptor desc;
+  grb_info info = resolve_desc(d, &desc);
+  if (info != GRB_SUCCESS) return info;
+  if (desc.flags & ~(uint32_t)GRB_PROFILE) return GRB_INVALID_VALUE;
+  size_t mb = 0;
+  if ((info = grb_workspace_size(GRB_OP_MXV, A, 0, &mb)) != GRB_SUCCESS) return info;
+  const int64_t n = A->nrows;
+  CcWs t = cc_layout(ws, n, mb);
+  if ((info = check_ws(ws, ws_bytes, t.bytes)) != GRB_SUCCESS) return info;
+  hipStream_t s = (hipStream_t)stream;
+  CcArgs a;
+  a.n = n;
+  a.nw = words_of(n);
+  a.f = t.f;
+  a.f_old = t.f_old;
+  a.gf = t.gf;
+  a.mngf = t.mngf;
+  a.labels = labels;
+  a.gf_bm = t.gf_bm;
+  a.mngf_bm = t.mngf_bm;
+  a.changed = t.changed;
+  int32_t it = 0;
+  if (n > 0) {
+    launch_cc_init(a, stream);
+    grb_vector_s gfv, mnv;
+    gfv.n = mnv.n = n;
+    gfv.type = mnv.type = GRB_INT32;
+    gfv.values = t.gf;
+    gfv.bitmap = t.gf_bm;
+    mnv.values = t.mngf;
+    mnv.bitmap = t.mngf_bm;
+    // the product: mngf = min(mngf, A (min, second) gf); a directed matrix
+    // also takes A^T (weak components)
+    grb_descriptor pd = desc;
+    pd.flags = 0;
+    grb_descriptor pt = pd;
+    pt.flags = GRB_TRAN_A;
+    const int64_t cap = desc.max_iter > 0 ? desc.max_iter : (int64_t)INT32_MAX;
+    int chunk = 4;
+    bool done = false;
+    // per-iteration change counts, a ring of kStatsCap slots (cleared before
+    // each batch reuses them); the first kStatsCap go to the stats
+    std::vector<int64_t> ch((size_t)kStatsCap, 0), rec_ch((size_t)kStatsCap, 0);
+    while (!done && it < cap) {
+      const int32_t it0 = it;
+      const int nb = (int)std::min<int64_t>(chunk, cap - it);
+      const int s0 = it0 % kStatsCap, s1 = std::min(kStatsCap, s0 + nb);
+      launch_fill_u64((uint64_t *)t.changed + s0, s1 - s0, 0ull, stream);
+      if (s0 + nb > kStatsCap) launch_fill_u64((uint64_t *)t.changed, s0 + nb - kStatsCap, 0ull, stream);
+      for (int i = 0; i < nb; ++i, ++it) {
+        info = grb_mxv(&mnv, nullptr, GRB_ACCUM_MIN, GRB_MIN_SECOND_INT32, A, &gfv, &pd, t.mxv,
+                       t.mxv_bytes, stream);
+        if (info == GRB_SUCCESS && !A->symmetric)
+          info = grb_mxv(&mnv, nullptr, GRB_ACCUM_MIN, GRB_MIN_SECOND_INT32, A, &gfv, &pt, t.mxv,
+                         t.mxv_bytes, stream);
+        if (info != GRB_SUCCESS) return info;
+        launch_cc_step(a, it % kStatsCap, stream);
+      }
+      if ((info = check_launch()) != GRB_SUCCESS) return info;
+      if (!read_back({{ch.data(), t.changed, (size_t)kStatsCap * sizeof(int64_t)}}, s))
+        return GRB_PANIC;
+      for (int32_t i = it0; i < it; ++i) {
+        const int64_t c = ch[(size_t)(i % kStatsCap)];
+        if (i < kStatsCap) rec_ch[(size_t)i] = c;
+        if (c == 0) {  // no grandparent changed: converged
+          it = i + 1;
+          done = true;
+          break;
+        }
+      }
+      chunk = std::min(chunk * 2, 64);
+    }
+    launch_cc_out(a, stream);
+    if ((info = check_launch()) != GRB_SUCCESS) return info;
+    if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
+    std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
+    for (int32_t i = 0; i < std::min<int32_t>(it, kStatsCap); ++i) {
+      rec[(size_t)i * kStatFields + 0] = rec_ch[(size_t)i];
+      rec[(size_t)i * kStatFields + 2] = GRB_DIR_PULL;
+    }
+    finish_stats(GRB_OP_CC, it, rec, {}, it * (A->symmetric ? 4 : 5), 0.0);
+  }
+  if (iters) *iters = it;
   return GRB_SUCCESS;
 }
 

@@ -337,6 +337,17 @@ void launch_msbfs_session_join(const MsbfsArgs &a, const int32_t *lanes, const i
 void launch_msbfs_session_extract(const MsbfsArgs &a, const int32_t *lanes, int32_t count,
                                   int32_t *out, void *stream);
 
+// connected components (grb_cc.hip): FastSV vectors in the workspace
+struct CcArgs {
+  int64_t n = 0, nw = 0;
+  int32_t *f = nullptr, *f_old = nullptr, *gf = nullptr, *mngf = nullptr, *labels = nullptr;
+  uint64_t *gf_bm = nullptr, *mngf_bm = nullptr;
+  int64_t *changed = nullptr;  // per iteration: vertices whose grandparent changed
+};
+void launch_cc_init(const CcArgs &a, void *stream);
+void launch_cc_step(const CcArgs &a, int32_t it, void *stream);  // hooking .. grandparents
+void launch_cc_out(const CcArgs &a, void *stream);
+
 // generic masked products (grb_mxv.hip)
 struct MxvArgs {
   int64_t n_out = 0, n_in = 0, nw_out = 0, nw_in = 0, nnz = 0;

@@ -985,41 +985,73 @@ __global__ __launch_bounds__(kBlock) void k_mxv_sweep(MxvArgs a) {
   }
 }
 
-// One wave per allowed long row: lane l combines the pieces l, l + 64, ...
-// in order, then the lanes' results are combined in a fixed order.
+// Epilogue of long row r from its combined pieces (output bit by atomic:
+// other rows of the word are written by other lanes and waves).
+template <int SR>
+__device__ __forceinline__ void long_row_out(const MxvArgs &a, int64_t r, bool has,
+                                             typename Sr<SR>::T acc) {
+  using T = typename Sr<SR>::T;
+  T out = acc;
+  const bool out_has = epilogue<SR>(a, r, true, has, acc, &out);
+  const unsigned long long bit = 1ull << (r & 63);
+  if (out_has) {
+    ((T *)a.w_val)[r] = out;
+    atomicOr((unsigned long long *)&a.w_bm[r >> 6], bit);
+  } else {
+    atomicAnd((unsigned long long *)&a.w_bm[r >> 6], ~bit);
+  }
+}
+
+// The allowed long rows not settled by their probes: each lane takes one row
+// of 64 and combines its pieces in order when it has at most kFixLanePieces;
+// a row with more is combined by the whole wave (lane l: pieces l, l + 64,
+// ..., then the lanes in a fixed order).  Either way one fixed order per row.
+constexpr int kFixLanePieces = 32;
+
 template <int SR>
 __global__ __launch_bounds__(kBlock) void k_mxv_fixup(MxvArgs a) {
   using T = typename Sr<SR>::T;
   if (mxv_dir(a) != GRB_DIR_PULL) return;
   const T *hv = (const T *)a.hp_val;
-  T *w = (T *)a.w_val;
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t k = gw; k < a.pull.nsplit_rows; k += nwaves) {
-    const int r = a.pull.split_rows[3 * k], first = a.pull.split_rows[3 * k + 1],
-              cnt = a.pull.split_rows[3 * k + 2];
-    if (!mask_allowed(a, r)) continue;  // the sweep wrote this row
-    if (Sr<SR>::lor && a.settled[r]) continue;  // ... and this one, settled by its probes
-    T acc = Sr<SR>::identity();
-    bool has = false;
-    for (int p = ln; p < cnt; p += 64) {
-      if (!a.hp_has[first + p]) continue;
-      has = true;
-      acc = Sr<SR>::add(acc, hv[first + p]);
+  for (int64_t k0 = gw * 64; k0 < a.pull.nsplit_rows; k0 += nwaves * 64) {
+    const int64_t k = k0 + ln;
+    int r = -1, first = 0, cnt = 0;
+    bool todo = false;
+    if (k < a.pull.nsplit_rows) {
+      r = a.pull.split_rows[3 * k];
+      first = a.pull.split_rows[3 * k + 1];
+      cnt = a.pull.split_rows[3 * k + 2];
+      // rows outside the mask were written by the sweep, and so were the OR
+      // rows their probes settled
+      todo = mask_allowed(a, r) && !(Sr<SR>::lor && a.settled[r]);
     }
-    has = __ballot(has) != 0ull;
-    acc = lane_last(wave_scan(acc, Sr<SR>::identity(), SrAdd<SR>()));
-    if (ln == 0) {
-      T out = acc;
-      const bool out_has = epilogue<SR>(a, r, true, has, acc, &out);
-      const unsigned long long bit = 1ull << (r & 63);
-      if (out_has) {
-        w[r] = out;
-        atomicOr((unsigned long long *)&a.w_bm[r >> 6], bit);
-      } else {
-        atomicAnd((unsigned long long *)&a.w_bm[r >> 6], ~bit);
+    const bool big = todo && cnt > kFixLanePieces;
+    if (todo && !big) {
+      T acc = Sr<SR>::identity();
+      bool has = false;
+      for (int p = 0; p < cnt; ++p) {
+        if (!a.hp_has[first + p]) continue;
+        has = true;
+        acc = Sr<SR>::add(acc, hv[first + p]);
       }
+      long_row_out<SR>(a, r, has, acc);
+    }
+    for (uint64_t bm = __ballot(big); bm; bm &= bm - 1) {
+      const int kk = __ffsll((unsigned long long)bm) - 1;
+      const int rr = __shfl(r, kk), ff = __shfl(first, kk), cc = __shfl(cnt, kk);
+      T acc = Sr<SR>::identity();
+      bool has = false;
+      for (int p = ln; p < cc; p += 64) {
+        if (!a.hp_has[ff + p]) continue;
+        has = true;
+        acc = Sr<SR>::add(acc, hv[ff + p]);
+      }
+      has = __ballot(has) != 0ull;
+      acc = lane_last(wave_scan(acc, Sr<SR>::identity(), SrAdd<SR>()));
+      if (ln == 0) long_row_out<SR>(a, rr, has, acc);
     }
   }
 }
@@ -1061,8 +1093,7 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
       launch_list_to_bitmap(a.u_list, a.u_cnt, a.n_in, const_cast<uint64_t *>(a.u_bm), s, &a.gate);
     hipLaunchKernelGGL(k_mxv_sweep<SR>, dim3(kSweepGrid), dim3(kBlock), 0, s, a);
     if (a.pull.nsplit_rows > 0) {
-      const int gf = (int)std::min<int64_t>(
-          (a.pull.nsplit_rows + kWavesPerBlock - 1) / kWavesPerBlock, kExpandGrid);
+      const int gf = (int)std::min<int64_t>((a.pull.nsplit_rows + kBlock - 1) / kBlock, kExpandGrid);
       hipLaunchKernelGGL(k_mxv_fixup<SR>, dim3(gf), dim3(kBlock), 0, s, a);
     }
   }
