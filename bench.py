@@ -169,6 +169,105 @@ def short_name(name):
     return name.split("(")[0][:60]
 
 
+def serve_report(paths):
+    """Markdown tables of the serving runs in the given bench output files
+    (one JSON line each): per load point and budget, p50/p99 per query type
+    and graph, batched sessions against the FIFO server."""
+    out = []
+    for path in paths:
+        with open(path) as f:
+            d = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
+        sv = d.get("serving")
+        if not sv:
+            continue
+        out.append(f"## {os.path.basename(path)}: budget {sv['budget_bytes'] >> 20} MiB, "
+                   f"{sv['queries_per_point']} queries per point, {sv['mix']}")
+        sat = sv["saturation"]
+        if "batched" in sat:
+            out.append(f"saturation (all queries at once): batched {sat['batched']['qps']} q/s, "
+                       f"FIFO {sat['fifo']['qps']} q/s")
+        else:
+            out.append(f"saturation rate given: {sat['batched_qps_given']} q/s ({sat['note']})")
+        out.append(f"session lanes: {sv['session_lanes']}")
+        graphs = sorted(sv["graphs"])
+
+        def rows(tag, st):
+            r = [f"| {tag} | all | {st['p50_ms']} | {st['p99_ms']} | {st['qps']} |"]
+            for kind in ("bfs", "sssp"):
+                r.append(f"| {tag} | {kind} | {st[kind]['p50_ms']} | {st[kind]['p99_ms']} | |")
+                for g in graphs:
+                    x = st["by_graph"].get(g, {}).get(kind)
+                    if x:
+                        r.append(f"| {tag} | {kind} {g} (n={x['n']}) | {x['p50_ms']} | "
+                                 f"{x['p99_ms']} | |")
+            return r
+        for pt in sv.get("points", []):
+            b, f = pt["batched"], pt["fifo"]
+            out.append("")
+            out.append(f"### load {pt['load_of_batched_saturation']} x saturation = "
+                       f"{pt['rate_qps']} q/s (batched: deferred {b['deferred_admissions']}, "
+                       f"drains {b.get('session_drains', 0)}, max sessions {b['max_sessions']}, "
+                       f"pool peak {b['pool_peak_bytes'] >> 20} MiB, mean batch {b['mean_batch']})")
+            out.append("| server | queries | p50 ms | p99 ms | q/s |")
+            out.append("|---|---|---|---|---|")
+            out += rows("batched", b) + rows("FIFO", f)
+        for sw in sv.get("budget_sweep", []):
+            st = sw["stats"]
+            out.append("")
+            out.append(f"### budget {sw['budget_bytes'] >> 20} MiB at 0.75 x saturation "
+                       f"(deferred {st['deferred_admissions']}, drains "
+                       f"{st.get('session_drains', 0)}, max sessions {st['max_sessions']}, "
+                       f"pool peak {st['pool_peak_bytes'] >> 20} MiB)")
+            out.append("| server | queries | p50 ms | p99 ms | q/s |")
+            out.append("|---|---|---|---|---|")
+            out += rows("batched", st)
+        out.append("")
+    return "\n".join(out)
+
+
+MXV_STAGES = [("k_mxv_init", "mxv_init"), ("k_compact", "compact"), ("k_mxv_list_prep", "list_prep"),
+              ("k_mxv_prep", "mxv_prep"), ("k_mxv_push", "mxv_push"), ("k_mxv_merge", "mxv_merge"),
+              ("k_mxv_sweep", "mxv_pull"), ("k_mxv_fixup", "mxv_pull_fixup")]
+
+
+def mxv_trace_summary(d):
+    """Per-stage kernel durations (us) of the mxv sweep from a rocprofv3
+    kernel trace (csv) of a bench run: calls start at each k_mxv_init and
+    come in the sweep's order (q, p, direction; one warm-up and five timed
+    calls each); the table gives the mean of the timed calls."""
+    paths = sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True))
+    rows = []
+    for path in paths:
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    calls = []
+    for r in rows:
+        name = r["Kernel_Name"]
+        stage = next((st for k, st in MXV_STAGES if k + "(" in name or k + "<" in name), None)
+        if stage is None:
+            continue
+        if stage == "mxv_init":
+            calls.append({})
+        if not calls:
+            continue
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        calls[-1][stage] = calls[-1].get(stage, 0.0) + us
+    points = [(q, p, c) for q in (0.0, 0.5) for p in (1e-4, 1e-3, 1e-2, 0.05, 0.2, 0.5)
+              for c in ("push", "pull", "auto")]
+    if len(calls) != 6 * len(points):
+        return f"expected {6 * len(points)} mxv calls in the trace, found {len(calls)}"
+    names = [st for _, st in MXV_STAGES]
+    out = [f"{'q':>4s} {'p':>7s} {'call':>6s} " + " ".join(f"{n:>14s}" for n in names)
+           + f" {'sum':>9s}"]
+    for i, (q, p, c) in enumerate(points):
+        grp = calls[6 * i + 1: 6 * i + 6]
+        mean = {n: sum(g.get(n, 0.0) for g in grp) / len(grp) for n in names}
+        out.append(f"{q:4.1f} {p:7g} {c:>6s} " + " ".join(f"{mean[n]:14.1f}" for n in names)
+                   + f" {sum(mean.values()):9.1f}")
+    return "\n".join(out)
+
+
 def rocprof_summary(d):
     lines = []
     for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
@@ -543,7 +642,12 @@ def bench_serve(grb, graphgen, torch, args):
     chunks = {"grid2000": 16, "grid3000": 16}
     full = args.serve_full
     nq = 10000 if full else args.serve_queries
-    loads = [0.25, 0.5, 0.75, 0.9, 1.1] if full else args.serve_load
+    loads = args.serve_load
+    if loads is None:
+        loads = [0.25, 0.5, 0.75, 0.9, 1.1] if full else [0.5, 0.9]
+    sweep_gib = args.serve_sweep
+    if sweep_gib is None:
+        sweep_gib = [1, 2, 4, 8] if full else []
     budget = args.serve_budget
 
     def prog(tag):
@@ -563,12 +667,17 @@ def bench_serve(grb, graphgen, torch, args):
            "session_lanes": {g: mk().lanes_for(g) for g in names}}
     mk().run(trace(4 * len(names), 1e6, 99), realtime=False)  # warm-up
     fifo().run(trace(2 * len(names), 1e6, 98), realtime=False)
-    sat = mk().run(trace(nq, 1e9, 0), realtime=False, progress=prog("saturation"))
-    fifo_sat = fifo().run(trace(max(nq // 4, 200), 1e9, 0), realtime=False,
-                          progress=prog("fifo saturation"))
-    out["saturation"] = {"batched": sat, "fifo": fifo_sat}
-    log(f"[bench] serve saturation: batched {sat['qps']} q/s, fifo {fifo_sat['qps']} q/s")
-    qps = sat["qps"]
+    if args.serve_sat is None:
+        sat = mk().run(trace(nq, 1e9, 0), realtime=False, progress=prog("saturation"))
+        fifo_sat = fifo().run(trace(max(nq // 4, 200), 1e9, 0), realtime=False,
+                              progress=prog("fifo saturation"))
+        out["saturation"] = {"batched": sat, "fifo": fifo_sat}
+        log(f"[bench] serve saturation: batched {sat['qps']} q/s, fifo {fifo_sat['qps']} q/s")
+        qps = sat["qps"]
+    else:
+        qps = float(args.serve_sat)
+        out["saturation"] = {"batched_qps_given": qps,
+                             "note": "measured by an earlier run of the same protocol"}
     points = []
     for frac in loads:
         rate = frac * qps
@@ -577,12 +686,13 @@ def bench_serve(grb, graphgen, torch, args):
         points.append({"rate_qps": round(rate, 1), "load_of_batched_saturation": frac,
                        "batched": b, "fifo": f})
         log(f"[bench] serve rate {rate:.1f}: batched p50 {b['p50_ms']} p99 {b['p99_ms']} "
-            f"(deferred {b['deferred_admissions']}) | fifo p50 {f['p50_ms']} p99 {f['p99_ms']}")
+            f"(deferred {b['deferred_admissions']}, drains {b['session_drains']}) "
+            f"| fifo p50 {f['p50_ms']} p99 {f['p99_ms']}")
     out["points"] = points
-    if full:
+    if sweep_gib:
         # budget sweep at 0.75 x saturation
         sweep = []
-        for bud in (1 << 30, 2 << 30, 4 << 30, 8 << 30):
+        for bud in (int(b * (1 << 30)) for b in sweep_gib):
             del ex
             torch.cuda.empty_cache()
             ex, mkb = batched(bud)
@@ -700,11 +810,30 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="full serving protocol: 10,000 queries per point, five loads, "
                          "budget sweep (minutes of GPU time)")
-    ap.add_argument("--serve-load", type=float, nargs="*", default=[0.5, 0.9])
+    ap.add_argument("--serve-load", type=float, nargs="*", default=None,
+                    help="loads as fractions of the batched saturation rate (default 0.5 0.9; "
+                         "with --serve-full 0.25 0.5 0.75 0.9 1.1)")
+    ap.add_argument("--serve-sweep", type=float, nargs="*", default=None,
+                    help="budgets in GiB of the sweep at 0.75 x saturation (default: none; "
+                         "with --serve-full 1 2 4 8)")
+    ap.add_argument("--serve-sat", type=float, default=None,
+                    help="batched saturation rate (q/s) of an earlier run of the same protocol: "
+                         "skips measuring it, so the protocol can be split over several runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
+    ap.add_argument("--mxv-trace", metavar="DIR",
+                    help="print the per-stage table of the mxv sweep from a rocprofv3 kernel trace")
+    ap.add_argument("--serve-report", metavar="BENCH_JSON", nargs="+",
+                    help="print markdown tables of the serving runs in these bench outputs")
     args = ap.parse_args()
+
+    if args.serve_report:
+        print(serve_report(args.serve_report))
+        return 0
+    if args.mxv_trace:
+        print(mxv_trace_summary(args.mxv_trace))
+        return 0
 
     if args.rocprof_summary:
         print(rocprof_summary(args.rocprof_summary))

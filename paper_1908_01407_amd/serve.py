@@ -16,7 +16,13 @@ admitted as memory and execution resources free up:
   every SSSP query's workspace and output are carved from one device pool
   of `budget` bytes (:class:`DevicePool`) and returned when they finish, so
   the device memory in use never exceeds the budget.  Work that does not
-  fit waits (counted as deferred) until memory is released.
+  fit waits (counted as deferred) until memory is released;
+* fairness: while another graph's BFS queries wait for memory to open a
+  session, a session that has been open for `session_quantum` seconds
+  takes no new queries, finishes the ones it holds and closes; its graph
+  then queues behind the waiting graph (the drain time counts as its
+  oldest waiting arrival), so large sessions rotate instead of holding the
+  pool for as long as their own queue stays non-empty.
 
 Sessions and slots overlap on the device.  A BFS result equals the query
 alone (levels exactly equal single-source BFS, whatever level it joined
@@ -106,6 +112,8 @@ class _Session:
     mem: int
     nbytes: int
     lanes: int
+    opened: float = 0.0
+    draining: bool = False
     thread: threading.Thread | None = None
 
 
@@ -113,9 +121,14 @@ class Server:
     """Runs a query trace over an executor (see the module text)."""
 
     def __init__(self, executor, slots: int = 4, lanes: int = 64, lane_mode: bool = True,
-                 level_chunk: dict | None = None, session_share: float = 0.5):
+                 level_chunk: dict | None = None, session_share: float = 0.5,
+                 session_quantum: float = 0.05):
         self.ex = executor
         self.session_share = float(session_share)
+        self.session_quantum = float(session_quantum)
+        self.blocked = False    # a graph's BFS queries wait for memory to open a session
+        self.requeued = {}      # graph -> time its session drained to make room
+        self.drains = 0
         self.pool = executor.pool
         self.slots = 1 if not lane_mode else int(slots)
         self.lanes = int(lanes)
@@ -153,8 +166,9 @@ class Server:
     def _open_sessions(self):
         """Opens sessions for graphs with waiting BFS queries (oldest first)
         while memory allows; called with the lock held."""
-        cand = [(dq[0].arrival, g) for g, dq in self.wait_bfs.items()
-                if dq and g not in self.sessions]
+        cand = [(max(dq[0].arrival, self.requeued.get(g, 0.0)), g)
+                for g, dq in self.wait_bfs.items() if dq and g not in self.sessions]
+        self.blocked = False
         for _, g in sorted(cand):
             k = self.lanes_for(g)
             need = self.ex.footprint_session(g, k)
@@ -166,8 +180,10 @@ class Server:
             off = self.pool.alloc(need)
             if off is None:
                 self.deferred += 1
+                self.blocked = True
                 break  # oldest first: later graphs wait too
-            s = _Session(g, off, need, k)
+            self.requeued.pop(g, None)
+            s = _Session(g, off, need, k, opened=self.now())
             self.sessions[g] = s
             self.max_sessions = max(self.max_sessions, len(self.sessions))
             s.thread = threading.Thread(target=self._drive, args=(s,), daemon=True)
@@ -244,7 +260,11 @@ class Server:
                 with self.cv:
                     joins = []
                     dq = self.wait_bfs[g]
-                    while free and dq:
+                    if (not s.draining and self.blocked
+                            and self.now() - s.opened >= self.session_quantum):
+                        s.draining = True  # make room for the waiting graph
+                        self.drains += 1
+                    while free and dq and not s.draining:
                         joins.append((free.pop(), dq.popleft()))
                     if not joins and not busy:
                         break
@@ -285,6 +305,8 @@ class Server:
                     pass
             with self.cv:
                 del self.sessions[g]
+                if s.draining:
+                    self.requeued[g] = self.now()
                 self.pool.release(s.mem, s.nbytes)
                 self._open_sessions()
                 self.cv.notify_all()
@@ -326,6 +348,7 @@ class Server:
         makespan = max(q.end for q in queries) - min(q.arrival for q in queries)
         st = summarize(queries, makespan)
         st["deferred_admissions"] = self.deferred
+        st["session_drains"] = self.drains
         st["max_sessions"] = self.max_sessions
         st["pool_peak_bytes"] = self.pool.peak
         return st

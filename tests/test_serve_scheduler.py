@@ -106,3 +106,20 @@ def test_fifo_mode_runs_one_query_at_a_time():
     assert all(q.batch == 1 for q in qs)
     order = sorted(qs, key=lambda q: q.start)
     assert [q.qid for q in order] == list(range(20))
+
+
+def test_sessions_rotate_when_another_graph_waits_for_memory():
+    # one session fits the budget; graph a's queue never empties, yet the
+    # BFS query on graph b gets a session after a's quantum and drain
+    ex = FakeExecutor({"a": 10, "b": 10}, budget=48 * 256, level_s=0.0005, depth=4)
+    ex.footprint_session = lambda g, lanes: 40 * 256
+    srv = Server(ex, slots=1, lanes=4, session_quantum=0.01)
+    qs = [mk(i, "bfs", "a", t=0.0005 * i, src=i) for i in range(400)]
+    qs.append(mk(1000, "bfs", "b", t=0.002, src=1))
+    st = srv.run(qs, realtime=True)
+    victim = next(q for q in qs if q.qid == 1000)
+    assert st["failed"] == 0 and st["max_sessions"] == 1
+    assert st["session_drains"] >= 1
+    assert all(q.result == ("bfs", q.graph, q.source) for q in qs)
+    # without rotation b would wait for a's whole stream (0.2 s)
+    assert victim.end - victim.arrival < 0.08
