@@ -281,6 +281,64 @@ __device__ __forceinline__ void pull_found(const BfsArgs &a, bool found, int64_t
   }
 }
 
+// Pull stream of the unsettled rows (one per lane: `act`, remaining
+// positions [rc, re)) as one concatenated list, K steps of 64 positions
+// laid out and loaded at once (K > 1 when the probes found the frontier
+// sparse, so that rows rarely stop early); the steps are then read in
+// order, so a row's first frontier neighbour (its smallest id: columns
+// ascend) is its parent.
+template <int K>
+__device__ __forceinline__ void pull_stream(const BfsArgs &a, int *mark, bool act, int &rc, int re,
+                                            bool &found, int &par) {
+  const int ln = threadIdx.x & 63;
+  const int32_t *ci = a.pull.ci;
+  for (bool more = true; more;) {
+    int pos[K], sev[K], exv[K];
+    bool st[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      pos[s] = -1;
+      sev[s] = exv[s] = 0;
+      st[s] = false;
+      if (!more) continue;
+      const int len = (act && !found) ? re - rc : 0;
+      const int incl = wave_incl_scan(len);
+      const int total = lane_last(incl);
+      if (total == 0) {
+        more = false;
+        continue;
+      }
+      const int excl = incl - len;
+      const bool starts = len > 0 && excl < 64;
+      const int r = slot_rows(mark, starts, excl);
+      const int rcur = __shfl(rc, r), rexcl = __shfl(excl, r);
+      if (ln < total) pos[s] = rcur + (ln - rexcl);
+      sev[s] = min(incl, 64);
+      exv[s] = excl;
+      st[s] = starts;
+      if (starts) rc += sev[s] - excl;
+    }
+    int c[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) c[s] = pos[s] >= 0 ? ci[pos[s]] : -1;
+    uint64_t fw[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) fw[s] = c[s] >= 0 ? a.fcur[c[s] >> 6] : 0ull;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const uint64_t hm = __ballot(c[s] >= 0 && ((fw[s] >> (c[s] & 63)) & 1ull));
+      const uint64_t seg = st[s] ? (mask_below(sev[s]) & ~mask_below(exv[s])) : 0ull;
+      const uint64_t h = hm & seg;
+      const int first = h ? (__ffsll((unsigned long long)h) - 1) : 0;
+      const int pc = __shfl(c[s], first);
+      if (h && !found) {
+        found = true;
+        par = pc;
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, int &fd, int &fl) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -335,15 +393,19 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
       // rows settled by their first two neighbours; the others (with more
       // edges left) are counted per batch for the stream below
       uint64_t rest[kPullRows];
-      int nrest = 0;
+      int nrest = 0, np = 0, nh = 0;
 #pragma unroll
       for (int q = 0; q < kPullRows; ++q) {
         bool found = false;
         int par = -1;
-        if (c0[q] >= 0 && ((b0[q] >> (c0[q] & 63)) & 1ull)) {
+        const bool h0 = c0[q] >= 0 && ((b0[q] >> (c0[q] & 63)) & 1ull);
+        const bool h1 = c1[q] >= 0 && ((b1[q] >> (c1[q] & 63)) & 1ull);
+        np += __popcll(__ballot(c0[q] >= 0)) + __popcll(__ballot(c1[q] >= 0));
+        nh += __popcll(__ballot(h0)) + __popcll(__ballot(h1));
+        if (h0) {
           found = true;
           par = c0[q];
-        } else if (c1[q] >= 0 && ((b1[q] >> (c1[q] & 63)) & 1ull)) {
+        } else if (h1) {
           found = true;
           par = c1[q];
         }
@@ -375,29 +437,9 @@ __device__ __forceinline__ void bfs_pull(const BfsArgs &a, int *mark, int &fc, i
         const int deg2 = re - (rc - 2);
         bool found = false;
         int par = -1;
-        for (;;) {
-          const int len = (act2 && !found) ? re - rc : 0;
-          const int incl2 = wave_incl_scan(len);
-          const int tot2 = lane_last(incl2);
-          if (tot2 == 0) break;
-          const int excl = incl2 - len;
-          const bool starts = len > 0 && excl < 64;
-          const int r = slot_rows(mark, starts, excl);
-          const int rcur = __shfl(rc, r), rexcl = __shfl(excl, r);
-          const bool valid = ln < tot2;
-          const int c = valid ? ci[rcur + (ln - rexcl)] : -1;
-          const uint64_t hm = __ballot(valid && bit_of(a.fcur, c));
-          const int se = min(incl2, 64);
-          const uint64_t seg = starts ? (mask_below(se) & ~mask_below(excl)) : 0ull;
-          const uint64_t h = hm & seg;
-          const int fl = h ? (__ffsll((unsigned long long)h) - 1) : 0;
-          const int pc = __shfl(c, fl);
-          if (h) {
-            found = true;
-            par = pc;
-          }
-          if (starts) rc += se - excl;
-        }
+        // a frontier the probes found below 1/8 dense: four steps at once
+        if (8 * nh < np) pull_stream<kUnroll>(a, mark, act2, rc, re, found, par);
+        else pull_stream<1>(a, mark, act2, rc, re, found, par);
         pull_found(a, found, rv, par, deg2, fc, fd, fl);
       }
     }
@@ -594,6 +636,70 @@ __device__ __forceinline__ void frontier_parents(const BfsArgs &a, int *mark) {
   }
 }
 
+// Parents of the frontier from the previous one: every vertex at level
+// d - 1 offers itself (atomicMin) to its out-neighbours at level d, whose
+// parents then hold the smallest such id (the claim's winner is one of
+// them).  Chosen over the in-edge pass above when the previous frontier's
+// degree sum and a scan of the levels cost less than this frontier's
+// in-edges.  Rows of at most kPushSplit edges: 64 vertices per wave step,
+// the selected rows' edges as one concatenated stream; longer rows through
+// the push CSR's pieces, dealt to the waves with a stride.
+__device__ __forceinline__ void prev_offers(const BfsArgs &a, int *mark) {
+  const int ln = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int32_t *rp = a.push.rp, *ci = a.push.ci;
+  const int tgt = a.d - 1;
+  for (int64_t b0 = gw * 64; b0 < a.n; b0 += nwaves * 64) {
+    const int64_t u = b0 + ln;
+    const bool sel = u < a.n && a.levels[u] == tgt;
+    int cur = sel ? rp[u] : 0;
+    const int end = sel ? rp[u + 1] : 0;
+    if (end - cur > kPushSplit) cur = end;  // pieces below
+    for (;;) {
+      const int len = end - cur;
+      const int incl = wave_incl_scan(len);
+      const int total = lane_last(incl);
+      if (total == 0) break;
+      const int excl = incl - len;
+      const bool starts = len > 0 && excl < 64;
+      const int r = slot_rows(mark, starts, excl);
+      const int rcur = __shfl(cur, r), rexcl = __shfl(excl, r);
+      if (ln < total) {
+        const int v = ci[rcur + (ln - rexcl)];
+        if (a.levels[v] == a.d) atomicMin((unsigned *)&a.parents[v], (unsigned)(b0 + r));
+      }
+      if (starts) cur += min(incl, 64) - excl;
+    }
+  }
+  for (int64_t hb = gw; hb < a.push.nsplit; hb += 64 * nwaves) {
+    const int64_t h = hb + (int64_t)ln * nwaves;
+    int u = -1, b = 0, e = 0;
+    if (h < a.push.nsplit) {
+      u = a.push.split[2 * h];
+      b = a.push.split[2 * h + 1];
+      if (a.levels[u] == tgt) e = min(b + kPushSplit, rp[u + 1]);
+      else u = -1;
+    }
+    for (uint64_t act = __ballot(u >= 0); act; act &= act - 1) {
+      const int k = __ffsll((unsigned long long)act) - 1;
+      const int pb = __shfl(b, k), pe = __shfl(e, k), pu = __shfl(u, k);
+      int v[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) {
+        const int pos = pb + s * 64 + ln;
+        v[s] = pos < pe ? ci[pos] : -1;
+      }
+      int lv[kUnroll];
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s) lv[s] = v[s] >= 0 ? a.levels[v[s]] : -1;
+#pragma unroll
+      for (int s = 0; s < kUnroll; ++s)
+        if (lv[s] == a.d) atomicMin((unsigned *)&a.parents[v[s]], (unsigned)pu);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
   parents_pass(a, s_mark[threadIdx.x >> 6]);
@@ -601,10 +707,11 @@ __global__ __launch_bounds__(kBlock) void k_bfs_parents(BfsArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   __shared__ int s_mark[kWavesPerBlock][64];
-  __shared__ int s_count, s_sumdeg, s_long, s_open;
+  __shared__ int s_count, s_sumdeg, s_long, s_open, s_prev_sd;
   __shared__ int s_red[kWavesPerBlock][kCntFields];
   if (threadIdx.x == 0) {
     s_open = a.parents ? a.ctrl->pushed[a.d % 3] : 0;
+    s_prev_sd = s_open ? a.ctrl->pushed_sd[a.d % 3] : 0;
     int c = 0, sd = 0, lr = 0;
     for (int t = 0; t < kCntStripes; ++t) {
       c += a.cnt_cur[kCntFields * t];
@@ -623,6 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
         // the next frontier's parents stay open when a push of several
         // vertices finds it
         a.ctrl->pushed[(a.d + 1) % 3] = (decide(a, c, sd) == GRB_DIR_PUSH && c > 1) ? 1 : 0;
+        a.ctrl->pushed_sd[(a.d + 1) % 3] = sd;
         if (a.stats && a.d < kStatsCap) {
           a.stats[a.d * kStatFields + 0] = c;
           a.stats[a.d * kStatFields + 1] = sd;
@@ -637,10 +745,15 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(BfsArgs a) {
   const int dir = decide(a, count, s_sumdeg);
   int fc = 0, fd = 0, fl = 0;
   // parents of this frontier, when a push of several vertices found it: a
-  // push over the same CSR offers them while it expands the frontier,
-  // otherwise a pass over the frontier's in-edges finds them first
+  // push over the same CSR offers them while it expands the frontier;
+  // otherwise the previous frontier offers them again when its degree sum
+  // and a scan of the levels cost less than this frontier's in-edges, and
+  // else a pass over those in-edges finds them first
   const bool offer = s_open && dir == GRB_DIR_PUSH && a.same_csr;
-  if (s_open && !offer) frontier_parents(a, s_mark[threadIdx.x >> 6]);
+  if (s_open && !offer) {
+    if ((int64_t)s_prev_sd + a.n / 16 < (int64_t)s_sumdeg) prev_offers(a, s_mark[threadIdx.x >> 6]);
+    else frontier_parents(a, s_mark[threadIdx.x >> 6]);
+  }
   if (dir == GRB_DIR_PUSH)
     bfs_push(a, s_mark[threadIdx.x >> 6], s_long > 0, count == 1, offer, fc, fd, fl);
   else

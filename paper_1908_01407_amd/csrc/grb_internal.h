@@ -103,6 +103,8 @@ struct Ctrl {
   int32_t error;              // batched BFS: a source id was out of range
   int32_t small_levels;       // BFS / SSSP: levels or rounds run by the one-workgroup loop
   int32_t spilled;            // ... which then handed a frontier to the wide kernels
+  int32_t pushed_sd[3];       // BFS: degree sum of the push that found the buffer's frontier
+  int32_t pad32;
   int64_t pad[2];
 };
 

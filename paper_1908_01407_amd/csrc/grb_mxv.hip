@@ -985,8 +985,8 @@ __global__ __launch_bounds__(kBlock) void k_mxv_sweep(MxvArgs a) {
   }
 }
 
-// Epilogue of long row r from its combined pieces (output bit by atomic:
-// other rows of the word are written by other lanes and waves).
+// Epilogue of long row r from its combined pieces, output bit by atomic
+// (other rows of the word are written by other lanes and waves).
 template <int SR>
 __device__ __forceinline__ void long_row_out(const MxvArgs &a, int64_t r, bool has,
                                              typename Sr<SR>::T acc) {
@@ -1002,10 +1002,18 @@ __device__ __forceinline__ void long_row_out(const MxvArgs &a, int64_t r, bool h
   }
 }
 
-// The allowed long rows not settled by their probes: each lane takes one row
-// of 64 and combines its pieces in order when it has at most kFixLanePieces;
-// a row with more is combined by the whole wave (lane l: pieces l, l + 64,
-// ..., then the lanes in a fixed order).  Either way one fixed order per row.
+// The allowed long rows not settled by their probes, in two phases.
+// First each wave takes 64 consecutive rows (ascending), a lane per row,
+// and combines the pieces of rows with at most kFixLanePieces in order, the
+// loads of eight pieces issued together; the rows of one bitmap word then
+// sit in consecutive lanes, and a segmented OR over the lanes gathers each
+// word's set and cleared bits in its last lane, which writes the word with
+// one read-modify-write (atomics for the first and last word of the step,
+// which neighbouring steps may share, and for words holding a row of the
+// second phase).  Then the rows with more pieces, which cluster at the hub
+// ids, are dealt to the waves with a stride (lane l of wave w: row
+// w + l * waves), each combined by the whole wave (lane l: pieces l,
+// l + 64, ..., then the lanes in a fixed order).  One fixed order per row.
 constexpr int kFixLanePieces = 32;
 
 template <int SR>
@@ -1016,11 +1024,12 @@ __global__ __launch_bounds__(kBlock) void k_mxv_fixup(MxvArgs a) {
   const int ln = threadIdx.x & 63;
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t k0 = gw * 64; k0 < a.pull.nsplit_rows; k0 += nwaves * 64) {
+  const int64_t nrows = a.pull.nsplit_rows;
+  for (int64_t k0 = gw * 64; k0 < nrows; k0 += nwaves * 64) {
     const int64_t k = k0 + ln;
     int r = -1, first = 0, cnt = 0;
     bool todo = false;
-    if (k < a.pull.nsplit_rows) {
+    if (k < nrows) {
       r = a.pull.split_rows[3 * k];
       first = a.pull.split_rows[3 * k + 1];
       cnt = a.pull.split_rows[3 * k + 2];
@@ -1029,16 +1038,74 @@ __global__ __launch_bounds__(kBlock) void k_mxv_fixup(MxvArgs a) {
       todo = mask_allowed(a, r) && !(Sr<SR>::lor && a.settled[r]);
     }
     const bool big = todo && cnt > kFixLanePieces;
+    unsigned long long set = 0, clr = 0;
+    int wide = big ? 1 : 0;
     if (todo && !big) {
       T acc = Sr<SR>::identity();
       bool has = false;
-      for (int p = 0; p < cnt; ++p) {
-        if (!a.hp_has[first + p]) continue;
-        has = true;
-        acc = Sr<SR>::add(acc, hv[first + p]);
+      for (int p0 = 0; p0 < cnt; p0 += 8) {
+        uint8_t hh[8];
+        T vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool ok = p0 + q < cnt;
+          hh[q] = ok ? a.hp_has[first + p0 + q] : (uint8_t)0;
+          vv[q] = ok ? hv[first + p0 + q] : Sr<SR>::identity();
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (hh[q]) {
+            has = true;
+            acc = Sr<SR>::add(acc, vv[q]);
+          }
       }
-      long_row_out<SR>(a, r, has, acc);
+      T out = acc;
+      const bool out_has = epilogue<SR>(a, r, true, has, acc, &out);
+      const unsigned long long bit = 1ull << (r & 63);
+      if (out_has) {
+        ((T *)a.w_val)[r] = out;
+        set = bit;
+      } else {
+        clr = bit;
+      }
     }
+    // segmented inclusive OR over lanes of the same word (rows ascend)
+    const int word = r >= 0 ? (r >> 6) : -1;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int wu = __shfl_up(word, d);
+      const unsigned long long su = __shfl_up(set, d), cu = __shfl_up(clr, d);
+      const int bu = __shfl_up(wide, d);
+      if (ln >= d && wu == word) {
+        set |= su;
+        clr |= cu;
+        wide |= bu;
+      }
+    }
+    const int wd = __shfl_down(word, 1);
+    const int w_first = __shfl(word, 0), w_last = __shfl(word, 63);
+    const bool seg_end = ln == 63 || wd != word;
+    if (word >= 0 && seg_end && (set | clr)) {
+      unsigned long long *wp = (unsigned long long *)&a.w_bm[word];
+      const bool shared = word == w_first || word == w_last || k0 + 64 >= nrows || wide;
+      if (shared) {
+        if (set) atomicOr(wp, set);
+        if (clr) atomicAnd(wp, ~clr);
+      } else {
+        *wp = (*wp | set) & ~clr;
+      }
+    }
+  }
+  for (int64_t hb = gw; hb < nrows; hb += 64 * nwaves) {
+    const int64_t k = hb + (int64_t)ln * nwaves;
+    int r = -1, first = 0, cnt = 0;
+    if (k < nrows) {
+      r = a.pull.split_rows[3 * k];
+      first = a.pull.split_rows[3 * k + 1];
+      cnt = a.pull.split_rows[3 * k + 2];
+    }
+    const bool big = r >= 0 && cnt > kFixLanePieces && mask_allowed(a, r) &&
+                     !(Sr<SR>::lor && a.settled[r]);
     for (uint64_t bm = __ballot(big); bm; bm &= bm - 1) {
       const int kk = __ffsll((unsigned long long)bm) - 1;
       const int rr = __shfl(r, kk), ff = __shfl(first, kk), cc = __shfl(cnt, kk);

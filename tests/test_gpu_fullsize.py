@@ -60,6 +60,20 @@ def test_bfs_rmat22_other_sources(grb, rmat22):
         assert np.array_equal(par.cpu().numpy(), ref_par), s
 
 
+def test_bfs_rmat22_low_degree_sources(grb, rmat22):
+    """Sources of degree 9 and 309: level 1 is a push of several vertices,
+    level 2 a pull whose frontier holds tens of millions of in-edges, so the
+    level-2 vertices' parents come from the level-1 vertices' offers."""
+    A, adj = rmat22
+    for s in (1122651, 2886679, 2662536):
+        ref_lev, ref_par, _ = oracle.bfs(adj, s)
+        lev, par = grb.bfs(A, s, desc=grb.descriptor(rule=1, flags=grb.GRB_PROFILE))
+        st = grb.last_stats()
+        assert st["direction"][:3] == [1, 1, 2], (s, st["direction"])
+        assert np.array_equal(lev.cpu().numpy(), ref_lev), s
+        assert np.array_equal(par.cpu().numpy(), ref_par), s
+
+
 @pytest.mark.parametrize("rule", [0, 1])
 def test_sssp_rmat22(grb, rmat22, rule):
     A, adj = rmat22
