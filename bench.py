@@ -177,7 +177,7 @@ def serve_report(paths):
     for path in paths:
         with open(path) as f:
             d = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
-        sv = d.get("serving")
+        sv = d.get("serving", d if "saturation" in d else None)  # bench line or --serve-out
         if not sv:
             continue
         out.append(f"## {os.path.basename(path)}: budget {sv['budget_bytes'] >> 20} MiB, "
@@ -230,20 +230,31 @@ MXV_STAGES = [("k_mxv_init", "mxv_init"), ("k_compact", "compact"), ("k_mxv_list
               ("k_mxv_sweep", "mxv_pull"), ("k_mxv_fixup", "mxv_pull_fixup")]
 
 
-def mxv_trace_summary(d):
-    """Per-stage kernel durations (us) of the mxv sweep from a rocprofv3
-    kernel trace (csv) of a bench run: calls start at each k_mxv_init and
-    come in the sweep's order (q, p, direction; one warm-up and five timed
-    calls each); the table gives the mean of the timed calls."""
-    paths = sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True))
-    rows = []
+def mxv_trace_summary(d, counter=None):
+    """Per-stage figures of the mxv sweep from a rocprofv3 run (csv) of a
+    bench run: kernel durations (us) from the kernel trace, or, with
+    `counter`, that counter's KiB per dispatch from the counter collection.
+    Calls start at each k_mxv_init and come in the sweep's order (q, p,
+    direction; one warm-up and five timed calls each); the table gives the
+    mean of the timed calls."""
+    pattern = "*counter_collection.csv" if counter else "*kernel_trace.csv"
+    paths = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    disp = {}  # dispatch -> [order key, kernel name, value]
     for path in paths:
         with open(path) as f:
-            rows += list(csv.DictReader(f))
-    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+            for r in csv.DictReader(f):
+                if counter:
+                    if r["Counter_Name"] != counter:
+                        continue
+                    key = int(r["Dispatch_Id"])
+                    e = disp.setdefault(key, [key, r["Kernel_Name"], 0.0])
+                    e[2] += float(r["Counter_Value"])
+                else:
+                    key = int(r["Start_Timestamp"])
+                    us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                    disp[(key, r["Dispatch_Id"])] = [key, r["Kernel_Name"], us]
     calls = []
-    for r in rows:
-        name = r["Kernel_Name"]
+    for _, name, val in sorted(disp.values(), key=lambda e: e[0]):
         stage = next((st for k, st in MXV_STAGES if k + "(" in name or k + "<" in name), None)
         if stage is None:
             continue
@@ -251,12 +262,11 @@ def mxv_trace_summary(d):
             calls.append({})
         if not calls:
             continue
-        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-        calls[-1][stage] = calls[-1].get(stage, 0.0) + us
+        calls[-1][stage] = calls[-1].get(stage, 0.0) + val
     points = [(q, p, c) for q in (0.0, 0.5) for p in (1e-4, 1e-3, 1e-2, 0.05, 0.2, 0.5)
               for c in ("push", "pull", "auto")]
     if len(calls) != 6 * len(points):
-        return f"expected {6 * len(points)} mxv calls in the trace, found {len(calls)}"
+        return f"expected {6 * len(points)} mxv calls in the run, found {len(calls)}"
     names = [st for _, st in MXV_STAGES]
     out = [f"{'q':>4s} {'p':>7s} {'call':>6s} " + " ".join(f"{n:>14s}" for n in names)
            + f" {'sum':>9s}"]
@@ -265,6 +275,71 @@ def mxv_trace_summary(d):
         mean = {n: sum(g.get(n, 0.0) for g in grp) / len(grp) for n in names}
         out.append(f"{q:4.1f} {p:7g} {c:>6s} " + " ".join(f"{mean[n]:14.1f}" for n in names)
                    + f" {sum(mean.values()):9.1f}")
+    return "\n".join(out)
+
+
+def _counter_means(d, counter):
+    """{kernel short name: (dispatches, mean KiB per dispatch)} of one counter
+    in the rocprofv3 counter collection(s) under d."""
+    per = {}
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (short_name(r["Kernel_Name"]), r["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    agg = {}
+    for (k, _), v in per.items():
+        a = agg.setdefault(k, [0, 0.0])
+        a[0] += 1
+        a[1] += v
+    return {k: (n, v / n) for k, (n, v) in agg.items()}
+
+
+def bfs_counters_file(fetch_dir, write_dir, bench_json):
+    """The k_bfs_level counter summary (the file bench.py reads its traffic
+    figure from) from two rocprofv3 --pmc runs of bench.py --calibrate-copy
+    (FETCH_SIZE, then WRITE_SIZE) and the bench output of one of them."""
+    fe = _counter_means(fetch_dir, "FETCH_SIZE")
+    wr = _counter_means(write_dir, "WRITE_SIZE")
+    with open(bench_json) as f:
+        b = json.loads([ln for ln in f.read().splitlines() if ln.startswith("{")][-1])
+    alg = float(b["roofline"]["algorithmic_bytes_per_launch"])
+    cal = "torch_elementwise_kernel(mul)"
+    sf = 262144.0 / fe[cal][1]
+    sw = 262144.0 / wr[cal][1]
+    kf, kw = fe["grb::k_bfs_level"][1], wr["grb::k_bfs_level"][1]
+    traffic = (kf * sf + kw * sw) * 1024.0
+    out = ["k_bfs_level on RMAT-22: HBM traffic from rocprofv3 counters",
+           "(FETCH_SIZE and WRITE_SIZE, KiB per dispatch, one run each)", "",
+           "commands (from the repository root on the GPU host):"]
+    for c, dd in (("FETCH_SIZE", "pmc_fetch"), ("WRITE_SIZE", "pmc_write")):
+        out.append(f"  export TMPDIR=/tmp; R=$GRAFT_REPO_ROOT; cd /tmp && rocprofv3 --pmc {c} "
+                   f"--output-format csv -d $R/gpurun_out/{dd} -o run -- python3 $R/bench.py "
+                   "--no-extras --no-msbfs --no-serve --no-cpu-baseline --rule exact --steps 3 "
+                   "--warmup 1 --calibrate-copy")
+    out += ["  python bench.py --bfs-counters gpurun_out/pmc_fetch gpurun_out/pmc_write "
+            "<bench output of the FETCH_SIZE run>", "",
+            "Each run does 1 warm-up, 3 timed and 3 profiled BFS runs (7 launches each)",
+            "and, last, one streaming kernel of known size (torch elementwise multiply",
+            "over 64 Mi fp32: 256 MiB read, 256 MiB written).", ""]
+    out.append(f"{'kernel':40s} {'counter':>12s} {'dispatches':>10s} {'KiB/dispatch':>14s}")
+    for name, tab, c in (("fetch", fe, "FETCH_SIZE"), ("write", wr, "WRITE_SIZE")):
+        for k in sorted(tab):
+            out.append(f"{k:40s} {c:>12s} {tab[k][0]:10d} {tab[k][1]:14.1f}")
+    out += ["", "calibration (streaming kernel, 262144 KiB each way):",
+            f"  FETCH_SIZE reads {fe[cal][1]:.1f} KiB -> scale {sf:.4f}",
+            f"  WRITE_SIZE reads {wr[cal][1]:.1f} KiB -> scale {sw:.4f}",
+            "k_bfs_level per launch (average over the launches of a BFS):",
+            f"  fetched {kf:.1f} KiB x {sf:.4f} + written {kw:.1f} KiB x {sw:.4f}",
+            f"  = {traffic / 1e6:.2f} MB per launch, against {alg / 1e6:.2f} MB of algorithmic bytes",
+            f"  ({traffic / alg:.1f}x): cache-line granularity of the random gathers (row",
+            "  starts of candidate rows, frontier and visited words) and the level / parent",
+            "  stores of scattered vertices", "",
+            f"traffic_bytes_per_launch: {int(round(traffic))}",
+            f"sources_sha256: {kernel_sources_digest()}",
+            "sources: " + ", ".join(KERNEL_SOURCES)]
     return "\n".join(out)
 
 
@@ -434,6 +509,18 @@ def bench_extras(grb, graphgen, torch, args):
                     "frontier distances (gathered, counted once), distances read, candidate "
                     "and next-frontier bitmaps"}
     del ws
+    # connected components (FastSV on the generic product) on the same graph
+    wsc = grb.workspace(grb.OP_CC, A)
+    grb.cc(A, ws=wsc)
+    ms = timed(lambda: grb.cc(A, ws=wsc), args.extra_steps, torch)
+    lab, it = grb.cc(A, ws=wsc)
+    lab = lab.cpu().numpy()
+    ex[f"cc_rmat{args.scale}"] = {
+        "ms": round(ms, 4), "iterations": it,
+        "components": int((lab == np.arange(lab.size)).sum()),
+        "note": "FastSV: per iteration one MIN_SECOND pull product with MIN accumulate, "
+                "hooking, shortcutting and grandparents; the last iteration finds no change"}
+    del wsc, lab
     # grid 3000 x 3000
     if not args.no_grid:
         gg = graphgen.grid(3000, 3000)
@@ -640,6 +727,9 @@ def bench_serve(grb, graphgen, torch, args):
     # high-diameter graphs: bucketed SSSP, several BFS levels per session step
     deltas = {"grid2000": 2048.0, "grid3000": 2048.0}
     chunks = {"grid2000": 16, "grid3000": 16}
+    # their BFS queries run alone in the slots: thousands of levels make a
+    # lane session slower per query than a single-source BFS
+    single = {"grid2000", "grid3000"}
     full = args.serve_full
     nq = 10000 if full else args.serve_queries
     loads = args.serve_load
@@ -653,10 +743,16 @@ def bench_serve(grb, graphgen, torch, args):
     def prog(tag):
         return lambda k: log(f"[bench] serve {tag}: {k} queries submitted")
 
+    def checkpoint():
+        if args.serve_out:
+            with open(args.serve_out, "w") as f:
+                json.dump(out, f)
+
     def batched(bud):
         ex = GpuExecutor(graphs, budget=bud, slots=args.serve_slots, keep_results=False,
                          sssp_delta=deltas)
-        return ex, (lambda: Server(ex, slots=args.serve_slots, lanes=64, level_chunk=chunks))
+        return ex, (lambda: Server(ex, slots=args.serve_slots, lanes=64, level_chunk=chunks,
+                                   single_bfs=single))
 
     ex, mk = batched(budget)
     fifo_ex = GpuExecutor(graphs, budget=budget, slots=1, keep_results=False, sssp_delta=deltas)
@@ -672,6 +768,7 @@ def bench_serve(grb, graphgen, torch, args):
         fifo_sat = fifo().run(trace(max(nq // 4, 200), 1e9, 0), realtime=False,
                               progress=prog("fifo saturation"))
         out["saturation"] = {"batched": sat, "fifo": fifo_sat}
+        checkpoint()
         log(f"[bench] serve saturation: batched {sat['qps']} q/s, fifo {fifo_sat['qps']} q/s")
         qps = sat["qps"]
     else:
@@ -685,6 +782,8 @@ def bench_serve(grb, graphgen, torch, args):
         f = fifo().run(trace(nq, rate, 1), realtime=True, progress=prog(f"fifo load {frac}"))
         points.append({"rate_qps": round(rate, 1), "load_of_batched_saturation": frac,
                        "batched": b, "fifo": f})
+        out["points"] = points
+        checkpoint()
         log(f"[bench] serve rate {rate:.1f}: batched p50 {b['p50_ms']} p99 {b['p99_ms']} "
             f"(deferred {b['deferred_admissions']}, drains {b['session_drains']}) "
             f"| fifo p50 {f['p50_ms']} p99 {f['p99_ms']}")
@@ -698,6 +797,8 @@ def bench_serve(grb, graphgen, torch, args):
             ex, mkb = batched(bud)
             r = mkb().run(trace(nq, 0.75 * qps, 2), realtime=True, progress=prog(f"budget {bud}"))
             sweep.append({"budget_bytes": bud, "stats": r})
+            out["budget_sweep"] = sweep
+            checkpoint()
             log(f"[bench] serve budget {bud >> 20} MiB: p50 {r['p50_ms']} p99 {r['p99_ms']} "
                 f"qps {r['qps']} deferred {r['deferred_admissions']}")
         out["budget_sweep"] = sweep
@@ -706,10 +807,11 @@ def bench_serve(grb, graphgen, torch, args):
 
 def cpu_oracle_other(g, graphgen, args):
     """The oracle timed on this host's cores for the other workloads, each on
-    a bounded sample: SSSP (Dijkstra, one core), PageRank (FP64 power
-    iteration, one core, three iterations), batched BFS (64 sources, one
-    query per thread on all cores) and the serving mix (64 queries of the
-    six graphs, one per thread on all cores)."""
+    a bounded sample: SSSP (Dijkstra, one core), connected components (one
+    core), PageRank (FP64 power iteration, one core, three iterations),
+    batched BFS (64 sources, one query per thread on all cores) and the
+    serving mix (64 queries of the six graphs, one per thread on all
+    cores)."""
     import concurrent.futures as cf
 
     import oracle
@@ -721,6 +823,11 @@ def cpu_oracle_other(g, graphgen, args):
     t = time.perf_counter() - t0
     res["sssp_rmat"] = {"ms": round(t * 1e3, 1), "gteps": round(adj.nnz / t / 1e9, 4), "cores": 1,
                         "sample": f"one Dijkstra from vertex 0 on RMAT-{args.scale}"}
+    t0 = time.perf_counter()
+    _, ncc = oracle.cc(adj)
+    t = time.perf_counter() - t0
+    res["cc_rmat"] = {"ms": round(t * 1e3, 1), "components": ncc, "cores": 1,
+                      "sample": f"minimum-label components of RMAT-{args.scale}, one core"}
     gd = graphgen.rmat(args.scale, symmetric=False, weights=False)
     adjd = oracle.Adjacency.from_raw(gd)
     t0 = time.perf_counter()
@@ -816,6 +923,8 @@ def main():
     ap.add_argument("--serve-sweep", type=float, nargs="*", default=None,
                     help="budgets in GiB of the sweep at 0.75 x saturation (default: none; "
                          "with --serve-full 1 2 4 8)")
+    ap.add_argument("--serve-out", metavar="JSON", default=None,
+                    help="write the serving results to this file after every measured point")
     ap.add_argument("--serve-sat", type=float, default=None,
                     help="batched saturation rate (q/s) of an earlier run of the same protocol: "
                          "skips measuring it, so the protocol can be split over several runs")
@@ -824,6 +933,11 @@ def main():
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--mxv-trace", metavar="DIR",
                     help="print the per-stage table of the mxv sweep from a rocprofv3 kernel trace")
+    ap.add_argument("--mxv-counter", metavar="COUNTER",
+                    help="with --mxv-trace: the table of this counter (KiB per dispatch) from a "
+                         "rocprofv3 --pmc run instead of durations")
+    ap.add_argument("--bfs-counters", metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"), nargs=3,
+                    help="print the k_bfs_level counter summary from two --pmc runs")
     ap.add_argument("--serve-report", metavar="BENCH_JSON", nargs="+",
                     help="print markdown tables of the serving runs in these bench outputs")
     args = ap.parse_args()
@@ -832,7 +946,10 @@ def main():
         print(serve_report(args.serve_report))
         return 0
     if args.mxv_trace:
-        print(mxv_trace_summary(args.mxv_trace))
+        print(mxv_trace_summary(args.mxv_trace, args.mxv_counter))
+        return 0
+    if args.bfs_counters:
+        print(bfs_counters_file(*args.bfs_counters))
         return 0
 
     if args.rocprof_summary:
@@ -840,7 +957,8 @@ def main():
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU "
-              "sharding of this workload is described in DESIGN.md but not built.",
+              "sharding of this workload (by rows of the output, by query for batched BFS and "
+              "serving) is not built.",
               file=sys.stderr)
         return 2
 

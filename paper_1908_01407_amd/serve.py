@@ -11,7 +11,10 @@ admitted as memory and execution resources free up:
   never drains before new queries start;
 * SSSP queries run one per execution slot (grb_sssp, or grb_sssp_delta on
   the graphs given a bucket width), the oldest first, each slot on its own
-  stream;
+  stream; so do the BFS queries of the graphs named in `single_bfs`
+  (high-diameter graphs, where a batched level costs several single-source
+  levels and thousands of levels make a session slower per query than a
+  BFS alone);
 * memory: every session's workspace, level block and extraction buffer and
   every SSSP query's workspace and output are carved from one device pool
   of `budget` bytes (:class:`DevicePool`) and returned when they finish, so
@@ -122,10 +125,11 @@ class Server:
 
     def __init__(self, executor, slots: int = 4, lanes: int = 64, lane_mode: bool = True,
                  level_chunk: dict | None = None, session_share: float = 0.5,
-                 session_quantum: float = 0.05):
+                 session_quantum: float = 0.05, single_bfs=()):
         self.ex = executor
         self.session_share = float(session_share)
         self.session_quantum = float(session_quantum)
+        self.single_bfs = set(single_bfs)
         self.blocked = False    # a graph's BFS queries wait for memory to open a session
         self.requeued = {}      # graph -> time its session drained to make room
         self.drains = 0
@@ -192,7 +196,7 @@ class Server:
     def submit(self, q: Query):
         with self.cv:
             self.pending += 1
-            if self.lane_mode and q.kind == "bfs":
+            if self.lane_mode and q.kind == "bfs" and q.graph not in self.single_bfs:
                 self.wait_bfs[q.graph].append(q)
                 self._open_sessions()
             else:

@@ -123,3 +123,19 @@ def test_sessions_rotate_when_another_graph_waits_for_memory():
     assert all(q.result == ("bfs", q.graph, q.source) for q in qs)
     # without rotation b would wait for a's whole stream (0.2 s)
     assert victim.end - victim.arrival < 0.08
+
+
+def test_single_bfs_graphs_run_in_slots():
+    # BFS queries of a graph named in single_bfs run alone in the slots (no
+    # session), the other graph's BFS queries still join lane sessions
+    ex = FakeExecutor({"grid": 10, "rmat": 10}, budget=4096 * 256, level_s=0.0005)
+    srv = Server(ex, slots=2, lanes=8, single_bfs={"grid"})
+    arr = graphgen.poisson_arrivals(60, rate=4000.0, seed=8)
+    qs = [mk(i, "bfs", "grid" if i % 3 == 0 else "rmat", float(arr[i]), src=i)
+          for i in range(60)]
+    st = srv.run(qs, realtime=True)
+    assert st["failed"] == 0
+    assert all(q.result == ("bfs", q.graph, q.source) for q in qs)
+    assert all(q.batch == 1 for q in qs if q.graph == "grid")
+    joined = {g for (g, _, _) in ex.joins}
+    assert joined == {"rmat"}
