@@ -662,6 +662,14 @@ def bench_msbfs(grb, graphgen, torch, args):
             stp = grb.last_stats()
             nlev = stp["iterations"]
             floor_b = 4 * reached + nlev * passes * (4 * A.nnz + 8 * A.nrows)
+            # the same floor level by level: (vertex, query) pairs reached at
+            # each level, counted in blocks of rows
+            hist = np.zeros(nlev + 1, np.int64)
+            for r0 in range(0, A.nrows, 1 << 18):
+                blk = (lev[r0: r0 + (1 << 18)] + 1).flatten().long()
+                hist += torch.bincount(blk, minlength=nlev + 1).cpu().numpy()[: nlev + 1]
+            lvl_b = [int(4 * hist[l + 1] + passes * (4 * A.nnz + 8 * A.nrows))
+                     for l in range(nlev)]
             kern_ms = stp["expand_ms_all"]
             # the timed batch's first 64 queries equal the sequential runs
             for q, s in enumerate(seq_src):
@@ -682,6 +690,9 @@ def bench_msbfs(grb, graphgen, torch, args):
                                "per_level_us": [round(x * 1e3, 1) for x in stp["kernel_ms"]],
                                "direction": stp["direction"][:nlev]},
                 "bytes_floor": floor_b,
+                "per_level_bytes_floor": lvl_b,
+                "per_level_floor_gbs": [round(b / (t * 1e-3) / 1e9, 1) if t > 0 else None
+                                        for b, t in zip(lvl_b, stp["kernel_ms"])],
                 "floor_gbs": round(floor_b / (kern_ms / 1e3) / 1e9, 1),
                 "floor_frac_hbm": round(floor_b / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                 "floor_model": "4 B per reached (vertex, query) level + per level and pass of "
