@@ -265,8 +265,9 @@ def mxv_trace_summary(d, counter=None):
         calls[-1][stage] = calls[-1].get(stage, 0.0) + val
     points = [(q, p, c) for q in (0.0, 0.5) for p in (1e-4, 1e-3, 1e-2, 0.05, 0.2, 0.5)
               for c in ("push", "pull", "auto")]
-    if len(calls) != 6 * len(points):
+    if len(calls) < 6 * len(points):
         return f"expected {6 * len(points)} mxv calls in the run, found {len(calls)}"
+    calls = calls[: 6 * len(points)]  # the sweep runs first; later products (CC) follow
     names = [st for _, st in MXV_STAGES]
     out = [f"{'q':>4s} {'p':>7s} {'call':>6s} " + " ".join(f"{n:>14s}" for n in names)
            + f" {'sum':>9s}"]
@@ -317,8 +318,8 @@ def bfs_counters_file(fetch_dir, write_dir, bench_json):
     for c, dd in (("FETCH_SIZE", "pmc_fetch"), ("WRITE_SIZE", "pmc_write")):
         out.append(f"  export TMPDIR=/tmp; R=$GRAFT_REPO_ROOT; cd /tmp && rocprofv3 --pmc {c} "
                    f"--output-format csv -d $R/gpurun_out/{dd} -o run -- python3 $R/bench.py "
-                   "--no-extras --no-msbfs --no-serve --no-cpu-baseline --rule exact --steps 3 "
-                   "--warmup 1 --calibrate-copy")
+                   "--no-extras --no-msbfs --no-serve --no-cpu-baseline --headline-only --rule exact "
+                   "--steps 3 --warmup 1 --calibrate-copy")
     out += ["  python bench.py --bfs-counters gpurun_out/pmc_fetch gpurun_out/pmc_write "
             "<bench output of the FETCH_SIZE run>", "",
             "Each run does 1 warm-up, 3 timed and 3 profiled BFS runs (7 launches each)",
@@ -340,6 +341,30 @@ def bfs_counters_file(fetch_dir, write_dir, bench_json):
             f"traffic_bytes_per_launch: {int(round(traffic))}",
             f"sources_sha256: {kernel_sources_digest()}",
             "sources: " + ", ".join(KERNEL_SOURCES)]
+    return "\n".join(out)
+
+
+def bfs_trace(d):
+    """Kernels of one BFS (the second-to-last in the trace) from a rocprofv3
+    kernel trace (csv) of a bench run: start, duration and the gap before
+    each launch, in us from the BFS's first kernel."""
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(path) as f:
+            rows += [r for r in csv.DictReader(f)
+                     if "k_bfs_start" in r["Kernel_Name"] or "k_bfs_level" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if "k_bfs_start" in r["Kernel_Name"]]
+    if len(starts) < 2:
+        return "fewer than two BFS runs in the trace"
+    grp = rows[starts[-2]: starts[-1]]
+    t0 = int(grp[0]["Start_Timestamp"])
+    out, prev_end = [], t0
+    for r in grp:
+        b, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        out.append(f"{short_name(r['Kernel_Name']):22s} start={(b - t0) / 1e3:8.2f} us  "
+                   f"dur={(e - b) / 1e3:7.2f} us  gap={(b - prev_end) / 1e3:6.2f} us")
+        prev_end = e
     return "\n".join(out)
 
 
@@ -909,6 +934,9 @@ def main():
                          "measured; results are identical under either)")
     ap.add_argument("--extra-steps", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the BFS runs from other sources and on RMAT-14 (so that a "
+                         "profile of the level kernel holds the headline BFS alone)")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-pr", action="store_true")
     ap.add_argument("--no-tc", action="store_true")
@@ -947,6 +975,8 @@ def main():
     ap.add_argument("--mxv-counter", metavar="COUNTER",
                     help="with --mxv-trace: the table of this counter (KiB per dispatch) from a "
                          "rocprofv3 --pmc run instead of durations")
+    ap.add_argument("--bfs-trace", metavar="DIR",
+                    help="print the kernels of one BFS from a rocprofv3 kernel trace")
     ap.add_argument("--bfs-counters", metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"), nargs=3,
                     help="print the k_bfs_level counter summary from two --pmc runs")
     ap.add_argument("--serve-report", metavar="BENCH_JSON", nargs="+",
@@ -961,6 +991,9 @@ def main():
         return 0
     if args.bfs_counters:
         print(bfs_counters_file(*args.bfs_counters))
+        return 0
+    if args.bfs_trace:
+        print(bfs_trace(args.bfs_trace))
         return 0
 
     if args.rocprof_summary:
@@ -1061,9 +1094,10 @@ def main():
         "per_level": [{"level": i, "dir": "push" if st["direction"][i] == 1 else "pull",
                        "frontier": st["frontier"][i], "edges": st["edges"][i],
                        "bytes": per_level[i], "kernel_us": round(st["kernel_ms"][i] * 1e3, 2)}
-                      for i in range(len(per_level))] + [
-            {"level": len(per_level), "dir": "empty level (ends the search)", "bytes": 0.0,
-             "kernel_us": round((st["expand_ms_all"] - sum(st["kernel_ms"])) * 1e3, 2)}],
+                      for i in range(len(per_level))] + (
+            [{"level": len(per_level), "dir": "empty level (ends the search)", "bytes": 0.0,
+              "kernel_us": round((st["expand_ms_all"] - sum(st["kernel_ms"])) * 1e3, 2)}]
+            if st["launches"] > len(per_level) else []),
     }
     out = {
         "metric": f"BFS GTEPS at RMAT-{args.scale} (direction-optimised, from vertex 0)",
@@ -1092,23 +1126,25 @@ def main():
     out["roofline"]["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 5)
     # the headline workload from three other sources (random, degree > 0)
     other = []
-    for s in graphgen.sources(g.src, g.dst, g.n, 3, seed=3):
+    for s in ([] if args.headline_only else graphgen.sources(g.src, g.dst, g.n, 3, seed=3)):
         grb.bfs(A, int(s), desc=desc, ws=ws, out=out_bufs)
         ms_s = timed(lambda: grb.bfs(A, int(s), desc=desc, ws=ws, out=out_bufs), 5, torch)
         other.append({"source": int(s), "ms": round(ms_s, 4), "levels": grb.last_stats()["iterations"],
                       "gteps": round(nnz / (ms_s / 1e3) / 1e9, 2)})
     out["config"]["other_sources"] = other
     # C1: the small configuration, a latency line (microseconds per BFS)
-    g14 = graphgen.rmat(14)
-    A14 = grb.Matrix.from_raw(g14)
-    ws14 = grb.workspace(grb.OP_BFS, A14)
-    for _ in range(3):
-        grb.bfs(A14, 0, desc=desc, ws=ws14)
-    ms14 = timed(lambda: grb.bfs(A14, 0, desc=desc, ws=ws14), 10, torch)
-    out["rmat14_bfs"] = {"us_per_bfs": round(ms14 * 1e3, 2), "levels": grb.last_stats()["iterations"],
-                         "gteps": round(A14.nnz / (ms14 / 1e3) / 1e9, 3), "runs": 10, "warmup": 3,
-                         "note": "levels + parents from vertex 0; L2-resident, a latency figure"}
-    del A14, ws14
+    if not args.headline_only:
+        g14 = graphgen.rmat(14)
+        A14 = grb.Matrix.from_raw(g14)
+        ws14 = grb.workspace(grb.OP_BFS, A14)
+        for _ in range(3):
+            grb.bfs(A14, 0, desc=desc, ws=ws14)
+        ms14 = timed(lambda: grb.bfs(A14, 0, desc=desc, ws=ws14), 10, torch)
+        out["rmat14_bfs"] = {
+            "us_per_bfs": round(ms14 * 1e3, 2), "levels": grb.last_stats()["iterations"],
+            "gteps": round(A14.nnz / (ms14 / 1e3) / 1e9, 3), "runs": 10, "warmup": 3,
+            "note": "levels + parents from vertex 0; L2-resident, a latency figure"}
+        del A14, ws14
     if args.calibrate_copy:
         # a plain streaming kernel of known traffic for the counter scale:
         # reads 256 MiB and writes 256 MiB (torch's elementwise multiply)

@@ -594,17 +594,19 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
     empty_seen = !hc.spilled;  // done, or stopped by the level cap
   }
   // The first batch covers the depth expected of a random graph of this
-  // size and mean degree, ln n / ln(nnz / n), plus the empty level that ends
-  // the search and one spare; later batches start at two levels and double,
-  // so a deeper search pays few empty launches.  Control block and level
+  // size and mean degree, ln n / ln(nnz / n), plus one spare; later batches
+  // start at two levels and double, so a deeper search pays few empty
+  // launches.  A batch whose last level found no next frontier ends the
+  // search without launching the empty level.  Control block and level
   // records come back in one copy.
-  int chunk = 7;
+  int chunk = 6;
   {
     const double dbar = n > 0 ? (double)A->nnz / (double)n : 0.0;
     if (n > 1 && dbar > 1.5)
-      chunk = (int)std::min(64.0, std::ceil(std::log((double)n) / std::log(dbar)) + 2.0);
+      chunk = (int)std::min(64.0, std::ceil(std::log((double)n) / std::log(dbar)) + 1.0);
   }
   bool first_batch = true;
+  bool capped = false;  // stopped by the level cap with a frontier left
   while (!empty_seen && d < cap) {
     for (int i = 0; i < chunk && d < cap; ++i, ++d) {
       at_level(d);
@@ -622,12 +624,19 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
       empty_seen = true;
       break;
     }
+    int32_t next = 0;  // frontier the last launched level found
+    for (int t = 0; t < kCntStripes; ++t) next += hc.lists[(d % 3) * kCntSlots + kCntFields * t];
+    if (next == 0) {
+      empty_seen = true;
+      break;
+    }
     chunk = first_batch ? 2 : std::min(chunk * 2, 256);
     first_batch = false;
   }
   // parents the level kernel did not resolve: a search stopped by the level
   // cap, or levels run by the one-workgroup loop
-  if (parents && (small || hc.nlev >= d)) {
+  capped = !empty_seen && hc.nlev >= d;
+  if (parents && (small || capped)) {
     launch_bfs_parents(ba, stream);
     if ((info = check_launch()) != GRB_SUCCESS) return info;
     if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;

@@ -46,7 +46,11 @@ def test_bfs_rmat22(grb, rmat22, mode):
     lev, par = grb.bfs(A, 0, desc=grb.descriptor(direction=mode[1], rule=mode[2]))
     assert np.array_equal(lev.cpu().numpy(), ref_lev)
     assert np.array_equal(par.cpu().numpy(), ref_par)
-    assert grb.last_stats()["iterations"] == nl
+    st = grb.last_stats()
+    assert st["iterations"] == nl
+    # the first batch of levels covers the search, and the empty next
+    # frontier of its last level ends it without another launch
+    assert st["launches"] == nl
 
 
 def test_bfs_rmat22_other_sources(grb, rmat22):
