@@ -39,13 +39,17 @@ __global__ void k_cc_init(CcArgs a) {
 }
 
 // hooking: the smallest neighbour grandparent hooks the old parent (scatter,
-// atomic minimum: several vertices may share a parent) and the vertex itself
+// atomic minimum: several vertices may share a parent) and the vertex itself.
+// Labels only decrease, so a target already at or below m never needs the
+// atomic; after the first iteration most vertices share a handful of roots,
+// and the read keeps millions of atomics off those few words.
 __global__ void k_cc_hook(CcArgs a) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t m = a.mngf[i];
-    atomicMin(&a.f[a.f_old[i]], m);
-    atomicMin(&a.f[i], m);
+    const int32_t p = a.f_old[i];
+    if (m < a.f[p]) atomicMin(&a.f[p], m);
+    if (m < a.f[i]) atomicMin(&a.f[i], m);
   }
 }
 
