@@ -67,13 +67,16 @@ __device__ __forceinline__ void claim_won(const BfsArgs &a, const int (&c)[kUnro
   }
 }
 
-// Out-degrees of the targets (0 for none), issued with the visited loads.
+// Row extents of the targets still unvisited at the filter read (0 for the
+// others: a visited target cannot be won), issued beside the claim atomics,
+// whose latency covers theirs.
 __device__ __forceinline__ void target_degrees(const BfsArgs &a, const int (&c)[kUnroll],
-                                               int (&d0)[kUnroll], int (&d1)[kUnroll]) {
+                                               const bool (&open)[kUnroll], int (&d0)[kUnroll],
+                                               int (&d1)[kUnroll]) {
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
-    d0[s] = c[s] >= 0 ? a.push.rp[c[s]] : 0;
-    d1[s] = c[s] >= 0 ? a.push.rp[c[s] + 1] : 0;
+    d0[s] = open[s] ? a.push.rp[c[s]] : 0;
+    d1[s] = open[s] ? a.push.rp[c[s] + 1] : 0;
   }
 }
 
@@ -93,7 +96,8 @@ __device__ __forceinline__ void offer_parents(const BfsArgs &a, const int (&c)[k
 // Claims the targets c[0..kUnroll) (-1: none) from a stream that may hold
 // one target twice.  The visited words of all of them are read first (a
 // plain read is only a filter, the atomic decides) and all atomics are
-// issued before any result is used, so their latencies overlap.
+// issued before any result is used, so their latencies overlap; the row
+// extents of the unvisited targets are loaded beside them.
 __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUnroll],
                                             const int (&par)[kUnroll], bool single, bool offer,
                                             int &fc, int &fd, int &fl) {
@@ -104,15 +108,17 @@ __device__ __forceinline__ void claim_batch(const BfsArgs &a, const int (&c)[kUn
     vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
     lv[s] = (offer && c[s] >= 0) ? a.levels[c[s]] : -2;
   }
-  target_degrees(a, c, d0, d1);
   if (offer) offer_parents(a, c, par, lv);
+  bool open[kUnroll];
   uint64_t old[kUnroll];
 #pragma unroll
   for (int s = 0; s < kUnroll; ++s) {
+    open[s] = c[s] >= 0 && !((vw[s] >> (c[s] & 63)) & 1ull);
     old[s] = ~0ull;
-    if (!((vw[s] >> (c[s] & 63)) & 1ull))
+    if (open[s])
       old[s] = atomicOr((unsigned long long *)&a.visited[c[s] >> 6], 1ull << (c[s] & 63));
   }
+  target_degrees(a, c, open, d0, d1);
   bool won[kUnroll];
   int dg[kUnroll];
 #pragma unroll
@@ -137,7 +143,6 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
     vw[s] = c[s] >= 0 ? a.visited[c[s] >> 6] : ~0ull;
     lv[s] = (offer && c[s] >= 0) ? a.levels[c[s]] : -2;
   }
-  target_degrees(a, c, d0, d1);
   if (offer) offer_parents(a, c, par, lv);
   bool want[kUnroll];
   uint64_t old[kUnroll], run[kUnroll];
@@ -152,6 +157,7 @@ __device__ __forceinline__ void claim_piece(const BfsArgs &a, const int (&c)[kUn
     if (run[s] && wd[s] >= 0)
       old[s] = atomicOr((unsigned long long *)&a.visited[wd[s]], (unsigned long long)run[s]);
   }
+  target_degrees(a, c, want, d0, d1);
   bool won[kUnroll];
   int dg[kUnroll];
 #pragma unroll
