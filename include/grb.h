@@ -101,6 +101,12 @@ typedef enum grb_binop {
 #define GRB_TRAN_A      0x4u /* transpose the matrix operand */
 #define GRB_REPLACE     0x8u /* clear output entries outside the mask */
 #define GRB_PROFILE     0x10u /* drivers: time expand kernels with HIP events */
+/* drivers, test hook for the failure path of the multi-workgroup level loop
+ * of BFS / bucketed SSSP on low-degree graphs: every barrier of the loop is
+ * given up at its first unfinished poll (as when some of the loop's
+ * workgroups are not resident), so the search continues in the level
+ * kernels from there; results are unchanged. */
+#define GRB_LOOP_NO_WAIT 0x20u
 
 /* Direction of a product (Section 4): push = sparse-vector SpMSpV over the
  * input's nonzeros; pull = masked SpMV over the allowed output rows. */
@@ -355,9 +361,13 @@ grb_info grb_vxm(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s,
  * Synchronises `stream` once per batch of levels (it reads the frontier
  * size back to detect the end).  d->max_iter caps the levels (0 = none).
  * On graphs whose rows are short (at most 64 entries: road-like, high
- * diameter) the levels run inside one workgroup while the frontier is small
- * (a launch per level would dominate); a frontier that outgrows it, or that
- * the switch rule would pull, continues with one kernel per level.
+ * diameter) the levels run back to back inside one kernel of 16 workgroups,
+ * separated by a barrier of its own, while the frontier is small (a launch
+ * per level would dominate); a frontier that outgrows its queues (more
+ * than 256 vertices found by one wave of 64 lanes, or 65,536 edges), that
+ * the switch rule would pull, or a barrier not reached by every workgroup
+ * within 1 ms, continues with one kernel per level.  Results do not depend
+ * on where that hand-over happens.
  */
 grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source,
                  const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
@@ -366,7 +376,7 @@ grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source
  * grb_bfs for callers that cannot allocate (code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation): the same BFS,
  * levels and parents as grb_bfs, with its workspace in a device array of
- * the library (8 MiB + 64 KiB, held on each GPU the library runs on until
+ * the library (8 MiB + 512 KiB, held on each GPU the library runs on until
  * the process ends) instead of a caller buffer; read-backs use no pinned
  * staging buffer; GRB_PROFILE is ignored (it would create timing events).
  * Graphs of more than 2^24 vertices: GRB_INSUFFICIENT_SPACE.  Runs on the
@@ -383,9 +393,8 @@ grb_info grb_bfs_noalloc(int32_t *levels, int32_t *parents, grb_matrix A, int32_
  * frontier sparsified to the vertices whose distance improved in the last
  * round; stops when none improved.  dist[n] (fp32): +inf where unreached.
  * A must carry FP32 values (else GRB_DOMAIN_MISMATCH), none negative or NaN
- * (checked by grb_matrix_prepare; else GRB_INVALID_VALUE).  On graphs whose
- * rows are short (at most 64 entries) the rounds run inside one workgroup
- * while the frontier is small.  Synchronises like grb_bfs.
+ * (checked by grb_matrix_prepare; else GRB_INVALID_VALUE).  Synchronises
+ * like grb_bfs.
  */
 grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descriptor *d,
                   void *ws, size_t ws_bytes, void *stream);
@@ -401,7 +410,10 @@ grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descripto
  * dist[n], A, workspace (GRB_OP_SSSP) and synchronisation as grb_sssp; the
  * descriptor's direction must be AUTO or PUSH (PULL: GRB_NOT_IMPLEMENTED);
  * delta not finite and positive: GRB_INVALID_VALUE.  Stats record per round
- * the pending count, the near degree sum, direction 1 and the bucket.
+ * the pending count, the near degree sum, direction 1 and the bucket.  On
+ * graphs whose rows are short (at most 64 entries) the rounds run back to
+ * back inside one kernel (the multi-workgroup loop of grb_bfs) while the
+ * pending set is small.
  */
 grb_info grb_sssp_delta(float *dist, grb_matrix A, int32_t source, float delta,
                         const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);

@@ -46,6 +46,7 @@ SEMIRINGS = {
 }
 ACCUMS = {None: 0, "min": 1, "plus": 2, "lor": 3}
 GRB_MASK_COMP, GRB_MASK_STRUCT, GRB_TRAN_A, GRB_REPLACE, GRB_PROFILE = 0x1, 0x2, 0x4, 0x8, 0x10
+GRB_LOOP_NO_WAIT = 0x20  # test hook: the multi-workgroup loop gives up every barrier at once
 DIR_AUTO, DIR_PUSH, DIR_PULL = 0, 1, 2
 SWITCH_PAPER, SWITCH_EXACT = 0, 1
 GRB_MATRIX_SYMMETRIC = 0x1

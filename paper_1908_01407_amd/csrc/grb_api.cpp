@@ -41,7 +41,8 @@ grb_info resolve_desc(const grb_descriptor *d, grb_descriptor *out) {
   grb_descriptor_init(out);
   if (!d) return GRB_SUCCESS;
   *out = *d;
-  const uint32_t known = GRB_MASK_COMP | GRB_MASK_STRUCT | GRB_TRAN_A | GRB_REPLACE | GRB_PROFILE;
+  const uint32_t known =
+      GRB_MASK_COMP | GRB_MASK_STRUCT | GRB_TRAN_A | GRB_REPLACE | GRB_PROFILE | GRB_LOOP_NO_WAIT;
   if (out->flags & ~known) return GRB_INVALID_VALUE;
   if (out->direction < GRB_DIR_AUTO || out->direction > GRB_DIR_PULL) return GRB_INVALID_VALUE;
   if (out->switch_rule != GRB_SWITCH_PAPER && out->switch_rule != GRB_SWITCH_EXACT)
@@ -70,6 +71,10 @@ struct BfsWs {
   Ctrl *ctrl;
   int64_t *stats;
   uint64_t *visited, *F[3];
+  CoopCtl *coop;  // multi-workgroup loop: shared state, two queues of kCoopSegs segments
+  int32_t *qv;
+  uint64_t *qe;
+  int32_t qseg;
   size_t bytes;
 };
 
@@ -81,6 +86,11 @@ BfsWs bfs_layout(void *ws, int64_t n) {
   t.stats = c.take<int64_t>((size_t)kStatsCap * kStatFields);
   t.visited = c.take<uint64_t>((size_t)nw);
   for (int i = 0; i < 3; ++i) t.F[i] = c.take<uint64_t>((size_t)nw);
+  t.qseg = (int32_t)std::max<int64_t>(std::min<int64_t>(kCoopSeg, n), 1);
+  t.coop = c.take<CoopCtl>(1);
+  const size_t qn = 2 * (size_t)kCoopSegs * (size_t)t.qseg;
+  t.qv = c.take<int32_t>(qn);
+  t.qe = c.take<uint64_t>(qn);
   t.bytes = c.off;
   return t;
 }
@@ -566,7 +576,6 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
     ba.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
   };
   at_level(0);
-  launch_bfs_start(ba, source, w.F[1], w.F[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
   const size_t rec_bytes = (size_t)kStatsCap * kStatFields * sizeof(int64_t);
@@ -576,14 +585,23 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
   bool empty_seen = false;
   int64_t launches = 0;  // kernel launches timed by the profile events
   std::vector<int64_t> launch_level;  // first level of each launch
-  // High-diameter, low-degree graphs: levels run in one workgroup while the
-  // frontier is small (no launch per level); a frontier that outgrows it
-  // continues with the level kernel below.
-  const bool small = A->a.max_deg <= kSmallMaxDeg && desc.direction != GRB_DIR_PULL;
+  // High-diameter, low-degree graphs: levels run back to back in the
+  // multi-workgroup loop while the frontier is small (no launch per level);
+  // a frontier that outgrows it, or a barrier it gave up, continues with the
+  // level kernel below.
+  const bool small = A->a.max_deg <= kCoopMaxDeg && desc.direction != GRB_DIR_PULL;
+  if (small) {
+    ba.coop = w.coop;
+    ba.qv = w.qv;
+    ba.qe = w.qe;
+    ba.qseg = w.qseg;
+  }
+  launch_bfs_start(ba, source, w.F[1], w.F[2], stream);
   if (small) {
     if (profile) (void)hipEventRecord(g_events.get(0), s);
     uint64_t *F[3] = {w.F[0], w.F[1], w.F[2]};
-    launch_bfs_small(ba, source, cap, F, stream);
+    launch_bfs_coop(ba, source, cap, F, (desc.flags & GRB_LOOP_NO_WAIT) ? 0 : kCoopWaitTicks,
+                    stream);
     if (profile) (void)hipEventRecord(g_events.get(1), s);
     launch_level.push_back(0);
     launches = 1;
@@ -634,7 +652,7 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
     first_batch = false;
   }
   // parents the level kernel did not resolve: a search stopped by the level
-  // cap, or levels run by the one-workgroup loop
+  // cap, or levels run by the multi-workgroup loop
   capped = !empty_seen && hc.nlev >= d;
   if (parents && (small || capped)) {
     launch_bfs_parents(ba, stream);
@@ -648,7 +666,7 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
-    // per level: a level launch's time; the one-workgroup loop's time is
+    // per level: a level launch's time; the multi-workgroup loop's time is
     // spread evenly over the levels it ran
     kms.assign((size_t)std::max(nrec, 0), 0.0f);
     for (int64_t i = 0; i < launches; ++i) {
@@ -782,6 +800,16 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
     sa.d = (int32_t)std::min<int64_t>(d, INT32_MAX);
   };
   at_round(0);
+  // low-degree graphs: rounds back to back in the multi-workgroup loop while
+  // the pending set is small (no launch per round); a larger set, or a
+  // barrier the loop gave up, continues with the round kernel
+  const bool small = A->a.max_deg <= kCoopMaxDeg;
+  if (small) {
+    sa.coop = w.coop;
+    sa.qv = w.qv;
+    sa.qe = w.qe;
+    sa.qseg = w.qseg;
+  }
   launch_sssp_delta_start(sa, source, w.F[1], w.F[2], stream);
   const int64_t cap = desc.max_iter > 0 ? desc.max_iter : INT64_MAX;
   int64_t d = 0;
@@ -792,13 +820,11 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
   bool done = false;
   int64_t launches = 0;
   std::vector<int64_t> launch_round;
-  // low-degree graphs: rounds in one workgroup while the pending set is
-  // small (no launch per round); a larger set continues with the round kernel
-  const bool small = A->a.max_deg <= kSmallMaxDeg;
   if (small) {
     if (profile) (void)hipEventRecord(g_events.get(0), s);
     uint64_t *F[3] = {w.F[0], w.F[1], w.F[2]};
-    launch_sssp_delta_small(sa, source, cap, F, stream);
+    launch_sssp_delta_coop(sa, cap, F, (desc.flags & GRB_LOOP_NO_WAIT) ? 0 : kCoopWaitTicks,
+                           stream);
     if (profile) (void)hipEventRecord(g_events.get(1), s);
     launch_round.push_back(0);
     launches = 1;
@@ -832,7 +858,7 @@ grb_info run_sssp_delta(grb_matrix A, int32_t source, float *dist, float delta,
   std::vector<float> kms;
   double ms_all = 0.0;
   if (profile) {
-    // per round: a round launch's time; the one-workgroup loop's time is
+    // per round: a round launch's time; the multi-workgroup loop's time is
     // spread evenly over the rounds it ran
     kms.assign((size_t)std::max(nrec, 0), 0.0f);
     for (int64_t i = 0; i < launches; ++i) {

@@ -842,161 +842,213 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
     a.cnt_cur[0] = 1;  // level 0 = {source}
     a.cnt_cur[1] = ds;
     a.cnt_cur[2] = ds > kPushSplit ? 1 : 0;
+    if (a.coop) {  // the multi-workgroup loop's first queue: {source}
+      a.coop->bar = 0ull;
+      for (int i = 0; i < kCoopSegs; ++i) a.coop->cnt[0][i] = a.coop->esum[0][i] = 0;
+      a.coop->cnt[0][0] = 1;
+      a.coop->esum[0][0] = ds;
+      a.qv[0] = source;
+      a.qe[0] = ((uint64_t)(uint32_t)ds << 32) | (uint32_t)a.push.rp[source];
+    }
   }
 }
 
-// ---- one-workgroup level loop for small frontiers -------------------------
-// Each level: a thread takes frontier entries t, t + 1024, ... of the LDS
-// list (vertex, row start, degree), writes their level (delayed from the
-// level that found them, so the stores overlap this level's loads), loads
-// their out-edges four at a time and claims each target with one atomicOr
-// on its visited word, loading the target's row extents at the same time;
-// the winners are appended to the next list (one LDS atomic per wave).
-// Two dependent global round trips and one barrier per level.
-__global__ __launch_bounds__(kSmallThreads) void k_bfs_small(BfsArgs a, int32_t source,
-                                                             int64_t max_levels, uint64_t *F0,
-                                                             uint64_t *F1, uint64_t *F2) {
-  __shared__ int s_v[2][kSmallCap], s_rs[2][kSmallCap], s_dg[2][kSmallCap];
-  __shared__ int s_n[2], s_e[2], s_long[2];
+// ---- multi-workgroup level loop for small frontiers -------------------------
+// Level d: workgroup w takes the entries [w nc / G, (w + 1) nc / G) of the
+// level's queue, a thread per entry.  The queue has one segment per wave of
+// the loop; an entry is found through the prefix of the segments' counts.
+// The thread writes the entry's level (deferred from the level that found
+// it, so the store overlaps this level's loads), claims the targets of four
+// out-edges per step with one atomicOr on their visited words (their row
+// extents loaded beside), and queues the winners in its wave's segment of
+// the next queue.  Entries past a segment's capacity get their level and go
+// straight into the next frontier's bitmap (the loop then spills that
+// frontier).  No counter is shared: each wave stores its segment's count
+// and degree sum with its entries, before the barrier.
+__global__ __launch_bounds__(kCoopThreads) void k_bfs_coop(BfsArgs a, int64_t max_levels,
+                                                           uint64_t wait_ticks, uint64_t *F0,
+                                                           uint64_t *F1, uint64_t *F2) {
+  __shared__ int s_pre[kCoopSegs + 1];
+  __shared__ int s_nc, s_ne, s_ovf, s_go;
   const int tid = threadIdx.x, ln = tid & 63;
   const int32_t *rp = a.push.rp, *ci = a.push.ci;
-  if (tid == 0) {
-    s_v[0][0] = source;
-    s_rs[0][0] = rp[source];
-    s_dg[0][0] = rp[source + 1] - rp[source];
-    s_n[0] = 1;
-    s_e[0] = s_dg[0][0];
-    s_long[0] = s_dg[0][0] > kPushSplit ? 1 : 0;
-  }
-  __syncthreads();
+  CoopCtl *cc = a.coop;
+  const int w = (int)blockIdx.x;
+  const int my_seg = w * (kCoopThreads / 64) + (tid >> 6);
+  const int seg = a.qseg, qsize = kCoopSegs * seg;
   int64_t d = 0;
-  int b = 0;
   bool spill = false;
   for (;;) {
-    const int nc = s_n[b];
+    const int sl = (int)(d & 1);
+    if (tid < 64) {  // the level's queue: segment counts, their prefix, degree sums
+      const int c = ld_coherent(&cc->cnt[sl][tid]);
+      const int e = ld_coherent(&cc->esum[sl][tid]);
+      const int incl = wave_incl_scan(c);
+      s_pre[tid + 1] = incl;
+      const int tot = lane_last(incl), etot = wave_sum(e);
+      const bool ovf = __ballot(c > seg) != 0ull;
+      if (tid == 0) {
+        s_pre[0] = 0;
+        s_nc = tot;
+        s_ne = etot;
+        s_ovf = ovf ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int nc = s_nc, ne = s_ne;
     if (nc == 0 || d >= max_levels) break;
-    // a frontier too large for the lists, or one the switch rule would
+    // a frontier that outgrew its segments, or one the switch rule would
     // pull, goes to the level kernel
-    if (nc > kSmallSpill || s_e[b] > kSmallEdges || decide(a, nc, s_e[b]) == GRB_DIR_PULL) {
+    if (s_ovf || ne > kCoopEdges || d >= kCoopMaxLevels || decide(a, nc, ne) == GRB_DIR_PULL) {
       spill = true;
       break;
     }
-    if (tid == 0) {
-      s_n[b ^ 1] = 0;
-      s_e[b ^ 1] = 0;
-      s_long[b ^ 1] = 0;
+    if (w == 0 && tid == 0) {
       a.ctrl->nlev = (int)d + 1;
       if (a.stats && d < kStatsCap) {
         a.stats[d * kStatFields + 0] = nc;
-        a.stats[d * kStatFields + 1] = s_e[b];
+        a.stats[d * kStatFields + 1] = ne;
         a.stats[d * kStatFields + 2] = GRB_DIR_PUSH;
       }
     }
-    __syncthreads();
-    for (int base = 0; base < nc; base += 4 * kSmallThreads) {
-      int v[4], rs[4], dg[4];
+    const int qin = sl * qsize, qout = (sl ^ 1) * qsize + my_seg * seg;
+    const int sx = (int)((d + 1) % 3);
+    uint64_t *fn = sx == 0 ? F0 : (sx == 1 ? F1 : F2);
+    const int lo = (int)((int64_t)nc * w / kCoopGrid);
+    const int hi = (int)((int64_t)nc * (w + 1) / kCoopGrid);
+    int wcnt = 0, wsum = 0;  // this wave's appends (uniform over the wave)
+    for (int base = lo; base < hi; base += kCoopThreads) {
+      const int i = base + tid;
+      int rs = 0, dg = 0;
+      if (i < hi) {
+        int s = 0;  // segment holding entry i: the last s with s_pre[s] <= i
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = base + k * kSmallThreads + tid;
-        v[k] = -1;
-        rs[k] = dg[k] = 0;
-        if (i < nc) {
-          v[k] = s_v[b][i];
-          rs[k] = s_rs[b][i];
-          dg[k] = s_dg[b][i];
-          if (d > 0) a.levels[v[k]] = (int)d;
-        }
+        for (int step = kCoopSegs / 2; step > 0; step >>= 1)
+          if (s_pre[s + step] <= i) s += step;
+        const int at = qin + s * seg + (i - s_pre[s]);
+        const int v = ld_coherent(a.qv + at);
+        const uint64_t e = load_relaxed_u64(a.qe + at);
+        rs = (int)(uint32_t)e;
+        dg = (int)(e >> 32);
+        if (d > 0) a.levels[v] = (int)d;
       }
-      const int mx = max(max(dg[0], dg[1]), max(dg[2], dg[3]));
-      for (int q0 = 0; __syncthreads_or(q0 < mx); q0 += 4) {
-        int c[16];
+      for (int q0 = 0; __ballot(q0 < dg) != 0ull; q0 += 4) {
+        int c[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int q = 0; q < 4; ++q) c[q] = q0 + q < dg ? ci[rs + q0 + q] : -1;
+        uint64_t old[4];
+        int r0[4], r1[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            c[k * 4 + q] = q0 + q < dg[k] ? ci[rs[k] + q0 + q] : -1;
-        uint64_t old[16];
-        int r0[16], r1[16];
-#pragma unroll
-        for (int x = 0; x < 16; ++x) {
-          old[x] = ~0ull;
-          r0[x] = r1[x] = 0;
-          if (c[x] >= 0) {
-            old[x] = atomicOr((unsigned long long *)&a.visited[c[x] >> 6], 1ull << (c[x] & 63));
-            r0[x] = rp[c[x]];
-            r1[x] = rp[c[x] + 1];
+        for (int q = 0; q < 4; ++q) {
+          old[q] = ~0ull;
+          r0[q] = r1[q] = 0;
+          if (c[q] >= 0) {
+            old[q] = atomicOr((unsigned long long *)&a.visited[c[q] >> 6], 1ull << (c[q] & 63));
+            r0[q] = rp[c[q]];
+            r1[q] = rp[c[q] + 1];
           }
         }
+        bool won[4];
+        int nw = 0, wdeg = 0;
 #pragma unroll
-        for (int x = 0; x < 16; ++x) {
-          const bool won = c[x] >= 0 && !((old[x] >> (c[x] & 63)) & 1ull);
-          const uint64_t wm = __ballot(won);
-          if (wm == 0ull) continue;
-          int base_slot = 0;
-          if (ln == 0) {
-            base_slot = atomicAdd(&s_n[b ^ 1], __popcll(wm));
+        for (int q = 0; q < 4; ++q) {
+          won[q] = c[q] >= 0 && !((old[q] >> (c[q] & 63)) & 1ull);
+          nw += won[q] ? 1 : 0;
+          wdeg += won[q] ? r1[q] - r0[q] : 0;
+        }
+        const int incl = wave_incl_scan(nw);
+        const int tot = lane_last(incl);
+        if (tot == 0) continue;
+        int slot = wcnt + incl - nw;
+        wcnt += tot;
+        wsum += wave_sum(wdeg);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!won[q]) continue;
+          if (slot < seg) {
+            st_coherent(a.qv + qout + slot, c[q]);
+            store_relaxed_u64(a.qe + qout + slot,
+                              ((uint64_t)(uint32_t)(r1[q] - r0[q]) << 32) | (uint32_t)r0[q]);
+          } else {
+            a.levels[c[q]] = (int)d + 1;
+            atomicOr((unsigned long long *)&fn[c[q] >> 6], 1ull << (c[q] & 63));
           }
-          base_slot = __shfl(base_slot, 0);
-          const int dgc = won ? r1[x] - r0[x] : 0;
-          const int esum = wave_sum(dgc), lsum = wave_sum(dgc > kPushSplit ? 1 : 0);
-          if (ln == 0) {
-            atomicAdd(&s_e[b ^ 1], esum);
-            if (lsum) atomicAdd(&s_long[b ^ 1], lsum);
-          }
-          if (won) {
-            const int slot = base_slot + __popcll(wm & mask_below(ln));
-            if (slot < kSmallCap) {
-              s_v[b ^ 1][slot] = c[x];
-              s_rs[b ^ 1][slot] = r0[x];
-              s_dg[b ^ 1][slot] = dgc;
-            } else {
-              // no room in the list: level and frontier bit at once (the
-              // loop hands this frontier to the wide kernel)
-              a.levels[c[x]] = (int)d + 1;
-              uint64_t *fn = ((d + 1) % 3 == 0) ? F0 : (((d + 1) % 3 == 1) ? F1 : F2);
-              atomicOr((unsigned long long *)&fn[c[x] >> 6], 1ull << (c[x] & 63));
-            }
-          }
+          ++slot;
         }
       }
     }
+    // the wave's segment count and degree sum go with its entries; the
+    // barrier follows once every memory operation of the workgroup is done
+    if (ln == 0) {
+      st_coherent(&cc->cnt[sl ^ 1][my_seg], wcnt);
+      st_coherent(&cc->esum[sl ^ 1][my_seg], wsum);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) s_go = coop_barrier(&cc->bar, kCoopGrid, d, wait_ticks);
     __syncthreads();
     ++d;
-    b ^= 1;
-  }
-  // levels of the last listed frontier (its loop iteration did not run)
-  const int nl = min(s_n[b], kSmallCap);
-  if (d > 0)
-    for (int i = tid; i < nl; i += kSmallThreads) a.levels[s_v[b][i]] = (int)d;
-  if (spill) {
-    // the frontier of level d goes to the wide kernel as its bitmap and
-    // counters; the start kernel's source bit in F0 is the only other bit set
-    uint64_t *fn = (d % 3 == 0) ? F0 : ((d % 3 == 1) ? F1 : F2);
-    if (tid == 0) F0[source >> 6] = 0ull;
-    for (int i = tid; i < 3 * kCntSlots; i += kSmallThreads) a.ctrl->lists[i] = 0;
-    __syncthreads();
-    for (int i = tid; i < nl; i += kSmallThreads)
-      atomicOr((unsigned long long *)&fn[s_v[b][i] >> 6], 1ull << (s_v[b][i] & 63));
-    if (tid == 0) {
-      int32_t *cnt = a.ctrl->lists + (d % 3) * kCntSlots;
-      cnt[0] = s_n[b];
-      cnt[1] = s_e[b];
-      cnt[2] = s_long[b];
-      a.ctrl->pushed[0] = a.ctrl->pushed[1] = a.ctrl->pushed[2] = 0;  // parents: final pass
+    if (!s_go) {
+      // barrier given up: the frontier of level d (found by every
+      // workgroup before the barrier) goes to the level kernel
+      spill = true;
+      break;
     }
   }
-  if (tid == 0) {
+  if (w == 0 && tid == 0) {
     a.ctrl->small_levels = (int)d;
     a.ctrl->spilled = spill ? 1 : 0;
   }
 }
 
+// After the loop: the frontier it left in its queue (level h =
+// ctrl->small_levels, whose levels are not written yet) gets its levels;
+// when the loop spilled it, it also becomes the bitmap and counters of
+// level h for the level kernel (the entries past a segment's capacity are
+// in the bitmap already).
+__global__ __launch_bounds__(kBlock) void k_bfs_coop_handover(BfsArgs a, int32_t source,
+                                                               uint64_t *F0, uint64_t *F1,
+                                                               uint64_t *F2) {
+  const bool spilled = a.ctrl->spilled != 0;
+  const int64_t h = a.ctrl->small_levels;
+  uint64_t *fh = (h % 3 == 0) ? F0 : ((h % 3 == 1) ? F1 : F2);
+  const int sl = (int)(h & 1), seg = a.qseg, qsize = kCoopSegs * seg;
+  const int32_t *qv = a.qv + sl * qsize;
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < qsize; t += gridDim.x * kBlock) {
+    const int s = t / seg, j = t - s * seg;
+    if (j < a.coop->cnt[sl][s]) {
+      const int v = qv[t];
+      if (h > 0) a.levels[v] = (int)h;
+      if (spilled) atomicOr((unsigned long long *)&fh[v >> 6], 1ull << (v & 63));
+    }
+  }
+  if (spilled && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the start kernel's source bit in F0 is the only other bit set
+    // (h > 0: the source is not in this frontier)
+    if (h > 0) atomicAnd((unsigned long long *)&F0[source >> 6], ~(1ull << (source & 63)));
+    int nq = 0, ne = 0;
+    for (int s = 0; s < kCoopSegs; ++s) {
+      nq += a.coop->cnt[sl][s];
+      ne += a.coop->esum[sl][s];
+    }
+    for (int i = 0; i < 3 * kCntSlots; ++i) a.ctrl->lists[i] = 0;
+    int32_t *cnt = a.ctrl->lists + (h % 3) * kCntSlots;
+    cnt[0] = nq;
+    cnt[1] = ne;
+    cnt[2] = 0;  // rows are at most kCoopMaxDeg long
+    a.ctrl->pushed[0] = a.ctrl->pushed[1] = a.ctrl->pushed[2] = 0;  // parents: final pass
+  }
+}
+
 }  // namespace
 
-void launch_bfs_small(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
-                      void *stream) {
-  hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kSmallThreads), 0, (hipStream_t)stream, a, source,
-                     max_levels, F[0], F[1], F[2]);
+void launch_bfs_coop(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
+                     uint64_t wait_ticks, void *stream) {
+  hipLaunchKernelGGL(k_bfs_coop, dim3(kCoopGrid), dim3(kCoopThreads), 0, (hipStream_t)stream, a,
+                     max_levels, wait_ticks, F[0], F[1], F[2]);
+  const int g = (kCoopSegs * a.qseg + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_bfs_coop_handover, dim3(g < 1 ? 1 : g), dim3(kBlock), 0,
+                     (hipStream_t)stream, a, source, F[0], F[1], F[2]);
 }
 
 void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,

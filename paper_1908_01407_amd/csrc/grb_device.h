@@ -244,6 +244,47 @@ __device__ __forceinline__ uint64_t load_relaxed_u64(uint64_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---- multi-workgroup loops ---------------------------------------------------
+// Device-coherent (agent-scope) 32-bit load and store, for what one
+// workgroup of a loop hands to another within one kernel.
+__device__ __forceinline__ int ld_coherent(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(int32_t *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier j of a multi-workgroup loop, called by one thread per workgroup
+// after the workgroup's memory operations have completed: one arrival on
+// the shared counter, then a wait bounded by wait_ticks of the 100 MHz
+// real-time clock.  A workgroup that waits longer gives the barrier up by
+// writing j + 1 into the counter's high half, with a compare-and-swap
+// against the word it read, so that it cannot give up a barrier the last
+// arrival completed in the meantime.  Every workgroup reaches the same
+// outcome: 1 when all have arrived, 0 when the barrier was given up (every
+// workgroup has then still done its work before barrier j, and all of them
+// leave the loop at barrier j).  Arrivals must stay below 2^32.
+__device__ __forceinline__ int coop_barrier(unsigned long long *bar, int groups, int64_t j,
+                                            uint64_t wait_ticks) {
+  const unsigned long long target = (unsigned long long)groups * (unsigned long long)(j + 1);
+  const unsigned long long mark = (unsigned long long)(j + 1) << 32;
+  __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    const unsigned long long w = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((w >> 32) != 0ull) return 0;  // given up (only barrier j can be)
+    if ((w & 0xffffffffull) >= target) return 1;
+    if (wall_clock64() - t0 >= wait_ticks) {
+      unsigned long long e = w;
+      if (__hip_atomic_compare_exchange_strong(bar, &e, w | mark, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return 0;
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
 // atomic min for floats of either sign (returns the previous value)
 __device__ __forceinline__ float atomic_min_f32(float *a, float v) {
   if (!(v < 0.0f)) return __int_as_float(atomicMin((int *)a, __float_as_int(v)));

@@ -101,7 +101,7 @@ struct Ctrl {
   int64_t active;             // adaptive PageRank: vertices still active
   int32_t ticket_list;        // generic product: list preparation workgroup tickets
   int32_t error;              // batched BFS: a source id was out of range
-  int32_t small_levels;       // BFS / SSSP: levels or rounds run by the one-workgroup loop
+  int32_t small_levels;       // BFS / SSSP: levels or rounds run by the multi-workgroup loop
   int32_t spilled;            // ... which then handed a frontier to the wide kernels
   int32_t pushed_sd[3];       // BFS: degree sum of the push that found the buffer's frontier
   int32_t pad32;
@@ -166,6 +166,35 @@ struct CompactArgs {
 int compact_blocks(int64_t nw);
 void launch_compact(const CompactArgs &a, void *stream);
 
+// Multi-workgroup level loop (high-diameter, low-degree graphs): a small grid
+// of workgroups runs BFS levels (SSSP bucket rounds) back to back, separated
+// by a barrier of its own (one arrival per workgroup on a shared counter,
+// then a bounded wait), with the frontier as a queue in device memory.
+// Everything one workgroup hands to another goes through device-coherent
+// (agent-scope) atomics, loads and stores, so no L2 write-back is needed.
+// State shared by the loop's workgroups:
+constexpr int kCoopThreads = 256;
+constexpr int kCoopGrid = 16;          // workgroups of the loop
+constexpr int kCoopSegs = kCoopGrid * (kCoopThreads / 64);  // one queue segment per wave (64)
+constexpr int kCoopSeg = 256;          // queue entries per wave and level (more: spill)
+constexpr int kCoopEdges = 65536;      // a frontier with more edges goes to the level kernel
+// Each level's queue has one segment per wave of the loop; the wave that
+// found the entries stores their count and degree sum (slot d & 1 for the
+// frontier of level d).
+struct CoopCtl {
+  unsigned long long bar;  // arrivals (low 32 bits) | 1 + the barrier given up (high 32 bits)
+  int32_t cnt[2][kCoopSegs];   // entries queued
+  int32_t esum[2][kCoopSegs];  // BFS: their degree sum; bucketed SSSP: that of the near ones
+  int32_t near[2][kCoopSegs];  // bucketed SSSP: entries below the round's limit
+  int32_t far[2][kCoopSegs];   // bucketed SSSP: smallest bucket of the others (INT_MAX: none)
+};
+constexpr int64_t kCoopMaxLevels = int64_t(1) << 24;  // arrivals stay below 2^32
+// A barrier not completed after this many ticks of the 100 MHz real-time
+// clock (1 ms: a level of the loop takes microseconds) is given up; the
+// frontier then continues with the level kernel.  Nothing waits unboundedly,
+// also when some of the loop's workgroups are not resident.
+constexpr uint64_t kCoopWaitTicks = 100000;
+
 // BFS with one kernel per level (grb_bfs.hip).  Each of the three rotating
 // frontier buffers has kCntStripes (count, degree sum) counter pairs.
 // per stripe: frontier size, its degree sum, its rows longer than kPushSplit
@@ -185,25 +214,26 @@ struct BfsArgs {
   int64_t *stats = nullptr;
   int32_t d = 0;
   int32_t rule = 0, denom = 10, forced = 0;
+  // multi-workgroup loop: shared state and the two level queues (entries:
+  // vertex, and row start | degree << 32; queue d & 1 at offset (d & 1) *
+  // kCoopSegs * qseg, segment s of a queue at s * qseg)
+  CoopCtl *coop = nullptr;
+  int32_t *qv = nullptr;
+  uint64_t *qe = nullptr;
+  int32_t qseg = 0;
 };
 void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                       void *stream);
 void launch_bfs_level(const BfsArgs &a, void *stream);
-// BFS levels in one workgroup while the frontier is small (high-diameter,
-// low-degree graphs): frontier lists in LDS, workgroup barriers only; hands
-// the frontier to the wide level kernel (as the bitmap and counters of
-// level ctrl->small_levels) when it outgrows the lists.  Starts at level 0
-// after launch_bfs_start; parents are left to the parents pass.
-constexpr int kSmallThreads = 1024;
-constexpr int kSmallCap = 4096;     // frontier vertices per level held in LDS
-// One workgroup streams a level through one CU: measured on the 3000 x 3000
-// grid it spends ~27 us on a 3000-vertex level against ~10 us for a level
-// launch, so the frontier goes to the level kernel well before the lists fill
-constexpr int kSmallSpill = 384;    // frontier vertices the loop still expands
-constexpr int kSmallEdges = 1536;   // ... and their edges
-constexpr int kSmallMaxDeg = 64;    // graphs whose rows are at most this long use the loop
-void launch_bfs_small(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
-                      void *stream);
+constexpr int kCoopMaxDeg = 64;  // graphs whose rows are at most this long use the loop
+// BFS levels in kCoopGrid workgroups while the frontier fits the queues
+// (kCoopSeg vertices per wave, kCoopEdges edges) and pushes; starts at level 0 after
+// launch_bfs_start (which fills the first queue), then a hand-over kernel
+// leaves a frontier that outgrew the loop (or a given-up barrier's next
+// frontier) as the bitmap and counters of level ctrl->small_levels.
+// Parents are left to the parents pass.
+void launch_bfs_coop(const BfsArgs &a, int32_t source, int64_t max_levels, uint64_t *const F[3],
+                     uint64_t wait_ticks, void *stream);
 void launch_bfs_parents(const BfsArgs &a, void *stream);
 
 // SSSP with one kernel per round (grb_sssp.hip); counters as BFS
@@ -225,6 +255,11 @@ struct SsspArgs {
   int64_t *stats = nullptr;
   int32_t d = 0;
   int32_t rule = 0, denom = 10, forced = 0;
+  // bucketed rounds in the multi-workgroup loop: as BfsArgs
+  CoopCtl *coop = nullptr;
+  int32_t *qv = nullptr;
+  uint64_t *qe = nullptr;
+  int32_t qseg = 0;
 };
 void launch_sssp_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2, float *fd1,
                        float *fd2, void *stream);
@@ -238,11 +273,12 @@ constexpr int kDeltaSlots = kDeltaFields * kCntStripes;
 void launch_sssp_delta_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                              void *stream);
 void launch_sssp_delta_round(const SsspArgs &a, void *stream);
-// bucket rounds in one workgroup while the pending set fits its LDS lists
-// (the BFS loop's limits); hands the set to the round kernel as the bitmap
-// and counters of round ctrl->small_levels when it outgrows them
-void launch_sssp_delta_small(const SsspArgs &a, int32_t source, int64_t max_rounds,
-                             uint64_t *const F[3], void *stream);
+// bucket rounds in the multi-workgroup loop (kCoopGrid workgroups, the BFS
+// loop's queues and limits), then a hand-over kernel that leaves a pending
+// set that outgrew it (or a given-up barrier's next set) as the bitmap and
+// counters of round ctrl->small_levels for the round kernel
+void launch_sssp_delta_coop(const SsspArgs &a, int64_t max_rounds, uint64_t *const F[3],
+                            uint64_t wait_ticks, void *stream);
 
 struct PrArgs {
   int64_t n = 0, nw = 0;

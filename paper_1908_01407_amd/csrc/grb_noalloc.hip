@@ -5,7 +5,7 @@
 //
 // The array holds the BFS workspace of graphs up to 2^24 vertices (visited
 // and three frontier bitmaps of n / 8 bytes each, plus the control block and
-// level records): 8 MiB + 64 KiB, held on every GPU the library runs on
+// level records): 8 MiB + 512 KiB, held on every GPU the library runs on
 // until the process ends.  Its device address is looked up once per device
 // (hipGetSymbolAddress, with that device current) on the first call there;
 // in host code the array's own name is not a device address.  Every call on
@@ -22,7 +22,7 @@ namespace grb {
 namespace {
 
 constexpr int64_t kNoAllocMaxVertices = (int64_t)1 << 24;
-constexpr size_t kNoAllocBytes = ((size_t)4 << 21) + ((size_t)64 << 10);
+constexpr size_t kNoAllocBytes = ((size_t)4 << 21) + ((size_t)512 << 10);
 
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 

@@ -306,207 +306,261 @@ __global__ __launch_bounds__(kBlock) void k_sssp_delta_start(SsspArgs a, int32_t
     a.cnt_cur[4] = 1;
     a.ctrl->nlev = 0;
     a.ctrl->bucket = 0;
+    if (a.coop) {  // the multi-workgroup loop's first queue: {source}, near
+      a.coop->bar = 0ull;
+      for (int i = 0; i < kCoopSegs; ++i) {
+        a.coop->cnt[0][i] = a.coop->esum[0][i] = a.coop->near[0][i] = 0;
+        a.coop->far[0][i] = INT_MAX;
+      }
+      a.coop->cnt[0][0] = 1;
+      a.coop->near[0][0] = 1;
+      a.coop->esum[0][0] = ds;
+      a.qv[0] = source;
+      a.qe[0] = ((uint64_t)(uint32_t)ds << 32) | (uint32_t)a.push.rp[source];
+    }
   }
 }
 
-// ---- one-workgroup bucket rounds while the pending set is small -----------
-// The pending set as two LDS lists (consumed / filled: vertex, row start,
-// degree) with membership bits in two bitmaps (F0, F1), so a vertex joins
-// the filled list once per round.  A round: each thread takes entries of the
-// consumed list, clears their bits, reads their distance together with
-// their first out-edges; an entry below the bucket's limit relaxes its edges
-// (atomicMin on the float bits, the target's row extents loaded beside it)
-// and every improved target joins the filled list; an entry above the limit
-// is carried.  The bucket moves to the nearest pending one when no member
-// below the limit is left.  A pending set too large for the lists goes to
-// the wide round kernel as its bitmap and counters.
-__device__ __forceinline__ void small_insert(bool want, int x, int rs, int dg, float dx, float limit,
-                                             float delta, uint64_t *fill, int (*s_v)[kSmallCap],
-                                             int (*s_rs)[kSmallCap], int (*s_dg)[kSmallCap],
-                                             int *s_n, int *s_near, int *s_sd, int *s_lng,
-                                             int *s_far, int nb) {
+// ---- multi-workgroup bucket rounds while the pending set is small ----------
+// The pending set as a queue in device memory (one segment per wave of the
+// loop; entries: vertex, row start | degree << 32) with membership bits in
+// F0 / F1 (round d consumes F[d & 1] and fills F[(d + 1) & 1]).  A vertex
+// may be queued more than once in a round (each improvement queues it); the
+// consumer whose atomicAnd clears its membership bit takes it, and the
+// other copies are skipped.  A round: workgroup w takes the entries
+// [w n / G, (w + 1) n / G), a thread per entry, which clears the member's
+// bit and reads its distance together with its first four out-edges and
+// weights; a member below the bucket's limit relaxes its edges (atomicMin
+// on the float bits, the target's row extents loaded beside) and queues
+// every target it improved, a member above it is queued again (carried).
+// Per wave: entries queued, near ones (below the limit), their degree sum,
+// the smallest bucket of the others.  The bucket moves to the nearest
+// pending one when no near member is left.  A pending set that outgrows
+// the segments (or the loop's edge limit) goes to the round kernel.
+// Queues in the wave's segment of the next queue (slots counted in wcnt);
+// every queued vertex gets its membership bit, also past the segment's end.
+__device__ __forceinline__ void coop_queue(bool want, int x, int rs, int dg, float dx, float limit,
+                                           float delta, uint64_t *fill, int32_t *qv, uint64_t *qe,
+                                           int seg, int &wcnt, int &wnear, int &wsd, int &wfar) {
   const int ln = threadIdx.x & 63;
-  bool first = false;
+  const uint64_t m = __ballot(want);
+  if (m == 0ull) return;
+  const bool nr = want && dx < limit;
+  wnear += wave_sum(nr ? 1 : 0);
+  wsd += wave_sum(nr ? dg : 0);
+  const int far = (want && !nr) ? bucket_of(dx, delta) : INT_MAX;
+  wfar = min(wfar, lane_last(wave_scan(far, INT_MAX, [](int p, int q) { return p < q ? p : q; })));
   if (want) {
-    const uint64_t bit = 1ull << (x & 63);
-    first = !(atomicOr((unsigned long long *)&fill[x >> 6], (unsigned long long)bit) & bit);
-  }
-  const uint64_t fm = __ballot(first);
-  if (fm == 0ull) return;
-  int base = 0;
-  if (ln == 0) base = atomicAdd(&s_n[nb], __popcll(fm));
-  base = __shfl(base, 0);
-  const bool nr = first && dx < limit;
-  const int c_near = wave_sum(nr ? 1 : 0), c_sd = wave_sum(nr ? dg : 0);
-  const int c_lng = wave_sum(nr && dg > kPushSplit ? 1 : 0);
-  int far = (first && !nr) ? bucket_of(dx, delta) : INT_MAX;
-  far = lane_last(wave_scan(far, INT_MAX, [](int p, int q) { return p < q ? p : q; }));
-  if (ln == 0) {
-    if (c_near) {
-      atomicAdd(&s_near[nb], c_near);
-      atomicAdd(&s_sd[nb], c_sd);
-      if (c_lng) atomicAdd(&s_lng[nb], c_lng);
+    const int slot = wcnt + __popcll(m & mask_below(ln));
+    atomicOr((unsigned long long *)&fill[x >> 6], 1ull << (x & 63));
+    if (slot < seg) {
+      st_coherent(qv + slot, x);
+      store_relaxed_u64(qe + slot, ((uint64_t)(uint32_t)dg << 32) | (uint32_t)rs);
     }
-    if (far != INT_MAX) atomicMin(&s_far[nb], far);
   }
-  if (first) {
-    const int slot = base + __popcll(fm & mask_below(ln));
-    if (slot < kSmallCap) {
-      s_v[nb][slot] = x;
-      s_rs[nb][slot] = rs;
-      s_dg[nb][slot] = dg;
-    }
-    // (a member past the lists' capacity stays in the bitmap only: the set
-    // then goes to the wide kernel, which reads the bitmap)
-  }
+  wcnt += __popcll(m);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_sssp_delta_small(SsspArgs a, int32_t source,
-                                                                    int64_t max_rounds,
-                                                                    uint64_t *F0, uint64_t *F1,
-                                                                    uint64_t *F2) {
-  __shared__ int s_v[2][kSmallCap], s_rs[2][kSmallCap], s_dg[2][kSmallCap];
-  __shared__ int s_n[2], s_near[2], s_sd[2], s_lng[2], s_far[2];
-  __shared__ int s_bucket;
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(kCoopThreads) void k_sssp_delta_coop(SsspArgs a, int64_t max_rounds,
+                                                                  uint64_t wait_ticks,
+                                                                  uint64_t *F0, uint64_t *F1) {
+  __shared__ int s_pre[kCoopSegs + 1];
+  __shared__ int s_n, s_near, s_sd, s_far, s_ovf, s_go;
+  const int tid = threadIdx.x, ln = tid & 63;
   const int32_t *rp = a.push.rp, *ci = a.push.ci;
+  const float *wt = a.wpush;
+  CoopCtl *cc = a.coop;
+  const int w = (int)blockIdx.x;
+  const int my_seg = w * (kCoopThreads / 64) + (tid >> 6);
+  const int seg = a.qseg, qsize = kCoopSegs * seg;
   const float delta = a.delta;
-  uint64_t *const bm[2] = {F0, F1};
-  if (tid == 0) {
-    const int dg = rp[source + 1] - rp[source];
-    s_v[0][0] = source;
-    s_rs[0][0] = rp[source];
-    s_dg[0][0] = dg;
-    s_n[0] = 1;
-    s_near[0] = 1;
-    s_sd[0] = dg;
-    s_lng[0] = dg > kPushSplit ? 1 : 0;
-    s_far[0] = INT_MAX;
-    s_bucket = 0;
-  }
-  __syncthreads();
+  int bucket = 0;
   int64_t d = 0;
-  int b = 0;
   bool spill = false;
   for (;;) {
-    const int n = s_n[b];
+    const int sl = (int)(d & 1);
+    if (tid < 64) {  // the round's queue: segment counts and their prefix, totals
+      const int c = ld_coherent(&cc->cnt[sl][tid]);
+      const int nr = ld_coherent(&cc->near[sl][tid]);
+      const int e = ld_coherent(&cc->esum[sl][tid]);
+      const int f = ld_coherent(&cc->far[sl][tid]);
+      const int incl = wave_incl_scan(c);
+      s_pre[tid + 1] = incl;
+      const int tot = lane_last(incl), nt = wave_sum(nr), et = wave_sum(e);
+      const int ft = lane_last(wave_scan(f, INT_MAX, [](int p, int q) { return p < q ? p : q; }));
+      const bool ovf = __ballot(c > seg) != 0ull;
+      if (tid == 0) {
+        s_pre[0] = 0;
+        s_n = tot;
+        s_near = nt;
+        s_sd = et;
+        s_far = ft;
+        s_ovf = ovf ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int n = s_n;
     if (n == 0 || d >= max_rounds) break;
-    if (n > kSmallSpill || s_sd[b] > kSmallEdges) {
+    if (s_ovf || s_sd > kCoopEdges || d >= kCoopMaxLevels) {
       spill = true;
       break;
     }
-    const int bucket = s_near[b] > 0 ? s_bucket : s_far[b];
-    __syncthreads();  // every thread has read the counters of list b
-    if (tid == 0) {
-      s_bucket = bucket;
-      s_n[b ^ 1] = s_near[b ^ 1] = s_sd[b ^ 1] = s_lng[b ^ 1] = 0;
-      s_far[b ^ 1] = INT_MAX;
+    bucket = s_near > 0 ? bucket : s_far;
+    if (w == 0 && tid == 0) {
       a.ctrl->nlev = (int)d + 1;
       a.ctrl->bucket = bucket;
       if (a.stats && d < kStatsCap) {
         a.stats[d * kStatFields + 0] = n;
-        a.stats[d * kStatFields + 1] = s_sd[b];
+        a.stats[d * kStatFields + 1] = s_sd;
         a.stats[d * kStatFields + 2] = GRB_DIR_PUSH;
         a.stats[d * kStatFields + 3] = bucket;
       }
     }
-    __syncthreads();
     const float limit = (float)(bucket + 1) * delta;
-    uint64_t *const cons = bm[d & 1], *const fill = bm[(d + 1) & 1];
-    for (int base = 0; base < n; base += 4 * kSmallThreads) {
-      int v[4], rs[4], dg[4];
-      float dv[4];
+    uint64_t *const cons = sl ? F1 : F0, *const fill = sl ? F0 : F1;
+    const int qin = sl * qsize, qout = (sl ^ 1) * qsize + my_seg * seg;
+    int32_t *const qvo = a.qv + qout;
+    uint64_t *const qeo = a.qe + qout;
+    const int lo = (int)((int64_t)n * w / kCoopGrid);
+    const int hi = (int)((int64_t)n * (w + 1) / kCoopGrid);
+    int wcnt = 0, wnear = 0, wsd = 0, wfar = INT_MAX;  // uniform over the wave
+    for (int base = lo; base < hi; base += kCoopThreads) {
+      const int i = base + tid;
+      int v = -1, rs = 0, dg = 0;
+      if (i < hi) {
+        int s = 0;  // segment holding entry i: the last s with s_pre[s] <= i
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = base + k * kSmallThreads + tid;
-        v[k] = -1;
-        rs[k] = dg[k] = 0;
-        dv[k] = 0.0f;
-        if (i < n) {
-          v[k] = s_v[b][i];
-          rs[k] = s_rs[b][i];
-          dg[k] = s_dg[b][i];
-          atomicAnd((unsigned long long *)&cons[v[k] >> 6], ~(1ull << (v[k] & 63)));
-          dv[k] = a.dist[v[k]];
-        }
+        for (int step = kCoopSegs / 2; step > 0; step >>= 1)
+          if (s_pre[s + step] <= i) s += step;
+        const int at = qin + s * seg + (i - s_pre[s]);
+        v = ld_coherent(a.qv + at);
+        const uint64_t e = load_relaxed_u64(a.qe + at);
+        rs = (int)(uint32_t)e;
+        dg = (int)(e >> 32);
       }
-      // carried: members above the limit stay pending
+      bool take = false;
+      float dv = 0.0f;
+      int c0[4];
+      float w0[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        small_insert(v[k] >= 0 && !(dv[k] < limit), v[k], rs[k], dg[k], dv[k], limit, delta, fill,
-                     s_v, s_rs, s_dg, s_n, s_near, s_sd, s_lng, s_far, b ^ 1);
-      int mx = 0;
+      for (int q = 0; q < 4; ++q) {
+        c0[q] = -1;
+        w0[q] = 0.0f;
+      }
+      if (v >= 0) {
+        const uint64_t bit = 1ull << (v & 63);
+        const uint64_t was = atomicAnd((unsigned long long *)&cons[v >> 6], ~bit);
+        dv = __int_as_float(ld_coherent((const int32_t *)&a.dist[v]));
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (v[k] >= 0 && dv[k] < limit) mx = max(mx, dg[k]);
-      for (int q0 = 0; __syncthreads_or(q0 < mx); q0 += 4) {
-        int c[16];
-        float nd[16];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const bool ok = v[k] >= 0 && dv[k] < limit && q0 + q < dg[k];
-            c[k * 4 + q] = ok ? ci[rs[k] + q0 + q] : -1;
-            nd[k * 4 + q] = ok ? dv[k] + a.wpush[rs[k] + q0 + q] : 0.0f;
+        for (int q = 0; q < 4; ++q)
+          if (q < dg) {
+            c0[q] = ci[rs + q];
+            w0[q] = wt[rs + q];
           }
-        int old[16], r0[16], r1[16];
+        take = (was & bit) != 0ull;
+      }
+      const bool relax = take && dv < limit;
+      // carried: a member above the limit stays pending
+      coop_queue(take && !relax, v, rs, dg, dv, limit, delta, fill, qvo, qeo, seg, wcnt, wnear,
+                 wsd, wfar);
+      for (int q0 = 0; __ballot(relax && q0 < dg) != 0ull; q0 += 4) {
+        int c[4];
+        float nd[4];
 #pragma unroll
-        for (int x = 0; x < 16; ++x) {
-          old[x] = 0;
-          r0[x] = r1[x] = 0;
-          if (c[x] >= 0) {
-            old[x] = atomicMin((int *)&a.dist[c[x]], __float_as_int(nd[x]));
-            r0[x] = rp[c[x]];
-            r1[x] = rp[c[x] + 1];
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = relax && q0 + q < dg;
+          c[q] = !ok ? -1 : (q0 == 0 ? c0[q] : ci[rs + q0 + q]);
+          nd[q] = !ok ? 0.0f : dv + (q0 == 0 ? w0[q] : wt[rs + q0 + q]);
+        }
+        int old[4], r0[4], r1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          old[q] = 0;
+          r0[q] = r1[q] = 0;
+          if (c[q] >= 0) {
+            old[q] = atomicMin((int *)&a.dist[c[q]], __float_as_int(nd[q]));
+            r0[q] = rp[c[q]];
+            r1[q] = rp[c[q] + 1];
           }
         }
 #pragma unroll
-        for (int x = 0; x < 16; ++x)
-          small_insert(c[x] >= 0 && nd[x] < __int_as_float(old[x]), c[x], r0[x], r1[x] - r0[x],
-                       nd[x], limit, delta, fill, s_v, s_rs, s_dg, s_n, s_near, s_sd, s_lng,
-                       s_far, b ^ 1);
+        for (int q = 0; q < 4; ++q)
+          coop_queue(c[q] >= 0 && nd[q] < __int_as_float(old[q]), c[q], r0[q], r1[q] - r0[q],
+                     nd[q], limit, delta, fill, qvo, qeo, seg, wcnt, wnear, wsd, wfar);
       }
     }
+    // the wave's segment counters go with its entries; the barrier follows
+    // once every memory operation of the workgroup is done
+    if (ln == 0) {
+      st_coherent(&cc->cnt[sl ^ 1][my_seg], wcnt);
+      st_coherent(&cc->near[sl ^ 1][my_seg], wnear);
+      st_coherent(&cc->esum[sl ^ 1][my_seg], wsd);
+      st_coherent(&cc->far[sl ^ 1][my_seg], wfar);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) s_go = coop_barrier(&cc->bar, kCoopGrid, d, wait_ticks);
     __syncthreads();
     ++d;
-    b ^= 1;
-  }
-  if (spill) {
-    // the pending set of round d: its bitmap (F[d % 2]) becomes the wide
-    // kernel's F[d % 3]; every other buffer is zero; counters and bucket
-    uint64_t *const F[3] = {F0, F1, F2};
-    uint64_t *src = F[d % 2], *dst = F[d % 3];
-    if (src != dst)
-      for (int64_t w = tid; w < a.nw; w += kSmallThreads) {
-        dst[w] = src[w];
-        src[w] = 0ull;
-      }
-    for (int i = tid; i < 3 * kDeltaSlots; i += kSmallThreads)
-      a.ctrl->lists[i] = (i % kDeltaFields) == 3 ? INT_MAX : 0;
-    __syncthreads();
-    if (tid == 0) {
-      int32_t *cnt = a.ctrl->lists + (d % 3) * kDeltaSlots;
-      cnt[0] = s_near[b];
-      cnt[1] = s_sd[b];
-      cnt[2] = s_lng[b];
-      cnt[3] = s_far[b];
-      cnt[4] = s_n[b];
-      a.ctrl->bucket = s_bucket;
+    if (!s_go) {
+      // barrier given up: the pending set of round d (complete: every
+      // workgroup finished round d - 1) goes to the round kernel
+      spill = true;
+      break;
     }
   }
-  if (tid == 0) {
+  if (w == 0 && tid == 0) {
     a.ctrl->small_levels = (int)d;
     a.ctrl->spilled = spill ? 1 : 0;
   }
 }
 
+// After the loop spilled at round h = ctrl->small_levels: its pending set
+// (bitmap F[h & 1] of F0 / F1) becomes the round kernel's F[h % 3] (every
+// other buffer is zero), with the counters and bucket of round h.
+__global__ __launch_bounds__(kBlock) void k_sssp_delta_coop_handover(SsspArgs a, uint64_t *F0,
+                                                                      uint64_t *F1,
+                                                                      uint64_t *F2) {
+  if (!a.ctrl->spilled) return;
+  const int64_t h = a.ctrl->small_levels;
+  uint64_t *const F[3] = {F0, F1, F2};
+  uint64_t *src = F[h & 1], *dst = F[h % 3];
+  if (src != dst)
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < a.nw;
+         w += (int64_t)gridDim.x * kBlock) {
+      dst[w] = src[w];
+      src[w] = 0ull;
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int sl = (int)(h & 1);
+    int nq = 0, nr = 0, sd = 0, far = INT_MAX;
+    for (int s = 0; s < kCoopSegs; ++s) {
+      nq += a.coop->cnt[sl][s];
+      nr += a.coop->near[sl][s];
+      sd += a.coop->esum[sl][s];
+      far = min(far, a.coop->far[sl][s]);
+    }
+    for (int i = 0; i < 3 * kDeltaSlots; ++i)
+      a.ctrl->lists[i] = (i % kDeltaFields) == 3 ? INT_MAX : 0;
+    int32_t *cnt = a.ctrl->lists + (h % 3) * kDeltaSlots;
+    cnt[0] = nr;
+    cnt[1] = sd;
+    cnt[2] = 0;  // rows are at most kCoopMaxDeg long
+    cnt[3] = far;
+    cnt[4] = nq;
+  }
+}
+
 }  // namespace
 
-void launch_sssp_delta_small(const SsspArgs &a, int32_t source, int64_t max_rounds,
-                             uint64_t *const F[3], void *stream) {
-  hipLaunchKernelGGL(k_sssp_delta_small, dim3(1), dim3(kSmallThreads), 0, (hipStream_t)stream, a,
-                     source, max_rounds, F[0], F[1], F[2]);
+void launch_sssp_delta_coop(const SsspArgs &a, int64_t max_rounds, uint64_t *const F[3],
+                            uint64_t wait_ticks, void *stream) {
+  hipLaunchKernelGGL(k_sssp_delta_coop, dim3(kCoopGrid), dim3(kCoopThreads), 0,
+                     (hipStream_t)stream, a, max_rounds, wait_ticks, F[0], F[1]);
+  int64_t g = (a.nw + kBlock - 1) / kBlock;
+  g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+  hipLaunchKernelGGL(k_sssp_delta_coop_handover, dim3((unsigned)g), dim3(kBlock), 0,
+                     (hipStream_t)stream, a, F[0], F[1], F[2]);
 }
 
 void launch_sssp_delta_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,

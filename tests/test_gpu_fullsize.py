@@ -157,9 +157,17 @@ def test_grid3000_bfs_sssp(grb, grid3000):
     assert nl == 5999
     assert np.array_equal(lev.cpu().numpy(), ref_lev)
     assert np.array_equal(par.cpu().numpy(), ref_par)
+    # the level loop's barriers given up from the start (hand-over at level 1)
+    lev, par = grb.bfs(A, 0, desc=grb.descriptor(flags=grb.GRB_LOOP_NO_WAIT))
+    assert np.array_equal(lev.cpu().numpy(), ref_lev)
+    assert np.array_equal(par.cpu().numpy(), ref_par)
     ref, _, _ = oracle.sssp(adj, 0)
     dist = grb.sssp(A, 0)
     assert np.array_equal(dist.cpu().numpy(), ref)
+    # bucketed rounds (multi-workgroup loop), also with its barriers given up
+    for flags in (0, grb.GRB_LOOP_NO_WAIT):
+        dist = grb.sssp(A, 0, delta=2048.0, desc=grb.descriptor(flags=flags))
+        assert np.array_equal(dist.cpu().numpy(), ref), flags
 
 
 def test_pagerank_rmat22_directed(grb):

@@ -140,7 +140,7 @@ def test_bfs_direction_sequence_and_work(grb, name):
 
 
 def test_bfs_level_cap_low_degree(grb):
-    """A level cap inside the one-workgroup loop (grid) and after it handed
+    """A level cap inside the multi-workgroup loop (grid) and after it handed
     the frontier to the level kernel (lowdeg): levels up to the cap, parents
     of every reached vertex by the min-id rule."""
     for name, caps in (("grid_33x70", (1, 5, 40)), ("lowdeg", (3, 8, 9))):
@@ -153,6 +153,27 @@ def test_bfs_level_cap_low_degree(grb):
             assert np.array_equal(lev.cpu().numpy(), want), (name, cap)
             wpar = np.where(ref_lev <= cap, ref_par, -1)
             assert np.array_equal(par.cpu().numpy(), wpar), (name, cap)
+
+
+@pytest.mark.parametrize("name", ["grid_33x70", "path", "lowdeg", "two_comp"])
+def test_bfs_loop_barrier_given_up(grb, name):
+    """The multi-workgroup level loop's failure path, forced from the host
+    (GRB_LOOP_NO_WAIT: every barrier is given up at its first unfinished
+    poll, as when some of its workgroups are not resident): the search
+    continues in the level kernels and gives the oracle's levels and parents."""
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    for s in _sources(name, g.n):
+        ref_lev, ref_par, nl = oracle.bfs(adj, s)
+        for cap in (0, 2, 7):
+            lev, par = grb.bfs(A, s, desc=grb.descriptor(flags=grb.GRB_LOOP_NO_WAIT,
+                                                         max_iter=cap))
+            want = ref_lev if cap == 0 else np.where(ref_lev <= cap, ref_lev, -1)
+            wpar = ref_par if cap == 0 else np.where(ref_lev <= cap, ref_par, -1)
+            assert np.array_equal(lev.cpu().numpy(), want), (name, s, cap)
+            assert np.array_equal(par.cpu().numpy(), wpar), (name, s, cap)
+            if cap == 0:
+                assert grb.last_stats()["iterations"] == nl
 
 
 @pytest.mark.parametrize("name", ["rmat_14", "grid_33x70", "star"])
@@ -210,7 +231,7 @@ def test_sssp_delta_parity(grb, name, delta):
 
 
 def test_sssp_delta_round_cap_low_degree(grb):
-    """A round cap inside the one-workgroup loop (grid) and after it handed
+    """A round cap inside the multi-workgroup loop (grid) and after it handed
     the pending set to the round kernel (lowdeg): the capped distances are
     never below the exact ones and run to them with enough rounds, and the
     round records agree with the rounds run."""
@@ -227,6 +248,21 @@ def test_sssp_delta_round_cap_low_degree(grb):
                 assert st["iterations"] <= cap
             full = grb.sssp(A, 0, delta=delta).cpu().numpy()
             assert np.array_equal(full, ref), (name, delta)
+
+
+@pytest.mark.parametrize("name", ["grid_33x70", "path", "lowdeg", "two_comp"])
+def test_sssp_delta_loop_barrier_given_up(grb, name):
+    """The multi-workgroup bucket-round loop's failure path, forced from the
+    host (GRB_LOOP_NO_WAIT): the pending set goes to the round kernel at the
+    first barrier and the distances are the oracle's."""
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    for s in _sources(name, g.n):
+        ref, _, _ = oracle.sssp(adj, s)
+        for delta in (7.5, 256.0):
+            dist = grb.sssp(A, s, delta=delta,
+                            desc=grb.descriptor(flags=grb.GRB_LOOP_NO_WAIT))
+            assert np.array_equal(dist.cpu().numpy(), ref), (name, s, delta)
 
 
 def test_sssp_negative_weights_rejected(grb):
