@@ -1982,6 +1982,7 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   a.part = t.part;
   a.ctrl = t.ctrl;
   a.gate.part = t.part;
+  a.gate.decided = &t.ctrl->dir;  // the control block is cleared by the first kernel
   a.gate.forced = desc.direction;
   a.gate.can_push = can_push;
   a.gate.can_pull = can_pull;

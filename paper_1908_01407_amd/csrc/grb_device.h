@@ -301,13 +301,18 @@ __device__ __forceinline__ double atomic_min_f64(double *a, double v) {
 }
 
 // Direction of a generic product (Section 4.3.1, Table 5), evaluated by a
-// wave from the first kernel's (count, degree sum) partials; forced
-// directions and single-orientation matrices need no partials.  All 64
-// lanes must be active; every lane gets the same answer.
+// wave from the first kernel's (count, degree sum) partials, or read from
+// the word an earlier kernel of the product left; forced directions and
+// single-orientation matrices need neither.  All 64 lanes must be active;
+// every lane gets the same answer.
 __device__ __forceinline__ int gate_dir(const DirGate &g) {
   if (g.forced) return g.forced;
   if (!g.can_pull) return GRB_DIR_PUSH;
   if (!g.can_push) return GRB_DIR_PULL;
+  if (g.decided) {  // left by an earlier kernel of the product
+    const int dd = *g.decided;
+    if (dd) return dd;
+  }
   const int ln = threadIdx.x & 63;
   int64_t c = 0, d = 0;
 #pragma unroll
@@ -319,7 +324,11 @@ __device__ __forceinline__ int gate_dir(const DirGate &g) {
   d = wave_sum64(d);
   const bool pull = g.rule == GRB_SWITCH_EXACT ? (int64_t)g.denom * d > g.nnz
                                                : (int64_t)g.denom * c > g.n_in;
-  return pull ? GRB_DIR_PULL : GRB_DIR_PUSH;
+  const int dir = pull ? GRB_DIR_PULL : GRB_DIR_PUSH;
+  // every evaluating wave stores the same value; a kernel launched later in
+  // the product reads it
+  if (g.decided && ln == 0) *g.decided = dir;
+  return dir;
 }
 
 }  // namespace grb

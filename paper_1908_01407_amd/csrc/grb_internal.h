@@ -138,6 +138,10 @@ constexpr int kMxvPartThreads = 1024;
 constexpr int kMxvListChunk = 4096;  // list entries per workgroup of the list preparation
 struct DirGate {
   const int64_t *part = nullptr;  // 2 * kMxvParts partials (unused when forced)
+  // the choice, left by the first kernel of the product that evaluated the
+  // rule (0 until then; cleared by the first kernel), so that later kernels
+  // read one word instead of the partials
+  int32_t *decided = nullptr;
   int forced = 0;                 // grb_direction: 0 = automatic
   bool can_push = true, can_pull = true;
   int rule = 0, denom = 10;
