@@ -761,7 +761,7 @@ def bench_serve(grb, graphgen, torch, args):
         return qs
 
     # high-diameter graphs: bucketed SSSP, several BFS levels per session step
-    deltas = {"grid2000": 2048.0, "grid3000": 2048.0}
+    deltas = {"grid2000": 256.0, "grid3000": 256.0}
     chunks = {"grid2000": 16, "grid3000": 16}
     # their BFS queries run alone in the slots: thousands of levels make a
     # lane session slower per query than a single-source BFS
