@@ -565,7 +565,7 @@ def bench_extras(grb, graphgen, torch, args):
                                "us_per_round": round(ms * 1e3 / max(st["iterations"], 1), 2),
                                "gteps": round(G.nnz / ms / 1e6, 4)}
         # bucketed rounds (grb_sssp_delta), same distances
-        for delta in (256.0, 2048.0):
+        for delta in (512.0, 2048.0):
             grb.sssp(G, 0, ws=wss, delta=delta)
             ms = timed(lambda: grb.sssp(G, 0, ws=wss, delta=delta), 2, torch)
             st = grb.last_stats()
@@ -761,7 +761,7 @@ def bench_serve(grb, graphgen, torch, args):
         return qs
 
     # high-diameter graphs: bucketed SSSP, several BFS levels per session step
-    deltas = {"grid2000": 256.0, "grid3000": 256.0}
+    deltas = {"grid2000": 512.0, "grid3000": 512.0}
     chunks = {"grid2000": 16, "grid3000": 16}
     # their BFS queries run alone in the slots: thousands of levels make a
     # lane session slower per query than a single-source BFS

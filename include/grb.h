@@ -376,7 +376,7 @@ grb_info grb_bfs(int32_t *levels, int32_t *parents, grb_matrix A, int32_t source
  * grb_bfs for callers that cannot allocate (code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation): the same BFS,
  * levels and parents as grb_bfs, with its workspace in a device array of
- * the library (8 MiB + 512 KiB, held on each GPU the library runs on until
+ * the library (9 MiB, held on each GPU the library runs on until
  * the process ends) instead of a caller buffer; read-backs use no pinned
  * staging buffer; GRB_PROFILE is ignored (it would create timing events).
  * Graphs of more than 2^24 vertices: GRB_INSUFFICIENT_SPACE.  Runs on the

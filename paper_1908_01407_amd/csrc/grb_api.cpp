@@ -71,7 +71,7 @@ struct BfsWs {
   Ctrl *ctrl;
   int64_t *stats;
   uint64_t *visited, *F[3];
-  CoopCtl *coop;  // multi-workgroup loop: shared state, two queues of kCoopSegs segments
+  CoopCtl *coop;  // multi-workgroup loop: shared state, two queues of kCoopSegsMax segments
   int32_t *qv;
   uint64_t *qe;
   int32_t qseg;
@@ -88,7 +88,7 @@ BfsWs bfs_layout(void *ws, int64_t n) {
   for (int i = 0; i < 3; ++i) t.F[i] = c.take<uint64_t>((size_t)nw);
   t.qseg = (int32_t)std::max<int64_t>(std::min<int64_t>(kCoopSeg, n), 1);
   t.coop = c.take<CoopCtl>(1);
-  const size_t qn = 2 * (size_t)kCoopSegs * (size_t)t.qseg;
+  const size_t qn = 2 * (size_t)kCoopSegsMax * (size_t)t.qseg;
   t.qv = c.take<int32_t>(qn);
   t.qe = c.take<uint64_t>(qn);
   t.bytes = c.off;

@@ -35,6 +35,14 @@
 namespace grb {
 namespace {
 
+// multi-workgroup loop of this file: workgroups, queue segments (one per
+// wave), segment counts read per lane of one wave
+constexpr int kCoopGrid = kCoopGridBfs;
+constexpr int kCoopSegs = kCoopGrid * (kCoopThreads / 64);
+constexpr int kCoopSegsPerLane = kCoopSegs / 64;
+static_assert(kCoopSegs % 64 == 0 && kCoopSegs <= kCoopSegsMax,
+              "segment counts are read by one wave");
+
 __device__ __forceinline__ int decide(const BfsArgs &a, int count, int sumdeg) {
   if (a.forced) return a.forced;
   if (!a.can_pull) return GRB_DIR_PUSH;
@@ -844,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_start(BfsArgs a, int32_t source,
     a.cnt_cur[2] = ds > kPushSplit ? 1 : 0;
     if (a.coop) {  // the multi-workgroup loop's first queue: {source}
       a.coop->bar = 0ull;
-      for (int i = 0; i < kCoopSegs; ++i) a.coop->cnt[0][i] = a.coop->esum[0][i] = 0;
+      for (int i = 0; i < kCoopSegsMax; ++i) a.coop->cnt[0][i] = a.coop->esum[0][i] = 0;
       a.coop->cnt[0][0] = 1;
       a.coop->esum[0][0] = ds;
       a.qv[0] = source;
@@ -881,12 +889,25 @@ __global__ __launch_bounds__(kCoopThreads) void k_bfs_coop(BfsArgs a, int64_t ma
   for (;;) {
     const int sl = (int)(d & 1);
     if (tid < 64) {  // the level's queue: segment counts, their prefix, degree sums
-      const int c = ld_coherent(&cc->cnt[sl][tid]);
-      const int e = ld_coherent(&cc->esum[sl][tid]);
-      const int incl = wave_incl_scan(c);
-      s_pre[tid + 1] = incl;
-      const int tot = lane_last(incl), etot = wave_sum(e);
-      const bool ovf = __ballot(c > seg) != 0ull;
+      // lane l holds segments kCoopSegsPerLane * l + r
+      int c[kCoopSegsPerLane], csum = 0, esum = 0;
+      bool over = false;
+#pragma unroll
+      for (int r = 0; r < kCoopSegsPerLane; ++r) {
+        c[r] = ld_coherent(&cc->cnt[sl][kCoopSegsPerLane * tid + r]);
+        esum += ld_coherent(&cc->esum[sl][kCoopSegsPerLane * tid + r]);
+        csum += c[r];
+        over |= c[r] > seg;
+      }
+      const int incl = wave_incl_scan(csum);
+      int run = incl - csum;
+#pragma unroll
+      for (int r = 0; r < kCoopSegsPerLane; ++r) {
+        run += c[r];
+        s_pre[kCoopSegsPerLane * tid + r + 1] = run;
+      }
+      const int tot = lane_last(incl), etot = wave_sum(esum);
+      const bool ovf = __ballot(over) != 0ull;
       if (tid == 0) {
         s_pre[0] = 0;
         s_nc = tot;

@@ -178,8 +178,13 @@ void launch_compact(const CompactArgs &a, void *stream);
 // (agent-scope) atomics, loads and stores, so no L2 write-back is needed.
 // State shared by the loop's workgroups:
 constexpr int kCoopThreads = 256;
-constexpr int kCoopGrid = 16;          // workgroups of the loop
-constexpr int kCoopSegs = kCoopGrid * (kCoopThreads / 64);  // one queue segment per wave (64)
+// workgroups of the loop: BFS levels carry few entries (the 3000 x 3000
+// grid's frontier holds at most 3,000 vertices), bucket rounds more (a
+// pending set of up to ~8,000 there), and a barrier costs more the more
+// workgroups arrive (measured: 0.85 us for 16, 1.0 for 32)
+constexpr int kCoopGridBfs = 16;
+constexpr int kCoopGridSssp = 32;
+constexpr int kCoopSegsMax = kCoopGridSssp * (kCoopThreads / 64);  // one queue segment per wave
 constexpr int kCoopSeg = 256;          // queue entries per wave and level (more: spill)
 constexpr int kCoopEdges = 65536;      // a frontier with more edges goes to the level kernel
 // Each level's queue has one segment per wave of the loop; the wave that
@@ -187,10 +192,10 @@ constexpr int kCoopEdges = 65536;      // a frontier with more edges goes to the
 // frontier of level d).
 struct CoopCtl {
   unsigned long long bar;  // arrivals (low 32 bits) | 1 + the barrier given up (high 32 bits)
-  int32_t cnt[2][kCoopSegs];   // entries queued
-  int32_t esum[2][kCoopSegs];  // BFS: their degree sum; bucketed SSSP: that of the near ones
-  int32_t near[2][kCoopSegs];  // bucketed SSSP: entries below the round's limit
-  int32_t far[2][kCoopSegs];   // bucketed SSSP: smallest bucket of the others (INT_MAX: none)
+  int32_t cnt[2][kCoopSegsMax];   // entries queued
+  int32_t esum[2][kCoopSegsMax];  // BFS: their degree sum; bucketed SSSP: that of the near ones
+  int32_t near[2][kCoopSegsMax];  // bucketed SSSP: entries below the round's limit
+  int32_t far[2][kCoopSegsMax];   // bucketed SSSP: smallest bucket of the others (INT_MAX: none)
 };
 constexpr int64_t kCoopMaxLevels = int64_t(1) << 24;  // arrivals stay below 2^32
 // A barrier not completed after this many ticks of the 100 MHz real-time
@@ -220,7 +225,7 @@ struct BfsArgs {
   int32_t rule = 0, denom = 10, forced = 0;
   // multi-workgroup loop: shared state and the two level queues (entries:
   // vertex, and row start | degree << 32; queue d & 1 at offset (d & 1) *
-  // kCoopSegs * qseg, segment s of a queue at s * qseg)
+  // kCoopSegsMax * qseg, segment s of a queue at s * qseg)
   CoopCtl *coop = nullptr;
   int32_t *qv = nullptr;
   uint64_t *qe = nullptr;
@@ -230,7 +235,7 @@ void launch_bfs_start(const BfsArgs &a, int32_t source, uint64_t *f1, uint64_t *
                       void *stream);
 void launch_bfs_level(const BfsArgs &a, void *stream);
 constexpr int kCoopMaxDeg = 64;  // graphs whose rows are at most this long use the loop
-// BFS levels in kCoopGrid workgroups while the frontier fits the queues
+// BFS levels in kCoopGridBfs workgroups while the frontier fits the queues
 // (kCoopSeg vertices per wave, kCoopEdges edges) and pushes; starts at level 0 after
 // launch_bfs_start (which fills the first queue), then a hand-over kernel
 // leaves a frontier that outgrew the loop (or a given-up barrier's next
@@ -277,7 +282,7 @@ constexpr int kDeltaSlots = kDeltaFields * kCntStripes;
 void launch_sssp_delta_start(const SsspArgs &a, int32_t source, uint64_t *f1, uint64_t *f2,
                              void *stream);
 void launch_sssp_delta_round(const SsspArgs &a, void *stream);
-// bucket rounds in the multi-workgroup loop (kCoopGrid workgroups, the BFS
+// bucket rounds in the multi-workgroup loop (kCoopGridSssp workgroups, the BFS
 // loop's queues and limits), then a hand-over kernel that leaves a pending
 // set that outgrew it (or a given-up barrier's next set) as the bitmap and
 // counters of round ctrl->small_levels for the round kernel

@@ -4,8 +4,9 @@
 // device array instead of a caller buffer.
 //
 // The array holds the BFS workspace of graphs up to 2^24 vertices (visited
-// and three frontier bitmaps of n / 8 bytes each, plus the control block and
-// level records): 8 MiB + 512 KiB, held on every GPU the library runs on
+// and three frontier bitmaps of n / 8 bytes each, the control block, level
+// records and the device-side level loop's queues): 9 MiB, held on every
+// GPU the library runs on
 // until the process ends.  Its device address is looked up once per device
 // (hipGetSymbolAddress, with that device current) on the first call there;
 // in host code the array's own name is not a device address.  Every call on
@@ -22,7 +23,7 @@ namespace grb {
 namespace {
 
 constexpr int64_t kNoAllocMaxVertices = (int64_t)1 << 24;
-constexpr size_t kNoAllocBytes = ((size_t)4 << 21) + ((size_t)512 << 10);
+constexpr size_t kNoAllocBytes = (size_t)9 << 20;
 
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 

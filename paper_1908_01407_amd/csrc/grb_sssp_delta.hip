@@ -27,6 +27,14 @@
 namespace grb {
 namespace {
 
+// multi-workgroup loop of this file: workgroups, queue segments (one per
+// wave), segment counts read per lane of one wave
+constexpr int kCoopGrid = kCoopGridSssp;
+constexpr int kCoopSegs = kCoopGrid * (kCoopThreads / 64);
+constexpr int kCoopSegsPerLane = kCoopSegs / 64;
+static_assert(kCoopSegs % 64 == 0 && kCoopSegs <= kCoopSegsMax,
+              "segment counts are read by one wave");
+
 struct DCount {
   int near = 0, sd = 0, lng = 0, far = INT_MAX, pend = 0;
 };
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_sssp_delta_start(SsspArgs a, int32_t
     a.ctrl->bucket = 0;
     if (a.coop) {  // the multi-workgroup loop's first queue: {source}, near
       a.coop->bar = 0ull;
-      for (int i = 0; i < kCoopSegs; ++i) {
+      for (int i = 0; i < kCoopSegsMax; ++i) {
         a.coop->cnt[0][i] = a.coop->esum[0][i] = a.coop->near[0][i] = 0;
         a.coop->far[0][i] = INT_MAX;
       }
@@ -380,15 +388,29 @@ __global__ __launch_bounds__(kCoopThreads) void k_sssp_delta_coop(SsspArgs a, in
   for (;;) {
     const int sl = (int)(d & 1);
     if (tid < 64) {  // the round's queue: segment counts and their prefix, totals
-      const int c = ld_coherent(&cc->cnt[sl][tid]);
-      const int nr = ld_coherent(&cc->near[sl][tid]);
-      const int e = ld_coherent(&cc->esum[sl][tid]);
-      const int f = ld_coherent(&cc->far[sl][tid]);
-      const int incl = wave_incl_scan(c);
-      s_pre[tid + 1] = incl;
+      // lane l holds segments kCoopSegsPerLane * l + r
+      int c[kCoopSegsPerLane], csum = 0, nr = 0, e = 0, f = INT_MAX;
+      bool over = false;
+#pragma unroll
+      for (int r = 0; r < kCoopSegsPerLane; ++r) {
+        const int sg = kCoopSegsPerLane * tid + r;
+        c[r] = ld_coherent(&cc->cnt[sl][sg]);
+        nr += ld_coherent(&cc->near[sl][sg]);
+        e += ld_coherent(&cc->esum[sl][sg]);
+        f = min(f, ld_coherent(&cc->far[sl][sg]));
+        csum += c[r];
+        over |= c[r] > seg;
+      }
+      const int incl = wave_incl_scan(csum);
+      int run = incl - csum;
+#pragma unroll
+      for (int r = 0; r < kCoopSegsPerLane; ++r) {
+        run += c[r];
+        s_pre[kCoopSegsPerLane * tid + r + 1] = run;
+      }
       const int tot = lane_last(incl), nt = wave_sum(nr), et = wave_sum(e);
       const int ft = lane_last(wave_scan(f, INT_MAX, [](int p, int q) { return p < q ? p : q; }));
-      const bool ovf = __ballot(c > seg) != 0ull;
+      const bool ovf = __ballot(over) != 0ull;
       if (tid == 0) {
         s_pre[0] = 0;
         s_n = tot;

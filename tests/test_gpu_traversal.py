@@ -413,3 +413,47 @@ def test_package_imported_before_torch():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=100)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-3000:]
+
+
+def test_loops_concurrent_streams(grb):
+    """Device-side level loops of several searches at once: two host threads,
+    each with its own stream and workspace, run BFS and bucketed SSSP on a
+    grid (hundreds of levels, so the loops' kernels overlap on the device);
+    every result equals the oracle's."""
+    import threading
+
+    g = graphgen.grid(300, 300)
+    adj = oracle.Adjacency.from_raw(g)
+    A = grb.Matrix.from_raw(g)
+    torch.cuda.synchronize()
+    ref_lev, ref_par, _ = oracle.bfs(adj, 0)
+    ref_d, _, _ = oracle.sssp(adj, 0)
+    errors = []
+
+    def work(seed):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                wsb = grb.workspace(grb.OP_BFS, A)
+                wss = grb.workspace(grb.OP_SSSP, A)
+                for i in range(3):
+                    if (i + seed) % 2 == 0:
+                        lev, par = grb.bfs(A, 0, ws=wsb, stream=s)
+                        s.synchronize()
+                        if not (np.array_equal(lev.cpu().numpy(), ref_lev)
+                                and np.array_equal(par.cpu().numpy(), ref_par)):
+                            errors.append(("bfs", seed, i))
+                    else:
+                        dist = grb.sssp(A, 0, delta=64.0, ws=wss, stream=s)
+                        s.synchronize()
+                        if not np.array_equal(dist.cpu().numpy(), ref_d):
+                            errors.append(("sssp", seed, i))
+        except Exception as e:  # reported below
+            errors.append(("exception", seed, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
