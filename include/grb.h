@@ -412,8 +412,10 @@ grb_info grb_sssp(float *dist, grb_matrix A, int32_t source, const grb_descripto
  * delta not finite and positive: GRB_INVALID_VALUE.  Stats record per round
  * the pending count, the near degree sum, direction 1 and the bucket.  On
  * graphs whose rows are short (at most 64 entries) the rounds run back to
- * back inside one kernel (the multi-workgroup loop of grb_bfs) while the
- * pending set is small.
+ * back inside one kernel of 32 workgroups (the device-side loop of
+ * grb_bfs, with its barrier, limits and hand-over) while the pending set
+ * is small; on the 3000 x 3000 grid a width of 384-512 keeps every round
+ * there.
  */
 grb_info grb_sssp_delta(float *dist, grb_matrix A, int32_t source, float delta,
                         const grb_descriptor *d, void *ws, size_t ws_bytes, void *stream);
