@@ -128,13 +128,12 @@ __device__ __forceinline__ int mxv_dir(const MxvArgs &a) { return gate_dir(a.gat
 
 // z / mask / REPLACE for one output index; returns whether w(i) is present
 // afterwards and its value in *out.
-// w_has: whether w(i) is present before the product.
 template <int SR>
-__device__ __forceinline__ bool epilogue_w(const MxvArgs &a, int64_t i, bool allowed, bool w_has,
-                                           bool t_has, typename Sr<SR>::T t,
-                                           typename Sr<SR>::T *out) {
+__device__ __forceinline__ bool epilogue(const MxvArgs &a, int64_t i, bool allowed, bool t_has,
+                                         typename Sr<SR>::T t, typename Sr<SR>::T *out) {
   using T = typename Sr<SR>::T;
   const T *w = (const T *)a.w_val;
+  const bool w_has = bit_of(a.w_bm, i);
   if (!allowed) {
     if (w_has && !a.replace) {
       *out = w[i];
@@ -155,12 +154,6 @@ __device__ __forceinline__ bool epilogue_w(const MxvArgs &a, int64_t i, bool all
   else if (a.accum == GRB_ACCUM_MIN) *out = old < t ? old : t;
   else *out = old + t;
   return true;
-}
-
-template <int SR>
-__device__ __forceinline__ bool epilogue(const MxvArgs &a, int64_t i, bool allowed, bool t_has,
-                                         typename Sr<SR>::T t, typename Sr<SR>::T *out) {
-  return epilogue_w<SR>(a, i, allowed, bit_of(a.w_bm, i), t_has, t, out);
 }
 
 // ---- first kernel: control block, direction partials ------------------------
@@ -441,59 +434,32 @@ __global__ __launch_bounds__(kBlock) void k_mxv_push(MxvArgs a) {
   }
 }
 
-// The push's result t into w: accum, mask, REPLACE per output word.  A wave
-// takes kMergeWords words at a time (the same words of every wave, strided by
-// the wave count) and issues their bitmap words' loads together before any
-// store, so each wave waits for one round of loads per group of words.
-constexpr int kMergeThreads = 1024;
-constexpr int kMergeWords = 4;
 template <int SR>
-__global__ __launch_bounds__(kMergeThreads) void k_mxv_merge(MxvArgs a) {
+__global__ __launch_bounds__(kBlock) void k_mxv_merge(MxvArgs a) {
   using T = typename Sr<SR>::T;
   if (mxv_dir(a) != GRB_DIR_PUSH) return;
   const int ln = threadIdx.x & 63;
-  constexpr int kWaves = kMergeThreads / 64;
-  const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   T *w = (T *)a.w_val;
-  for (int64_t wd0 = gw; wd0 < a.nw_out; wd0 += kMergeWords * nwaves) {
-    uint64_t tb[kMergeWords], tv[kMergeWords], wb[kMergeWords];
-    T tval[kMergeWords];
-    bool allowed[kMergeWords];
-#pragma unroll
-    for (int k = 0; k < kMergeWords; ++k) {
-      const int64_t wd = wd0 + k * nwaves, i = wd * 64 + ln;
-      const bool valid = wd < a.nw_out;
-      tb[k] = valid ? a.t_bm[wd] : 0ull;
-      wb[k] = valid ? a.w_bm[wd] : 0ull;
-      tv[k] = 0ull;
-      tval[k] = (T)0;
+  for (int64_t wd = gw; wd < a.nw_out; wd += nwaves) {
+    const int64_t i = wd * 64 + ln;
+    bool has = false;
+    if (i < a.n_out) {
+      bool t_has = bit_of(a.t_bm, i);
+      T tv;
       if constexpr (Sr<SR>::lor) {
-        tv[k] = valid ? a.t_vb[wd] : 0ull;
+        tv = (T)bit_of(a.t_vb, i);
+        t_has = t_has || tv;
       } else {
-        if (valid && i < a.n_out) tval[k] = ((const T *)a.t_val)[i];
+        tv = ((const T *)a.t_val)[i];
       }
-      allowed[k] = valid && i < a.n_out && mask_allowed(a, i);
+      T out = tv;
+      has = epilogue<SR>(a, i, mask_allowed(a, i), t_has, tv, &out);
+      if (has) w[i] = out;
     }
-#pragma unroll
-    for (int k = 0; k < kMergeWords; ++k) {
-      const int64_t wd = wd0 + k * nwaves, i = wd * 64 + ln;
-      if (wd >= a.nw_out) break;
-      bool has = false;
-      if (i < a.n_out) {
-        bool t_has = (tb[k] >> ln) & 1ull;
-        T tvv = tval[k];
-        if constexpr (Sr<SR>::lor) {
-          tvv = (T)((tv[k] >> ln) & 1ull);
-          t_has = t_has || tvv;
-        }
-        T out = tvv;
-        has = epilogue_w<SR>(a, i, allowed[k], (wb[k] >> ln) & 1ull, t_has, tvv, &out);
-        if (has) w[i] = out;
-      }
-      const uint64_t bits = __ballot(has);
-      if (ln == 0) a.w_bm[wd] = bits;
-    }
+    const uint64_t bits = __ballot(has);
+    if (ln == 0) a.w_bm[wd] = bits;
   }
 }
 
@@ -1187,10 +1153,7 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
     }
     if (!Sr<SR>::lor) hipLaunchKernelGGL(k_mxv_prep<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_mxv_push<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
-    const int64_t per_wg = (int64_t)(kMergeThreads / 64) * kMergeWords;
-    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>((a.nw_out + per_wg - 1) / per_wg,
-                                                               1 << 16));
-    hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(gm), dim3(kMergeThreads), 0, s, a);
+    hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
   }
   if (want_pull) {
     if (a.u_from_list)
