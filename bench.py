@@ -322,7 +322,8 @@ def bfs_counters_file(fetch_dir, write_dir, bench_json):
                    "--steps 3 --warmup 1 --calibrate-copy")
     out += ["  python bench.py --bfs-counters gpurun_out/pmc_fetch gpurun_out/pmc_write "
             "<bench output of the FETCH_SIZE run>", "",
-            "Each run does 1 warm-up, 3 timed and 3 profiled BFS runs (7 launches each)",
+            f"Each run does 1 warm-up, 3 timed and 3 profiled BFS runs "
+            f"({fe['grb::k_bfs_level'][0] // 7} level launches each)",
             "and, last, one streaming kernel of known size (torch elementwise multiply",
             "over 64 Mi fp32: 256 MiB read, 256 MiB written).", ""]
     out.append(f"{'kernel':40s} {'counter':>12s} {'dispatches':>10s} {'KiB/dispatch':>14s}")
