@@ -173,7 +173,7 @@ PrWs pr_layout(void *ws, int64_t n, const Csr &pull, int esize) {
 
 struct MxvWs {
   Ctrl *ctrl;
-  int64_t *part;
+  int64_t *part, *blk_part;
   uint64_t *status, *status_out, *status_list, *t_bm, *t_vb;
   int32_t *list, *degpre, *rowstart, *tiles;
   int64_t tiles_cap;
@@ -192,6 +192,7 @@ MxvWs mxv_layout(void *ws, int64_t n_in, int64_t n_out, int64_t nnz, int64_t npi
   t.nblk_list = (int)std::max<int64_t>(1, (n_in + kMxvListChunk - 1) / kMxvListChunk);
   t.ctrl = c.take<Ctrl>(1);
   t.part = c.take<int64_t>((size_t)2 * kMxvParts);
+  t.blk_part = c.take<int64_t>((size_t)2 * t.nblk);
   t.status = c.take<uint64_t>((size_t)2 * t.nblk);
   t.status_out = c.take<uint64_t>((size_t)2 * t.nblk_out);
   t.status_list = c.take<uint64_t>((size_t)t.nblk_list);
@@ -1980,6 +1981,7 @@ grb_info run_product(bool is_vxm, grb_vector w, grb_vector mask, grb_binop accum
   a.nblk_out = t.nblk_out;
   a.nblk_list = t.nblk_list;
   a.part = t.part;
+  a.blk_part = t.blk_part;
   a.ctrl = t.ctrl;
   a.gate.part = t.part;
   a.gate.decided = &t.ctrl->dir;  // the control block is cleared by the first kernel

@@ -166,6 +166,9 @@ struct CompactArgs {
   DirGate gate;
   int32_t *count_out = nullptr;  // optional: the list's length is also stored here
   int64_t nbits = 0;             // bits of the bitmap that count (0 = all nw * 64)
+  // optional: every block's (entries, degree sum), computed by an earlier
+  // kernel; the blocks' offsets then come from their prefix, with no look-back
+  const int64_t *blk_part = nullptr;
 };
 int compact_blocks(int64_t nw);
 void launch_compact(const CompactArgs &a, void *stream);
@@ -430,6 +433,9 @@ struct MxvArgs {
   uint64_t *status = nullptr, *status_out = nullptr, *status_list = nullptr;
   int nblk = 0, nblk_out = 0, nblk_list = 0;
   int64_t *part = nullptr;      // direction partials of the first kernel
+  // per compaction block of a bitmap input (nblk of them): entries and their
+  // degree sum, left by the first kernel when the product may push
+  int64_t *blk_part = nullptr;
   Ctrl *ctrl = nullptr;
   DirGate gate;
 };

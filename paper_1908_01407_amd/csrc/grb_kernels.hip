@@ -33,7 +33,8 @@ __device__ __forceinline__ int64_t status_cnt(uint64_t s) { return (int64_t)((s 
 __device__ __forceinline__ int64_t status_deg(uint64_t s) { return (int64_t)(s & 0x7fffffffull); }
 
 // Each workgroup (16 waves) compacts 256 bitmap words; its position in the
-// output comes from a decoupled look-back over the workgroups before it
+// output comes from the blocks' sums when an earlier kernel left them
+// (blk_part), else from a decoupled look-back over the workgroups before it
 // (tickets, not blockIdx, order the workgroups, so every workgroup a
 // look-back waits on is already running).  The status word packs
 // flag (2 bits) | count (31 bits) | degree sum (31 bits).
@@ -49,11 +50,13 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
   if (a.skip_if_empty && a.ctrl->count == 0) return;
   // a generic product that pulls needs no list
   if (a.gated && gate_dir(a.gate) != GRB_DIR_PUSH) return;
-  if (tid == 0) s_blk = atomicAdd(&a.ctrl->ticket, 1);
+  // with the blocks' sums given, a block's offset needs no other block to
+  // run first (workgroup id = block); otherwise tickets order the look-back
+  if (tid == 0) s_blk = a.blk_part ? (int)blockIdx.x : atomicAdd(&a.ctrl->ticket, 1);
   __syncthreads();
   const int blk = s_blk;
   const int64_t w0 = (int64_t)blk * kCompactWords + wid * WPW;
-  if (tid == 0) a.status_next[blk] = 0ull;
+  if (tid == 0 && !a.blk_part) a.status_next[blk] = 0ull;
 
   // bits at positions >= nbits (a bitmap's padding) never enter the list
   const int64_t nbits = a.nbits > 0 ? a.nbits : a.nw * 64;
@@ -97,7 +100,14 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
       de += d[i];
     }
     int64_t ec = 0, ed = 0;
-    if (blk > 0) {
+    if (a.blk_part) {  // the sums of the blocks before this one
+      for (int j = ln; j < blk; j += 64) {
+        ec += a.blk_part[2 * j];
+        ed += a.blk_part[2 * j + 1];
+      }
+      ec = wave_sum64(ec);
+      ed = wave_sum64(ed);
+    } else if (blk > 0) {
       if (ln == 0) store_relaxed_u64(&a.status_cur[blk], pack_status(kFlagAgg, ctot, dtot));
       int jhi = blk - 1;
       for (;;) {  // window of 128 predecessors, nearest first
@@ -123,7 +133,8 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
       }
     }
     if (ln == 0) {
-      store_relaxed_u64(&a.status_cur[blk], pack_status(kFlagPre, ec + ctot, ed + dtot));
+      if (!a.blk_part)
+        store_relaxed_u64(&a.status_cur[blk], pack_status(kFlagPre, ec + ctot, ed + dtot));
       s_base_c = (int)ec;
       s_base_d = (int)ed;
       if (blk == (int)gridDim.x - 1) {

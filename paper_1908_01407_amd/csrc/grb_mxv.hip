@@ -183,10 +183,60 @@ __global__ __launch_bounds__(kMxvPartThreads) void k_mxv_init(MxvArgs a) {
   // OR pull: long rows' "settled by the probes" flags
   if (Sr<SR>::lor && a.gate.can_pull && a.gate.forced != GRB_DIR_PUSH)
     for (int64_t k = gt; k < a.pull.nsplit_rows; k += nthr) a.settled[a.pull.split_rows[3 * k]] = 0;
-  if (a.gate.forced || !a.gate.can_push || !a.gate.can_pull) return;
+  const bool auto_dir = !a.gate.forced && a.gate.can_push && a.gate.can_pull;
+  const int32_t *rp = a.push.rp;
+  if (a.blk_part && !a.u_list && a.n_in > 0 && a.gate.can_push &&
+      a.gate.forced != GRB_DIR_PULL) {
+    // every compaction block of the bitmap input (kCompactWords words, the
+    // compaction's layout: 16 words per wave): entries and their degree
+    // sum, so that the compaction takes its offsets from their prefix; the
+    // same sums are the direction partials
+    static_assert(kMxvPartThreads == kCompactThreads, "one block per workgroup pass");
+    constexpr int WPW = kCompactWords / (kCompactThreads / 64);
+    const int64_t wlast = (a.n_in - 1) >> 6;
+    const uint64_t mlast = mask_below((int)(a.n_in - wlast * 64));
+    int64_t tc = 0, td = 0;  // this workgroup's totals (thread 0)
+    for (int64_t b = blockIdx.x; b < a.nblk; b += gridDim.x) {
+      int wc = 0, wdg = 0;
+#pragma unroll 4
+      for (int k = 0; k < WPW; ++k) {
+        const int64_t w = b * kCompactWords + wv * WPW + k;
+        const uint64_t word = w < a.nw_in ? (a.u_bm[w] & (w == wlast ? mlast : ~0ull)) : 0ull;
+        if ((word >> ln) & 1ull) {
+          const int64_t v = w * 64 + ln;
+          wc += 1;
+          wdg += rp[v + 1] - rp[v];
+        }
+      }
+      wc = wave_sum(wc);
+      wdg = wave_sum(wdg);
+      if (ln == 0) {
+        s_c[wv] = wc;
+        s_d[wv] = wdg;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int64_t bc = 0, bd = 0;
+        for (int k = 0; k < kMxvPartThreads / 64; ++k) {
+          bc += s_c[k];
+          bd += s_d[k];
+        }
+        a.blk_part[2 * b] = bc;
+        a.blk_part[2 * b + 1] = bd;
+        tc += bc;
+        td += bd;
+      }
+      __syncthreads();
+    }
+    if (auto_dir && tid == 0) {
+      a.part[2 * blockIdx.x] = tc;
+      a.part[2 * blockIdx.x + 1] = td;
+    }
+    return;
+  }
+  if (!auto_dir) return;
   // partials of the input's entry count and degree sum (rows of the push CSR)
   const bool exact = a.gate.rule == GRB_SWITCH_EXACT;
-  const int32_t *rp = a.push.rp;
   int64_t c = 0, d = 0;
   if (a.u_list) {
     int64_t cnt = *a.u_cnt;
@@ -1149,6 +1199,7 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
       ca.ctrl = a.ctrl;
       ca.gated = true;
       ca.gate = a.gate;
+      ca.blk_part = a.n_in > 0 ? a.blk_part : nullptr;  // left by the first kernel
       launch_compact(ca, s);
     }
     if (!Sr<SR>::lor) hipLaunchKernelGGL(k_mxv_prep<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
