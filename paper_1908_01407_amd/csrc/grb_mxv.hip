@@ -492,6 +492,42 @@ __global__ __launch_bounds__(kBlock) void k_mxv_merge(MxvArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   T *w = (T *)a.w_val;
+  if constexpr (Sr<SR>::lor) {
+    if (!a.has_mask || a.mask_struct || !a.m_val) {
+      // one output word per lane, 64 words per wave: presence by word
+      // operations; a value is written only where the product sets it
+      // (kept entries outside the mask and accumulated entries with no
+      // product keep their value)
+      const bool acc = a.accum != GRB_NOACCUM;
+      const int64_t wlast = a.nw_out - 1;
+      const uint64_t mlast = mask_below((int)(a.n_out - wlast * 64));
+      for (int64_t w0 = gw * 64; w0 < a.nw_out; w0 += nwaves * 64) {
+        const int64_t wd = w0 + ln;
+        uint64_t wr = 0ull, tvb = 0ull, plain = 0ull;
+        if (wd < a.nw_out) {
+          const uint64_t valid = wd == wlast ? mlast : ~0ull;
+          const uint64_t A = allowed_word(a, wd), W = a.w_bm[wd];
+          tvb = a.t_vb[wd];
+          const uint64_t th = a.t_bm[wd] | tvb;
+          const uint64_t keep = a.replace ? 0ull : (~A & W);
+          plain = A & (acc ? ~W : ~0ull);          // w = t where t is present
+          const uint64_t accw = acc ? (A & W) : 0ull;  // w = w (+) t, present either way
+          a.w_bm[wd] = (keep | (plain & th) | accw) & valid;
+          wr = (plain | accw) & th & valid;
+        }
+        for (uint64_t any = __ballot(wr != 0ull); any; any &= any - 1) {
+          const int j = __builtin_ctzll(any);
+          const uint64_t wrj = __shfl(wr, j), tvj = __shfl(tvb, j), pj = __shfl(plain, j);
+          if ((wrj >> ln) & 1ull) {
+            const int64_t i = (w0 + j) * 64 + ln;
+            const bool tv = (tvj >> ln) & 1ull;
+            w[i] = ((pj >> ln) & 1ull) ? (T)tv : (T)((w[i] != 0) || tv);
+          }
+        }
+      }
+      return;
+    }
+  }
   for (int64_t wd = gw; wd < a.nw_out; wd += nwaves) {
     const int64_t i = wd * 64 + ln;
     bool has = false;
@@ -1204,7 +1240,12 @@ void run_mxv(const MxvArgs &a, hipStream_t s) {
     }
     if (!Sr<SR>::lor) hipLaunchKernelGGL(k_mxv_prep<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_mxv_push<SR>, dim3(kExpandGrid), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(gw_out), dim3(kBlock), 0, s, a);
+    // the OR semiring's word form takes 64 output words per wave
+    const bool word_merge = Sr<SR>::lor && (!a.has_mask || a.mask_struct || !a.m_val);
+    const int gm = word_merge ? (int)std::max<int64_t>(
+                                    1, (a.nw_out + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock))
+                              : gw_out;
+    hipLaunchKernelGGL(k_mxv_merge<SR>, dim3(std::min(gm, 1 << 16)), dim3(kBlock), 0, s, a);
   }
   if (want_pull) {
     if (a.u_from_list)
