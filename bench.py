@@ -1141,14 +1141,16 @@ def main():
         g14 = graphgen.rmat(14)
         A14 = grb.Matrix.from_raw(g14)
         ws14 = grb.workspace(grb.OP_BFS, A14)
+        out14 = (torch.empty(A14.nrows, dtype=torch.int32, device="cuda"),
+                 torch.empty(A14.nrows, dtype=torch.int32, device="cuda"))
         for _ in range(3):
-            grb.bfs(A14, 0, desc=desc, ws=ws14)
-        ms14 = timed(lambda: grb.bfs(A14, 0, desc=desc, ws=ws14), 10, torch)
+            grb.bfs(A14, 0, desc=desc, ws=ws14, out=out14)
+        ms14 = timed(lambda: grb.bfs(A14, 0, desc=desc, ws=ws14, out=out14), 10, torch)
         out["rmat14_bfs"] = {
             "us_per_bfs": round(ms14 * 1e3, 2), "levels": grb.last_stats()["iterations"],
             "gteps": round(A14.nnz / (ms14 / 1e3) / 1e9, 3), "runs": 10, "warmup": 3,
             "note": "levels + parents from vertex 0; L2-resident, a latency figure"}
-        del A14, ws14
+        del A14, ws14, out14
     if args.calibrate_copy:
         # a plain streaming kernel of known traffic for the counter scale:
         # reads 256 MiB and writes 256 MiB (torch's elementwise multiply)

@@ -613,16 +613,20 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
     empty_seen = !hc.spilled;  // done, or stopped by the level cap
   }
   // The first batch covers the depth expected of a random graph of this
-  // size and mean degree, ln n / ln(nnz / n), plus one spare; later batches
-  // start at two levels and double, so a deeper search pays few empty
-  // launches.  A batch whose last level found no next frontier ends the
-  // search without launching the empty level.  Control block and level
+  // size and mean degree, ln n / ln(nnz / n), plus one spare, or the depth
+  // of the last search on this matrix where that is larger (up to twice the
+  // estimate: skewed degrees make searches deeper than the estimate); later
+  // batches start at two levels and double, so a deeper search pays few
+  // empty launches.  A batch whose last level found no next frontier ends
+  // the search without launching the empty level.  Control block and level
   // records come back in one copy.
   int chunk = 6;
   {
     const double dbar = n > 0 ? (double)A->nnz / (double)n : 0.0;
     if (n > 1 && dbar > 1.5)
       chunk = (int)std::min(64.0, std::ceil(std::log((double)n) / std::log(dbar)) + 1.0);
+    const int last = A->bfs_depth.load(std::memory_order_relaxed);
+    chunk = std::max(chunk, std::min(last, 2 * chunk));
   }
   bool first_batch = true;
   bool capped = false;  // stopped by the level cap with a frontier left
@@ -661,6 +665,7 @@ grb_info run_bfs(grb_matrix A, int32_t source, int32_t *levels, int32_t *parents
     if (hipStreamSynchronize(s) != hipSuccess) return GRB_PANIC;
   }
   const int iters = hc.nlev;
+  A->bfs_depth.store(iters, std::memory_order_relaxed);
   std::vector<int64_t> rec((size_t)kStatsCap * kStatFields, 0);
   const int nrec = std::min(iters, (int)kStatsCap);
   std::memcpy(rec.data(), host.data() + head, rec_bytes);

@@ -1,6 +1,7 @@
 // Internal definitions shared by the host API layer and the HIP kernels.
 #pragma once
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 
@@ -68,6 +69,9 @@ struct grb_matrix_s {
   grb::Csr at;  // CSR of A^T (aliases a for symmetric matrices)
   bool symmetric = false;
   bool prepared = false;
+  // levels of the last BFS on this matrix: a hint for how many level
+  // launches to queue before the first read-back (speed only)
+  std::atomic<int32_t> bfs_depth{0};
 };
 
 struct grb_vector_s {
