@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
       const int64_t v = w * 64 + ln;
       if (a.rp) deg = a.rp[v + 1] - a.rp[v];
     }
-    const int ds = wave_sum(deg);
+    const int ds = word ? wave_sum(deg) : 0;  // the word is the same in every lane
     if (ln == 0) {
       s_cnt[wid * WPW + k] = __popcll(word);
       s_deg[wid * WPW + k] = ds;

@@ -208,8 +208,10 @@ __global__ __launch_bounds__(kMxvPartThreads) void k_mxv_init(MxvArgs a) {
           wdg += rp[v + 1] - rp[v];
         }
       }
-      wc = wave_sum(wc);
-      wdg = wave_sum(wdg);
+      if (__ballot(wc != 0)) {
+        wc = wave_sum(wc);
+        wdg = wave_sum(wdg);
+      }
       if (ln == 0) {
         s_c[wv] = wc;
         s_d[wv] = wdg;

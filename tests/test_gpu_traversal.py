@@ -155,6 +155,38 @@ def test_bfs_level_cap_low_degree(grb):
             assert np.array_equal(par.cpu().numpy(), wpar), (name, cap)
 
 
+def test_bfs_first_batch_follows_last_depth(grb):
+    """The number of level launches queued before the first read-back is the
+    random-graph estimate ceil(ln n / ln(nnz / n)) + 1, raised to the depth
+    of the last search on the same matrix (at most twice the estimate).  A
+    deep search followed by shallow ones still gives the oracle's levels
+    and parents; the extra launches find an empty frontier."""
+    import math
+    name = "rmat_14"
+    g, adj = graph(name)
+    A = matrix(grb, name)
+    est = min(64, math.ceil(math.log(g.n) / math.log(adj.nnz / g.n)) + 1)
+    off, _, _ = adj.arrays(weights=False)
+    deg = np.diff(off)
+    # the deepest of a few sources of degree 1
+    cands = np.flatnonzero(deg == 1)[:40]
+    depths = [oracle.bfs(adj, int(v), parents=False)[2] for v in cands]
+    deep = int(cands[int(np.argmax(depths))])
+    prev = None
+    for s in (deep, 0, 0, deep):
+        lev, par = grb.bfs(A, s)
+        ref_lev, ref_par, nl = oracle.bfs(adj, s)
+        assert np.array_equal(lev.cpu().numpy(), ref_lev), s
+        assert np.array_equal(par.cpu().numpy(), ref_par), s
+        st = grb.last_stats()
+        assert st["iterations"] == nl
+        if prev is not None:
+            first = max(est, min(prev, 2 * est))
+            if nl <= first:  # one batch: every queued launch ran
+                assert st["launches"] == first, (s, prev, nl)
+        prev = nl
+
+
 @pytest.mark.parametrize("name", ["grid_33x70", "path", "lowdeg", "two_comp"])
 def test_bfs_loop_barrier_given_up(grb, name):
     """The multi-workgroup level loop's failure path, forced from the host
