@@ -216,6 +216,75 @@ def test_push_equals_pull_rmat(grb, semiring):
             assert float(outs[0][i]) == float(ref[i])
 
 
+def _dense_vector(grb, vals, has, dtype):
+    """A device vector from value and presence arrays (presence as bitmap words)."""
+    n = has.shape[0]
+    v = grb.Vector(n, dtype)
+    npdt = {torch.uint8: np.uint8, torch.float32: np.float32, torch.int32: np.int32}[dtype]
+    v.values[:n] = torch.from_numpy(np.where(has, vals, 0).astype(npdt)).to(v.values.device)
+    b = np.packbits(has.astype(np.uint8), bitorder="little")
+    b = np.concatenate([b, np.zeros((-len(b)) % 8, np.uint8)]).view(np.int64)
+    v.bitmap[: len(b)] = torch.from_numpy(b).to(v.values.device)
+    return v
+
+
+@pytest.mark.parametrize("semiring", ["lor_land", "min_plus_fp32"])
+def test_push_ragged_blocks(grb, semiring):
+    """Forced push, pull and automatic products on a graph of 19,493
+    vertices: not a multiple of the compaction block (4,096 positions) nor
+    of 64, with edges into the last partial word and its last vertex in
+    every input.  Complemented structural mask with REPLACE, then an
+    accumulating product into an existing output without REPLACE (outputs
+    outside the mask kept); element by element against the oracle."""
+    import oracle
+    base = graphgen.rmat(14)
+    n = 16384 + 3 * 1024 + 37
+    rng = np.random.default_rng(fixed_seed("ragged", semiring))
+    k = 4000
+    src = np.concatenate([base.src, rng.integers(16384, n, k), [n - 1]])
+    dst = np.concatenate([base.dst, rng.integers(0, n, k), [0]])
+    w = np.concatenate([base.w, rng.integers(1, 65, k + 1)])
+    g = graphgen.from_edges("ragged", n, src, dst, w)
+    A = grb.Matrix.from_raw(g)
+    adj = oracle.Adjacency.from_raw(g)
+    dt = torch.uint8 if semiring == "lor_land" else torch.float32
+    ws = grb.workspace(grb.OP_MXV, A)
+    comp = grb.GRB_MASK_COMP | grb.GRB_MASK_STRUCT
+    for p in (2e-3, 0.05, 0.7):
+        u_has = rng.random(n) < p
+        u_has[n - 1] = True
+        if semiring == "lor_land":
+            u_val = (rng.random(n) >= 0.1).astype(np.float64)
+        else:
+            u_val = rng.integers(0, 20, n).astype(np.float64)
+        m_has = rng.random(n) < 0.3
+        w_has = rng.random(n) < 0.2
+        w_val = np.ones(n) if semiring == "lor_land" else rng.integers(0, 30, n).astype(np.float64)
+        accum = "lor" if semiring == "lor_land" else "min"
+        U = _dense_vector(grb, u_val, u_has, dt)
+        Mk = _dense_vector(grb, m_has.astype(np.float64), m_has, torch.uint8)
+        for flags, acc in ((comp | grb.GRB_REPLACE, None), (comp, accum)):
+            ref_v, ref_h = oracle.mxv_dense(
+                adj, semiring, u_val, u_has, w_val=w_val if acc else None,
+                w_has=w_has if acc else None, mask_val=m_has, mask_has=m_has, flags=flags,
+                accum=acc)
+            for direction in (1, 2, 0):
+                W = (_dense_vector(grb, w_val, w_has, dt) if acc else grb.Vector(n, dt))
+                grb.mxv(W, Mk, acc, semiring, A, U,
+                        desc=grb.descriptor(direction=direction, flags=flags), ws=ws)
+                torch.cuda.synchronize()
+                words = W.bitmap.cpu().numpy().view(np.uint8)
+                got_h = np.unpackbits(words, bitorder="little")[:n].astype(bool)
+                case = (p, flags, direction)
+                assert np.array_equal(got_h, ref_h), (case, int((got_h != ref_h).sum()))
+                assert not np.unpackbits(words, bitorder="little")[n:].any(), case
+                got_v = W.values[:n].cpu().numpy().astype(np.float64)
+                if semiring == "lor_land":
+                    assert np.array_equal(got_v[ref_h] != 0, ref_v[ref_h] != 0), case
+                else:
+                    assert np.array_equal(got_v[ref_h], ref_v[ref_h]), case
+
+
 def test_plus_times_float_tolerance(grb):
     """Real-valued plus-times: both directions within the summation bound
     gamma_m * sum |a u| of the fp64 result; pull repeats bit for bit."""
