@@ -359,7 +359,11 @@ grb_info grb_vxm(grb_vector w, grb_vector mask, grb_binop accum, grb_semiring s,
  * stored entries A(u, v) from u to v (push reads the CSR of A, pull the
  * CSR of A^T; a symmetric matrix serves both).
  * Synchronises `stream` once per batch of levels (it reads the frontier
- * size back to detect the end).  d->max_iter caps the levels (0 = none).
+ * size back to detect the end); the first batch covers the depth expected
+ * of a random graph of A's size and mean degree, or the depth of the last
+ * search on A where that is larger (up to twice the estimate).  A's handle
+ * keeps that depth (an atomic int, so concurrent calls on one matrix stay
+ * safe; it affects speed only).  d->max_iter caps the levels (0 = none).
  * On graphs whose rows are short (at most 64 entries: road-like, high
  * diameter) the levels run back to back inside one kernel of 16 workgroups,
  * separated by a barrier of its own, while the frontier is small (a launch
