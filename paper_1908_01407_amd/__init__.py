@@ -257,9 +257,15 @@ def _ptr(t):
 
 
 def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    # the current stream's raw handle without building a Stream object
+    # (about 3 us per call that way); the public call where torch lacks it
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(raw(torch.cuda.current_device()))
 
 
 def workspace(op: int, A: "Matrix", k: int = 0, device=None):
@@ -509,7 +515,9 @@ def bfs(A: Matrix, source: int, *, parents: bool = True, desc: Descriptor | None
     check(_lib.grb_bfs(_ptr(lev), _ptr(par), A.handle, int(source),
                        ctypes.byref(desc) if desc is not None else None, _ptr(ws), ws.numel(),
                        _stream(stream)), "grb_bfs")
-    return lev[: A.nrows], (par[: A.nrows] if par is not None else None)
+    n = A.nrows  # views only where the buffers are longer than n
+    return (lev if lev.numel() == n else lev[:n]), \
+        (par if par is None or par.numel() == n else par[:n])
 
 
 def sssp(A: Matrix, source: int, *, delta: float | None = None, desc: Descriptor | None = None,
