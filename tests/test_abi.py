@@ -193,3 +193,24 @@ def test_mxm_argument_errors(grb):
     sz = ctypes.c_size_t()
     assert grb.grb_workspace_size(6, None, 0, ctypes.byref(sz)) == 0 and sz.value >= 8
     assert grb.grb_matrix_free(ctypes.byref(h)) == 0
+
+
+def test_stream_handle_lookup(grb, monkeypatch):
+    """The binding passes the current stream's raw handle: through torch's
+    raw-handle call for the current device when torch has it, else through
+    the public Stream object; an explicit stream's handle is used as given."""
+    import types
+
+    calls = []
+    fast = types.SimpleNamespace(
+        _C=types.SimpleNamespace(_cuda_getCurrentRawStream=lambda dev: calls.append(dev) or 0x5000 + dev),
+        cuda=types.SimpleNamespace(current_device=lambda: 3,
+                                   current_stream=lambda: pytest.fail("public path taken")))
+    monkeypatch.setattr(grb, "_torch", lambda: fast)
+    assert grb._stream(None).value == 0x5003 and calls == [3]
+    slow = types.SimpleNamespace(
+        _C=types.SimpleNamespace(),
+        cuda=types.SimpleNamespace(current_stream=lambda: types.SimpleNamespace(cuda_stream=0x77)))
+    monkeypatch.setattr(grb, "_torch", lambda: slow)
+    assert grb._stream(None).value == 0x77
+    assert grb._stream(types.SimpleNamespace(cuda_stream=0x99)).value == 0x99
